@@ -1,0 +1,256 @@
+"""FP64 CPU oracle for the HISQ even-odd Dslash, CG, multi-shift CG, PTC
+preconditioner and flexible CG.
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the library.  It shares no code with the
+HIP path.  The arithmetic lives in ``hisq_oracle.c`` (plain C, OpenMP over
+sites); this module marshals numpy arrays into it and adds the plain Adam
+step used to check the optimiser kernel.
+
+Every function pins to something outside itself in ``tests/test_oracle_*.py``
+(anti-Hermiticity, free-field closed form, gauge covariance, dense solves,
+finite differences).  The one exception is noted where it occurs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hisq_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+    return _lib
+
+
+_IA4 = ctypes.c_int * 4
+
+
+def _dims(dims):
+    return _IA4(*[int(x) for x in dims])
+
+
+def _c(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _links(fat, lng):
+    f, fp = _c(fat)
+    l, lp = _c(lng)
+    return (f, l), fp, lp
+
+
+def dslash_full(dims, fat, lng, psi):
+    """D psi on the full lattice; psi [V][3] -> [V][3]."""
+    lib = _load()
+    keep, fp, lp = _links(fat, lng)
+    a, ap = _c(psi)
+    out = np.empty_like(a)
+    lib.orc_dslash_full(_dims(dims), fp, lp, ap, out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def dslash_half(dims, fat, lng, out_parity, psi_half):
+    """D_eo (out_parity 0) or D_oe (1) on half vectors [V/2][3]."""
+    lib = _load()
+    keep, fp, lp = _links(fat, lng)
+    a, ap = _c(psi_half)
+    out = np.empty_like(a)
+    lib.orc_dslash_half(_dims(dims), fp, lp, ctypes.c_int(out_parity), ap,
+                        out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def apply_A(dims, fat, lng, mass, psi_even, sigma=0.0):
+    """(4 m^2 + sigma - D_eo D_oe) psi on even vectors."""
+    lib = _load()
+    keep, fp, lp = _links(fat, lng)
+    a, ap = _c(psi_even)
+    out = np.empty_like(a)
+    lib.orc_apply_A(_dims(dims), fp, lp, ctypes.c_double(mass), ctypes.c_double(sigma), ap,
+                    out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def true_residual(dims, fat, lng, mass, b, x, sigma=0.0):
+    """||b - (A + sigma) x|| / ||b|| in FP64."""
+    lib = _load()
+    lib.orc_true_residual.restype = ctypes.c_double
+    keep, fp, lp = _links(fat, lng)
+    bb, bp = _c(b)
+    xx, xp = _c(x)
+    return lib.orc_true_residual(_dims(dims), fp, lp, ctypes.c_double(mass),
+                                 ctypes.c_double(sigma), bp, xp)
+
+
+def cg(dims, fat, lng, mass, b, tol=1e-10, maxiter=100000, sigma=0.0, x0=None):
+    """Returns (x, iterations, true relative residual, converged)."""
+    lib = _load()
+    keep, fp, lp = _links(fat, lng)
+    bb, bp = _c(b)
+    x = np.zeros_like(bb) if x0 is None else np.array(x0, dtype=np.complex128, copy=True)
+    it = ctypes.c_int(0)
+    tr = ctypes.c_double(0)
+    rc = lib.orc_cg(_dims(dims), fp, lp, ctypes.c_double(mass), ctypes.c_double(sigma), bp,
+                    x.ctypes.data_as(ctypes.c_void_p), ctypes.c_double(tol),
+                    ctypes.c_int(maxiter), ctypes.byref(it), ctypes.byref(tr))
+    return x, it.value, tr.value, rc == 0
+
+
+def multishift(dims, fat, lng, mass, shifts, b, tol=1e-8, maxiter=100000):
+    """Returns (x [nshift][h][3], iters[nshift], rel[nshift], converged)."""
+    lib = _load()
+    keep, fp, lp = _links(fat, lng)
+    bb, bp = _c(b)
+    shifts = np.ascontiguousarray(shifts, dtype=np.float64)
+    ns = len(shifts)
+    x = np.zeros((ns,) + bb.shape, dtype=np.complex128)
+    iters = np.zeros(ns, dtype=np.int32)
+    rel = np.zeros(ns)
+    rc = lib.orc_multishift(_dims(dims), fp, lp, ctypes.c_double(mass), ctypes.c_int(ns),
+                            shifts.ctypes.data_as(ctypes.c_void_p), bp,
+                            x.ctypes.data_as(ctypes.c_void_p), ctypes.c_double(tol),
+                            ctypes.c_int(maxiter), iters.ctypes.data_as(ctypes.c_void_p),
+                            rel.ctypes.data_as(ctypes.c_void_p))
+    return x, iters, rel, rc == 0
+
+
+def ptc_layer(dims, fat, w, act):
+    """One PTC layer: w [cout][cin][9], act [cin][V][3] -> [cout][V][3]."""
+    lib = _load()
+    f, fp = _c(fat)
+    w, wp = _c(w)
+    a, ap = _c(act)
+    cout, cin = w.shape[0], w.shape[1]
+    out = np.empty((cout,) + a.shape[1:], dtype=np.complex128)
+    lib.orc_ptc_layer(_dims(dims), fp, ctypes.c_int(cin), ctypes.c_int(cout), wp, ap,
+                      out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def ptc_layer_adj(dims, fat, w, act, gout, need_gin=True):
+    """(g_in or None, g_w) of one PTC layer for output gradient gout."""
+    lib = _load()
+    f, fp = _c(fat)
+    w, wp = _c(w)
+    a, ap = _c(act)
+    g, gp = _c(gout)
+    cout, cin = w.shape[0], w.shape[1]
+    gw = np.empty_like(w)
+    gin = np.empty_like(a) if need_gin else None
+    lib.orc_ptc_layer_adj(_dims(dims), fp, ctypes.c_int(cin), ctypes.c_int(cout), wp, ap, gp,
+                          gin.ctypes.data_as(ctypes.c_void_p) if need_gin else None,
+                          gw.ctypes.data_as(ctypes.c_void_p))
+    return gin, gw
+
+
+def _flat_weights(weights):
+    return np.concatenate([np.ascontiguousarray(w, dtype=np.complex128).ravel()
+                           for w in weights])
+
+
+def ptc_apply(dims, fat, weights, r_even):
+    """z = M(r): even embed -> layers -> even projection.  weights: list of
+    [cout][cin][9] arrays."""
+    lib = _load()
+    f, fp = _c(fat)
+    chans = np.array([weights[0].shape[1]] + [w.shape[0] for w in weights], dtype=np.int32)
+    wf = _flat_weights(weights)
+    r, rp = _c(r_even)
+    z = np.empty_like(r)
+    lib.orc_ptc_apply(_dims(dims), fp, ctypes.c_int(len(weights)),
+                      chans.ctypes.data_as(ctypes.c_void_p),
+                      wf.ctypes.data_as(ctypes.c_void_p), rp,
+                      z.ctypes.data_as(ctypes.c_void_p))
+    return z
+
+
+def fcg(dims, fat, lng, mass, weights, b, tol=1e-10, maxiter=100000):
+    """Flexible CG with the PTC network as preconditioner (weights=None: the
+    identity).  Returns (x, iterations, true relative residual, converged)."""
+    lib = _load()
+    keep, fp, lp = _links(fat, lng)
+    bb, bp = _c(b)
+    x = np.zeros_like(bb)
+    it = ctypes.c_int(0)
+    tr = ctypes.c_double(0)
+    if weights:
+        chans = np.array([weights[0].shape[1]] + [w.shape[0] for w in weights], dtype=np.int32)
+        wf = _flat_weights(weights)
+        nl, cp, wp = len(weights), chans.ctypes.data_as(ctypes.c_void_p), \
+            wf.ctypes.data_as(ctypes.c_void_p)
+    else:
+        nl, cp, wp = 0, None, None
+    rc = lib.orc_fcg(_dims(dims), fp, lp, ctypes.c_double(mass), ctypes.c_int(nl), cp, wp,
+                     bp, x.ctypes.data_as(ctypes.c_void_p), ctypes.c_double(tol),
+                     ctypes.c_int(maxiter), ctypes.byref(it), ctypes.byref(tr))
+    return x, it.value, tr.value, rc == 0
+
+
+def ptc_loss_and_grad(dims, fat, weights, r_even_batch, e_even_batch):
+    """Loss = mean_i ||M(r_i) - e_i||^2 / ||e_i||^2 and its weight gradients
+    (dL/dRe w + i dL/dIm w), by the layer adjoints, over a batch of pairs."""
+    V = int(np.prod(dims))
+    nl = len(weights)
+    even = _even_lex(dims)
+    grads = [np.zeros_like(w, dtype=np.complex128) for w in weights]
+    loss = 0.0
+    npair = len(r_even_batch)
+    for r, e in zip(r_even_batch, e_even_batch):
+        a = np.zeros((1, V, 3), dtype=np.complex128)
+        a[0, even] = r
+        acts = [a]
+        for w in weights:
+            acts.append(ptc_layer(dims, fat, w, acts[-1]))
+        z = acts[-1][0, even]
+        ee = float(np.vdot(e, e).real)
+        diff = z - e
+        loss += float(np.vdot(diff, diff).real) / ee / npair
+        g = np.zeros((1, V, 3), dtype=np.complex128)
+        g[0, even] = 2.0 * diff / ee / npair
+        for l in range(nl - 1, -1, -1):
+            gin, gw = ptc_layer_adj(dims, fat, weights[l], acts[l], g, need_gin=(l > 0))
+            grads[l] += gw
+            g = gin
+    return loss, grads
+
+
+def _even_lex(dims):
+    L0, L1, L2, L3 = dims
+    t, z, y, x = np.meshgrid(np.arange(L3), np.arange(L2), np.arange(L1), np.arange(L0),
+                             indexing="ij")
+    par = ((x + y + z + t) % 2).reshape(-1)
+    return np.nonzero(par == 0)[0]
+
+
+def adam_step(param, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam (Kingma & Ba 2015) on real arrays; step counts from 1.  Returns the
+    new (param, m, v).  Complex parameters are handled as (Re, Im) pairs by the
+    caller."""
+    m = beta1 * m + (1 - beta1) * grad
+    v = beta2 * v + (1 - beta2) * grad * grad
+    mhat = m / (1 - beta1 ** step)
+    vhat = v / (1 - beta2 ** step)
+    return param - lr * mhat / (np.sqrt(vhat) + eps), m, v

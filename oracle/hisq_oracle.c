@@ -1,0 +1,464 @@
+/*
+ * CPU oracle for the HISQ staggered even-odd solver hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, FP64 statement of
+ * what the GPU library computes.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load it; the library never does, and the
+ * two share no code, headers or tables.
+ *
+ * The paper (Sections 4 and 4.1) benchmarks the staggered single-mass and
+ * multi-shift conjugate gradient of MILC's HISQ action, a matrix-vector
+ * stencil at low arithmetic intensity (Section 4.2, the 0.26 flop/byte
+ * figure).  It never writes the operator down, so the definitions below are
+ * the standard ones, stated here:
+ *
+ *   geometry  lex(x) = x0 + L0 (x1 + L1 (x2 + L2 x3)), periodic, parity
+ *             (x0+x1+x2+x3) mod 2; even-parity vectors are indexed by lex/2.
+ *   Dslash    (D psi)(x) = sum_mu [ F_mu(x) psi(x+mu) - F_mu(x-mu)^+ psi(x-mu)
+ *                                 + L_mu(x) psi(x+3mu) - L_mu(x-3mu)^+ psi(x-3mu) ]
+ *             with the staggered phases already folded into F (fat) and L
+ *             (long); no factor 1/2.  M = 2m + D, so on even sites
+ *             M^+M = A = 4 m^2 - D_eo D_oe.
+ *   CG        Hestenes-Stiefel on A (+ sigma), true-residual restart.
+ *   MS-CG     shifted CG with collinear residuals (Jegerlehner,
+ *             hep-lat/9612014), base system = smallest shift.
+ *   PTC       gauge-covariant parallel-transport convolution layer and its
+ *             exact adjoint (input and weight gradients).
+ *   FCG       flexible CG with truncation 1 (Notay 2000) with the PTC network
+ *             as preconditioner.
+ *
+ * Complex numbers are C99 double complex; fields are site-major:
+ *   links   [V][4][3][3]          (row-major 3x3)
+ *   vectors [V][3] (full) or [V/2][3] (one parity, index lex/2)
+ *   PTC activations [C][V][3], weights [Cout][Cin][9] with path
+ *   0 = identity, 1+2mu = +mu hop F_mu(x) psi(x+mu),
+ *   2+2mu = -mu hop F_mu(x-mu)^+ psi(x-mu).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ---------------------------------------------------------------- geometry */
+
+static long vol(const int d[4]) { return (long)d[0] * d[1] * d[2] * d[3]; }
+
+static void coords_of(const int d[4], long s, int x[4])
+{
+    x[0] = (int)(s % d[0]); s /= d[0];
+    x[1] = (int)(s % d[1]); s /= d[1];
+    x[2] = (int)(s % d[2]); s /= d[2];
+    x[3] = (int)s;
+}
+
+static long lex_of(const int d[4], const int x[4])
+{
+    return x[0] + (long)d[0] * (x[1] + (long)d[1] * (x[2] + (long)d[2] * x[3]));
+}
+
+/* site reached from s by k steps along mu, periodic */
+static long hop(const int d[4], long s, int mu, int k)
+{
+    int x[4];
+    coords_of(d, s, x);
+    x[mu] = ((x[mu] + k) % d[mu] + d[mu]) % d[mu];
+    return lex_of(d, x);
+}
+
+static int parity_of(const int d[4], long s)
+{
+    int x[4];
+    coords_of(d, s, x);
+    return (x[0] + x[1] + x[2] + x[3]) & 1;
+}
+
+/* ------------------------------------------------------- 3x3 helpers */
+
+/* y += U v */
+static void mv_add(cplx *y, const cplx *U, const cplx *v, cplx c)
+{
+    for (int i = 0; i < 3; i++) {
+        cplx a = 0;
+        for (int j = 0; j < 3; j++) a += U[3 * i + j] * v[j];
+        y[i] += c * a;
+    }
+}
+
+/* y += U^+ v */
+static void mhv_add(cplx *y, const cplx *U, const cplx *v, cplx c)
+{
+    for (int i = 0; i < 3; i++) {
+        cplx a = 0;
+        for (int j = 0; j < 3; j++) a += conj(U[3 * j + i]) * v[j];
+        y[i] += c * a;
+    }
+}
+
+static const cplx *link(const cplx *f, long s, int mu) { return f + (s * 4 + mu) * 9; }
+
+/* ------------------------------------------------------------- Dslash */
+
+/* Full-lattice D (eq. above).  in, out: [V][3]. */
+void orc_dslash_full(const int d[4], const cplx *fat, const cplx *lng,
+                     const cplx *in, cplx *out)
+{
+    long V = vol(d);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        cplx acc[3] = {0, 0, 0};
+        for (int mu = 0; mu < 4; mu++) {
+            long sp1 = hop(d, s, mu, 1), sm1 = hop(d, s, mu, -1);
+            long sp3 = hop(d, s, mu, 3), sm3 = hop(d, s, mu, -3);
+            mv_add(acc, link(fat, s, mu), in + 3 * sp1, 1.0);
+            mhv_add(acc, link(fat, sm1, mu), in + 3 * sm1, -1.0);
+            mv_add(acc, link(lng, s, mu), in + 3 * sp3, 1.0);
+            mhv_add(acc, link(lng, sm3, mu), in + 3 * sm3, -1.0);
+        }
+        for (int c = 0; c < 3; c++) out[3 * s + c] = acc[c];
+    }
+}
+
+/* Half-lattice D restricted to output parity `par` (0: D_eo, 1: D_oe).
+ * in_half: [V/2][3] on parity 1-par, out_half: [V/2][3] on parity par,
+ * both indexed by lex/2. */
+void orc_dslash_half(const int d[4], const cplx *fat, const cplx *lng, int par,
+                     const cplx *in_half, cplx *out_half)
+{
+    long V = vol(d);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        if (parity_of(d, s) != par) continue;
+        cplx acc[3] = {0, 0, 0};
+        for (int mu = 0; mu < 4; mu++) {
+            long sp1 = hop(d, s, mu, 1), sm1 = hop(d, s, mu, -1);
+            long sp3 = hop(d, s, mu, 3), sm3 = hop(d, s, mu, -3);
+            mv_add(acc, link(fat, s, mu), in_half + 3 * (sp1 / 2), 1.0);
+            mhv_add(acc, link(fat, sm1, mu), in_half + 3 * (sm1 / 2), -1.0);
+            mv_add(acc, link(lng, s, mu), in_half + 3 * (sp3 / 2), 1.0);
+            mhv_add(acc, link(lng, sm3, mu), in_half + 3 * (sm3 / 2), -1.0);
+        }
+        for (int c = 0; c < 3; c++) out_half[3 * (s / 2) + c] = acc[c];
+    }
+}
+
+/* out = (4 m^2 + sigma) in - D_eo D_oe in, on even vectors */
+void orc_apply_A(const int d[4], const cplx *fat, const cplx *lng, double mass,
+                 double sigma, const cplx *in, cplx *out)
+{
+    long h3 = vol(d) / 2 * 3;
+    cplx *t = malloc(sizeof(cplx) * h3);
+    orc_dslash_half(d, fat, lng, 1, in, t);
+    orc_dslash_half(d, fat, lng, 0, t, out);
+    double diag = 4.0 * mass * mass + sigma;
+    for (long i = 0; i < h3; i++) out[i] = diag * in[i] - out[i];
+    free(t);
+}
+
+/* ------------------------------------------------------- vector helpers */
+
+static double nrm2(const cplx *a, long n)
+{
+    double s = 0;
+    for (long i = 0; i < n; i++) s += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
+    return s;
+}
+
+static cplx dotc(const cplx *a, const cplx *b, long n) /* a^+ b */
+{
+    cplx s = 0;
+    for (long i = 0; i < n; i++) s += conj(a[i]) * b[i];
+    return s;
+}
+
+/* ||b - (A+sigma) x|| / ||b|| */
+double orc_true_residual(const int d[4], const cplx *fat, const cplx *lng, double mass,
+                         double sigma, const cplx *b, const cplx *x)
+{
+    long n = vol(d) / 2 * 3;
+    cplx *Ax = malloc(sizeof(cplx) * n);
+    orc_apply_A(d, fat, lng, mass, sigma, x, Ax);
+    double rr = 0;
+    for (long i = 0; i < n; i++) {
+        cplx r = b[i] - Ax[i];
+        rr += creal(r) * creal(r) + cimag(r) * cimag(r);
+    }
+    free(Ax);
+    return sqrt(rr / nrm2(b, n));
+}
+
+/* ------------------------------------------------------------------ CG */
+
+/* Conjugate gradient on (A + sigma) x = b.  x is the initial guess on entry
+ * (pass zeros for a cold start).  Stops when the recursive residual reaches
+ * tol*||b||, then recomputes the true residual and restarts from x if that is
+ * still above tol.  Returns 0 on convergence, 1 otherwise; *iters is the
+ * total iteration count and *true_rel the final true relative residual. */
+int orc_cg(const int d[4], const cplx *fat, const cplx *lng, double mass, double sigma,
+           const cplx *b, cplx *x, double tol, int maxiter, int *iters, double *true_rel)
+{
+    long n = vol(d) / 2 * 3;
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n),
+         *Ap = malloc(sizeof(cplx) * n);
+    double bb = nrm2(b, n);
+    int it = 0, ok = 0;
+    for (int restart = 0; restart < 10 && it < maxiter; restart++) {
+        orc_apply_A(d, fat, lng, mass, sigma, x, Ap);
+        for (long i = 0; i < n; i++) r[i] = b[i] - Ap[i];
+        double rr = nrm2(r, n);
+        if (rr <= tol * tol * bb) { ok = 1; break; }
+        memcpy(p, r, sizeof(cplx) * n);
+        while (it < maxiter) {
+            orc_apply_A(d, fat, lng, mass, sigma, p, Ap);
+            double pAp = creal(dotc(p, Ap, n));
+            double alpha = rr / pAp;
+            for (long i = 0; i < n; i++) { x[i] += alpha * p[i]; r[i] -= alpha * Ap[i]; }
+            double rr_new = nrm2(r, n);
+            it++;
+            if (rr_new <= tol * tol * bb) break;
+            double beta = rr_new / rr;
+            for (long i = 0; i < n; i++) p[i] = r[i] + beta * p[i];
+            rr = rr_new;
+        }
+        double tr = orc_true_residual(d, fat, lng, mass, sigma, b, x);
+        if (tr <= tol) { ok = 1; break; }
+    }
+    *iters = it;
+    *true_rel = orc_true_residual(d, fat, lng, mass, sigma, b, x);
+    free(r); free(p); free(Ap);
+    return ok ? 0 : 1;
+}
+
+/* ---------------------------------------------------------- multi-shift CG */
+
+/* Solves (A + shifts[k]) x_k = b for all k with one Krylov space built on the
+ * smallest shift.  x: [nshift][V/2][3] (overwritten; cold start).  Shift k
+ * stops updating once |zeta_k| ||r|| <= tol ||b||.  Afterwards each shift
+ * whose true residual is above tol is refined with orc_cg from its x_k.
+ * iters[k]: Krylov iterations that updated shift k (plus refinement);
+ * rel[k]: final true relative residual. */
+int orc_multishift(const int d[4], const cplx *fat, const cplx *lng, double mass,
+                   int nshift, const double *shifts, const cplx *b, cplx *x,
+                   double tol, int maxiter, int *iters, double *rel)
+{
+    long n = vol(d) / 2 * 3;
+    int k0 = 0;
+    for (int k = 1; k < nshift; k++) if (shifts[k] < shifts[k0]) k0 = k;
+    double s0 = shifts[k0];
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n),
+         *Ap = malloc(sizeof(cplx) * n), *ps = malloc(sizeof(cplx) * n * nshift);
+    double *zeta = malloc(sizeof(double) * nshift), *zeta_old = malloc(sizeof(double) * nshift);
+    int *active = malloc(sizeof(int) * nshift);
+    double bb = nrm2(b, n);
+    memcpy(r, b, sizeof(cplx) * n);
+    memcpy(p, b, sizeof(cplx) * n);
+    for (int k = 0; k < nshift; k++) {
+        memcpy(ps + k * n, b, sizeof(cplx) * n);
+        memset(x + k * n, 0, sizeof(cplx) * n);
+        zeta[k] = zeta_old[k] = 1.0;
+        active[k] = 1;
+        iters[k] = 0;
+    }
+    double rr = bb, alpha_old = 1.0, beta_old = 0.0;
+    int it = 0;
+    while (it < maxiter) {
+        orc_apply_A(d, fat, lng, mass, s0, p, Ap);
+        double alpha = rr / creal(dotc(p, Ap, n));
+        for (long i = 0; i < n; i++) r[i] -= alpha * Ap[i];
+        double rr_new = nrm2(r, n);
+        double beta = rr_new / rr;
+        int any = 0;
+        for (int k = 0; k < nshift; k++) {
+            if (!active[k]) continue;
+            double dk = shifts[k] - s0;
+            double z = zeta[k], zo = zeta_old[k];
+            double zn = z * zo * alpha_old /
+                        (alpha * beta_old * (zo - z) + zo * alpha_old * (1.0 + dk * alpha));
+            double ak = alpha * zn / z;
+            double bk = beta * (zn / z) * (zn / z);
+            cplx *xk = x + k * n, *pk = ps + k * n;
+            for (long i = 0; i < n; i++) {
+                xk[i] += ak * pk[i];
+                pk[i] = zn * r[i] + bk * pk[i];
+            }
+            zeta_old[k] = z;
+            zeta[k] = zn;
+            iters[k]++;
+            if (fabs(zn) * sqrt(rr_new) <= tol * sqrt(bb)) active[k] = 0;
+            else any = 1;
+        }
+        for (long i = 0; i < n; i++) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+        alpha_old = alpha;
+        beta_old = beta;
+        it++;
+        if (!any) break;
+    }
+    int ok = 1;
+    for (int k = 0; k < nshift; k++) {
+        double tr = orc_true_residual(d, fat, lng, mass, shifts[k], b, x + k * n);
+        if (tr > tol) {
+            int more = 0;
+            double tr2;
+            if (orc_cg(d, fat, lng, mass, shifts[k], b, x + k * n, tol, maxiter, &more, &tr2))
+                ok = 0;
+            iters[k] += more;
+        }
+        rel[k] = orc_true_residual(d, fat, lng, mass, shifts[k], b, x + k * n);
+    }
+    free(r); free(p); free(Ap); free(ps); free(zeta); free(zeta_old); free(active);
+    return ok ? 0 : 1;
+}
+
+/* ------------------------------------------------------------ PTC layer */
+
+/* out[c](x) = sum_{c'} sum_k w[c][c'][k] (T_k in[c'])(x),
+ *   T_0 psi = psi, T_{1+2mu} psi(x) = F_mu(x) psi(x+mu),
+ *   T_{2+2mu} psi(x) = F_mu(x-mu)^+ psi(x-mu).
+ * in: [cin][V][3], out: [cout][V][3], w: [cout][cin][9]. */
+void orc_ptc_layer(const int d[4], const cplx *fat, int cin, int cout, const cplx *w,
+                   const cplx *in, cplx *out)
+{
+    long V = vol(d);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        for (int c = 0; c < cout; c++) {
+            cplx acc[3] = {0, 0, 0};
+            for (int cp = 0; cp < cin; cp++) {
+                const cplx *wk = w + ((long)c * cin + cp) * 9;
+                const cplx *ps = in + (long)cp * V * 3;
+                for (int j = 0; j < 3; j++) acc[j] += wk[0] * ps[3 * s + j];
+                for (int mu = 0; mu < 4; mu++) {
+                    long sp = hop(d, s, mu, 1), sm = hop(d, s, mu, -1);
+                    mv_add(acc, link(fat, s, mu), ps + 3 * sp, wk[1 + 2 * mu]);
+                    mhv_add(acc, link(fat, sm, mu), ps + 3 * sm, wk[2 + 2 * mu]);
+                }
+            }
+            for (int j = 0; j < 3; j++) out[((long)c * V + s) * 3 + j] = acc[j];
+        }
+    }
+}
+
+/* Adjoint of orc_ptc_layer for a real loss.  With g_out = dL/dRe(out) +
+ * i dL/dIm(out):
+ *   g_in[c'](y) = sum_c [ conj(w0) g_c(y) + sum_mu conj(w_{+mu}) F_mu(y-mu)^+ g_c(y-mu)
+ *                                        + conj(w_{-mu}) F_mu(y) g_c(y+mu) ]
+ *   g_w[c][c'][k] = sum_x (T_k in[c'])(x)^+ g_c(x).
+ * g_in may be NULL (first layer). */
+void orc_ptc_layer_adj(const int d[4], const cplx *fat, int cin, int cout, const cplx *w,
+                       const cplx *in, const cplx *gout, cplx *gin, cplx *gw)
+{
+    long V = vol(d);
+    if (gin) {
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < V; s++) {
+            for (int cp = 0; cp < cin; cp++) {
+                cplx acc[3] = {0, 0, 0};
+                for (int c = 0; c < cout; c++) {
+                    const cplx *wk = w + ((long)c * cin + cp) * 9;
+                    const cplx *g = gout + (long)c * V * 3;
+                    for (int j = 0; j < 3; j++) acc[j] += conj(wk[0]) * g[3 * s + j];
+                    for (int mu = 0; mu < 4; mu++) {
+                        long sp = hop(d, s, mu, 1), sm = hop(d, s, mu, -1);
+                        mhv_add(acc, link(fat, sm, mu), g + 3 * sm, conj(wk[1 + 2 * mu]));
+                        mv_add(acc, link(fat, s, mu), g + 3 * sp, conj(wk[2 + 2 * mu]));
+                    }
+                }
+                for (int j = 0; j < 3; j++) gin[((long)cp * V + s) * 3 + j] = acc[j];
+            }
+        }
+    }
+    for (int c = 0; c < cout; c++)
+        for (int cp = 0; cp < cin; cp++) {
+            cplx sum[9] = {0};
+            const cplx *ps = in + (long)cp * V * 3;
+            const cplx *g = gout + (long)c * V * 3;
+            for (long s = 0; s < V; s++) {
+                cplx t[9][3];
+                memset(t, 0, sizeof t);
+                for (int j = 0; j < 3; j++) t[0][j] = ps[3 * s + j];
+                for (int mu = 0; mu < 4; mu++) {
+                    long sp = hop(d, s, mu, 1), sm = hop(d, s, mu, -1);
+                    mv_add(t[1 + 2 * mu], link(fat, s, mu), ps + 3 * sp, 1.0);
+                    mhv_add(t[2 + 2 * mu], link(fat, sm, mu), ps + 3 * sm, 1.0);
+                }
+                for (int k = 0; k < 9; k++)
+                    for (int j = 0; j < 3; j++) sum[k] += conj(t[k][j]) * g[3 * s + j];
+            }
+            for (int k = 0; k < 9; k++) gw[((long)c * cin + cp) * 9 + k] = sum[k];
+        }
+}
+
+/* -------------------------------------------------- PTC network + FCG */
+
+/* Preconditioner z = M(r) on even vectors: embed r on even sites (zeros on
+ * odd), apply nlayer PTC layers with channel counts chans[0..nlayer], project
+ * the output onto even sites.  weights: concatenation of every layer's
+ * [Cout][Cin][9] block.  chans[0] = chans[nlayer] = 1. */
+void orc_ptc_apply(const int d[4], const cplx *fat, int nlayer, const int *chans,
+                   const cplx *weights, const cplx *r_even, cplx *z_even)
+{
+    long V = vol(d);
+    int cmax = 1;
+    for (int l = 0; l <= nlayer; l++) if (chans[l] > cmax) cmax = chans[l];
+    cplx *a = calloc((size_t)cmax * V * 3, sizeof(cplx));
+    cplx *b = calloc((size_t)cmax * V * 3, sizeof(cplx));
+    for (long s = 0; s < V; s++)
+        if (parity_of(d, s) == 0)
+            for (int j = 0; j < 3; j++) a[3 * s + j] = r_even[3 * (s / 2) + j];
+    const cplx *w = weights;
+    for (int l = 0; l < nlayer; l++) {
+        orc_ptc_layer(d, fat, chans[l], chans[l + 1], w, a, b);
+        w += (long)chans[l] * chans[l + 1] * 9;
+        cplx *t = a; a = b; b = t;
+    }
+    for (long s = 0; s < V; s++)
+        if (parity_of(d, s) == 0)
+            for (int j = 0; j < 3; j++) z_even[3 * (s / 2) + j] = a[3 * s + j];
+    free(a); free(b);
+}
+
+/* Flexible CG, truncation 1, on A x = b with z = M(r) (M = the PTC network
+ * above, or the identity when nlayer == 0):
+ *   r = b - A x, z = M(r), p = z; repeat { q = A p; alpha = (p,r)/(p,q);
+ *   x += alpha p; r -= alpha q; z = M(r); beta = -(q,z)/(q,p); p = z + beta p },
+ * with (a,b) = a^+ b.  beta makes the new p A-orthogonal to the old one,
+ * (p_new, A p_old) = 0; for complex vectors that puts q in the first slot.
+ * Stop on the recursive residual, then check the true residual and restart
+ * from x if needed.  Returns 0 on convergence. */
+int orc_fcg(const int d[4], const cplx *fat, const cplx *lng, double mass, int nlayer,
+            const int *chans, const cplx *weights, const cplx *b, cplx *x, double tol,
+            int maxiter, int *iters, double *true_rel)
+{
+    long n = vol(d) / 2 * 3;
+    cplx *r = malloc(sizeof(cplx) * n), *z = malloc(sizeof(cplx) * n),
+         *p = malloc(sizeof(cplx) * n), *q = malloc(sizeof(cplx) * n);
+    double bb = nrm2(b, n);
+    int it = 0, ok = 0;
+    for (int restart = 0; restart < 10 && it < maxiter; restart++) {
+        orc_apply_A(d, fat, lng, mass, 0.0, x, q);
+        for (long i = 0; i < n; i++) r[i] = b[i] - q[i];
+        if (nrm2(r, n) <= tol * tol * bb) { ok = 1; break; }
+        if (nlayer > 0) orc_ptc_apply(d, fat, nlayer, chans, weights, r, z);
+        else memcpy(z, r, sizeof(cplx) * n);
+        memcpy(p, z, sizeof(cplx) * n);
+        while (it < maxiter) {
+            orc_apply_A(d, fat, lng, mass, 0.0, p, q);
+            cplx pq = dotc(p, q, n);
+            cplx alpha = dotc(p, r, n) / pq;
+            for (long i = 0; i < n; i++) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+            it++;
+            if (nrm2(r, n) <= tol * tol * bb) break;
+            if (nlayer > 0) orc_ptc_apply(d, fat, nlayer, chans, weights, r, z);
+            else memcpy(z, r, sizeof(cplx) * n);
+            cplx beta = -dotc(q, z, n) / conj(pq);
+            for (long i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+        }
+        if (orc_true_residual(d, fat, lng, mass, 0.0, b, x) <= tol) { ok = 1; break; }
+    }
+    *iters = it;
+    *true_rel = orc_true_residual(d, fat, lng, mass, 0.0, b, x);
+    free(r); free(z); free(p); free(q);
+    return ok ? 0 : 1;
+}

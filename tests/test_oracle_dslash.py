@@ -1,0 +1,193 @@
+"""Pins for the oracle's Dslash and normal operator, each from outside the
+oracle: a dense matrix assembled here from the stencil definition, the
+anti-Hermiticity of D, parity structure, the closed-form free-field spectrum,
+an FFT statement of D^2 on unit links, and gauge covariance."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_00143_amd import synth
+
+
+def _dense_D(dims, fat, lng):
+    """Dense full-lattice D assembled term by term from
+    (D psi)(x) = sum_mu F(x)psi(x+mu) - F(x-mu)^+psi(x-mu) + L(x)psi(x+3mu) - L(x-3mu)^+psi(x-3mu).
+    Terms that alias on small lattices accumulate (+=)."""
+    V = synth.volume(dims)
+    c = synth.coords(dims)
+    D = np.zeros((3 * V, 3 * V), dtype=np.complex128)
+
+    def lex(x):
+        return int(x[0] + dims[0] * (x[1] + dims[1] * (x[2] + dims[2] * x[3])))
+
+    for s in range(V):
+        for mu in range(4):
+            for k, U in ((1, fat), (3, lng)):
+                xp = c[s].copy(); xp[mu] = (xp[mu] + k) % dims[mu]
+                xm = c[s].copy(); xm[mu] = (xm[mu] - k) % dims[mu]
+                sp, sm = lex(xp), lex(xm)
+                D[3 * s:3 * s + 3, 3 * sp:3 * sp + 3] += U[s, mu]
+                D[3 * s:3 * s + 3, 3 * sm:3 * sm + 3] -= U[sm, mu].conj().T
+    return D
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (4, 2, 6, 4)])
+def test_dslash_matches_dense_assembly(dims):
+    fat, lng = synth.make_links(dims, 0.3, seed=11)
+    D = _dense_D(dims, fat, lng)
+    V = synth.volume(dims)
+    psi = synth.gaussian_full(dims, 5)[0]
+    out = oracle.dslash_full(dims, fat, lng, psi)
+    ref = (D @ psi.reshape(-1)).reshape(V, 3)
+    assert np.linalg.norm(out - ref) <= 1e-13 * np.linalg.norm(ref)
+    # half-lattice versions are blocks of the same matrix
+    ev, od = synth.even_sites(dims), synth.odd_sites(dims)
+    psi_o = psi[od]
+    full = np.zeros((V, 3), complex); full[od] = psi_o
+    ref_e = (D @ full.reshape(-1)).reshape(V, 3)[ev]
+    out_e = oracle.dslash_half(dims, fat, lng, 0, psi_o)
+    assert np.linalg.norm(out_e - ref_e) <= 1e-13 * np.linalg.norm(ref_e)
+    psi_e = psi[ev]
+    full = np.zeros((V, 3), complex); full[ev] = psi_e
+    ref_o = (D @ full.reshape(-1)).reshape(V, 3)[od]
+    out_o = oracle.dslash_half(dims, fat, lng, 1, psi_e)
+    assert np.linalg.norm(out_o - ref_o) <= 1e-13 * np.linalg.norm(ref_o)
+
+
+def test_even_odd_index_is_lex_half():
+    dims = (4, 2, 6, 4)
+    ev, od = synth.even_sites(dims), synth.odd_sites(dims)
+    assert np.array_equal(ev // 2, np.arange(len(ev)))
+    assert np.array_equal(od // 2, np.arange(len(od)))
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 8, 10)])
+def test_anti_hermitian(dims):
+    fat, lng = synth.make_links(dims, 0.3, seed=3)
+    h = synth.volume(dims) // 2
+    rng = np.random.default_rng(9)
+    phi_e = rng.standard_normal((h, 3)) + 1j * rng.standard_normal((h, 3))
+    psi_o = rng.standard_normal((h, 3)) + 1j * rng.standard_normal((h, 3))
+    lhs = np.vdot(phi_e, oracle.dslash_half(dims, fat, lng, 0, psi_o))
+    rhs = -np.vdot(oracle.dslash_half(dims, fat, lng, 1, phi_e), psi_o)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    # full operator: <a, D b> = -<D a, b>
+    a = synth.gaussian_full(dims, 1)[0]
+    b = synth.gaussian_full(dims, 2)[0]
+    l2 = np.vdot(a, oracle.dslash_full(dims, fat, lng, b))
+    r2 = -np.vdot(oracle.dslash_full(dims, fat, lng, a), b)
+    assert abs(l2 - r2) <= 1e-13 * abs(l2)
+
+
+def test_parity_blocks_vanish():
+    dims = (4, 4, 4, 6)
+    fat, lng = synth.make_links(dims, 0.3, seed=4)
+    V = synth.volume(dims)
+    ev, od = synth.even_sites(dims), synth.odd_sites(dims)
+    psi = np.zeros((V, 3), complex)
+    psi[ev] = synth.gaussian_even(dims, 8)
+    out = oracle.dslash_full(dims, fat, lng, psi)
+    assert np.abs(out[ev]).max() == 0.0          # D_ee = 0
+    assert np.abs(out[od]).max() > 0.1
+
+
+def _free_spectrum(dims):
+    """4 sum_mu (sin p_mu - sin 3p_mu / 24)^2 for every momentum."""
+    ps = [2 * np.pi * np.arange(L) / L for L in dims]
+    vals = []
+    for p in itertools.product(*ps):
+        vals.append(4 * sum((math.sin(q) - math.sin(3 * q) / 24) ** 2 for q in p))
+    return np.array(vals)
+
+
+def test_free_field_spectrum_4444():
+    """Unit links: spec(-D_eo D_oe) is half the multiset of the momentum-space
+    eigenvalues of -D^2, times 3 colours; on 4^4 that is {4 (25/24)^2 k} with
+    multiplicity 24*C(4,k)."""
+    dims = (4, 4, 4, 4)
+    fat, lng = synth.unit_links(dims)
+    m = 0.1
+    h = synth.volume(dims) // 2
+    A = np.zeros((3 * h, 3 * h), complex)
+    I = np.eye(3 * h)
+    for j in range(3 * h):
+        A[:, j] = oracle.apply_A(dims, fat, lng, m, I[j].reshape(h, 3)).reshape(-1)
+    assert np.abs(A - A.conj().T).max() < 1e-14
+    ev = np.sort(np.linalg.eigvalsh(A) - 4 * m * m)
+    golden = np.loadtxt(__file__.replace("test_oracle_dslash.py", "golden/free_field_4444.txt"))
+    expect = np.sort(np.repeat(golden[:, 0], golden[:, 1].astype(int)))
+    assert len(expect) == 3 * h
+    assert np.abs(ev - expect).max() < 1e-12
+    # and the same from the momentum sum
+    mom = np.sort(np.repeat(_free_spectrum(dims), 3))[::2]
+    assert np.abs(np.sort(mom) - expect).max() < 1e-12
+
+
+def test_free_field_D_squared_fft():
+    """On unit links D^2 = sum_mu nabla_mu^2 with nabla = (T - T^-1) - (T^3 - T^-3)/24,
+    diagonal in momentum space with eigenvalue -4 sum_mu (sin p - sin 3p/24)^2."""
+    dims = (6, 4, 8, 10)
+    fat, lng = synth.unit_links(dims)
+    psi = synth.gaussian_full(dims, 12)[0]
+    D2 = oracle.dslash_full(dims, fat, lng, oracle.dslash_full(dims, fat, lng, psi))
+    L0, L1, L2, L3 = dims
+    f = psi.reshape(L3, L2, L1, L0, 3)
+    fk = np.fft.fftn(f, axes=(0, 1, 2, 3))
+    lam = np.zeros((L3, L2, L1, L0))
+    for mu, L in enumerate(dims):
+        p = 2 * np.pi * np.arange(L) / L
+        s = (np.sin(p) - np.sin(3 * p) / 24) ** 2
+        shape = [1, 1, 1, 1]
+        shape[3 - mu] = L
+        lam = lam + s.reshape(shape)
+    ref = np.fft.ifftn(-4 * lam[..., None] * fk, axes=(0, 1, 2, 3)).reshape(-1, 3)
+    assert np.linalg.norm(D2 - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_gauge_covariance():
+    dims = (4, 6, 4, 8)
+    fat, lng = synth.make_links(dims, 0.3, seed=21)
+    V = synth.volume(dims)
+    G = synth.random_su3(V, seed=22)
+
+    def shifted(a, mu, k):
+        return synth._shift(a, dims, mu, k)
+
+    fat2 = np.empty_like(fat)
+    lng2 = np.empty_like(lng)
+    for mu in range(4):
+        fat2[:, mu] = G @ fat[:, mu] @ np.conj(np.swapaxes(shifted(G, mu, 1), -1, -2))
+        lng2[:, mu] = G @ lng[:, mu] @ np.conj(np.swapaxes(shifted(G, mu, 3), -1, -2))
+    psi = synth.gaussian_full(dims, 23)[0]
+    out = oracle.dslash_full(dims, fat, lng, psi)
+    out2 = oracle.dslash_full(dims, fat2, lng2, np.einsum("sij,sj->si", G, psi))
+    ref = np.einsum("sij,sj->si", G, out)
+    assert np.linalg.norm(out2 - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_normal_operator_bounds():
+    dims = (4, 4, 4, 4)
+    fat, lng = synth.make_links(dims, 0.3, seed=0)
+    m = 0.1
+    h = synth.volume(dims) // 2
+    I = np.eye(3 * h)
+    A = np.stack([oracle.apply_A(dims, fat, lng, m, I[j].reshape(h, 3)).reshape(-1)
+                  for j in range(3 * h)], axis=1)
+    assert np.abs(A - A.conj().T).max() < 1e-13
+    lam = np.linalg.eigvalsh(A)
+    assert lam.min() >= 4 * m * m - 1e-12
+
+
+def test_long_link_phase_fold_order():
+    """eta_mu does not depend on x_mu, so folding the phases before or after
+    the three-link product gives the same long links."""
+    dims = (4, 4, 6, 4)
+    fb = synth.base_links(dims, 0.3, 5)
+    eta = synth.staggered_phases(dims)[:, :, None, None]
+    lb_after = synth.fold_phases(synth.long_from_base(fb, dims), dims)
+    fp = fb * eta
+    prod = synth.long_from_base(fp, dims)   # eta^3 = eta
+    assert np.abs(prod - lb_after).max() < 1e-15
