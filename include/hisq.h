@@ -1,0 +1,211 @@
+/*
+ * hisq.h -- C ABI of the MI355X HISQ staggered Dslash / CG library.
+ *
+ * What it computes.  The paper (DeTar, Gottlieb, Li, Toussaint, "MILC Code
+ * Performance on High End CPU and GPU Supercomputer Clusters", Lattice 2017)
+ * benchmarks MILC's staggered multi-shift and single-mass conjugate gradient
+ * for HISQ quarks (Section 4, Section 4.1), whose inner work is the
+ * matrix-vector stencil (Section 4.2).  The operator is the standard even-odd
+ * HISQ staggered Dslash on a periodic local lattice:
+ *
+ *   (D psi)(x) = sum_mu [ F_mu(x) psi(x+mu) - F_mu(x-mu)^+ psi(x-mu)
+ *                       + L_mu(x) psi(x+3mu) - L_mu(x-3mu)^+ psi(x-3mu) ],
+ *
+ * with fat links F and long (Naik) links L that already carry the staggered
+ * phases eta_mu(x) = (-1)^(x_0+...+x_{mu-1}).  M = 2m + D, and the solvers
+ * work on even sites with A = M^+M|_even = 4m^2 - D_eo D_oe (+ sigma).
+ *
+ * Conventions shared by every entry point:
+ *   - lattice extents L0..L3 are even and >= 2; lex(x) = x0 + L0(x1 + L1(x2 + L2 x3));
+ *   - links: complex FP64 [V][4][3][3] (re, im interleaved, row-major 3x3),
+ *     V = L0 L1 L2 L3 sites in lex order, mu = 0..3 <-> x, y, z, t;
+ *   - a parity vector holds V/2 sites, site index lex(x)/2 over the sites of
+ *     that parity, 3 colours per site: complex [V/2][3];
+ *     device vectors may be FP64 (16 B per complex), FP32 (8 B) or FP16:
+ *     an FP16 vector is [V/2][3] half2 followed immediately by [V/2] float
+ *     per-site scales (value = half * scale); nrhs vectors are stored back to
+ *     back;
+ *   - every function returns a hisq_status; nothing throws or aborts across
+ *     the ABI.  Details of the last error: hisq_last_error().
+ *   - ownership: the caller owns every pointer it passes; the library copies
+ *     what it needs before returning (solvers) or before the enqueued work
+ *     completes (hisq_dslash with device pointers) and keeps no caller
+ *     pointer.  hisq_destroy frees everything the handle allocated.
+ *   - streams: all device work of a handle goes to its stream.  Solvers return
+ *     synchronised; hisq_dslash on device pointers is asynchronous.
+ *   - threads: one handle per host thread at a time.
+ */
+#ifndef HISQ_H
+#define HISQ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hisq_lattice_s *hisq_lattice;
+typedef struct hisq_ptc_s *hisq_ptc;
+
+typedef enum {
+    HISQ_OK = 0,
+    HISQ_ERR_ARG = -1,            /* invalid argument (extents, mass, tol, sizes, null pointers) */
+    HISQ_ERR_HIP = -2,            /* a HIP runtime call failed */
+    HISQ_ERR_OOM = -3,            /* device allocation failed */
+    HISQ_ERR_STATE = -4,          /* call out of order (e.g. no links loaded) */
+    HISQ_ERR_RECON = -5,          /* links are not a * sign * SU(3): recon-12 impossible */
+    HISQ_ERR_NOT_CONVERGED = -6,  /* maxiter reached; x and info hold the best iterate */
+    HISQ_ERR_BREAKDOWN = -7       /* non-positive p.Ap or non-finite scalar */
+} hisq_status;
+
+typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16 = 2 } hisq_prec;
+typedef enum { HISQ_RECON_18 = 18, HISQ_RECON_12 = 12 } hisq_recon;
+typedef enum { HISQ_EVEN = 0, HISQ_ODD = 1 } hisq_parity;
+
+enum {
+    HISQ_DEVICE_PTR = 1,   /* vector / link pointers are device pointers */
+    HISQ_X_IS_GUESS = 2,   /* solvers: x holds an initial guess (else cold start) */
+    HISQ_USE_GRAPH = 4,    /* solvers: replay captured HIP graphs of iteration chunks */
+    HISQ_NO_TUNE = 8       /* use default launch shapes, skip the autotuner */
+};
+
+typedef struct {
+    double tol;          /* target FP64 true relative residual ||b - A x|| / ||b|| */
+    int maxiter;         /* iteration cap (Krylov iterations, all precisions) */
+    hisq_prec sloppy;    /* precision of the iteration: F64 = plain CG; F32 / F16 = mixed
+                            precision with FP64 reliable updates */
+    hisq_recon recon;    /* link reconstruction of the sloppy operator */
+    double delta;        /* reliable update when ||r|| < delta * max ||r|| since the last one */
+    int check_every;     /* iterations per launched chunk between host status checks */
+    int flags;           /* HISQ_DEVICE_PTR | HISQ_X_IS_GUESS | HISQ_USE_GRAPH | HISQ_NO_TUNE */
+} hisq_solver_params;
+
+typedef struct {
+    int iters;               /* Krylov iterations */
+    int reliable_updates;    /* FP64 true-residual recomputations */
+    int converged;           /* 1 if the FP64 true residual reached tol */
+    int status;              /* hisq_status of this solve */
+    double true_residual;    /* final FP64 ||b - A x|| / ||b|| */
+    double time_s;           /* wall time of the solve call (excludes link loading) */
+    double dslash_bytes;     /* algorithmic bytes moved by the Dslash applications */
+    double flops;            /* algorithmic flops (1146 per half-Dslash output site) */
+    double t_done_s;         /* batch solves: device time from start to convergence */
+} hisq_solver_info;
+
+/* Fill params with defaults: tol 1e-10, maxiter 100000, F64, recon 18,
+ * delta 0.1, check_every 16, flags 0. */
+void hisq_default_params(hisq_solver_params *p);
+
+const char *hisq_status_string(hisq_status s);
+
+/* Last error message of the handle (or of the last failed hisq_create when
+ * lat is NULL), copied into buf (n bytes, NUL-terminated). */
+hisq_status hisq_last_error(hisq_lattice lat, char *buf, size_t n);
+
+/* Create a handle for one periodic local lattice on `device`.  stream: a
+ * hipStream_t to enqueue on, or NULL for a stream the handle creates (default
+ * priority).  Errors: HISQ_ERR_ARG for extents that are odd or < 2. */
+hisq_status hisq_create(const int dims[4], int device, void *stream, hisq_lattice *out);
+hisq_status hisq_destroy(hisq_lattice lat);
+
+/* Load fat and long links (layout above, phases folded; host pointers, or
+ * device pointers with HISQ_DEVICE_PTR).  Keeps a device FP64 copy and packs
+ * the FP64 recon-18 operator.  Discards earlier link sets. */
+hisq_status hisq_load_links(hisq_lattice lat, const double *fat, const double *lng, int flags);
+
+/* Build the packed operator in precision `prec` with reconstruction `recon`
+ * from the loaded FP64 links (on the device).  Recon-12 requires each link to
+ * be c * SU(3), c = s * eta_mu(x) * a with one a > 0 and one s = +-1 per
+ * field; it returns HISQ_ERR_RECON if row 3 is not recovered to 1e-10 * a. */
+hisq_status hisq_prepare_links(hisq_lattice lat, hisq_prec prec, hisq_recon recon);
+
+/* out = D_{out_parity, 1-out_parity} in, i.e. D_eo (HISQ_EVEN) or D_oe
+ * (HISQ_ODD).  `prec` is the precision of links and vectors; the link set
+ * (prec, recon) must have been prepared (FP64 recon-18 always is).  With
+ * HISQ_DEVICE_PTR, in/out are device vectors in precision prec, nrhs of them
+ * back to back (nrhs > 1 uses the multi-right-hand-side kernel, FP32/FP16
+ * only); without it they are host FP64 vectors, converted by the library.
+ * Asynchronous on device pointers. */
+hisq_status hisq_dslash(hisq_lattice lat, hisq_parity out_parity, hisq_prec prec,
+                        hisq_recon recon, const void *in, void *out, int nrhs, int flags);
+
+/* Solve (4m^2 - D_eo D_oe) x = b on even sites (host FP64 vectors, or device
+ * FP64 with HISQ_DEVICE_PTR).  Plain FP64 CG when params->sloppy == HISQ_F64;
+ * otherwise the iteration runs in FP32 or FP16 storage (FP32 arithmetic) and
+ * FP64 reliable updates recompute x and the true residual.  Stops when the
+ * FP64 true residual is <= tol.  info may be NULL. */
+hisq_status hisq_cg(hisq_lattice lat, double mass, const double *b, double *x,
+                    const hisq_solver_params *params, hisq_solver_info *info);
+
+/* Multi-shift CG (Section 4.1): solve (A + shifts[k]) x_{j,k} = b_j for
+ * nshift <= 64 shifts and nrhs right-hand sides with one Krylov space per
+ * right-hand side (base system = smallest shift, FP64 zeta/alpha/beta
+ * recurrences on the device), the nrhs spaces sharing one multi-RHS Dslash.
+ * b: nrhs host FP64 vectors back to back; x: nrhs*nshift vectors, index
+ * j*nshift + k.  Each shift stops when |zeta_k| ||r|| <= tol ||b||; shifts
+ * whose FP64 true residual is above tol are then refined with mixed CG.
+ * info: nrhs*nshift entries (or NULL). */
+hisq_status hisq_multishift_cg(hisq_lattice lat, double mass, int nshift, const double *shifts,
+                               int nrhs, const double *b, double *x,
+                               const hisq_solver_params *params, hisq_solver_info *info);
+
+/* Batched solve of nprob independent systems, one per handle (each with its
+ * own links, extents and mass), all advanced by the same kernel launches over
+ * a flattened tile list, with per-problem FP64 scalars and a device status
+ * mask.  b[k], x[k]: host FP64 vectors of problem k.  All handles must be on
+ * the same device; the first handle's stream is used.  info: nprob entries. */
+hisq_status hisq_batch_cg(int nprob, const hisq_lattice *lats, const double *masses,
+                          const double *const *b, double *const *x,
+                          const hisq_solver_params *params, hisq_solver_info *info);
+
+/* ---- learned preconditioner: gauge-covariant parallel-transport network ----
+ *
+ * Layer l maps C_in to C_out channels of full-lattice colour vectors:
+ *   out_c(x) = sum_{c'} [ w0 psi_c'(x) + sum_mu ( w_{+mu} F_mu(x) psi_c'(x+mu)
+ *                                         + w_{-mu} F_mu(x-mu)^+ psi_c'(x-mu) ) ]
+ * with 9 complex weights per (c, c') (path order: 0 = identity,
+ * 1+2mu = +mu, 2+2mu = -mu) and the fat links F.  The network embeds an even
+ * vector on the full lattice (zeros on odd sites), applies the layers and
+ * projects the output back to even sites; z = M(r) is the preconditioner of
+ * the flexible CG.
+ */
+
+/* nlayer layers, chans[0..nlayer] channel counts (chans[0] = chans[nlayer] = 1,
+ * all <= 8).  Weights start at zero. */
+hisq_status hisq_ptc_create(hisq_lattice lat, int nlayer, const int *chans, hisq_ptc *out);
+hisq_status hisq_ptc_destroy(hisq_ptc net);
+/* Weights as complex FP64, layer by layer [Cout][Cin][9]; set writes the
+ * FP32 master copy and the FP16 inference copy. */
+hisq_status hisq_ptc_set_weights(hisq_ptc net, const double *w);
+hisq_status hisq_ptc_get_weights(hisq_ptc net, double *w);
+/* One layer on device FP32 activations [C][V][3] complex (lex order):
+ * forward out = L_l(in); backward gin = L_l^+(gout) (gin may be NULL) and
+ * gw = sum_x (T_k in)^+ gout (complex FP64 [Cout][Cin][9], host or device
+ * per flags). */
+hisq_status hisq_ptc_layer_forward(hisq_ptc net, int layer, const void *in, void *out, int flags);
+hisq_status hisq_ptc_layer_backward(hisq_ptc net, int layer, const void *in, const void *gout,
+                                    void *gin, double *gw, int flags);
+/* z = M(r) on device even vectors (FP32 complex), using the FP16 weights. */
+hisq_status hisq_ptc_apply(hisq_ptc net, const void *r, void *z, int flags);
+/* Generate training pairs: plain FP32/FP64 CG on b (host FP64), storing the
+ * residual r_i and error e_i = x* - x_i every `every` iterations, at most
+ * maxpairs.  Pairs are appended to the network's device pair store.
+ * Returns the number of pairs stored in *npairs. */
+hisq_status hisq_ptc_harvest(hisq_ptc net, hisq_lattice lat, double mass, const double *b,
+                             int every, int maxpairs, int *npairs);
+/* Train on the stored pairs (all from lattices whose links are those of the
+ * handle each pair was harvested on): `steps` Adam steps (lr, beta1 0.9,
+ * beta2 0.999, eps 1e-8) on minibatches of `batch` pairs drawn with `seed`.
+ * Loss = mean ||M(r) - e||^2 / ||e||^2.  losses: steps entries or NULL. */
+hisq_status hisq_ptc_train(hisq_ptc net, int steps, int batch, double lr, unsigned long long seed,
+                           double *losses);
+/* Flexible CG (truncation 1) with z = M(r), FP32 iteration and FP64 true
+ * residual; falls back to hisq_cg from the current x on breakdown or if the
+ * iteration count exceeds params->maxiter / 2. */
+hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double mass, const double *b,
+                            double *x, const hisq_solver_params *params, hisq_solver_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HISQ_H */

@@ -1,0 +1,201 @@
+// Half-lattice HISQ Dslash: for every site x of the output parity,
+//   out(x) = sum_mu [ F_mu(x) in(x+mu) - F_mu(x-mu)^+ in(x-mu)
+//                   + L_mu(x) in(x+3mu) - L_mu(x-3mu)^+ in(x-3mu) ]
+// (fat one-hop plus Naik three-hop, staggered phases folded into the links).
+// The paper describes this matrix-vector stencil as the inner work of the
+// staggered CG (Section 4.2: matrix-vector multiplies, 0.26 flop/byte).
+//
+// Work decomposition: a block owns one 64-site tile; its W wavefronts split
+// the 16 hop directions (16/W each), so every load instruction of a wave reads
+// 64 consecutive link records of one direction block.  Partial colour vectors
+// are summed through LDS in a fixed order, and wave 0 runs the epilogue:
+//   PLAIN  out = D in
+//   AX     out = diag*aux - D in,   partial Re(aux^+ out)      (CG: A p, p.Ap)
+//   RES    out = b - diag*aux + D in, partial |out|^2           (FP64 true residual)
+// Reductions finish inside the kernel (last tile of each problem).
+#include "finish.h"
+#include "fields.h"
+#include "launch.h"
+#include "reduce.h"
+
+namespace hisq {
+
+template <class LT, int R, class ST, class OT, int W, int EPI>
+__global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
+{
+    using A = typename AccOf<LT>::type;
+    static_assert(16 % W == 0, "W must divide 16");
+    constexpr int DPW = 16 / W;
+    using F = LinkFmt<LT, R>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, a.remap);
+    const int prob = a.tile2prob ? a.tile2prob[tile] : 0;
+    const ProbDesc &pd = a.probs[prob];
+    if (a.states && a.states[prob].status != a.want) return;
+    const int i = (tile - pd.tile_begin) * TILE + lane;
+    const bool valid = i < pd.h;
+    const int h = pd.h;
+    const LinkSet &ls = pd.ls[a.lslot];
+
+    Cx<A> acc[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) acc[c] = {(A)0, (A)0};
+
+    Coord co;
+    if (valid) {
+        co = cb_to_coord(i, a.out_par, pd.L);
+        const char *lbase = (const char *)ls.ptr[a.out_par];
+        Spin<ST> in{(ST *)a.in, (float *)a.in_nrm};
+#pragma unroll
+        for (int dd = 0; dd < DPW; dd++) {
+            const int d = wave * DPW + dd;
+            const int mu = d >> 2;
+            const int n = hop_cb(co, mu, dir_step(d), pd.L);
+            Cx<A> u[3][3], v[3];
+            load_link<LT, R, A>(lbase + (size_t)d * h * F::BYTES, i, h, u);
+            load_spinor<ST, A>(in, pd.voff + n, v);
+            Cx<A> y[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                Cx<A> s = cmul(u[r][0], v[0]);
+                Cx<A> t1 = cmul(u[r][1], v[1]);
+                Cx<A> t2 = cmul(u[r][2], v[2]);
+                y[r] = {s.re + t1.re + t2.re, s.im + t1.im + t2.im};
+            }
+            if constexpr (R == 12 || sizeof(LT) == 2) {
+                const int fld = (d & 2) ? 1 : 0;
+                A coef = (A)ls.a[fld];
+                if constexpr (R == 12) {
+                    int sg = ls.s[fld] * eta_sign(co, mu) * ((d & 1) ? -1 : 1);
+                    coef = sg < 0 ? -coef : coef;
+                }
+#pragma unroll
+                for (int r = 0; r < 3; r++) {
+                    acc[r].re += coef * y[r].re;
+                    acc[r].im += coef * y[r].im;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 3; r++) {
+                    acc[r].re += y[r].re;
+                    acc[r].im += y[r].im;
+                }
+            }
+        }
+    }
+
+    if constexpr (W > 1) {
+        __shared__ A red[(W > 1 ? W - 1 : 1) * 6 * 64];
+        if (wave > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                red[((wave - 1) * 6 + 2 * c) * 64 + lane] = acc[c].re;
+                red[((wave - 1) * 6 + 2 * c + 1) * 64 + lane] = acc[c].im;
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            for (int w = 1; w < W; w++) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    acc[c].re += red[((w - 1) * 6 + 2 * c) * 64 + lane];
+                    acc[c].im += red[((w - 1) * 6 + 2 * c + 1) * 64 + lane];
+                }
+            }
+        }
+    }
+
+    double part = 0.0;
+    if (wave == 0 && valid) {
+        const long long o = pd.voff + i;
+        Spin<OT> out{(OT *)a.out, a.out_nrm};
+        if constexpr (EPI == EPI_PLAIN) {
+            store_spinor<OT, A>(out, o, acc);
+        } else if constexpr (EPI == EPI_AX) {
+            Spin<ST> aux{(ST *)a.aux, (float *)a.aux_nrm};
+            Cx<A> p[3], v[3];
+            load_spinor<ST, A>(aux, o, p);
+            const A dg = (A)pd.diag;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                v[c] = {dg * p[c].re - acc[c].re, dg * p[c].im - acc[c].im};
+                part += (double)p[c].re * (double)v[c].re + (double)p[c].im * (double)v[c].im;
+            }
+            store_spinor<OT, A>(out, o, v);
+        } else {  // EPI_RES
+            Spin<ST> aux{(ST *)a.aux, (float *)a.aux_nrm};
+            Cx<A> x[3], v[3];
+            load_spinor<ST, A>(aux, o, x);
+            const double2 *b = reinterpret_cast<const double2 *>(a.bvec) + o * 3;
+            const A dg = (A)pd.diag;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                double2 bb = b[c];
+                v[c] = {(A)bb.x - dg * x[c].re + acc[c].re, (A)bb.y - dg * x[c].im + acc[c].im};
+                part += (double)v[c].re * (double)v[c].re + (double)v[c].im * (double)v[c].im;
+            }
+            store_spinor<OT, A>(out, o, v);
+        }
+    }
+    if constexpr (EPI != EPI_PLAIN) {
+        if (a.fin != FIN_NONE) {
+            double mine[1] = {part}, tot[1];
+            if (publish_and_reduce<1>(mine, a.partials, tile, pd, &a.states[prob], tot)) {
+                if (threadIdx.x == 0) run_finisher(a.fin, &a.states[prob], tot);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+template <class LT, int R, class ST, class OT, int EPI>
+static hipError_t launch_w(int W, const DslashLaunch &a, int nblocks, hipStream_t s)
+{
+    switch (W) {
+    case 1: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 1, EPI>), dim3(nblocks), dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 2, EPI>), dim3(nblocks), dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 4, EPI>), dim3(nblocks), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 8, EPI>), dim3(nblocks), dim3(512), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 16, EPI>), dim3(nblocks), dim3(1024), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class LT, class ST, class OT, int EPI>
+static hipError_t launch_r(int recon, int W, const DslashLaunch &a, int nb, hipStream_t s)
+{
+    return recon == 12 ? launch_w<LT, 12, ST, OT, EPI>(W, a, nb, s)
+                       : launch_w<LT, 18, ST, OT, EPI>(W, a, nb, s);
+}
+
+// prec: 0 = FP64, 1 = FP32, 2 = FP16 (links and input vectors); out_prec may
+// differ from prec only for FP16 (out FP32).
+hipError_t launch_dslash(int prec, int recon, int out_prec, int epi, int W, const DslashLaunch &a,
+                         int nblocks, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (prec == 0) {
+        if (out_prec != 0) return hipErrorInvalidValue;
+        switch (epi) {
+        case EPI_PLAIN: return launch_r<double, double, double, EPI_PLAIN>(recon, W, a, nblocks, s);
+        case EPI_AX: return launch_r<double, double, double, EPI_AX>(recon, W, a, nblocks, s);
+        case EPI_RES: return launch_r<double, double, double, EPI_RES>(recon, W, a, nblocks, s);
+        }
+    } else if (prec == 1) {
+        if (out_prec != 1) return hipErrorInvalidValue;
+        switch (epi) {
+        case EPI_PLAIN: return launch_r<float, float, float, EPI_PLAIN>(recon, W, a, nblocks, s);
+        case EPI_AX: return launch_r<float, float, float, EPI_AX>(recon, W, a, nblocks, s);
+        }
+    } else if (prec == 2) {
+        if (epi == EPI_PLAIN && out_prec == 2)
+            return launch_r<__half, __half, __half, EPI_PLAIN>(recon, W, a, nblocks, s);
+        if (epi == EPI_AX && out_prec == 1)
+            return launch_r<__half, __half, float, EPI_AX>(recon, W, a, nblocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace hisq

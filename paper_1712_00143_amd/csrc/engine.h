@@ -1,0 +1,90 @@
+// Host-side engine: lattice handles, device workspaces, launch-shape tuner and
+// the solver drivers behind the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hisq.h"
+#include "launch.h"
+
+namespace hisq {
+
+struct DVec {
+    void *p = nullptr;
+    float *n = nullptr;     // FP16 per-site scales (inside the same allocation)
+    size_t bytes = 0;
+    int prec = -1;
+    long long sites = 0;
+};
+
+size_t vec_bytes(int prec, long long sites);
+hipError_t dvec_alloc(DVec &v, int prec, long long sites);
+void dvec_free(DVec &v);
+
+// Work set of one (possibly batched) solve: concatenated parity vectors of
+// nprob problems, per-problem descriptors and FP64 states.
+struct SolveSet {
+    int nprob = 0;
+    int ntile = 0;
+    long long nsite = 0;
+    int mode = -1;
+    std::vector<ProbDesc> hdesc;
+    ProbDesc *ddesc = nullptr;
+    int *dt2p = nullptr;        // nullptr when nprob == 1
+    SolveState *dst = nullptr;
+    SolveState *hst = nullptr;  // pinned host mirror
+    double *dpart = nullptr;
+    DVec b, xhi, rhi, thi, xlo, rlo, Ap, p, t;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::string gkey;
+    ~SolveSet();
+    void release();
+};
+
+struct TuneChoice {
+    int W = 4;
+    int remap = 1;
+    double us = 0;
+};
+
+// Launch-shape autotuner: times every candidate block shape of a kernel for a
+// given problem geometry once, caches the fastest (in memory and, when
+// HISQ_TUNE_CACHE names a file, on disk).
+class Tuner {
+  public:
+    static Tuner &get();
+    bool lookup(const std::string &key, TuneChoice &c);
+    void store(const std::string &key, const TuneChoice &c);
+
+  private:
+    Tuner();
+    std::mutex mu_;
+    std::map<std::string, TuneChoice> cache_;
+    std::string path_;
+};
+
+}  // namespace hisq
+
+struct hisq_lattice_s {
+    int L[4];
+    long long V = 0, h = 0;
+    int ntile = 0;
+    int device = 0;
+    hipStream_t s = nullptr;
+    bool own_stream = false;
+    double *fat64 = nullptr, *lng64 = nullptr;     // device FP64 copies [V][4][3][3]
+    void *lk[hisq::NLINKSET][2] = {};
+    hisq::LinkSet ls[hisq::NLINKSET] = {};
+    bool loaded = false;
+    std::string err;
+    hisq::SolveSet cg;         // single-lattice solve workspace
+    hisq::SolveSet batch;      // batched solves led by this handle
+    hisq::DVec tmp_in, tmp_out, tmp64a, tmp64b;  // host-pointer Dslash staging
+    hisq::ProbDesc *ddesc = nullptr;             // this lattice alone
+    double *dpart = nullptr;
+};

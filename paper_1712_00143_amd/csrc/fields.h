@@ -1,0 +1,152 @@
+// Storage formats of links and colour vectors, and the small complex 3x3
+// algebra the stencil kernels use.
+//
+// Links: per output parity, 16 direction blocks of h links; a link of R reals
+// (R = 18: full 3x3 complex, row-major; R = 12: the first two rows) is split
+// into 16-byte chunks stored plane by plane ([dir][chunk][h]) followed by one
+// remainder plane of 4 or 8 bytes, so that each load instruction of a
+// wavefront reads one contiguous 1 KiB (or 256/512 B) segment.
+//
+// Colour vectors: [site][3] complex of double, float or half; half vectors
+// carry a per-site float scale (the max |component|), stored separately.
+#pragma once
+#include "hisq_dev.h"
+
+namespace hisq {
+
+template <class T> struct AccOf { using type = float; };
+template <> struct AccOf<double> { using type = double; };
+
+template <class T, int R> struct LinkFmt {
+    static constexpr int BYTES = R * (int)sizeof(T);
+    static constexpr int NQ = BYTES / 16;
+    static constexpr int REM = BYTES % 16;
+};
+
+template <class A> struct Cx {
+    A re, im;
+};
+
+template <class A> __device__ __forceinline__ Cx<A> cmul(Cx<A> a, Cx<A> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+template <class A> __device__ __forceinline__ Cx<A> cconjmul(Cx<A> a, Cx<A> b)  // conj(a) b
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+
+template <class T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
+template <> __device__ __forceinline__ float to_f<__half>(__half v) { return __half2float(v); }
+
+// Load one packed link (R reals) of direction block `dirbase` at site i into
+// a 3x3 complex matrix; recon-12 rebuilds row 2 as conj(row0 x row1).
+template <class LT, int R, class A>
+__device__ __forceinline__ void load_link(const char *__restrict__ dirbase, int i, int h,
+                                          Cx<A> u[3][3])
+{
+    using F = LinkFmt<LT, R>;
+    uint32_t raw[F::BYTES / 4];
+#pragma unroll
+    for (int q = 0; q < F::NQ; q++) {
+        uint4 v = *reinterpret_cast<const uint4 *>(dirbase + ((size_t)q * h + i) * 16);
+        raw[4 * q + 0] = v.x;
+        raw[4 * q + 1] = v.y;
+        raw[4 * q + 2] = v.z;
+        raw[4 * q + 3] = v.w;
+    }
+    if constexpr (F::REM == 8) {
+        uint2 v = *reinterpret_cast<const uint2 *>(dirbase + (size_t)F::NQ * h * 16 + (size_t)i * 8);
+        raw[4 * F::NQ + 0] = v.x;
+        raw[4 * F::NQ + 1] = v.y;
+    } else if constexpr (F::REM == 4) {
+        uint32_t v = *reinterpret_cast<const uint32_t *>(dirbase + (size_t)F::NQ * h * 16 + (size_t)i * 4);
+        raw[4 * F::NQ] = v;
+    }
+    const LT *e = reinterpret_cast<const LT *>(raw);
+    constexpr int ROWS = R == 18 ? 3 : 2;
+#pragma unroll
+    for (int r = 0; r < ROWS; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            if constexpr (sizeof(LT) == 2) {
+                u[r][c].re = (A)to_f(e[6 * r + 2 * c]);
+                u[r][c].im = (A)to_f(e[6 * r + 2 * c + 1]);
+            } else {
+                u[r][c].re = (A)e[6 * r + 2 * c];
+                u[r][c].im = (A)e[6 * r + 2 * c + 1];
+            }
+        }
+    if constexpr (R == 12) {
+        // row2 = conj(row0 x row1)
+        Cx<A> a0 = u[0][0], a1 = u[0][1], a2 = u[0][2];
+        Cx<A> b0 = u[1][0], b1 = u[1][1], b2 = u[1][2];
+        Cx<A> c0 = cmul(a1, b2), c1 = cmul(a2, b0), c2 = cmul(a0, b1);
+        Cx<A> d0 = cmul(a2, b1), d1 = cmul(a0, b2), d2 = cmul(a1, b0);
+        u[2][0] = {c0.re - d0.re, -(c0.im - d0.im)};
+        u[2][1] = {c1.re - d1.re, -(c1.im - d1.im)};
+        u[2][2] = {c2.re - d2.re, -(c2.im - d2.im)};
+    }
+}
+
+// Colour-vector access --------------------------------------------------
+
+template <class ST> struct Spin {
+    ST *v;        // [sites][3] complex
+    float *nrm;   // per-site scale (half only)
+};
+
+template <class ST, class A>
+__device__ __forceinline__ void load_spinor(const Spin<ST> &s, long long i, Cx<A> out[3])
+{
+    if constexpr (sizeof(ST) == 8) {
+        const double2 *p = reinterpret_cast<const double2 *>(s.v) + i * 3;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            double2 v = p[c];
+            out[c] = {(A)v.x, (A)v.y};
+        }
+    } else if constexpr (sizeof(ST) == 4) {
+        const float2 *p = reinterpret_cast<const float2 *>(s.v) + i * 3;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            float2 v = p[c];
+            out[c] = {(A)v.x, (A)v.y};
+        }
+    } else {
+        const __half2 *p = reinterpret_cast<const __half2 *>(s.v) + i * 3;
+        float n = s.nrm[i];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            float2 v = __half22float2(p[c]);
+            out[c] = {(A)(v.x * n), (A)(v.y * n)};
+        }
+    }
+}
+
+template <class ST, class A>
+__device__ __forceinline__ void store_spinor(const Spin<ST> &s, long long i, const Cx<A> in[3])
+{
+    if constexpr (sizeof(ST) == 8) {
+        double2 *p = reinterpret_cast<double2 *>(s.v) + i * 3;
+#pragma unroll
+        for (int c = 0; c < 3; c++) p[c] = make_double2((double)in[c].re, (double)in[c].im);
+    } else if constexpr (sizeof(ST) == 4) {
+        float2 *p = reinterpret_cast<float2 *>(s.v) + i * 3;
+#pragma unroll
+        for (int c = 0; c < 3; c++) p[c] = make_float2((float)in[c].re, (float)in[c].im);
+    } else {
+        float m = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; c++) m = fmaxf(m, fmaxf(fabsf((float)in[c].re), fabsf((float)in[c].im)));
+        float inv = m > 0.f ? 1.f / m : 0.f;
+        __half2 *p = reinterpret_cast<__half2 *>(s.v) + i * 3;
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            p[c] = __floats2half2_rn((float)in[c].re * inv, (float)in[c].im * inv);
+        s.nrm[i] = m;
+    }
+}
+
+}  // namespace hisq

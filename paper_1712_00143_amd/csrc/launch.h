@@ -1,0 +1,97 @@
+// Kernel launch descriptors and launcher prototypes (host <-> kernel files).
+#pragma once
+#include "hisq_dev.h"
+
+namespace hisq {
+
+enum : int { EPI_PLAIN = 0, EPI_AX = 1, EPI_RES = 2 };
+
+struct DslashLaunch {
+    const ProbDesc *probs;
+    const int *tile2prob;   // nullptr: a single problem
+    int remap;              // XCD-aware tile order
+    int out_par;
+    int lslot;              // link set slot (prec*2 + (recon==12))
+    int want;               // status a problem must have to be processed
+    SolveState *states;     // nullptr: no status gating, no reductions
+    const void *in;
+    const float *in_nrm;
+    void *out;
+    float *out_nrm;
+    const void *aux;
+    const float *aux_nrm;
+    const double *bvec;
+    double *partials;
+    int fin;
+    int pad;
+};
+
+hipError_t launch_dslash(int prec, int recon, int out_prec, int epi, int W, const DslashLaunch &a,
+                         int nblocks, hipStream_t s);
+
+// Multi-RHS Dslash: nrhs vectors at stride vstride sites, links read once.
+struct MrhsLaunch {
+    const ProbDesc *probs;
+    int remap;
+    int out_par;
+    int lslot;
+    int nrhs;
+    long long vstride;     // sites between consecutive right-hand sides
+    const void *in;
+    void *out;
+    const void *aux;       // EPI_AX: p vectors (same stride)
+    double *partials;      // [tile][NPART]: per-rhs Re(p.Ap)
+    SolveState *states;    // per-rhs states (nrhs of them), nullptr for plain
+    const int *rhs_active; // nullptr: all
+    int epi;
+    int want;
+    double diag_shift;     // added to desc diag (multi-shift base shift)
+};
+
+hipError_t launch_dslash_mrhs(int prec, int recon, int nrhs, int W, const MrhsLaunch &a, int nblocks,
+                              hipStream_t s);
+
+// ---- packing
+struct PackLaunch {
+    const double *fat;   // device FP64 [V][4][3][3] complex
+    const double *lng;
+    int L[4];
+    int h;
+    int out_par;
+    void *dst;           // packed destination for this parity
+    double a[2];
+    int s[2];
+    unsigned long long *maxerr;  // recon-12 check: max |U - c*recon(W)| / a as double bits
+};
+hipError_t launch_pack(int prec, int recon, const PackLaunch &p, hipStream_t s);
+hipError_t launch_det_probe(const double *fat, const double *lng, double *out4, hipStream_t s);
+hipError_t launch_maxabs(const double *links, long long n, unsigned long long *out, hipStream_t s);
+
+// ---- CG vector kernels (blas.hip)
+struct BlasLaunch {
+    const ProbDesc *probs;
+    const int *tile2prob;
+    SolveState *states;
+    int want;
+    int fin;
+    double *partials;
+    void *v[6];
+    float *n[6];
+    double coef;
+};
+enum : int {
+    BL_RUPDATE = 0,   // r -= alpha Ap; x += alpha p; partial |r|^2; FIN_BETA
+    BL_PUPDATE = 1,   // p = r + beta p
+    BL_XACCUM = 2,    // x_hi += x_lo; x_lo = 0
+    BL_RESUME = 3,    // r_lo = r_hi; p = r_lo + beta p
+    BL_NORM = 4,      // partial |v0|^2 (FP64 vector)
+    BL_INIT = 5,      // r_lo = b; p = b; x_lo = 0 (cold start)
+    BL_STATUS = 6,    // RESUME -> RUNNING (one thread per problem)
+    BL_COPY_D2F = 7,  // v1 (prec) = v0 (FP64)
+    BL_COPY_F2D = 8,  // v1 (FP64) = v0 (prec)
+    BL_START = 9,     // r_lo = r_hi (v4); p = r_hi; x_lo = 0 (warm start)
+};
+hipError_t launch_stamp(long long *out, hipStream_t s);
+hipError_t launch_blas(int op, int prec, const BlasLaunch &a, int ntiles, int nprob, hipStream_t s);
+
+}  // namespace hisq

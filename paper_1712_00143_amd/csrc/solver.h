@@ -1,0 +1,31 @@
+// Solver drivers shared by the C-ABI entry points.
+#pragma once
+#include <vector>
+
+#include "engine.h"
+
+hisq_status set_err(hisq_lattice lat, hisq_status st, const std::string &msg);
+hisq_status hip_err(hisq_lattice lat, hipError_t e, const char *what);
+
+namespace hisq {
+
+ProbDesc lattice_desc(hisq_lattice lat);
+TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *ddesc, const int *dt2p,
+                      int ntile, long long nsite, int nprob, bool no_tune);
+
+// Describe nprob problems (one per handle) in S: descriptors, tile map,
+// states, partials.  sigma is added to every diagonal (4 m^2 + sigma).
+hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lattice> &lats,
+                      const std::vector<double> &masses, double sigma);
+
+// Mixed / plain CG over every problem of S.  b[k], x[k]: FP64 vectors
+// (host, or device with HISQ_DEVICE_PTR).  info: nprob entries or nullptr.
+hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm,
+                   const double *const *b, double *const *x, hisq_solver_info *info);
+
+size_t link_site_bytes(int prec, int recon);
+
+}  // namespace hisq
+
+hisq_status hisq_dslash_mrhs_impl(hisq_lattice lat, int out_parity, int prec, int recon,
+                                  const void *in, void *out, int nrhs, int flags);

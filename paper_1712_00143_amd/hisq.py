@@ -1,0 +1,251 @@
+"""ctypes binding of libhisq.so (the C ABI declared in include/hisq.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Functions keep the C names; ``Lattice`` and ``PTC`` wrap the
+handles.  Arrays may be numpy (host, complex128) or torch tensors on the GPU
+(passed by device pointer with HISQ_DEVICE_PTR).  The library must have been
+built (``paper_1712_00143_amd.build.build()``); importing this module without
+it raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhisq.so")
+
+HISQ_OK = 0
+HISQ_ERR_ARG = -1
+HISQ_ERR_HIP = -2
+HISQ_ERR_OOM = -3
+HISQ_ERR_STATE = -4
+HISQ_ERR_RECON = -5
+HISQ_ERR_NOT_CONVERGED = -6
+HISQ_ERR_BREAKDOWN = -7
+
+HISQ_F64, HISQ_F32, HISQ_F16 = 0, 1, 2
+HISQ_RECON_18, HISQ_RECON_12 = 18, 12
+HISQ_EVEN, HISQ_ODD = 0, 1
+HISQ_DEVICE_PTR, HISQ_X_IS_GUESS, HISQ_USE_GRAPH, HISQ_NO_TUNE = 1, 2, 4, 8
+
+EXPORTS = [
+    "hisq_default_params", "hisq_status_string", "hisq_last_error", "hisq_create", "hisq_destroy",
+    "hisq_load_links", "hisq_prepare_links", "hisq_dslash", "hisq_cg", "hisq_multishift_cg",
+    "hisq_batch_cg", "hisq_ptc_create", "hisq_ptc_destroy", "hisq_ptc_set_weights",
+    "hisq_ptc_get_weights", "hisq_ptc_layer_forward", "hisq_ptc_layer_backward", "hisq_ptc_apply",
+    "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned",
+]
+
+
+class hisq_solver_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("sloppy", ctypes.c_int),
+                ("recon", ctypes.c_int), ("delta", ctypes.c_double), ("check_every", ctypes.c_int),
+                ("flags", ctypes.c_int)]
+
+
+class hisq_solver_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int),
+                ("converged", ctypes.c_int), ("status", ctypes.c_int),
+                ("true_residual", ctypes.c_double), ("time_s", ctypes.c_double),
+                ("dslash_bytes", ctypes.c_double), ("flops", ctypes.c_double),
+                ("t_done_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class HisqError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # torch carries its own HIP runtime (same soname as the system one).
+        # Load it first so that the library binds to that runtime and one
+        # process never runs two HIP runtimes side by side.
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -m paper_1712_00143_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.hisq_status_string.restype = ctypes.c_char_p
+        L.hisq_default_params.restype = None
+        _lib = L
+    return _lib
+
+
+def hisq_status_string(status: int) -> str:
+    return lib().hisq_status_string(ctypes.c_int(status)).decode()
+
+
+def hisq_last_error(handle=None) -> str:
+    buf = ctypes.create_string_buffer(512)
+    lib().hisq_last_error(handle, buf, ctypes.c_size_t(512))
+    return buf.value.decode()
+
+
+def _check(st, handle=None, what=""):
+    if st != HISQ_OK:
+        raise HisqError(st, f"{what}: {hisq_status_string(st)}: {hisq_last_error(handle)}")
+
+
+def hisq_default_params(**kw) -> hisq_solver_params:
+    p = hisq_solver_params()
+    lib().hisq_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(a):
+    """(pointer, is_device, keepalive) for numpy arrays or torch tensors."""
+    if a is None:
+        return None, False, None
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            if not a.is_contiguous():
+                raise ValueError("tensor must be contiguous")
+            return ctypes.c_void_p(a.data_ptr()), a.is_cuda, a
+    except ImportError:
+        pass
+    arr = np.ascontiguousarray(a)
+    if arr.dtype == np.complex128 or arr.dtype == np.float64:
+        return arr.ctypes.data_as(ctypes.c_void_p), False, arr
+    raise TypeError(f"unsupported array type {type(a)} / {getattr(a, 'dtype', None)}")
+
+
+def hisq_create(dims, device=0, stream=None):
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int * 4)(*[int(x) for x in dims])
+    st = lib().hisq_create(d, ctypes.c_int(device), stream, ctypes.byref(h))
+    _check(st, None, "hisq_create")
+    return h
+
+
+def hisq_destroy(h):
+    return lib().hisq_destroy(h)
+
+
+def current_stream_ptr():
+    """torch's current HIP stream as a void* (None on the null stream)."""
+    import torch
+    s = torch.cuda.current_stream().cuda_stream
+    return ctypes.c_void_p(s) if s else None
+
+
+class Lattice:
+    """One periodic local lattice on one GPU (a library handle)."""
+
+    def __init__(self, dims, device=0, stream=None, use_torch_stream=False):
+        self.dims = tuple(int(x) for x in dims)
+        self.V = int(np.prod(self.dims))
+        self.h = self.V // 2
+        if use_torch_stream:
+            stream = current_stream_ptr()
+        self.handle = hisq_create(self.dims, device, stream)
+
+    def close(self):
+        if self.handle is not None:
+            hisq_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self):
+        return hisq_last_error(self.handle)
+
+    def load_links(self, fat, lng):
+        fp, fdev, k1 = _ptr(fat)
+        lp, ldev, k2 = _ptr(lng)
+        flags = HISQ_DEVICE_PTR if fdev else 0
+        if fdev != ldev:
+            raise ValueError("fat and long links must both be host or both device arrays")
+        _check(lib().hisq_load_links(self.handle, fp, lp, ctypes.c_int(flags)), self.handle,
+               "hisq_load_links")
+
+    def prepare_links(self, prec, recon):
+        st = lib().hisq_prepare_links(self.handle, ctypes.c_int(prec), ctypes.c_int(recon))
+        _check(st, self.handle, "hisq_prepare_links")
+
+    def dslash(self, out_parity, prec, recon, inp, out, nrhs=1, flags=0):
+        ip, idev, k1 = _ptr(inp)
+        op, odev, k2 = _ptr(out)
+        if idev:
+            flags |= HISQ_DEVICE_PTR
+        st = lib().hisq_dslash(self.handle, ctypes.c_int(out_parity), ctypes.c_int(prec),
+                               ctypes.c_int(recon), ip, op, ctypes.c_int(nrhs), ctypes.c_int(flags))
+        _check(st, self.handle, "hisq_dslash")
+        return out
+
+    def cg(self, mass, b, x=None, params=None, raise_on_fail=True):
+        """Solve (4m^2 - D_eo D_oe) x = b; returns (x, info dict)."""
+        params = params or hisq_default_params()
+        if x is None:
+            x = np.zeros((self.h, 3), dtype=np.complex128)
+        bp, bdev, k1 = _ptr(b)
+        xp, xdev, k2 = _ptr(x)
+        if bdev:
+            params.flags |= HISQ_DEVICE_PTR
+        info = hisq_solver_info()
+        st = lib().hisq_cg(self.handle, ctypes.c_double(mass), bp, xp, ctypes.byref(params),
+                           ctypes.byref(info))
+        if raise_on_fail:
+            _check(st, self.handle, "hisq_cg")
+        return x, info.as_dict()
+
+    def multishift_cg(self, mass, shifts, b, params=None, raise_on_fail=True):
+        """b: [nrhs][h][3] host; returns x [nrhs][nshift][h][3] and info list."""
+        params = params or hisq_default_params(tol=1e-8)
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        if b.ndim == 2:
+            b = b[None]
+        nrhs = b.shape[0]
+        shifts = np.ascontiguousarray(shifts, dtype=np.float64)
+        ns = len(shifts)
+        x = np.zeros((nrhs, ns) + b.shape[1:], dtype=np.complex128)
+        infos = (hisq_solver_info * (nrhs * ns))()
+        st = lib().hisq_multishift_cg(self.handle, ctypes.c_double(mass), ctypes.c_int(ns),
+                                      shifts.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(nrhs),
+                                      b.ctypes.data_as(ctypes.c_void_p),
+                                      x.ctypes.data_as(ctypes.c_void_p), ctypes.byref(params), infos)
+        if raise_on_fail:
+            _check(st, self.handle, "hisq_multishift_cg")
+        return x, [i.as_dict() for i in infos]
+
+
+def hisq_batch_cg(lattices, masses, bs, params=None, raise_on_fail=True):
+    """Batched CG over several Lattice objects; returns (xs, infos)."""
+    n = len(lattices)
+    params = params or hisq_default_params()
+    hs = (ctypes.c_void_p * n)(*[l.handle.value for l in lattices])
+    ms = np.ascontiguousarray(masses, dtype=np.float64)
+    bs = [np.ascontiguousarray(b, dtype=np.complex128) for b in bs]
+    xs = [np.zeros_like(b) for b in bs]
+    bp = (ctypes.c_void_p * n)(*[b.ctypes.data for b in bs])
+    xp = (ctypes.c_void_p * n)(*[x.ctypes.data for x in xs])
+    infos = (hisq_solver_info * n)()
+    st = lib().hisq_batch_cg(ctypes.c_int(n), hs, ms.ctypes.data_as(ctypes.c_void_p), bp, xp,
+                             ctypes.byref(params), infos)
+    if raise_on_fail:
+        _check(st, lattices[0].handle, "hisq_batch_cg")
+    return xs, [i.as_dict() for i in infos]

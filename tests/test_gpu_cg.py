@@ -1,0 +1,134 @@
+"""GPU CG solves checked against the oracle: every solution's FP64 true
+residual is recomputed by the oracle, and small systems are compared with the
+oracle's (dense-pinned) solution within kappa * tol."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_00143_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _hisq():
+    from paper_1712_00143_amd import hisq
+    return hisq
+
+
+def test_c0_plain_fp64_cg():
+    H = _hisq()
+    w = synth.C0
+    fat, lng = w.links()
+    b = w.sources()[0]
+    lat = H.Lattice(w.dims)
+    lat.load_links(fat, lng)
+    x, info = lat.cg(w.mass, b, params=H.hisq_default_params(tol=1e-10))
+    assert info["converged"] == 1
+    tr = oracle.true_residual(w.dims, fat, lng, w.mass, b, x)
+    assert tr <= 1e-10
+    xo, it, tro, ok = oracle.cg(w.dims, fat, lng, w.mass, b, tol=1e-12)
+    # kappa of A on 4^4 at m = 0.1 is below 500
+    assert np.linalg.norm(x - xo) <= 500 * 1e-10 * np.linalg.norm(xo)
+    assert abs(info["true_residual"] - tr) <= 1e-3 * tr + 1e-14
+    lat.close()
+
+
+@pytest.mark.parametrize("sloppy,recon", [(1, 18), (1, 12), (2, 12), (2, 18), (0, 12)])
+def test_mixed_precision_cg(sloppy, recon):
+    H = _hisq()
+    dims = (8, 8, 8, 12)
+    fat, lng = synth.make_links(dims, 0.2, seed=77)
+    m = 0.05
+    b = synth.gaussian_even(dims, 577)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(sloppy, recon)
+    p = H.hisq_default_params(tol=1e-10, sloppy=sloppy, recon=recon)
+    x, info = lat.cg(m, b, params=p)
+    assert info["converged"] == 1
+    assert info["reliable_updates"] >= 1
+    tr = oracle.true_residual(dims, fat, lng, m, b, x)
+    assert tr <= 1e-10, (tr, info)
+    lat.close()
+
+
+def test_graph_replay_matches_eager_bitwise():
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    fat, lng = synth.make_links(dims, 0.3, seed=5)
+    b = synth.gaussian_even(dims, 6)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    p0 = H.hisq_default_params(tol=1e-10, sloppy=1, check_every=8)
+    p1 = H.hisq_default_params(tol=1e-10, sloppy=1, check_every=8, flags=H.HISQ_USE_GRAPH)
+    x0, i0 = lat.cg(0.05, b, params=p0)
+    x1, i1 = lat.cg(0.05, b, params=p1)
+    x2, i2 = lat.cg(0.05, b, params=p1)      # replay an already captured graph
+    assert i0["iters"] == i1["iters"] == i2["iters"]
+    assert np.array_equal(x0, x1) and np.array_equal(x1, x2)
+    lat.close()
+
+
+def test_warm_start_and_zero_source():
+    H = _hisq()
+    dims = (4, 4, 4, 8)
+    fat, lng = synth.make_links(dims, 0.3, seed=9)
+    b = synth.gaussian_even(dims, 10)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    xo, _, _, _ = oracle.cg(dims, fat, lng, 0.1, b, tol=1e-13)
+    x0 = xo * (1 + 1e-4)
+    p = H.hisq_default_params(tol=1e-10, flags=H.HISQ_X_IS_GUESS)
+    x, info = lat.cg(0.1, b, x=x0.copy(), params=p)
+    assert oracle.true_residual(dims, fat, lng, 0.1, b, x) <= 1e-10
+    _, it_cold = lat.cg(0.1, b)
+    assert info["iters"] < it_cold["iters"]
+    z, iz = lat.cg(0.1, np.zeros_like(b))
+    assert iz["converged"] == 1 and np.abs(z).max() == 0.0
+    lat.close()
+
+
+def test_not_converged_reports_best_iterate():
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    fat, lng = synth.make_links(dims, 0.3, seed=11)
+    b = synth.gaussian_even(dims, 12)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    p = H.hisq_default_params(tol=1e-10, maxiter=20, check_every=4)
+    x, info = lat.cg(0.01, b, params=p, raise_on_fail=False)
+    assert info["converged"] == 0 and info["status"] == H.HISQ_ERR_NOT_CONVERGED
+    assert 20 <= info["iters"] <= 24
+    tr = oracle.true_residual(dims, fat, lng, 0.01, b, x)
+    assert tr < 1.0
+    with pytest.raises(H.HisqError):
+        lat.cg(-0.1, b)
+    lat.close()
+
+
+def test_batch_cg_uneven():
+    H = _hisq()
+    shapes = [(4, 4, 4, 4), (8, 8, 8, 8), (6, 6, 6, 6), (8, 8, 8, 16)]
+    lats, bs, ms, links = [], [], [], []
+    for j, d in enumerate(shapes):
+        fat, lng = synth.make_links(d, 0.1 + 0.1 * j, seed=3000 + j)
+        L = H.Lattice(d)
+        L.load_links(fat, lng)
+        L.prepare_links(1, 18)
+        lats.append(L)
+        links.append((fat, lng))
+        bs.append(synth.gaussian_even(d, 3500 + j))
+        ms.append([0.2, 0.05, 0.1, 0.02][j])
+    p = H.hisq_default_params(tol=1e-10, sloppy=1, flags=H.HISQ_USE_GRAPH)
+    xs, infos = H.hisq_batch_cg(lats, ms, bs, params=p)
+    for j, d in enumerate(shapes):
+        assert infos[j]["converged"] == 1
+        tr = oracle.true_residual(d, *links[j], ms[j], bs[j], xs[j])
+        assert tr <= 1e-10
+        # the batched solve follows the same recurrence as a lone solve
+        x1, i1 = lats[j].cg(ms[j], bs[j], params=H.hisq_default_params(tol=1e-10, sloppy=1))
+        assert abs(i1["iters"] - infos[j]["iters"]) <= 16
+    assert infos[0]["iters"] < infos[3]["iters"]
+    for L in lats:
+        L.close()
