@@ -225,6 +225,7 @@ hisq_status hisq_destroy(hisq_lattice lat)
     if (lat->s) (void)hipStreamSynchronize(lat->s);
     lat->cg.release();
     lat->batch.release();
+    lat->msref.release();
     for (auto &pp : lat->lk)
         for (auto &q : pp)
             if (q) (void)hipFree(q);

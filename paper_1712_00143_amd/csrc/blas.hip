@@ -141,10 +141,145 @@ __global__ void __launch_bounds__(192) k_blas(BlasLaunch a)
     }
 
     if (a.fin != FIN_NONE) {
-        double mine[1] = {part}, tot[1];
-        if (publish_and_reduce<1>(mine, a.partials, tile, pd, st_, tot))
-            if (threadIdx.x == 0) run_finisher(a.fin, st_, tot);
+        double mine[1] = {part};
+        publish_partials<1>(mine, a.partials, tile);
     }
+}
+
+// One block per problem: fixed-order sum of the problem's tile partials, then
+// the finisher (FP64 scalar recurrences) on the totals.
+__global__ void __launch_bounds__(256) k_finish(const ProbDesc *probs, SolveState *states, const double *partials,
+                                                int fin, int want, int nv, ShiftState *ms)
+{
+    __shared__ double lds[16 * NPART];
+    const ProbDesc &pd = probs[blockIdx.x];
+    SolveState *st_ = &states[blockIdx.x];
+    if (st_->status != want) return;
+    double acc[NPART];
+#pragma unroll
+    for (int k = 0; k < NPART; k++) acc[k] = 0.0;
+    for (int j = threadIdx.x; j < pd.ntile; j += blockDim.x) {
+        const double *p = partials + (size_t)(pd.tile_begin + j) * NPART;
+        for (int k = 0; k < nv; k++) acc[k] += p[k];
+    }
+    block_sum<NPART>(acc, lds);
+    if (threadIdx.x == 0) run_finisher(fin, st_, acc, ms ? &ms[blockIdx.x] : nullptr);
+}
+
+hipError_t launch_finish(const ProbDesc *probs, SolveState *states, const double *partials, int fin, int want,
+                         int nv, int nprob, hipStream_t s, ShiftState *ms)
+{
+    hipLaunchKernelGGL(k_finish, dim3(nprob), dim3(256), 0, s, probs, states, partials, fin, want, nv, ms);
+    return hipGetLastError();
+}
+
+__global__ void k_convert(const void *src, int sprec, void *dst, int dprec, long long n)
+{
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        double2 v;
+        if (sprec == 0) v = reinterpret_cast<const double2 *>(src)[k];
+        else {
+            float2 f = reinterpret_cast<const float2 *>(src)[k];
+            v = make_double2(f.x, f.y);
+        }
+        if (dprec == 0) reinterpret_cast<double2 *>(dst)[k] = v;
+        else reinterpret_cast<float2 *>(dst)[k] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+hipError_t launch_convert(const void *src, int sprec, void *dst, int dprec, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    long long nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_convert, dim3((unsigned)nb), dim3(256), 0, s, src, sprec, dst, dprec, n);
+    return hipGetLastError();
+}
+
+// Multi-shift vector kernels (FP32 vectors, FP64 scalars).  Problem = one
+// right-hand side; tiles of problem j cover its h sites.
+template <int OP>
+__global__ void __launch_bounds__(192) k_ms(BlasLaunch a)
+{
+    __shared__ float lds[192];
+    const int tile = blockIdx.x;
+    const int prob = a.tile2prob ? a.tile2prob[tile] : 0;
+    const ProbDesc &pd = a.probs[prob];
+    SolveState *st_ = &a.states[prob];
+    const int stat = st_->status;
+    if (OP == BL_MS_UPDATE ? (stat != ST_RUNNING && stat != ST_MS_LAST) : stat != a.want) return;
+    const ShiftState *ms = &a.ms[prob];
+    const int e = threadIdx.x;
+    const long long site0 = (long long)(tile - pd.tile_begin) * TILE;
+    const bool ok = site0 * 3 + e < (long long)pd.h * 3;
+    const long long f = (pd.voff + site0) * 3 + e;       // this rhs's vectors
+    const long long h3 = (long long)pd.h * 3;
+    const int ns = ms->nshift;
+    const int j = prob;                                   // rhs index
+    double part = 0.0;
+    float2 *r = reinterpret_cast<float2 *>(a.v[0]);
+    float2 *p = reinterpret_cast<float2 *>(a.v[3]);
+    float2 *xs = reinterpret_cast<float2 *>(a.v[2]);
+    float2 *ps = reinterpret_cast<float2 *>(a.v[4]);
+    const long long fk0 = (long long)j * ns * h3 + site0 * 3 + e;   // shift 0 of rhs j
+    if constexpr (OP == BL_MS_INIT) {
+        if (ok) {
+            double2 b = reinterpret_cast<const double2 *>(a.v[5])[f];
+            float2 bf = make_float2((float)b.x, (float)b.y);
+            r[f] = bf;
+            p[f] = bf;
+            for (int k = 0; k < ns; k++) {
+                ps[fk0 + k * h3] = bf;
+                xs[fk0 + k * h3] = make_float2(0.f, 0.f);
+            }
+            part = b.x * b.x + b.y * b.y;
+        }
+    } else if constexpr (OP == BL_MS_RUPDATE) {
+        const float al = (float)st_->alpha;
+        if (ok) {
+            float2 rv = r[f], q = reinterpret_cast<const float2 *>(a.v[1])[f];
+            rv.x -= al * q.x;
+            rv.y -= al * q.y;
+            r[f] = rv;
+            part = (double)rv.x * rv.x + (double)rv.y * rv.y;
+        }
+    } else if constexpr (OP == BL_MS_UPDATE) {
+        if (ok) {
+            const float2 rv = r[f];
+            const float2 pv = p[f];
+            for (int k = 0; k < ns; k++) {
+                if (!ms->upd[k]) continue;
+                const float ak = (float)ms->ak[k], bk = (float)ms->bk[k], zk = (float)ms->zeta[k];
+                const long long fk = fk0 + k * h3;
+                float2 pk = ps[fk], xk = xs[fk];
+                xk.x += ak * pk.x;
+                xk.y += ak * pk.y;
+                pk.x = zk * rv.x + bk * pk.x;
+                pk.y = zk * rv.y + bk * pk.y;
+                xs[fk] = xk;
+                ps[fk] = pk;
+            }
+            const float be = (float)st_->beta;
+            p[f] = make_float2(rv.x + be * pv.x, rv.y + be * pv.y);
+        }
+    }
+    (void)lds;
+    if (a.fin != FIN_NONE) {
+        double mine[1] = {part};
+        publish_partials<1>(mine, a.partials, tile);
+    }
+}
+
+hipError_t launch_ms(int op, const BlasLaunch &a, int ntiles, hipStream_t s)
+{
+    dim3 g(ntiles), b(192);
+    switch (op) {
+    case BL_MS_INIT: hipLaunchKernelGGL(k_ms<BL_MS_INIT>, g, b, 0, s, a); break;
+    case BL_MS_RUPDATE: hipLaunchKernelGGL(k_ms<BL_MS_RUPDATE>, g, b, 0, s, a); break;
+    case BL_MS_UPDATE: hipLaunchKernelGGL(k_ms<BL_MS_UPDATE>, g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 __global__ void k_status(SolveState *states, int nprob, int from, int to)
@@ -185,6 +320,11 @@ static hipError_t launch_m(int op, const BlasLaunch &a, int nt, hipStream_t s)
 
 hipError_t launch_blas(int op, int prec, const BlasLaunch &a, int ntiles, int nprob, hipStream_t s)
 {
+    if (op == BL_STATUS_MS) {
+        hipLaunchKernelGGL(k_status, dim3((nprob + 63) / 64), dim3(64), 0, s, a.states, nprob,
+                           (int)ST_MS_LAST, (int)ST_CONVERGED);
+        return hipGetLastError();
+    }
     if (op == BL_STATUS) {
         hipLaunchKernelGGL(k_status, dim3((nprob + 63) / 64), dim3(64), 0, s, a.states, nprob,
                            (int)ST_RESUME, (int)ST_RUNNING);

@@ -43,7 +43,7 @@ size_t link_site_bytes(int prec, int recon)
 static size_t spinor_site_bytes(int prec) { return prec == 0 ? 48 : prec == 1 ? 24 : 16; }
 
 hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lattice> &lats,
-                      const std::vector<double> &masses, double sigma)
+                      const std::vector<double> &masses, double sigma, const std::vector<double> *sigmas)
 {
     const int n = (int)lats.size();
     int ntile = 0;
@@ -55,7 +55,7 @@ hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lat
         hd[k].tile_begin = ntile;
         hd[k].voff = nsite;
         hd[k].mass = masses[k];
-        hd[k].diag = 4.0 * masses[k] * masses[k] + sigma;
+        hd[k].diag = 4.0 * masses[k] * masses[k] + (sigmas ? (*sigmas)[k] : sigma);
         for (int j = 0; j < hd[k].ntile; j++) t2p.push_back(k);
         ntile += hd[k].ntile;
         nsite += hd[k].h;
@@ -113,7 +113,9 @@ static hipError_t enqueue_dslash(SolveSet &S, const CgPlan &pl, int prec, int ls
     const bool sloppy_op = lslot == pl.slot;
     const int W = sloppy_op ? pl.W : 8;
     const int recon = sloppy_op ? pl.recon : 18;
-    return launch_dslash(prec, recon, out_prec, epi, W, a, S.ntile, s);
+    hipError_t e = launch_dslash(prec, recon, out_prec, epi, W, a, S.ntile, s);
+    if (e != hipSuccess || fin == FIN_NONE) return e;
+    return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, 1, S.nprob, s);
 }
 
 static hipError_t enqueue_blas(SolveSet &S, int op, int mode, int want, int fin, hipStream_t s)
@@ -136,7 +138,9 @@ static hipError_t enqueue_blas(SolveSet &S, int op, int mode, int want, int fin,
     b.n[3] = S.p.n;
     b.v[4] = (op == BL_RESUME || op == BL_START) ? S.rhi.p : S.xhi.p;
     b.v[5] = S.b.p;
-    return launch_blas(op, mode, b, S.ntile, S.nprob, s);
+    hipError_t e = launch_blas(op, mode, b, S.ntile, S.nprob, s);
+    if (e != hipSuccess || fin == FIN_NONE) return e;
+    return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, 1, S.nprob, s);
 }
 
 static hipError_t enqueue_iters(SolveSet &S, const CgPlan &pl, int k, hipStream_t s)
@@ -388,7 +392,3 @@ hisq_status hisq_batch_cg(int nprob, const hisq_lattice *lats, const double *mas
 
 }  // extern "C"
 
-hisq_status hisq_dslash_mrhs_impl(hisq_lattice lat, int, int, int, const void *, void *, int, int)
-{
-    return set_err(lat, HISQ_ERR_ARG, "multi-RHS Dslash not available");
-}

@@ -12,7 +12,7 @@
 //   PLAIN  out = D in
 //   AX     out = diag*aux - D in,   partial Re(aux^+ out)      (CG: A p, p.Ap)
 //   RES    out = b - diag*aux + D in, partial |out|^2           (FP64 true residual)
-// Reductions finish inside the kernel (last tile of each problem).
+// Reductions leave per-tile FP64 partials for k_finish.
 #include "finish.h"
 #include "fields.h"
 #include "launch.h"
@@ -33,52 +33,86 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
     const ProbDesc &pd = a.probs[prob];
     if (a.states && a.states[prob].status != a.want) return;
     const int i = (tile - pd.tile_begin) * TILE + lane;
-    const bool valid = i < pd.h;
     const int h = pd.h;
+    const bool valid = i < h;
+    const int par = a.out_par;
     const LinkSet &ls = pd.ls[a.lslot];
+    const char *lbase = (const char *)ls.ptr[par];
+    const long long voff = pd.voff;
+    const int L0 = pd.L[0], L1 = pd.L[1], L2 = pd.L[2], L3 = pd.L[3];
 
     Cx<A> acc[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) acc[c] = {(A)0, (A)0};
 
-    Coord co;
     if (valid) {
-        co = cb_to_coord(i, a.out_par, pd.L);
-        const char *lbase = (const char *)ls.ptr[a.out_par];
+        const Coord co = cb_to_coord(i, par, pd.L);
+        const int lex = 2 * i + (co.x[0] & 1);
+        // prefix parities for eta_mu(x)
+        const int e1 = co.x[0] & 1, e2 = (co.x[0] + co.x[1]) & 1, e3 = (co.x[0] + co.x[1] + co.x[2]) & 1;
         Spin<ST> in{(ST *)a.in, (float *)a.in_nrm};
+        // Stage the work in groups of G directions: all index maths, then all
+        // link loads, then all neighbour gathers, then the arithmetic, so that
+        // G links are in flight per thread.
+        constexpr int G = DPW < (sizeof(LT) == 8 ? 2 : 4) ? DPW : (sizeof(LT) == 8 ? 2 : 4);
 #pragma unroll
-        for (int dd = 0; dd < DPW; dd++) {
-            const int d = wave * DPW + dd;
-            const int mu = d >> 2;
-            const int n = hop_cb(co, mu, dir_step(d), pd.L);
-            Cx<A> u[3][3], v[3];
-            load_link<LT, R, A>(lbase + (size_t)d * h * F::BYTES, i, h, u);
-            load_spinor<ST, A>(in, pd.voff + n, v);
-            Cx<A> y[3];
+        for (int g0 = 0; g0 < DPW; g0 += G) {
+            int nb[G];
 #pragma unroll
-            for (int r = 0; r < 3; r++) {
-                Cx<A> s = cmul(u[r][0], v[0]);
-                Cx<A> t1 = cmul(u[r][1], v[1]);
-                Cx<A> t2 = cmul(u[r][2], v[2]);
-                y[r] = {s.re + t1.re + t2.re, s.im + t1.im + t2.im};
+            for (int g = 0; g < G; g++) {
+                const int d = wave * DPW + g0 + g;
+                const int mu = d >> 2;
+                const int k = dir_step(d);
+                const int x = mu == 0 ? co.x[0] : mu == 1 ? co.x[1] : mu == 2 ? co.x[2] : co.x[3];
+                const int Lm = mu == 0 ? L0 : mu == 1 ? L1 : mu == 2 ? L2 : L3;
+                const int Sm = mu == 0 ? 1 : mu == 1 ? L0 : mu == 2 ? L0 * L1 : L0 * L1 * L2;
+                int v = x + k;
+                v -= v >= Lm ? Lm : 0;
+                v -= v >= Lm ? Lm : 0;
+                v += v < 0 ? Lm : 0;
+                v += v < 0 ? Lm : 0;
+                nb[g] = (lex + (v - x) * Sm) >> 1;
             }
-            if constexpr (R == 12 || sizeof(LT) == 2) {
-                const int fld = (d & 2) ? 1 : 0;
-                A coef = (A)ls.a[fld];
-                if constexpr (R == 12) {
-                    int sg = ls.s[fld] * eta_sign(co, mu) * ((d & 1) ? -1 : 1);
-                    coef = sg < 0 ? -coef : coef;
-                }
+            RawLink<LT, R> raw[G];
+#pragma unroll
+            for (int g = 0; g < G; g++)
+                load_link_raw<LT, R>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
+            Cx<A> v[G][3];
+#pragma unroll
+            for (int g = 0; g < G; g++) load_spinor<ST, A>(in, voff + nb[g], v[g]);
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const int d = wave * DPW + g0 + g;
+                const int mu = d >> 2;
+                Cx<A> u[3][3];
+                decode_link<LT, R, A>(raw[g], u);
+                Cx<A> y[3];
 #pragma unroll
                 for (int r = 0; r < 3; r++) {
-                    acc[r].re += coef * y[r].re;
-                    acc[r].im += coef * y[r].im;
+                    Cx<A> s0 = cmul(u[r][0], v[g][0]);
+                    Cx<A> t1 = cmul(u[r][1], v[g][1]);
+                    Cx<A> t2 = cmul(u[r][2], v[g][2]);
+                    y[r] = {s0.re + t1.re + t2.re, s0.im + t1.im + t2.im};
                 }
-            } else {
+                if constexpr (R == 12 || sizeof(LT) == 2) {
+                    const int fld = (d & 2) ? 1 : 0;
+                    A coef = (A)ls.a[fld];
+                    if constexpr (R == 12) {
+                        const int eb = mu == 0 ? 0 : mu == 1 ? e1 : mu == 2 ? e2 : e3;
+                        const int neg = (ls.s[fld] < 0) ^ eb ^ (d & 1);
+                        coef = neg ? -coef : coef;
+                    }
 #pragma unroll
-                for (int r = 0; r < 3; r++) {
-                    acc[r].re += y[r].re;
-                    acc[r].im += y[r].im;
+                    for (int r = 0; r < 3; r++) {
+                        acc[r].re += coef * y[r].re;
+                        acc[r].im += coef * y[r].im;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 3; r++) {
+                        acc[r].re += y[r].re;
+                        acc[r].im += y[r].im;
+                    }
                 }
             }
         }
@@ -107,7 +141,7 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
 
     double part = 0.0;
     if (wave == 0 && valid) {
-        const long long o = pd.voff + i;
+        const long long o = voff + i;
         Spin<OT> out{(OT *)a.out, a.out_nrm};
         if constexpr (EPI == EPI_PLAIN) {
             store_spinor<OT, A>(out, o, acc);
@@ -139,10 +173,8 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
     }
     if constexpr (EPI != EPI_PLAIN) {
         if (a.fin != FIN_NONE) {
-            double mine[1] = {part}, tot[1];
-            if (publish_and_reduce<1>(mine, a.partials, tile, pd, &a.states[prob], tot)) {
-                if (threadIdx.x == 0) run_finisher(a.fin, &a.states[prob], tot);
-            }
+            double mine[1] = {part};
+            publish_partials<1>(mine, a.partials, tile);
         }
     }
 }

@@ -84,6 +84,7 @@ struct hisq_lattice_s {
     std::string err;
     hisq::SolveSet cg;         // single-lattice solve workspace
     hisq::SolveSet batch;      // batched solves led by this handle
+    hisq::SolveSet msref;      // multi-shift refinement (one problem per rhs x shift)
     hisq::DVec tmp_in, tmp_out, tmp64a, tmp64b;  // host-pointer Dslash staging
     hisq::ProbDesc *ddesc = nullptr;             // this lattice alone
     double *dpart = nullptr;

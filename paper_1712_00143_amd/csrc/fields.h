@@ -40,31 +40,47 @@ template <class A> __device__ __forceinline__ Cx<A> cconjmul(Cx<A> a, Cx<A> b)  
 template <class T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
 template <> __device__ __forceinline__ float to_f<__half>(__half v) { return __half2float(v); }
 
-// Load one packed link (R reals) of direction block `dirbase` at site i into
-// a 3x3 complex matrix; recon-12 rebuilds row 2 as conj(row0 x row1).
-template <class LT, int R, class A>
-__device__ __forceinline__ void load_link(const char *__restrict__ dirbase, int i, int h,
-                                          Cx<A> u[3][3])
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Raw bytes of one packed link (R reals of LT).
+template <class LT, int R> struct RawLink {
+    uint32_t w[LinkFmt<LT, R>::BYTES / 4];
+};
+
+// Issue the loads of one packed link of direction block `dirbase` at site i.
+// Links are streamed exactly once per Dslash, so they are loaded
+// non-temporally to leave the caches to the gathered colour vectors.
+template <class LT, int R>
+__device__ __forceinline__ void load_link_raw(const char *__restrict__ dirbase, int i, int h,
+                                              RawLink<LT, R> &raw)
 {
     using F = LinkFmt<LT, R>;
-    uint32_t raw[F::BYTES / 4];
 #pragma unroll
     for (int q = 0; q < F::NQ; q++) {
-        uint4 v = *reinterpret_cast<const uint4 *>(dirbase + ((size_t)q * h + i) * 16);
-        raw[4 * q + 0] = v.x;
-        raw[4 * q + 1] = v.y;
-        raw[4 * q + 2] = v.z;
-        raw[4 * q + 3] = v.w;
+        u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(dirbase + ((size_t)q * h + i) * 16));
+        raw.w[4 * q + 0] = v.x;
+        raw.w[4 * q + 1] = v.y;
+        raw.w[4 * q + 2] = v.z;
+        raw.w[4 * q + 3] = v.w;
     }
     if constexpr (F::REM == 8) {
-        uint2 v = *reinterpret_cast<const uint2 *>(dirbase + (size_t)F::NQ * h * 16 + (size_t)i * 8);
-        raw[4 * F::NQ + 0] = v.x;
-        raw[4 * F::NQ + 1] = v.y;
+        u32x2 v = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x2 *>(dirbase + (size_t)F::NQ * h * 16 + (size_t)i * 8));
+        raw.w[4 * F::NQ + 0] = v.x;
+        raw.w[4 * F::NQ + 1] = v.y;
     } else if constexpr (F::REM == 4) {
-        uint32_t v = *reinterpret_cast<const uint32_t *>(dirbase + (size_t)F::NQ * h * 16 + (size_t)i * 4);
-        raw[4 * F::NQ] = v;
+        raw.w[4 * F::NQ] = __builtin_nontemporal_load(
+            reinterpret_cast<const uint32_t *>(dirbase + (size_t)F::NQ * h * 16 + (size_t)i * 4));
     }
-    const LT *e = reinterpret_cast<const LT *>(raw);
+}
+
+// Unpack a raw link into a 3x3 complex matrix; recon-12 rebuilds row 2 as
+// conj(row0 x row1).
+template <class LT, int R, class A>
+__device__ __forceinline__ void decode_link(const RawLink<LT, R> &raw, Cx<A> u[3][3])
+{
+    const LT *e = reinterpret_cast<const LT *>(raw.w);
     constexpr int ROWS = R == 18 ? 3 : 2;
 #pragma unroll
     for (int r = 0; r < ROWS; r++)
@@ -79,7 +95,6 @@ __device__ __forceinline__ void load_link(const char *__restrict__ dirbase, int 
             }
         }
     if constexpr (R == 12) {
-        // row2 = conj(row0 x row1)
         Cx<A> a0 = u[0][0], a1 = u[0][1], a2 = u[0][2];
         Cx<A> b0 = u[1][0], b1 = u[1][1], b2 = u[1][2];
         Cx<A> c0 = cmul(a1, b2), c1 = cmul(a2, b0), c2 = cmul(a0, b1);
@@ -88,6 +103,14 @@ __device__ __forceinline__ void load_link(const char *__restrict__ dirbase, int 
         u[2][1] = {c1.re - d1.re, -(c1.im - d1.im)};
         u[2][2] = {c2.re - d2.re, -(c2.im - d2.im)};
     }
+}
+
+template <class LT, int R, class A>
+__device__ __forceinline__ void load_link(const char *__restrict__ dirbase, int i, int h, Cx<A> u[3][3])
+{
+    RawLink<LT, R> raw;
+    load_link_raw<LT, R>(dirbase, i, h, raw);
+    decode_link<LT, R, A>(raw, u);
 }
 
 // Colour-vector access --------------------------------------------------

@@ -14,6 +14,7 @@ enum : int {
     FIN_NORM_B = 4,     // tot[0] = |b|^2: initialise the solve state
     FIN_STORE = 5,      // store tot[0..NPART) into st->cplx
     FIN_INIT_R = 6,     // tot[0] = |b - A x0|^2 (warm start): initial residual
+    FIN_MS = 7,         // tot[0] = |r_new|^2: base beta and every shift's zeta, alpha_k, beta_k
 };
 
 __device__ __forceinline__ long long dev_clock()
@@ -21,9 +22,45 @@ __device__ __forceinline__ long long dev_clock()
     return (long long)wall_clock64();
 }
 
-__device__ __forceinline__ void run_finisher(int fin, SolveState *st, const double *tot)
+// Shifted CG with collinear residuals (Jegerlehner, hep-lat/9612014): with the
+// base system's alpha_i, beta_i, the residual of shift k is zeta_k r and
+//   zeta_{i+1} = zeta_i zeta_{i-1} alpha_{i-1} /
+//                [alpha_i beta_{i-1} (zeta_{i-1} - zeta_i) + zeta_{i-1} alpha_{i-1} (1 + d_k alpha_i)],
+//   alpha_k = alpha_i zeta_{i+1} / zeta_i,  beta_k = beta_i (zeta_{i+1} / zeta_i)^2,
+// d_k = sigma_k - sigma_base.  A shift stops once |zeta_k| |r| <= tol |b|.
+__device__ __forceinline__ void ms_finish(SolveState *st, ShiftState *ms, double rn)
+{
+    const double al = st->alpha, be = rn / st->rr;
+    int any = 0;
+    for (int k = 0; k < ms->nshift; k++) {
+        ms->upd[k] = ms->active[k];
+        if (!ms->active[k]) continue;
+        const double z = ms->zeta[k], zo = ms->zeta_old[k];
+        const double zn = z * zo * ms->alpha_old /
+                          (al * ms->beta_old * (zo - z) + zo * ms->alpha_old * (1.0 + ms->shift[k] * al));
+        ms->ak[k] = al * zn / z;
+        ms->bk[k] = be * (zn / z) * (zn / z);
+        ms->zeta_old[k] = z;
+        ms->zeta[k] = zn;
+        ms->iters[k] += 1;
+        if (fabs(zn) * sqrt(rn) <= sqrt(st->tol2 * st->bb)) ms->active[k] = 0;
+        else any = 1;
+    }
+    ms->alpha_old = al;
+    ms->beta_old = be;
+    st->beta = be;
+    st->rr_old = st->rr;
+    st->rr = rn;
+    st->iter += 1;
+    if (!any || st->iter >= st->maxiter || !isfinite(rn)) st->status = ST_MS_LAST;
+}
+
+__device__ __forceinline__ void run_finisher(int fin, SolveState *st, const double *tot, ShiftState *ms = nullptr)
 {
     switch (fin) {
+    case FIN_MS:
+        ms_finish(st, ms, tot[0]);
+        break;
     case FIN_ALPHA: {
         double pap = tot[0];
         st->pAp = pap;

@@ -24,6 +24,7 @@ enum : int {
     ST_CONVERGED = 3,
     ST_BREAKDOWN = 4,
     ST_IDLE = 5,       // not part of the current solve
+    ST_MS_LAST = 6,    // multi-shift: apply this iteration's shift updates, then stop
 };
 
 // One packed link set (precision x reconstruction) of one lattice.
@@ -79,8 +80,9 @@ struct ShiftState {
     double zeta_old[MAXSHIFT];
     double ak[MAXSHIFT];
     double bk[MAXSHIFT];
-    double shift[MAXSHIFT];
+    double shift[MAXSHIFT];   // sigma_k - sigma_base
     int active[MAXSHIFT];
+    int upd[MAXSHIFT];     // shift updated by the current iteration
     int iters[MAXSHIFT];
     double alpha_old, beta_old;
     int nshift;

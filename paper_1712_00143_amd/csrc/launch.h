@@ -45,7 +45,7 @@ struct MrhsLaunch {
     const int *rhs_active; // nullptr: all
     int epi;
     int want;
-    double diag_shift;     // added to desc diag (multi-shift base shift)
+    double diag;           // EPI_AX: out = diag * aux - D in
 };
 
 hipError_t launch_dslash_mrhs(int prec, int recon, int nrhs, int W, const MrhsLaunch &a, int nblocks,
@@ -72,6 +72,7 @@ struct BlasLaunch {
     const ProbDesc *probs;
     const int *tile2prob;
     SolveState *states;
+    ShiftState *ms;
     int want;
     int fin;
     double *partials;
@@ -90,8 +91,19 @@ enum : int {
     BL_COPY_D2F = 7,  // v1 (prec) = v0 (FP64)
     BL_COPY_F2D = 8,  // v1 (FP64) = v0 (prec)
     BL_START = 9,     // r_lo = r_hi (v4); p = r_hi; x_lo = 0 (warm start)
+    BL_MS_RUPDATE = 10,  // multi-shift: r -= alpha Ap; partial |r|^2 (FIN_MS)
+    BL_MS_UPDATE = 11,   // multi-shift: x_k += a_k p_k; p_k = z_k r + b_k p_k; p = r + beta p
+    BL_MS_INIT = 12,     // multi-shift: r = p = b (FP32); p_k = b; x_k = 0; partial |b|^2
+    BL_STATUS_MS = 13,   // MS_LAST -> CONVERGED (one thread per problem)
 };
+// vector roles for the multi-shift ops: v0 = r, v1 = Ap, v3 = p, v5 = b (FP64),
+// v2 = x_k base, v4 = p_k base ([rhs][shift][h][3] FP32); ms = per-rhs ShiftState
 hipError_t launch_stamp(long long *out, hipStream_t s);
+hipError_t launch_finish(const ProbDesc *probs, SolveState *states, const double *partials, int fin, int want,
+                         int nv, int nprob, hipStream_t s, ShiftState *ms = nullptr);
+// contiguous complex arrays: FP64 <-> FP32 (prec 0 / 1), n complex numbers
+hipError_t launch_convert(const void *src, int sprec, void *dst, int dprec, long long n, hipStream_t s);
 hipError_t launch_blas(int op, int prec, const BlasLaunch &a, int ntiles, int nprob, hipStream_t s);
+hipError_t launch_ms(int op, const BlasLaunch &a, int ntiles, hipStream_t s);
 
 }  // namespace hisq

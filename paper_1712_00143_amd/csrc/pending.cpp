@@ -6,8 +6,6 @@ extern "C" {
 #define PENDING(name, ...)                                                   \
     hisq_status name(__VA_ARGS__) { return set_err(nullptr, HISQ_ERR_STATE, #name " is not built yet"); }
 
-PENDING(hisq_multishift_cg, hisq_lattice, double, int, const double *, int, const double *, double *,
-        const hisq_solver_params *, hisq_solver_info *)
 PENDING(hisq_ptc_create, hisq_lattice, int, const int *, hisq_ptc *)
 PENDING(hisq_ptc_destroy, hisq_ptc)
 PENDING(hisq_ptc_set_weights, hisq_ptc, const double *)

@@ -16,7 +16,8 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
 // Describe nprob problems (one per handle) in S: descriptors, tile map,
 // states, partials.  sigma is added to every diagonal (4 m^2 + sigma).
 hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lattice> &lats,
-                      const std::vector<double> &masses, double sigma);
+                      const std::vector<double> &masses, double sigma,
+                      const std::vector<double> *sigmas = nullptr);
 
 // Mixed / plain CG over every problem of S.  b[k], x[k]: FP64 vectors
 // (host, or device with HISQ_DEVICE_PTR).  info: nprob entries or nullptr.

@@ -1,0 +1,137 @@
+"""Multi-RHS Dslash and multi-shift CG on the GPU against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_00143_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _hisq():
+    from paper_1712_00143_amd import hisq
+    return hisq
+
+
+@pytest.mark.parametrize("nrhs", [2, 3, 4, 6])
+@pytest.mark.parametrize("prec,recon,tol", [(1, 18, 5e-6), (1, 12, 5e-6), (2, 12, 2e-3)])
+def test_mrhs_dslash_matches_oracle(nrhs, prec, recon, tol):
+    H = _hisq()
+    dims = (6, 4, 8, 4)
+    fat, lng = synth.make_links(dims, 0.3, seed=51)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(prec, recon)
+    psi = synth.gaussian_even(dims, 52, nrhs)
+    out = np.zeros_like(psi)
+    for par in (0, 1):
+        lat.dslash(par, prec, recon, psi, out, nrhs=nrhs)
+        for j in range(nrhs):
+            ref = oracle.dslash_half(dims, fat, lng, par, psi[j])
+            assert np.linalg.norm(out[j] - ref) <= tol * np.linalg.norm(ref)
+    lat.close()
+
+
+def test_mrhs_dslash_device_matches_single():
+    import torch
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    fat, lng = synth.make_links(dims, 0.2, seed=53)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    psi = synth.gaussian_even(dims, 54, 4).astype(np.complex64)
+    x = torch.from_numpy(psi.view(np.float32).reshape(-1)).cuda()
+    y = torch.empty_like(x)
+    lat.dslash(0, 1, 18, x, y, nrhs=4)
+    torch.cuda.synchronize()
+    h = psi.shape[1]
+    for j in range(4):
+        yj = torch.empty(6 * h, device="cuda", dtype=torch.float32)
+        lat.dslash(0, 1, 18, x[j * 6 * h:(j + 1) * 6 * h].contiguous(), yj)
+        torch.cuda.synchronize()
+        # same arithmetic per right-hand side, different summation grouping
+        a, b = y[j * 6 * h:(j + 1) * 6 * h], yj
+        assert (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item() < 1e-6
+    lat.close()
+
+
+def test_multishift_small_vs_oracle_and_dense():
+    H = _hisq()
+    dims = (4, 4, 4, 4)
+    fat, lng = synth.make_links(dims, 0.2, seed=2000)
+    m = 0.01
+    shifts = synth.shifts_log(12)
+    b = synth.gaussian_even(dims, 2500, 4)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    x, infos = lat.multishift_cg(m, shifts, b, params=H.hisq_default_params(tol=1e-8, sloppy=1))
+    for j in range(4):
+        xo, it, rel, ok = oracle.multishift(dims, fat, lng, m, shifts, b[j], tol=1e-10)
+        for k, s in enumerate(shifts):
+            tr = oracle.true_residual(dims, fat, lng, m, b[j], x[j, k], sigma=s)
+            assert tr <= 1e-8, (j, k, tr)
+            assert infos[j * 12 + k]["converged"] == 1
+            # kappa(A + s) <= 16.7 / (4 m^2 + s) on this lattice
+            kappa = 16.7 / (4 * m * m + s)
+            assert np.linalg.norm(x[j, k] - xo[k]) <= kappa * 1.1e-8 * np.linalg.norm(xo[k])
+    lat.close()
+
+
+def test_multishift_fp16_recon12():
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    fat, lng = synth.make_links(dims, 0.2, seed=2100)
+    m = 0.02
+    shifts = np.array([0.0, 1e-3, 1e-2, 0.1, 1.0])
+    b = synth.gaussian_even(dims, 2600, 2)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(2, 12)
+    x, infos = lat.multishift_cg(m, shifts, b, params=H.hisq_default_params(tol=1e-9, sloppy=2, recon=12))
+    for j in range(2):
+        for k, s in enumerate(shifts):
+            assert oracle.true_residual(dims, fat, lng, m, b[j], x[j, k], sigma=s) <= 1e-9
+    # smaller shifts need more iterations
+    its = [infos[k]["iters"] for k in range(5)]
+    assert its[0] >= its[-1]
+    lat.close()
+
+
+def test_multishift_full_size_24x24x24x48():
+    """The multi-shift workload at full size: 24^3x48, 12 shifts in [1e-4, 1],
+    4 sources, m = 0.01, tolerance 1e-8 on every shift (FP64 true residual
+    recomputed by the oracle)."""
+    H = _hisq()
+    w = synth.C2
+    fat, lng = w.links()
+    b = w.sources()
+    shifts = synth.shifts_log(12)
+    lat = H.Lattice(w.dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    x, infos = lat.multishift_cg(w.mass, shifts, b, params=H.hisq_default_params(
+        tol=1e-8, sloppy=1, flags=H.HISQ_USE_GRAPH))
+    lat.close()
+    for j in range(4):
+        for k, s in enumerate(shifts):
+            assert infos[j * 12 + k]["converged"] == 1
+            tr = oracle.true_residual(w.dims, fat, lng, w.mass, b[j], x[j, k], sigma=s)
+            assert tr <= 1e-8, (j, k, tr)
+
+
+def test_multishift_errors():
+    H = _hisq()
+    dims = (4, 4, 4, 4)
+    lat = H.Lattice(dims)
+    fat, lng = synth.make_links(dims, 0.2, seed=1)
+    lat.load_links(fat, lng)
+    b = synth.gaussian_even(dims, 1, 1)
+    with pytest.raises(H.HisqError) as ei:
+        lat.multishift_cg(0.1, np.zeros(65), b)
+    assert ei.value.status == H.HISQ_ERR_ARG
+    with pytest.raises(H.HisqError) as ei:
+        lat.multishift_cg(0.1, [0.1, 0.2], b)          # FP32 link set not prepared
+    assert ei.value.status == H.HISQ_ERR_STATE
+    lat.close()
