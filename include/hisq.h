@@ -90,6 +90,8 @@ typedef struct {
     double dslash_bytes;     /* algorithmic bytes moved by the Dslash applications */
     double flops;            /* algorithmic flops (1146 per half-Dslash output site) */
     double t_done_s;         /* batch solves: device time from start to convergence */
+    int fell_back;           /* learned solver: 1 if it handed over to plain CG */
+    int fcg_iters;           /* learned solver: flexible-CG iterations before any hand-over */
 } hisq_solver_info;
 
 /* Fill params with defaults: tol 1e-10, maxiter 100000, F64, recon 18,
@@ -164,28 +166,35 @@ hisq_status hisq_batch_cg(int nprob, const hisq_lattice *lats, const double *mas
  *   out_c(x) = sum_{c'} [ w0 psi_c'(x) + sum_mu ( w_{+mu} F_mu(x) psi_c'(x+mu)
  *                                         + w_{-mu} F_mu(x-mu)^+ psi_c'(x-mu) ) ]
  * with 9 complex weights per (c, c') (path order: 0 = identity,
- * 1+2mu = +mu, 2+2mu = -mu) and the fat links F.  The network embeds an even
- * vector on the full lattice (zeros on odd sites), applies the layers and
- * projects the output back to even sites; z = M(r) is the preconditioner of
- * the flexible CG.
+ * 1+2mu = +mu, 2+2mu = -mu) and the fat links F; no bias, which would break
+ * gauge covariance.  With K = L_n ... L_1 the layer stack and E the embedding
+ * of an even vector on the full lattice (zeros on odd sites), the
+ * preconditioner of the flexible CG is z = M(r), M = 1 + E^+ K^+ K E: the
+ * layers, then their exact adjoints in reverse order, the even projection,
+ * plus the identity.  M is Hermitian positive definite by construction, like
+ * the A^-1 it approximates, and M = 1 (plain CG) for zero weights.
+ *
+ * Activation layout of the layer calls (device FP32): channel c is
+ * [2 parities][V/2 sites][3 colours] complex, even sites first, each parity in
+ * lex(x)/2 order.
  */
 
-/* nlayer layers, chans[0..nlayer] channel counts (chans[0] = chans[nlayer] = 1,
- * all <= 8).  Weights start at zero. */
+/* nlayer layers (<= 8), chans[0..nlayer] channel counts (chans[0] = 1; each
+ * 1, 2, 4 or 8).  Weights start at zero (M = 1). */
 hisq_status hisq_ptc_create(hisq_lattice lat, int nlayer, const int *chans, hisq_ptc *out);
 hisq_status hisq_ptc_destroy(hisq_ptc net);
 /* Weights as complex FP64, layer by layer [Cout][Cin][9]; set writes the
  * FP32 master copy and the FP16 inference copy. */
 hisq_status hisq_ptc_set_weights(hisq_ptc net, const double *w);
 hisq_status hisq_ptc_get_weights(hisq_ptc net, double *w);
-/* One layer on device FP32 activations [C][V][3] complex (lex order):
- * forward out = L_l(in); backward gin = L_l^+(gout) (gin may be NULL) and
- * gw = sum_x (T_k in)^+ gout (complex FP64 [Cout][Cin][9], host or device
- * per flags). */
+/* One layer on device FP32 activations (layout above, HISQ_DEVICE_PTR
+ * required): forward out = L_l(in); backward gin = L_l^+(gout) (gin may be
+ * NULL) and gw = sum_x (T_k in)^+ gout (complex FP64 [Cout][Cin][9], host). */
 hisq_status hisq_ptc_layer_forward(hisq_ptc net, int layer, const void *in, void *out, int flags);
 hisq_status hisq_ptc_layer_backward(hisq_ptc net, int layer, const void *in, const void *gout,
                                     void *gin, double *gw, int flags);
-/* z = M(r) on device even vectors (FP32 complex), using the FP16 weights. */
+/* z = M(r) on device even vectors (FP32 complex), using the FP16 weights
+ * (HISQ_DEVICE_PTR required). */
 hisq_status hisq_ptc_apply(hisq_ptc net, const void *r, void *z, int flags);
 /* Generate training pairs: plain FP32/FP64 CG on b (host FP64), storing the
  * residual r_i and error e_i = x* - x_i every `every` iterations, at most
@@ -193,10 +202,18 @@ hisq_status hisq_ptc_apply(hisq_ptc net, const void *r, void *z, int flags);
  * Returns the number of pairs stored in *npairs. */
 hisq_status hisq_ptc_harvest(hisq_ptc net, hisq_lattice lat, double mass, const double *b,
                              int every, int maxpairs, int *npairs);
+/* Number of stored pairs, and pair `index` (in storage order) as host FP64
+ * even vectors r, e ([V/2][3] complex each, as stored: FP32 values). */
+hisq_status hisq_ptc_pair_count(hisq_ptc net, int *count);
+hisq_status hisq_ptc_get_pair(hisq_ptc net, int index, double *r, double *e);
 /* Train on the stored pairs (all from lattices whose links are those of the
  * handle each pair was harvested on): `steps` Adam steps (lr, beta1 0.9,
  * beta2 0.999, eps 1e-8) on minibatches of `batch` pairs drawn with `seed`.
- * Loss = mean ||M(r) - e||^2 / ||e||^2.  losses: steps entries or NULL. */
+ * Loss of a minibatch: L = 1 - |S|^2 / (B Q), S = sum_b <M r_b, e_b>/|e_b|^2,
+ * Q = sum_b |M r_b|^2/|e_b|^2: the normalised misfit of M r_b ~ c e_b with one
+ * common c (M A close to a multiple of 1 on the error directions), invariant
+ * to the scale of M, which the flexible CG does not see.
+ * losses: steps entries or NULL. */
 hisq_status hisq_ptc_train(hisq_ptc net, int steps, int batch, double lr, unsigned long long seed,
                            double *losses);
 /* Flexible CG (truncation 1) with z = M(r), FP32 iteration and FP64 true

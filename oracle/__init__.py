@@ -209,27 +209,72 @@ def fcg(dims, fat, lng, mass, weights, b, tol=1e-10, maxiter=100000):
     return x, it.value, tr.value, rc == 0
 
 
+def ptc_layer_adjoint(dims, fat, w, g):
+    """L^+ g for the layer with weights w ([cout][cin][9]): [cout][V][3] -> [cin][V][3]."""
+    lib = _load()
+    f, fp = _c(fat)
+    w, wp = _c(w)
+    gg, gp = _c(g)
+    cout, cin = w.shape[0], w.shape[1]
+    gin = np.empty((cin,) + gg.shape[1:], dtype=np.complex128)
+    lib.orc_ptc_layer_adj(_dims(dims), fp, ctypes.c_int(cin), ctypes.c_int(cout), wp, None, gp,
+                          gin.ctypes.data_as(ctypes.c_void_p), None)
+    return gin
+
+
+def adjoint_weights(w):
+    """Weights of L^+ for the layer with weights w: W'[c'][c][k'] = conj(W[c][c'][k]),
+    k' the reversed path (identity stays, +mu <-> -mu)."""
+    perm = [0] + [k + 1 if (k - 1) % 2 == 0 else k - 1 for k in range(1, 9)]
+    return np.conj(np.transpose(w, (1, 0, 2))[:, :, perm])
+
+
 def ptc_loss_and_grad(dims, fat, weights, r_even_batch, e_even_batch):
-    """Loss = mean_i ||M(r_i) - e_i||^2 / ||e_i||^2 and its weight gradients
-    (dL/dRe w + i dL/dIm w), by the layer adjoints, over a batch of pairs."""
+    """Loss of a batch of (residual, error) pairs for z_i = M(r_i),
+    M = 1 + E^+ K^+ K E (K the layer stack):
+        L = 1 - |S|^2 / (B Q),  S = sum_i <z_i, e_i> / |e_i|^2,
+                                Q = sum_i |z_i|^2 / |e_i|^2,
+    i.e. min_c sum_i |z_i - c e_i|^2 / |e_i|^2, normalised by sum_i |z_i|^2/|e_i|^2:
+    it asks for one common c with M A e_i = M r_i ~ c e_i on every pair (M A
+    close to a multiple of 1) and is invariant to the scale of M, which the
+    flexible CG does not see.  Gradient (dL/dRe z + i dL/dIm z):
+        g_i = -2 (conj(S) e_i Q - |S|^2 z_i) / (B Q^2 |e_i|^2).
+    Weight gradients follow by the layer adjoints; the adjoint half uses the
+    weights W' = adjoint_weights(W), and a gradient G' with respect to W'
+    contributes adjoint_weights(G') to that of W."""
     V = int(np.prod(dims))
     nl = len(weights)
     even = _even_lex(dims)
     grads = [np.zeros_like(w, dtype=np.complex128) for w in weights]
-    loss = 0.0
+    wadj = [adjoint_weights(w) for w in weights]
     npair = len(r_even_batch)
+    fwd = []
+    S, Q = 0j, 0.0
     for r, e in zip(r_even_batch, e_even_batch):
         a = np.zeros((1, V, 3), dtype=np.complex128)
         a[0, even] = r
         acts = [a]
         for w in weights:
             acts.append(ptc_layer(dims, fat, w, acts[-1]))
-        z = acts[-1][0, even]
+        bs = [None] * (nl + 1)
+        bs[nl] = acts[nl]
+        for l in range(nl, 0, -1):
+            bs[l - 1] = ptc_layer(dims, fat, wadj[l - 1], bs[l])
+        z = r + bs[0][0, even]          # M = 1 + E^+ K^+ K E
         ee = float(np.vdot(e, e).real)
-        diff = z - e
-        loss += float(np.vdot(diff, diff).real) / ee / npair
+        S += np.vdot(z, e) / ee
+        Q += float(np.vdot(z, z).real) / ee
+        fwd.append((acts, bs, z, e, ee))
+    loss = 1.0 - abs(S) ** 2 / (npair * Q)
+    for acts, bs, z, e, ee in fwd:
         g = np.zeros((1, V, 3), dtype=np.complex128)
-        g[0, even] = 2.0 * diff / ee / npair
+        g[0, even] = -2.0 * (np.conj(S) * e * Q - abs(S) ** 2 * z) / (npair * Q * Q * ee)
+        # adjoint half, in reverse order of application
+        for l in range(1, nl + 1):
+            gin, gw = ptc_layer_adj(dims, fat, wadj[l - 1], bs[l], g)
+            grads[l - 1] += adjoint_weights(gw)
+            g = gin
+        # forward half
         for l in range(nl - 1, -1, -1):
             gin, gw = ptc_layer_adj(dims, fat, weights[l], acts[l], g, need_gin=(l > 0))
             grads[l] += gw

@@ -369,6 +369,7 @@ void orc_ptc_layer_adj(const int d[4], const cplx *fat, int cin, int cout, const
             }
         }
     }
+    if (!gw) return;
     for (int c = 0; c < cout; c++)
         for (int cp = 0; cp < cin; cp++) {
             cplx sum[9] = {0};
@@ -392,10 +393,13 @@ void orc_ptc_layer_adj(const int d[4], const cplx *fat, int cin, int cout, const
 
 /* -------------------------------------------------- PTC network + FCG */
 
-/* Preconditioner z = M(r) on even vectors: embed r on even sites (zeros on
- * odd), apply nlayer PTC layers with channel counts chans[0..nlayer], project
- * the output onto even sites.  weights: concatenation of every layer's
- * [Cout][Cin][9] block.  chans[0] = chans[nlayer] = 1. */
+/* Preconditioner z = M(r) on even vectors, M = 1 + E^+ K^+ K E: embed r on
+ * even sites (zeros on odd), apply the nlayer PTC layers K = L_n ... L_1
+ * (channel counts chans[0..nlayer], chans[0] = 1), then their adjoints in
+ * reverse order, project the output onto even sites and add r.  M is
+ * Hermitian positive definite by construction, as the inverse it
+ * approximates is, and M = 1 (plain CG) when the weights vanish.  weights:
+ * concatenation of every layer's [Cout][Cin][9] block. */
 void orc_ptc_apply(const int d[4], const cplx *fat, int nlayer, const int *chans,
                    const cplx *weights, const cplx *r_even, cplx *z_even)
 {
@@ -413,9 +417,15 @@ void orc_ptc_apply(const int d[4], const cplx *fat, int nlayer, const int *chans
         w += (long)chans[l] * chans[l + 1] * 9;
         cplx *t = a; a = b; b = t;
     }
+    for (int l = nlayer - 1; l >= 0; l--) {
+        w -= (long)chans[l] * chans[l + 1] * 9;
+        orc_ptc_layer_adj(d, fat, chans[l], chans[l + 1], w, NULL, a, b, NULL);
+        cplx *t = a; a = b; b = t;
+    }
     for (long s = 0; s < V; s++)
         if (parity_of(d, s) == 0)
-            for (int j = 0; j < 3; j++) z_even[3 * (s / 2) + j] = a[3 * s + j];
+            for (int j = 0; j < 3; j++)
+                z_even[3 * (s / 2) + j] = r_even[3 * (s / 2) + j] + a[3 * s + j];
     free(a); free(b);
 }
 

@@ -175,7 +175,7 @@ static hipError_t enqueue_reliable(SolveSet &S, const CgPlan &pl, hipStream_t s)
 }
 
 hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm, const double *const *b,
-                   double *const *x, hisq_solver_info *info)
+                   double *const *x, hisq_solver_info *info, ChunkHook hook, void *hook_ctx)
 {
     auto t0 = std::chrono::steady_clock::now();
     const int mode = (int)prm.sloppy;
@@ -280,6 +280,7 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
         else HIPCHK(lat0, enqueue_iters(S, pl, kchunk, s));
         HIPCHK(lat0, hipMemcpyAsync(S.hst, S.dst, sizeof(SolveState) * S.nprob, hipMemcpyDeviceToHost, s));
         HIPCHK(lat0, hipStreamSynchronize(s));
+        if (hook) HIPCHK(lat0, hook(S, hook_ctx, s));
         bool rel = false;
         for (int k = 0; k < S.nprob; k++)
             if (S.hst[k].status == ST_RELIABLE) rel = true;

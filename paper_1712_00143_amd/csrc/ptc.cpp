@@ -1,0 +1,644 @@
+// Learned preconditioner: the PTC network's C ABI, training-pair harvesting
+// and training (forward, backward and Adam on the GPU).
+//
+// The preconditioner is M = 1 + E^+ K^+ K E: E embeds an even vector on the
+// full lattice, K = L_n ... L_1 is the stack of PTC layers and K^+ its exact
+// adjoint (the layers with adjoint weights, in reverse order).  M is Hermitian
+// positive definite by construction, like the inverse A^-1 it stands in for,
+// which keeps the flexible CG that uses it well behaved; with zero weights it
+// is the identity and the flexible CG is plain CG.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "finish.h"
+#include "ptc.h"
+#include "solver.h"
+
+using namespace hisq;
+
+#define HIPCHK(lat, x)                                     \
+    do {                                                   \
+        hipError_t e_ = (x);                               \
+        if (e_ != hipSuccess) return hip_err(lat, e_, #x); \
+    } while (0)
+
+namespace {
+
+struct PairBlock {
+    hisq_lattice lat;
+    float *mem;         // [n][2][h][3] complex: r_i then e_i
+    std::vector<double> ee;
+    int n;
+};
+
+}  // namespace
+
+struct hisq_ptc_s {
+    hisq_lattice lat = nullptr;
+    int nlayer = 0;
+    std::vector<int> chans;
+    std::vector<int> woff;   // complex offset of each layer
+    int nw = 0;              // complex weights in total
+    float *w32 = nullptr, *m = nullptr, *v = nullptr;
+    float *wa32 = nullptr;   // adjoint weights of every layer (FP32)
+    __half *w16 = nullptr, *wa16 = nullptr;
+    double *gw = nullptr, *gtmp = nullptr;
+    int step = 0;
+    std::vector<PairBlock> pairs;
+    // training workspace
+    int wsB = 0;
+    long long wsV = 0;
+    float *act = nullptr;
+    double *part = nullptr;
+    size_t part_n = 0;
+    double *dloss = nullptr, *dee = nullptr;
+    // inference workspace
+    float *inf = nullptr;
+    long long infV = 0;
+};
+
+namespace {
+
+int cmax(const hisq_ptc_s *n)
+{
+    int c = 1;
+    for (int x : n->chans) c = std::max(c, x);
+    return c;
+}
+
+hisq_status ensure_fp32_links(hisq_lattice lat)
+{
+    if (lat->ls[2].valid) return HISQ_OK;
+    return hisq_prepare_links(lat, HISQ_F32, HISQ_RECON_18);
+}
+
+// adjoint weights (FP32 and FP16) of every layer from the FP32 master
+hipError_t refresh_adjoint(hisq_ptc_s *n, hipStream_t s)
+{
+    for (int l = 0; l < n->nlayer; l++) {
+        hipError_t e = launch_ptc_adjoint(n->w32 + 2 * n->woff[l], n->chans[l], n->chans[l + 1],
+                                          n->wa32 + 2 * n->woff[l], s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_to_half(n->wa32, n->wa16, 2 * n->nw, s);
+}
+
+PtcLaunch base_launch(hisq_lattice lat, int lslot)
+{
+    PtcLaunch a;
+    memset(&a, 0, sizeof a);
+    a.probs = lat->ddesc;
+    a.lslot = lslot;
+    a.in_zero_par = -1;
+    a.out_pstride = 2;
+    a.g_pstride = 2;
+    return a;
+}
+
+// One layer application over output parities [plo, phi].
+hipError_t run_layer(hisq_lattice lat, int lslot, int prec, int recon, bool w16, const void *w, int cin, int cout,
+                     const float *in, long long in_bs, int in_zero, float *out, long long out_bs, int out_pstride,
+                     int plo, int phi, int batch, hipStream_t stream)
+{
+    PtcLaunch a = base_launch(lat, lslot);
+    a.w = w;
+    a.in = in;
+    a.in_bstride = in_bs;
+    a.in_zero_par = in_zero;
+    a.out = out;
+    a.out_bstride = out_bs;
+    a.out_pstride = out_pstride;
+    a.out_par0 = plo;
+    a.par_lo = plo;
+    const int nblk = lat->ntile * (phi - plo + 1);
+    return launch_ptc_layer(prec, recon, w16, cin, cout, 3, a, nblk, batch, stream);
+}
+
+// Weight gradient of one layer application, summed over the output parities
+// where g lives (g_pstride 1: even only), added into gw (FP64, the layer's
+// own [cout][cin][9] layout).
+hipError_t run_wgrad(hisq_ptc_s *n, hisq_lattice lat, int cin, int cout, const float *in, long long in_bs, int in_zero,
+                     const float *g, long long g_bs, int g_pstride, int batch, double *gw, int accumulate,
+                     hipStream_t s)
+{
+    PtcLaunch a = base_launch(lat, 2);
+    a.in = in;
+    a.in_bstride = in_bs;
+    a.in_zero_par = in_zero;
+    a.g = g;
+    a.g_bstride = g_bs;
+    a.g_pstride = g_pstride;
+    a.partials = n->part;
+    hipError_t e = launch_ptc_wgrad(cin, cout, a, lat->ntile * g_pstride, batch, s);
+    if (e != hipSuccess) return e;
+    return launch_ptc_wsum(n->part, (long long)lat->ntile * g_pstride * batch, cin, cout, gw, accumulate, s);
+}
+
+// z = M(r) for `batch` even vectors (FP32 [batch][h][3]); `ws` holds two
+// full-lattice activations of cmax channels per batch entry.
+hipError_t apply_net(hisq_ptc_s *n, hisq_lattice lat, int lslot, int prec, int recon, bool w16, const float *r,
+                     float *z, float *ws, int batch, hipStream_t s)
+{
+    const long long h = lat->h;
+    const long long act = (long long)cmax(n) * 2 * h * 6;   // floats per batch entry
+    float *bufs[2] = {ws, ws + act * batch};
+    const float *cur = r;
+    long long cur_bs = h * 6;
+    int cur_zero = 1;   // the input is an even vector embedded with zero odd sites
+    int k = 0;
+    for (int l = 0; l < n->nlayer; l++) {
+        const void *w = w16 ? (const void *)(n->w16 + 2 * n->woff[l]) : (const void *)(n->w32 + 2 * n->woff[l]);
+        hipError_t e = run_layer(lat, lslot, prec, recon, w16, w, n->chans[l], n->chans[l + 1], cur, cur_bs, cur_zero,
+                                 bufs[k], act, 2, 0, 1, batch, s);
+        if (e != hipSuccess) return e;
+        cur = bufs[k];
+        cur_bs = act;
+        cur_zero = -1;
+        k ^= 1;
+    }
+    for (int l = n->nlayer - 1; l >= 0; l--) {
+        const void *w = w16 ? (const void *)(n->wa16 + 2 * n->woff[l]) : (const void *)(n->wa32 + 2 * n->woff[l]);
+        const bool last = l == 0;
+        hipError_t e = last ? run_layer(lat, lslot, prec, recon, w16, w, n->chans[l + 1], n->chans[l], cur, cur_bs,
+                                        -1, z, h * 6, 1, 0, 0, batch, s)
+                            : run_layer(lat, lslot, prec, recon, w16, w, n->chans[l + 1], n->chans[l], cur, cur_bs,
+                                        -1, bufs[k], act, 2, 0, 1, batch, s);
+        if (e != hipSuccess) return e;
+        cur = bufs[k];
+        k ^= 1;
+    }
+    return launch_add_f32(z, r, (long long)batch * h * 6, s);   // the identity term
+}
+
+}  // namespace
+
+// z = M(r) for the flexible CG: FP16 weights, transports on link set `lslot`.
+hipError_t ptc_apply_internal(hisq_ptc n, hisq_lattice lat, int lslot, int prec, int recon, const float *r, float *z)
+{
+    const long long need = (long long)cmax(n) * 2 * lat->h * 6 * 2;
+    if (n->infV < need) {
+        if (n->inf) (void)hipFree(n->inf);
+        hipError_t e = hipMalloc(&n->inf, need * 4);
+        if (e != hipSuccess) return e;
+        n->infV = need;
+    }
+    return apply_net(n, lat, lslot, prec, recon, true, r, z, n->inf, 1, lat->s);
+}
+
+extern "C" {
+
+hisq_status hisq_ptc_create(hisq_lattice lat, int nlayer, const int *chans, hisq_ptc *out)
+{
+    if (!lat || !chans || !out || nlayer < 1 || nlayer > 8) return set_err(lat, HISQ_ERR_ARG, "bad network arguments");
+    if (chans[0] != 1) return set_err(lat, HISQ_ERR_ARG, "the first channel count must be 1");
+    for (int l = 0; l <= nlayer; l++)
+        if (chans[l] != 1 && chans[l] != 2 && chans[l] != 4 && chans[l] != 8)
+            return set_err(lat, HISQ_ERR_ARG, "channel counts must be 1, 2, 4 or 8");
+    for (int l = 0; l < nlayer; l++) {
+        int a = chans[l], b = chans[l + 1];
+        bool ok = (a == 1 || b == 1 || a == b || (a == 2 && b == 4) || (a == 4 && b == 2));
+        if (!ok || (a == 1 && b == 1 && false)) return set_err(lat, HISQ_ERR_ARG, "unsupported channel transition");
+        if ((a == 8 && b != 8 && b != 1) || (b == 8 && a != 8 && a != 1))
+            return set_err(lat, HISQ_ERR_ARG, "unsupported channel transition");
+    }
+    HIPCHK(lat, hipSetDevice(lat->device));
+    hisq_ptc n = new hisq_ptc_s();
+    n->lat = lat;
+    n->nlayer = nlayer;
+    n->chans.assign(chans, chans + nlayer + 1);
+    int maxw = 0;
+    for (int l = 0; l < nlayer; l++) {
+        n->woff.push_back(n->nw);
+        n->nw += 9 * chans[l] * chans[l + 1];
+        maxw = std::max(maxw, 9 * chans[l] * chans[l + 1]);
+    }
+    const size_t nf = (size_t)2 * n->nw;
+    if (hipMalloc(&n->w32, nf * 4) != hipSuccess || hipMalloc(&n->m, nf * 4) != hipSuccess ||
+        hipMalloc(&n->v, nf * 4) != hipSuccess || hipMalloc(&n->wa32, nf * 4) != hipSuccess ||
+        hipMalloc(&n->w16, nf * 2) != hipSuccess || hipMalloc(&n->wa16, nf * 2) != hipSuccess ||
+        hipMalloc(&n->gw, nf * 8) != hipSuccess || hipMalloc(&n->gtmp, (size_t)2 * maxw * 8) != hipSuccess ||
+        hipMalloc(&n->dloss, 8 * 65536) != hipSuccess) {
+        hisq_ptc_destroy(n);
+        return set_err(lat, HISQ_ERR_OOM, "network allocation failed");
+    }
+    for (void *p : {(void *)n->w32, (void *)n->m, (void *)n->v, (void *)n->wa32}) (void)hipMemset(p, 0, nf * 4);
+    (void)hipMemset(n->w16, 0, nf * 2);
+    (void)hipMemset(n->wa16, 0, nf * 2);
+    (void)hipMemset(n->gw, 0, nf * 8);
+    *out = n;
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_destroy(hisq_ptc n)
+{
+    if (!n) return HISQ_ERR_ARG;
+    (void)hipSetDevice(n->lat->device);
+    (void)hipStreamSynchronize(n->lat->s);
+    for (void *p : {(void *)n->w32, (void *)n->m, (void *)n->v, (void *)n->wa32, (void *)n->w16, (void *)n->wa16,
+                    (void *)n->gw, (void *)n->gtmp, (void *)n->act, (void *)n->part, (void *)n->dloss,
+                    (void *)n->dee, (void *)n->inf})
+        if (p) (void)hipFree(p);
+    for (auto &pb : n->pairs)
+        if (pb.mem) (void)hipFree(pb.mem);
+    delete n;
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_set_weights(hisq_ptc n, const double *w)
+{
+    if (!n || !w) return HISQ_ERR_ARG;
+    hisq_lattice lat = n->lat;
+    std::vector<float> f(2 * n->nw);
+    for (int j = 0; j < 2 * n->nw; j++) f[j] = (float)w[j];
+    HIPCHK(lat, hipMemcpy(n->w32, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    // the FP16 inference copies are rounded from the FP32 master on the device
+    // (round to nearest even), as after every Adam step
+    HIPCHK(lat, launch_to_half(n->w32, n->w16, 2 * n->nw, lat->s));
+    HIPCHK(lat, refresh_adjoint(n, lat->s));
+    HIPCHK(lat, hipMemsetAsync(n->m, 0, f.size() * 4, lat->s));
+    HIPCHK(lat, hipMemsetAsync(n->v, 0, f.size() * 4, lat->s));
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    n->step = 0;
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_get_weights(hisq_ptc n, double *w)
+{
+    if (!n || !w) return HISQ_ERR_ARG;
+    std::vector<float> f(2 * n->nw);
+    HIPCHK(n->lat, hipStreamSynchronize(n->lat->s));
+    HIPCHK(n->lat, hipMemcpy(f.data(), n->w32, f.size() * 4, hipMemcpyDeviceToHost));
+    for (int j = 0; j < 2 * n->nw; j++) w[j] = f[j];
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_layer_forward(hisq_ptc n, int layer, const void *in, void *out, int flags)
+{
+    if (!n || !in || !out || layer < 0 || layer >= n->nlayer) return HISQ_ERR_ARG;
+    hisq_lattice lat = n->lat;
+    if (!(flags & HISQ_DEVICE_PTR)) return set_err(lat, HISQ_ERR_ARG, "layer calls take device pointers");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    hisq_status st = ensure_fp32_links(lat);
+    if (st != HISQ_OK) return st;
+    const int cin = n->chans[layer], cout = n->chans[layer + 1];
+    HIPCHK(lat, run_layer(lat, 2, 1, 18, false, n->w32 + 2 * n->woff[layer], cin, cout, (const float *)in, 0, -1,
+                          (float *)out, 0, 2, 0, 1, 1, lat->s));
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_layer_backward(hisq_ptc n, int layer, const void *in, const void *gout, void *gin, double *gw,
+                                    int flags)
+{
+    if (!n || !in || !gout || layer < 0 || layer >= n->nlayer) return HISQ_ERR_ARG;
+    hisq_lattice lat = n->lat;
+    if (!(flags & HISQ_DEVICE_PTR)) return set_err(lat, HISQ_ERR_ARG, "layer calls take device pointers");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    hisq_status st = ensure_fp32_links(lat);
+    if (st != HISQ_OK) return st;
+    const int cin = n->chans[layer], cout = n->chans[layer + 1];
+    hipStream_t s = lat->s;
+    if (gin)
+        HIPCHK(lat, run_layer(lat, 2, 1, 18, false, n->wa32 + 2 * n->woff[layer], cout, cin, (const float *)gout, 0,
+                              -1, (float *)gin, 0, 2, 0, 1, 1, s));
+    if (gw) {
+        const size_t need = (size_t)2 * lat->ntile * 9 * cin * cout * 2;
+        if (n->part_n < need) {
+            if (n->part) (void)hipFree(n->part);
+            HIPCHK(lat, hipMalloc(&n->part, need * 8));
+            n->part_n = need;
+        }
+        HIPCHK(lat, run_wgrad(n, lat, cin, cout, (const float *)in, 0, -1, (const float *)gout, 0, 2, 1, n->gtmp, 0, s));
+        HIPCHK(lat, hipMemcpyAsync(gw, n->gtmp, sizeof(double) * 2 * 9 * cin * cout, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(lat, hipStreamSynchronize(s));
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_apply(hisq_ptc n, const void *r, void *z, int flags)
+{
+    if (!n || !r || !z) return HISQ_ERR_ARG;
+    hisq_lattice lat = n->lat;
+    if (!(flags & HISQ_DEVICE_PTR)) return set_err(lat, HISQ_ERR_ARG, "hisq_ptc_apply takes device pointers");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    hisq_status st = ensure_fp32_links(lat);
+    if (st != HISQ_OK) return st;
+    HIPCHK(lat, ptc_apply_internal(n, lat, 2, 1, 18, (const float *)r, (float *)z));
+    return HISQ_OK;
+}
+
+// Plain FP64 CG on b (to 1e-12), snapshotting x_i every `every` iterations;
+// pairs r_i = b - A x_i (FP64) and e_i = x* - x_i, kept on the device in FP32.
+hisq_status hisq_ptc_harvest(hisq_ptc n, hisq_lattice lat, double mass, const double *b, int every, int maxpairs,
+                             int *npairs)
+{
+    if (!n || !lat || !b || every < 1 || maxpairs < 1) return HISQ_ERR_ARG;
+    if (npairs) *npairs = 0;
+    if (!lat->loaded) return set_err(lat, HISQ_ERR_STATE, "no links loaded");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    hisq_status st = ensure_fp32_links(lat);
+    if (st != HISQ_OK) return st;
+    const long long h = lat->h;
+    hipStream_t s = lat->s;
+    std::vector<hisq_lattice> lats{lat};
+    std::vector<double> ms{mass};
+    SolveSet &S = lat->cg;
+    st = build_set(lat, S, lats, ms, 0.0);
+    if (st != HISQ_OK) return st;
+    double *xs = nullptr, *x_cur = nullptr, *bd = nullptr;
+    HIPCHK(lat, hipMalloc(&xs, (size_t)maxpairs * h * 48));
+    HIPCHK(lat, hipMalloc(&x_cur, (size_t)h * 48));
+    HIPCHK(lat, hipMalloc(&bd, (size_t)h * 48));
+    HIPCHK(lat, hipMemcpy(bd, b, (size_t)h * 48, hipMemcpyHostToDevice));
+    hisq_solver_params prm;
+    hisq_default_params(&prm);
+    prm.sloppy = HISQ_F64;
+    prm.check_every = every;
+    prm.flags = HISQ_DEVICE_PTR;
+    // The reference x* is solved well beyond the 1e-10 target so that
+    // e_i = x* - x_i is accurate: A e_i = r_i - r*, with |r*| <= 1e-12 |b|.
+    prm.tol = 1e-12;
+    // Plain FP64 CG: with no intermediate reliable update the iterate lives in
+    // x_lo, which the chunk hook copies out every `every` iterations.
+    struct Snap {
+        double *xs;
+        long long h;
+        int max, taken;
+    } snap{xs, h, maxpairs, 1};
+    HIPCHK(lat, hipMemsetAsync(xs, 0, (size_t)h * 48, s));   // x_0 = 0
+    auto hook = [](SolveSet &S, void *ctx, hipStream_t st) -> hipError_t {
+        Snap *sn = (Snap *)ctx;
+        if (sn->taken >= sn->max || S.hst[0].status != ST_RUNNING) return hipSuccess;
+        hipError_t e = hipMemcpyAsync(sn->xs + (size_t)sn->taken * sn->h * 6, S.xlo.p, (size_t)sn->h * 48,
+                                      hipMemcpyDeviceToDevice, st);
+        sn->taken++;
+        return e;
+    };
+    hisq_solver_info info;
+    const double *bb[1] = {bd};
+    double *xx[1] = {x_cur};
+    st = run_cg(lat, S, prm, bb, xx, &info, hook, &snap);
+    if (st != HISQ_OK) {
+        (void)hipFree(xs); (void)hipFree(x_cur); (void)hipFree(bd);
+        return st;
+    }
+    const int taken = snap.taken;
+    PairBlock pb;
+    pb.lat = lat;
+    pb.n = taken;
+    HIPCHK(lat, hipMalloc(&pb.mem, (size_t)taken * 2 * h * 24));
+    std::vector<double> xh((size_t)h * 6), xsh((size_t)h * 6), rh((size_t)h * 6);
+    HIPCHK(lat, hipMemcpy(xsh.data(), x_cur, (size_t)h * 48, hipMemcpyDeviceToHost));
+    double *t_odd = nullptr, *r_hi = nullptr;
+    HIPCHK(lat, hipMalloc(&t_odd, (size_t)h * 48));
+    HIPCHK(lat, hipMalloc(&r_hi, (size_t)h * 48));
+    ProbDesc d = lattice_desc(lat);
+    d.diag = 4.0 * mass * mass;
+    ProbDesc *dd = nullptr;
+    HIPCHK(lat, hipMalloc(&dd, sizeof d));
+    HIPCHK(lat, hipMemcpy(dd, &d, sizeof d, hipMemcpyHostToDevice));
+    pb.ee.resize(taken);
+    std::vector<double> rr(taken, 0.0);
+    double b2 = 0.0;
+    for (int i = 0; i < taken; i++) {
+        double *xi = xs + (size_t)i * h * 6;
+        // r_i = b - A x_i with the FP64 operator
+        DslashLaunch a;
+        memset(&a, 0, sizeof a);
+        a.probs = dd;
+        a.out_par = 1;
+        a.lslot = 0;
+        a.in = xi;
+        a.out = t_odd;
+        HIPCHK(lat, launch_dslash(0, 18, 0, EPI_PLAIN, 8, a, lat->ntile, s));
+        a.out_par = 0;
+        a.in = t_odd;
+        a.out = r_hi;
+        a.aux = xi;
+        a.bvec = bd;
+        HIPCHK(lat, launch_dslash(0, 18, 0, EPI_RES, 8, a, lat->ntile, s));
+        HIPCHK(lat, hipStreamSynchronize(s));
+        HIPCHK(lat, hipMemcpy(xh.data(), xi, (size_t)h * 48, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < xh.size(); k++) xh[k] = xsh[k] - xh[k];      // e_i in FP64
+        double ee = 0;
+        for (double v : xh) ee += v * v;
+        pb.ee[i] = ee;
+        std::vector<float> ef(xh.begin(), xh.end());
+        HIPCHK(lat, hipMemcpy(pb.mem + ((size_t)2 * i + 1) * h * 6, ef.data(), ef.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(lat, launch_convert(r_hi, 0, pb.mem + (size_t)2 * i * h * 6, 1, h * 3, s));
+        HIPCHK(lat, hipStreamSynchronize(s));
+        HIPCHK(lat, hipMemcpy(rh.data(), r_hi, (size_t)h * 48, hipMemcpyDeviceToHost));
+        double r2 = 0;
+        for (double v : rh) r2 += v * v;
+        rr[i] = r2;
+        if (i == 0) b2 = r2;   // x_0 = 0: r_0 = b
+    }
+    (void)hipFree(dd); (void)hipFree(t_odd); (void)hipFree(r_hi);
+    (void)hipFree(xs); (void)hipFree(x_cur); (void)hipFree(bd);
+    // keep the pairs whose residual is well above the reference's own
+    // (|r_i| >= 1e-9 |b|, i.e. 1e3 times |r*|), compacted in order
+    int keep = 0;
+    for (int i = 0; i < taken; i++) {
+        if (!(rr[i] >= 1e-18 * b2) || pb.ee[i] == 0.0) continue;
+        if (keep != i)
+            HIPCHK(lat, hipMemcpy(pb.mem + (size_t)2 * keep * h * 6, pb.mem + (size_t)2 * i * h * 6, (size_t)h * 48,
+                                  hipMemcpyDeviceToDevice));
+        pb.ee[keep++] = pb.ee[i];
+    }
+    pb.n = keep;
+    pb.ee.resize(keep);
+    if (keep > 0) n->pairs.push_back(pb);
+    else (void)hipFree(pb.mem);
+    if (npairs) *npairs = keep;
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_pair_count(hisq_ptc n, int *count)
+{
+    if (!n || !count) return HISQ_ERR_ARG;
+    int c = 0;
+    for (auto &pb : n->pairs) c += pb.n;
+    *count = c;
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_get_pair(hisq_ptc n, int index, double *r, double *e)
+{
+    if (!n || !r || !e || index < 0) return HISQ_ERR_ARG;
+    for (auto &pb : n->pairs) {
+        if (index >= pb.n) {
+            index -= pb.n;
+            continue;
+        }
+        const long long h = pb.lat->h;
+        std::vector<float> f((size_t)h * 12);
+        HIPCHK(pb.lat, hipStreamSynchronize(pb.lat->s));
+        HIPCHK(pb.lat, hipMemcpy(f.data(), pb.mem + (size_t)2 * index * h * 6, (size_t)h * 48, hipMemcpyDeviceToHost));
+        for (long long k = 0; k < h * 6; k++) {
+            r[k] = f[k];
+            e[k] = f[h * 6 + k];
+        }
+        return HISQ_OK;
+    }
+    return HISQ_ERR_ARG;
+}
+
+// Training step on a minibatch (all pairs of one lattice):
+//   forward   a_0 = E r, a_l = L_l a_{l-1} (l = 1..n), b_n = a_n,
+//             b_{l-1} = L_l^+ b_l, z = E^+ b_0;
+//   loss      scale-invariant (k_ptc_loss_*), g_{b_0} on even sites;
+//   backward  through the adjoint half (l = 1..n): the weight gradient of the
+//             adjoint application, mapped back to W_l by the adjoint-weight
+//             transform, and g_{b_l} = L_l g_{b_{l-1}}; then through the
+//             forward half (l = n..1) with g_{a_n} = g_{b_n}:
+//             the weight gradient and g_{a_{l-1}} = L_l^+ g_{a_l};
+//   update    Adam on the FP32 master, refreshed FP16 and adjoint copies.
+hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned long long seed, double *losses)
+{
+    if (!n || steps < 0 || batch < 1 || !(lr > 0)) return HISQ_ERR_ARG;
+    hisq_lattice lat0 = n->lat;
+    if (n->pairs.empty()) return set_err(lat0, HISQ_ERR_STATE, "no training pairs (hisq_ptc_harvest)");
+    if (steps > 65536) return set_err(lat0, HISQ_ERR_ARG, "at most 65536 steps per call");
+    HIPCHK(lat0, hipSetDevice(lat0->device));
+    hipStream_t s = lat0->s;
+    const int C = cmax(n);
+    long long V = 0;
+    for (auto &pb : n->pairs) {
+        V = std::max(V, pb.lat->V);
+        if (pb.lat->s != s) HIPCHK(lat0, hipStreamSynchronize(pb.lat->s));
+    }
+    const long long h = V / 2;
+    const int nl = n->nlayer;
+    // workspace per batch entry: a_1..a_n and b_1..b_{n-1} (full, C channels),
+    // two gradient buffers (full), and z, g_{b_0}, r, e (even)
+    const long long actf = (long long)C * 2 * h * 6;
+    const size_t nbuf = (size_t)(2 * nl + 1);
+    const size_t need = (size_t)batch * (actf * nbuf + h * 6 * 4);
+    if (n->wsB != batch || n->wsV != V) {
+        if (n->act) (void)hipFree(n->act);
+        if (n->dee) (void)hipFree(n->dee);
+        n->act = nullptr;
+        n->dee = nullptr;
+        HIPCHK(lat0, hipMalloc(&n->act, need * 4));
+        HIPCHK(lat0, hipMalloc(&n->dee, sizeof(double) * batch));
+        n->wsB = batch;
+        n->wsV = V;
+    }
+    const size_t ntl = (size_t)((h + 63) / 64);
+    const size_t pneed = (size_t)batch * 2 * ntl * 9 * C * C * 2 + 64;
+    const size_t lneed = (size_t)batch * ntl * NPART + 4 * (size_t)batch + 4;
+    if (n->part_n < std::max(pneed, lneed)) {
+        if (n->part) (void)hipFree(n->part);
+        n->part_n = std::max(pneed, lneed);
+        HIPCHK(lat0, hipMalloc(&n->part, n->part_n * 8));
+    }
+    float *A = n->act;
+    auto full = [&](size_t k) { return A + (size_t)batch * actf * k; };
+    std::vector<float *> acts(nl + 1), bs(nl + 1);
+    for (int l = 1; l <= nl; l++) acts[l] = full(l - 1);
+    for (int l = 1; l < nl; l++) bs[l] = full(nl + l - 1);
+    bs[nl] = acts[nl];
+    float *gbuf[2] = {full(2 * nl - 1), full(2 * nl)};
+    float *zb = full(nbuf);
+    float *g0 = zb + (size_t)batch * h * 6;
+    float *rb = g0 + (size_t)batch * h * 6;
+    float *eb = rb + (size_t)batch * h * 6;
+    long long total = 0;
+    for (auto &pb : n->pairs) total += pb.n;
+    std::mt19937_64 rng(seed);
+    for (int it = 0; it < steps; it++) {
+        // draw a lattice (weighted by its pair count), then `batch` pairs of it
+        long long pick = (long long)(rng() % (unsigned long long)total);
+        size_t g = 0;
+        while (pick >= n->pairs[g].n) pick -= n->pairs[g++].n;
+        PairBlock &pb = n->pairs[g];
+        hisq_lattice lat = pb.lat;
+        hisq_status st = ensure_fp32_links(lat);
+        if (st != HISQ_OK) return st;
+        const long long hl = lat->h;
+        const long long af = (long long)C * 2 * hl * 6;
+        std::vector<double> ee(batch);
+        for (int b = 0; b < batch; b++) {
+            const int i = (int)(rng() % (unsigned long long)pb.n);
+            HIPCHK(lat0, hipMemcpyAsync(rb + (size_t)b * hl * 6, pb.mem + (size_t)2 * i * hl * 6, hl * 24,
+                                        hipMemcpyDeviceToDevice, s));
+            HIPCHK(lat0, hipMemcpyAsync(eb + (size_t)b * hl * 6, pb.mem + ((size_t)2 * i + 1) * hl * 6, hl * 24,
+                                        hipMemcpyDeviceToDevice, s));
+            ee[b] = pb.ee[i];
+        }
+        HIPCHK(lat0, hipMemcpyAsync(n->dee, ee.data(), sizeof(double) * batch, hipMemcpyHostToDevice, s));
+        // forward half
+        for (int l = 1; l <= nl; l++) {
+            const bool first = l == 1;
+            HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, n->w32 + 2 * n->woff[l - 1], n->chans[l - 1], n->chans[l],
+                                   first ? rb : acts[l - 1], first ? hl * 6 : af, first ? 1 : -1, acts[l], af, 2, 0, 1,
+                                   batch, s));
+        }
+        // adjoint half
+        for (int l = nl; l >= 1; l--) {
+            const float *w = n->wa32 + 2 * n->woff[l - 1];
+            if (l == 1)
+                HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, w, n->chans[l], n->chans[l - 1], bs[1], af, -1, zb,
+                                       hl * 6, 1, 0, 0, batch, s));
+            else
+                HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, w, n->chans[l], n->chans[l - 1], bs[l], af, -1, bs[l - 1],
+                                       af, 2, 0, 1, batch, s));
+        }
+        // z = r + E^+ b_0, then the loss and g_z = g_{b_0}
+        HIPCHK(lat0, launch_add_f32(zb, rb, (long long)batch * hl * 6, s));
+        PtcLaunch la = base_launch(lat, 2);
+        la.in = zb;
+        la.in_bstride = hl * 6;
+        la.tgt = eb;
+        la.tgt_bstride = hl * 6;
+        la.out = g0;
+        la.out_bstride = hl * 6;
+        la.ee = n->dee;
+        la.partials = n->part;
+        HIPCHK(lat0, launch_ptc_loss(la, lat->ntile, batch, n->dloss + it, s));
+        HIPCHK(lat0, hipMemsetAsync(n->gw, 0, sizeof(double) * 2 * n->nw, s));
+        // backward through the adjoint half
+        const float *gcur = g0;
+        long long g_bs = hl * 6;
+        int g_pstride = 1;
+        int k = 0;
+        for (int l = 1; l <= nl; l++) {
+            const int ci = n->chans[l], co = n->chans[l - 1];   // the adjoint application maps ci -> co
+            HIPCHK(lat0, run_wgrad(n, lat, ci, co, bs[l], af, -1, gcur, g_bs, g_pstride, batch, n->gtmp, 0, s));
+            HIPCHK(lat0, launch_ptc_gadj(n->gtmp, ci, co, n->gw + 2 * n->woff[l - 1], s));
+            HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, n->w32 + 2 * n->woff[l - 1], co, ci, gcur, g_bs,
+                                   g_pstride == 1 ? 1 : -1, gbuf[k], af, 2, 0, 1, batch, s));
+            gcur = gbuf[k];
+            g_bs = af;
+            g_pstride = 2;
+            k ^= 1;
+        }
+        // backward through the forward half
+        for (int l = nl; l >= 1; l--) {
+            const int ci = n->chans[l - 1], co = n->chans[l];
+            const bool first = l == 1;
+            HIPCHK(lat0, run_wgrad(n, lat, ci, co, first ? rb : acts[l - 1], first ? hl * 6 : af, first ? 1 : -1, gcur,
+                                   af, 2, batch, n->gw + 2 * n->woff[l - 1], 1, s));
+            if (!first) {
+                HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, n->wa32 + 2 * n->woff[l - 1], co, ci, gcur, af, -1,
+                                       gbuf[k], af, 2, 0, 1, batch, s));
+                gcur = gbuf[k];
+                k ^= 1;
+            }
+        }
+        n->step += 1;
+        HIPCHK(lat0, launch_adam(n->w32, n->m, n->v, n->gw, 2 * n->nw, n->step, (float)lr, n->w16, s));
+        HIPCHK(lat0, refresh_adjoint(n, s));
+    }
+    if (losses && steps > 0)
+        HIPCHK(lat0, hipMemcpyAsync(losses, n->dloss, sizeof(double) * steps, hipMemcpyDeviceToHost, s));
+    HIPCHK(lat0, hipStreamSynchronize(s));
+    return HISQ_OK;
+}
+
+}  // extern "C"

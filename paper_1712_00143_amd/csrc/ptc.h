@@ -1,0 +1,54 @@
+// Launch descriptors of the PTC preconditioner and flexible-CG kernels.
+#pragma once
+#include "hisq_dev.h"
+
+namespace hisq {
+
+struct PtcLaunch {
+    const ProbDesc *probs;   // the lattice (links, geometry)
+    int lslot;               // link set for the transports
+    int in_zero_par;         // parity whose input is known zero (-1: none)
+    const void *w;           // weights [Cout][Cin][9] complex (float2 or half2)
+    const float *in;         // input activations [B][Cin][2][h][3] complex
+    long long in_bstride;    // floats between batch entries
+    float *out;              // output [B][Cout][out_pstride][h][3]
+    long long out_bstride;
+    int out_pstride;         // parities stored per output channel (1 or 2)
+    int out_par0;            // first stored output parity
+    int par_lo;              // first output parity computed (grid: npar * ntile blocks)
+    int pad;
+    const float *g;          // weight gradient: output gradient [B][Cout][g_pstride][h][3]
+    long long g_bstride;
+    int g_pstride, g_par0;
+    double *partials;
+    const float *tgt;        // loss: targets [B][h][3]
+    long long tgt_bstride;
+    const double *ee;        // loss: |target|^2 per batch entry
+};
+
+hipError_t launch_ptc_layer(int prec, int recon, bool w16, int cin, int cout, int W, const PtcLaunch &a, int nblk,
+                            int batch, hipStream_t s);
+hipError_t launch_ptc_wgrad(int cin, int cout, const PtcLaunch &a, int nblk, int batch, hipStream_t s);
+hipError_t launch_ptc_wsum(const double *partials, long long nrow, int cin, int cout, double *gw, int accumulate,
+                           hipStream_t s);
+hipError_t launch_ptc_loss(const PtcLaunch &a, int ntile, int batch, double *loss, hipStream_t s);
+hipError_t launch_adam(float *w, float *m, float *v, const double *g, int n, int step, float lr, __half *w16,
+                       hipStream_t s);
+hipError_t launch_ptc_adjoint(const float *w, int cin, int cout, float *wadj, hipStream_t s);
+hipError_t launch_to_half(const float *w, __half *w16, int n, hipStream_t s);
+hipError_t launch_ptc_gadj(const double *gp, int cin_p, int cout_p, double *gw, hipStream_t s);
+hipError_t launch_add_f32(float *z, const float *r, long long n, hipStream_t s);
+
+// flexible CG vector kernels (FP32 vectors, complex FP64 scalars in SolveState::cplx)
+struct FcgLaunch {
+    const ProbDesc *probs;
+    SolveState *states;
+    int want;
+    int op;
+    double *partials;
+    float *r, *x, *p, *q, *z;
+};
+enum : int { FCG_DOTS_A = 0, FCG_XR = 1, FCG_DOTS_B = 2, FCG_P = 3 };
+hipError_t launch_fcg(const FcgLaunch &a, int ntile, hipStream_t s);
+
+}  // namespace hisq

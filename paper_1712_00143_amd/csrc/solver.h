@@ -21,8 +21,12 @@ hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lat
 
 // Mixed / plain CG over every problem of S.  b[k], x[k]: FP64 vectors
 // (host, or device with HISQ_DEVICE_PTR).  info: nprob entries or nullptr.
+// hook: called after every chunk (after the status read, before any reliable
+// update) with ctx; used to snapshot iterates.
+typedef hipError_t (*ChunkHook)(SolveSet &S, void *ctx, hipStream_t s);
 hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm,
-                   const double *const *b, double *const *x, hisq_solver_info *info);
+                   const double *const *b, double *const *x, hisq_solver_info *info,
+                   ChunkHook hook = nullptr, void *hook_ctx = nullptr);
 
 size_t link_site_bytes(int prec, int recon);
 

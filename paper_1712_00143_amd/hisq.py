@@ -36,7 +36,7 @@ EXPORTS = [
     "hisq_load_links", "hisq_prepare_links", "hisq_dslash", "hisq_cg", "hisq_multishift_cg",
     "hisq_batch_cg", "hisq_ptc_create", "hisq_ptc_destroy", "hisq_ptc_set_weights",
     "hisq_ptc_get_weights", "hisq_ptc_layer_forward", "hisq_ptc_layer_backward", "hisq_ptc_apply",
-    "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned",
+    "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
 ]
 
 
@@ -51,7 +51,8 @@ class hisq_solver_info(ctypes.Structure):
                 ("converged", ctypes.c_int), ("status", ctypes.c_int),
                 ("true_residual", ctypes.c_double), ("time_s", ctypes.c_double),
                 ("dslash_bytes", ctypes.c_double), ("flops", ctypes.c_double),
-                ("t_done_s", ctypes.c_double)]
+                ("t_done_s", ctypes.c_double), ("fell_back", ctypes.c_int),
+                ("fcg_iters", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -231,6 +232,117 @@ class Lattice:
         if raise_on_fail:
             _check(st, self.handle, "hisq_multishift_cg")
         return x, [i.as_dict() for i in infos]
+
+
+class PTC:
+    """Learned parallel-transport preconditioner bound to one lattice."""
+
+    def __init__(self, lattice, chans=(1, 4, 4, 1)):
+        self.lat = lattice
+        self.chans = tuple(int(c) for c in chans)
+        self.nlayer = len(self.chans) - 1
+        self.nw = sum(9 * a * b for a, b in zip(self.chans[:-1], self.chans[1:]))
+        h = ctypes.c_void_p()
+        c = (ctypes.c_int * len(self.chans))(*self.chans)
+        _check(lib().hisq_ptc_create(lattice.handle, ctypes.c_int(self.nlayer), c, ctypes.byref(h)),
+               lattice.handle, "hisq_ptc_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle is not None:
+            lib().hisq_ptc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st, what):
+        _check(st, self.lat.handle, what)
+
+    def set_weights(self, weights):
+        """weights: list of complex [Cout][Cin][9] arrays, layer by layer."""
+        flat = np.concatenate([np.ascontiguousarray(w, dtype=np.complex128).ravel() for w in weights])
+        assert flat.size == self.nw
+        self._err(lib().hisq_ptc_set_weights(self.handle, flat.ctypes.data_as(ctypes.c_void_p)),
+                  "hisq_ptc_set_weights")
+
+    def get_weights(self):
+        flat = np.zeros(self.nw, dtype=np.complex128)
+        self._err(lib().hisq_ptc_get_weights(self.handle, flat.ctypes.data_as(ctypes.c_void_p)),
+                  "hisq_ptc_get_weights")
+        out, o = [], 0
+        for a, b in zip(self.chans[:-1], self.chans[1:]):
+            out.append(flat[o:o + 9 * a * b].reshape(b, a, 9))
+            o += 9 * a * b
+        return out
+
+    def layer_forward(self, layer, inp, out):
+        ip, _, k1 = _ptr(inp)
+        op, _, k2 = _ptr(out)
+        self._err(lib().hisq_ptc_layer_forward(self.handle, ctypes.c_int(layer), ip, op,
+                                               ctypes.c_int(HISQ_DEVICE_PTR)), "hisq_ptc_layer_forward")
+
+    def layer_backward(self, layer, inp, gout, gin=None):
+        """Returns the weight gradient [Cout][Cin][9] (complex, host)."""
+        ip, _, k1 = _ptr(inp)
+        gp, _, k2 = _ptr(gout)
+        gi, _, k3 = _ptr(gin)
+        a, b = self.chans[layer], self.chans[layer + 1]
+        gw = np.zeros((b, a, 9), dtype=np.complex128)
+        self._err(lib().hisq_ptc_layer_backward(self.handle, ctypes.c_int(layer), ip, gp, gi,
+                                                gw.ctypes.data_as(ctypes.c_void_p),
+                                                ctypes.c_int(HISQ_DEVICE_PTR)), "hisq_ptc_layer_backward")
+        return gw
+
+    def apply(self, r, z):
+        rp, _, k1 = _ptr(r)
+        zp, _, k2 = _ptr(z)
+        self._err(lib().hisq_ptc_apply(self.handle, rp, zp, ctypes.c_int(HISQ_DEVICE_PTR)), "hisq_ptc_apply")
+
+    def harvest(self, lattice, mass, b, every=10, maxpairs=64):
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        n = ctypes.c_int(0)
+        self._err(lib().hisq_ptc_harvest(self.handle, lattice.handle, ctypes.c_double(mass),
+                                         b.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(every),
+                                         ctypes.c_int(maxpairs), ctypes.byref(n)), "hisq_ptc_harvest")
+        return n.value
+
+    def pair_count(self):
+        n = ctypes.c_int(0)
+        self._err(lib().hisq_ptc_pair_count(self.handle, ctypes.byref(n)), "hisq_ptc_pair_count")
+        return n.value
+
+    def get_pair(self, index, h):
+        r = np.zeros((h, 3), dtype=np.complex128)
+        e = np.zeros((h, 3), dtype=np.complex128)
+        self._err(lib().hisq_ptc_get_pair(self.handle, ctypes.c_int(index), r.ctypes.data_as(ctypes.c_void_p),
+                                          e.ctypes.data_as(ctypes.c_void_p)), "hisq_ptc_get_pair")
+        return r, e
+
+    def train(self, steps, batch=8, lr=1e-3, seed=0):
+        losses = np.zeros(max(steps, 1))
+        self._err(lib().hisq_ptc_train(self.handle, ctypes.c_int(steps), ctypes.c_int(batch),
+                                       ctypes.c_double(lr), ctypes.c_ulonglong(seed),
+                                       losses.ctypes.data_as(ctypes.c_void_p)), "hisq_ptc_train")
+        return losses[:steps]
+
+    def cg_learned(self, lattice, mass, b, x=None, params=None, raise_on_fail=True):
+        params = params or hisq_default_params()
+        if x is None:
+            x = np.zeros((lattice.h, 3), dtype=np.complex128)
+        bp, bdev, k1 = _ptr(b)
+        xp, _, k2 = _ptr(x)
+        if bdev:
+            params.flags |= HISQ_DEVICE_PTR
+        info = hisq_solver_info()
+        st = lib().hisq_cg_learned(lattice.handle, self.handle, ctypes.c_double(mass), bp, xp,
+                                   ctypes.byref(params), ctypes.byref(info))
+        if raise_on_fail:
+            _check(st, lattice.handle, "hisq_cg_learned")
+        return x, info.as_dict()
 
 
 def hisq_batch_cg(lattices, masses, bs, params=None, raise_on_fail=True):

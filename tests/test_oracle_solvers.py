@@ -187,6 +187,47 @@ def test_ptc_loss_gradient_finite_differences():
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (l, idx, part, fd, an)
 
 
+def test_ptc_network_is_hermitian_psd_and_adjoint_weights():
+    """M = E^+ K^+ K E is Hermitian and positive semidefinite, and the layer
+    with adjoint_weights(W) is the adjoint layer of W."""
+    dims = (4, 4, 4, 6)
+    fat, _ = synth.make_links(dims, 0.25, seed=44)
+    ws = _rand_weights([1, 3, 2], 45, scale=0.7, ident=False)
+    u = synth.gaussian_even(dims, 46)
+    v = synth.gaussian_even(dims, 47)
+    Mu = oracle.ptc_apply(dims, fat, ws, u)
+    Mv = oracle.ptc_apply(dims, fat, ws, v)
+    assert abs(np.vdot(u, Mv) - np.vdot(Mu, v)) <= 1e-12 * abs(np.vdot(u, Mv))
+    assert np.vdot(v, Mv).real > 0 and abs(np.vdot(v, Mv).imag) <= 1e-12 * abs(np.vdot(v, Mv))
+    g = synth.gaussian_full(dims, 48, 3)
+    a = oracle.ptc_layer_adjoint(dims, fat, ws[0], g)
+    b = oracle.ptc_layer(dims, fat, oracle.adjoint_weights(ws[0]), g)
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(a)
+
+
+def test_ptc_loss_scale_invariance_and_exact_target():
+    """The loss depends only on the direction of M(r) relative to the target:
+    it is unchanged when the target is scaled by a complex number, vanishes
+    when the target is a multiple of M(r), and equals 1 when the target is
+    orthogonal to M(r).  With zero weights M is the identity."""
+    dims = (4, 4, 4, 4)
+    fat, _ = synth.make_links(dims, 0.25, seed=40)
+    ws = _rand_weights([1, 2, 1], 41, scale=0.5)
+    r = synth.gaussian_even(dims, 42)
+    e = synth.gaussian_even(dims, 43)
+    l0, g0 = oracle.ptc_loss_and_grad(dims, fat, ws, [r], [e])
+    l1, _ = oracle.ptc_loss_and_grad(dims, fat, ws, [r], [(2.0 - 1.5j) * e])
+    assert 0.0 < l0 < 1.0 and abs(l0 - l1) < 1e-14
+    zero = [np.zeros_like(w) for w in ws]
+    assert np.array_equal(oracle.ptc_apply(dims, fat, zero, r), r)
+    z = oracle.ptc_apply(dims, fat, ws, r)
+    lz, gz = oracle.ptc_loss_and_grad(dims, fat, ws, [r], [(0.3 + 0.7j) * z])
+    assert abs(lz) < 1e-14 and max(np.abs(g).max() for g in gz) < 1e-10
+    ortho = e - np.vdot(z, e) / np.vdot(z, z) * z
+    lo, _ = oracle.ptc_loss_and_grad(dims, fat, ws, [r], [ortho])
+    assert abs(lo - 1.0) < 1e-12
+
+
 def test_adam_first_step_closed_form():
     """At step 1 the bias-corrected moments are g and g^2, so the update is
     -lr * g / (|g| + eps)."""
