@@ -1,23 +1,30 @@
 """Benchmark of the HISQ Dslash + CG hot path on one MI355X.
 
-One step = one pass of the hot path over the 16^3x32 workload (eps 0.2,
-m 0.02, links already resident in HBM):
+Default (the headline line): the 16^3x32 workload (eps 0.2, m 0.02), links
+already resident in HBM.  One step is one pass of the hot path:
   * half-lattice Dslash D_eo and D_oe in FP32 recon-18, FP32 recon-12,
-    FP16 recon-12 and FP64 recon-18 (device vectors);
-  * CG to FP64 true residual 1e-10: plain FP64, mixed FP32 (recon-18) and
-    mixed FP16 storage (recon-12), all from the same source.
-value = FP32 recon-18 Dslash throughput in algorithmic GB/s (16 links +
-1 input + 1 output colour vector per output site), from HIP events recorded
-on the stream the kernels run on.  The CG times-to-solution, the other
-storage formats and a 32^4 lattice whose links do not fit the 256 MB
-Infinity Cache are reported beside it, with the FP64 CPU oracle timed on the
-host cores on a bounded sample.
+    FP16 recon-12 and FP64 recon-18 on device vectors;
+  * CG to FP64 true residual 1e-10 from the same source: plain FP64, mixed
+    FP32 (recon-18), mixed FP16 storage (recon-12), and the flexible CG with
+    the learned preconditioner (trained before the timed region on pairs
+    the solver harvests from two other sources).
+value = FP32 recon-18 Dslash throughput in algorithmic GB/s (16 links + one
+input + one output colour vector per output site) from HIP events recorded on
+the stream the kernels run on.  Reported beside it: the other formats, a 32^4
+lattice whose links exceed the 256 MB Infinity Cache, the solver times, and
+the FP64 CPU oracle timed on the host cores over a bounded sample.
+
+Other workloads (--workload): c0 (4^4 plain FP64 CG), c2 (24^3x48
+multi-shift, 12 shifts x 4 sources), c3 (64 uneven solves in one batch),
+c4 (16^4 learned preconditioner: 32 training fields, 8 held-out fields).
+Each prints one JSON line of its own.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -28,6 +35,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+METRIC = "Dslash GB/s (% HBM peak); CG time-to-1e-10: plain vs mixed/learned"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def site_bytes(prec, recon):
@@ -46,8 +58,8 @@ def kernel_hash():
 
 
 def traffic_entry():
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
+    """Measured HBM bytes per launch from the committed counter summary, if it
+    was taken on the current kernel source."""
     p = os.path.join(ROOT, "profiles", "dslash_f32r18_16x16x16x32_traffic.json")
     if not os.path.exists(p):
         return None
@@ -58,68 +70,97 @@ def traffic_entry():
     return d.get("hbm_bytes_per_launch")
 
 
-def timed_dslash(H, torch, lat, prec, recon, h, stream, reps):
-    """Average duration (s) of one half-Dslash launch, both parities,
-    measured with events on the library's stream."""
+def _vec(torch, prec, h, seed):
     dt = {0: torch.float64, 1: torch.float32, 2: torch.float16}[prec]
-    nreal = {0: 6 * h, 1: 6 * h, 2: 8 * h}[prec]    # FP16: 6h halves + h float scales (= 2h halves)
-    g = torch.Generator(device="cuda").manual_seed(7)
-    x = torch.randn(nreal, device="cuda", dtype=torch.float32, generator=g).to(dt)
+    n = {0: 6 * h, 1: 6 * h, 2: 8 * h}[prec]     # FP16: 6h halves + h float scales
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    x = torch.randn(n, device="cuda", dtype=torch.float32, generator=g).to(dt)
     if prec == 2:
         x[6 * h:] = 1.0
+    return x
+
+
+def timed_dslash(torch, lat, prec, recon, h, stream, reps):
+    """Average duration (s) of one half-Dslash launch (both parities alternate),
+    from events recorded on the library's stream around 2*reps back-to-back
+    launches.  A launch takes longer on the device than on the host, so the
+    queue never drains and the figure is the kernels' own time."""
+    x = _vec(torch, prec, h, 7)
     y = torch.empty_like(x)
     torch.cuda.synchronize()
-    lat.dslash(0, prec, recon, x, y)
+    lat.dslash(0, prec, recon, x, y)      # tunes the block shape first
     lat.dslash(1, prec, recon, y, x)
+    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        e0.record(stream)
-        for _ in range(reps):
-            lat.dslash(0, prec, recon, x, y)
-            lat.dslash(1, prec, recon, y, x)
-        e1.record(stream)
+    e0.record(stream)
+    for _ in range(reps):
+        lat.dslash(0, prec, recon, x, y)
+        lat.dslash(1, prec, recon, y, x)
+    e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1000.0 / (2 * reps)
 
 
-def cpu_baseline(w, fat, lng, budget_s=12.0):
-    """The FP64 oracle Dslash on the same lattice, as many half-Dslash
+def cpu_baseline(dims, fat, lng, budget_s=12.0):
+    """The FP64 oracle Dslash on the same lattice: as many half-Dslash
     applications as fit in budget_s seconds of host time."""
     import oracle
     from paper_1712_00143_amd import synth
-    psi = synth.gaussian_even(w.dims, 99)
+    psi = synth.gaussian_even(dims, 99)
     h = psi.shape[0]
-    oracle.dslash_half(w.dims, fat, lng, 0, psi)
+    oracle.dslash_half(dims, fat, lng, 0, psi)
     n = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        psi = oracle.dslash_half(w.dims, fat, lng, n % 2, psi)
+        psi = oracle.dslash_half(dims, fat, lng, n % 2, psi)
         psi /= np.linalg.norm(psi)
         n += 1
     dt = time.perf_counter() - t0
     gbs = n * h * site_bytes(0, 18) / dt / 1e9
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} FP64 half-Dslash applications on {w.dims} in {dt:.1f} s "
-                      f"(plain C oracle, OpenMP over sites)"}
+            "sample": f"{n} FP64 half-Dslash applications on {'x'.join(map(str, dims))} in {dt:.1f} s "
+                      f"(plain C oracle, OpenMP over sites, same byte model)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--reps", type=int, default=50, help="Dslash launches per parity per step")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-hbm", action="store_true", help="skip the 32^4 (beyond-cache) lattice")
-    ap.add_argument("--dslash-only", action="store_true", help="time only the Dslash (profiling)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU halo-exchange design is documented, not built)", file=sys.stderr)
-        sys.exit(2)
+def solve_timed(torch, stream, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
 
+
+def train_preconditioner(H, synth, dims, eps, mass, seed0, nfield, nsrc, steps, chans=(1, 4, 4, 1),
+                         every=10, maxpairs=60, batch=8, lr=3e-3):
+    """Harvest (residual, error) pairs with the solver on nfield seeded fields
+    and train the network on the GPU.  Returns (net, lattices, seconds, losses)."""
+    t0 = time.perf_counter()
+    lats, net = [], None
+    for j in range(nfield):
+        fat, lng = synth.make_links(dims, eps, seed=seed0 + j)
+        L = H.Lattice(dims)
+        L.load_links(fat, lng)
+        L.prepare_links(1, 18)
+        lats.append(L)
+        if net is None:
+            net = H.PTC(L, chans)
+            rng = np.random.default_rng(seed0)
+            net.set_weights([0.05 * (rng.standard_normal((b, a, 9)) + 1j * rng.standard_normal((b, a, 9)))
+                             for a, b in zip(chans[:-1], chans[1:])])
+        for s in range(nsrc):
+            net.harvest(L, mass, synth.gaussian_even(dims, seed0 + j + 500 + 100 * s), every=every,
+                        maxpairs=maxpairs)
+        log(f"harvested field {j + 1}/{nfield}: {net.pair_count()} pairs")
+    losses = net.train(steps, batch=batch, lr=lr, seed=seed0)
+    log(f"trained {steps} steps: loss {losses[:10].mean():.4f} -> {losses[-50:].mean():.4f}")
+    return net, lats, time.perf_counter() - t0, losses
+
+
+# ----------------------------------------------------------------- headline
+
+def run_headline(args):
     import torch
     from paper_1712_00143_amd import hisq as H
     from paper_1712_00143_amd import synth
@@ -129,7 +170,8 @@ def main():
     b = w.sources()[0]
     h = synth.volume(w.dims) // 2
     stream = torch.cuda.Stream()
-    lat = H.Lattice(w.dims, stream=H.ctypes.c_void_p(stream.cuda_stream))
+    sp = H.ctypes.c_void_p(stream.cuda_stream)
+    lat = H.Lattice(w.dims, stream=sp)
     lat.load_links(fat, lng)
     formats = [(1, 18), (1, 12), (2, 12), (0, 18)]
     for p, r in formats:
@@ -140,28 +182,49 @@ def main():
         "mixed_f32_r18": H.hisq_default_params(tol=1e-10, sloppy=1, recon=18, flags=H.HISQ_USE_GRAPH),
         "mixed_f16_r12": H.hisq_default_params(tol=1e-10, sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH),
     }
+    net = None
+    train_info = None
+    if not args.no_learned and not args.dslash_only:
+        # trained outside the timed region, on pairs from two other sources
+        net = H.PTC(lat, (1, 4, 4, 1))
+        rng = np.random.default_rng(1)
+        net.set_weights([0.05 * (rng.standard_normal((bb, a, 9)) + 1j * rng.standard_normal((bb, a, 9)))
+                         for a, bb in zip((1, 4, 4), (4, 4, 1))])
+        t0 = time.perf_counter()
+        srcs = w.sources()
+        npair = sum(net.harvest(lat, w.mass, srcs[k], every=20, maxpairs=60) for k in (1, 2))
+        losses = net.train(300, batch=8, lr=3e-3, seed=1)
+        train_info = {"pairs": npair, "steps": 300, "seconds": round(time.perf_counter() - t0, 3),
+                      "loss_first10": round(float(losses[:10].mean()), 4),
+                      "loss_last50": round(float(losses[-50:].mean()), 4)}
 
     def step():
         res = {"dslash_s": {}, "cg": {}}
         for p, r in formats:
-            res["dslash_s"][(p, r)] = timed_dslash(H, torch, lat, p, r, h, stream, args.reps)
+            res["dslash_s"][(p, r)] = timed_dslash(torch, lat, p, r, h, stream, args.reps)
         if not args.dslash_only:
             for name, prm in solves.items():
                 xd = torch.zeros_like(bd)
-                with torch.cuda.stream(stream):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    _, info = lat.cg(w.mass, bd, x=xd, params=prm)
-                    t1 = time.perf_counter()
-                info["wall_s"] = t1 - t0
-                res["cg"][name] = (info, xd)
+                (_, info), dt = solve_timed(torch, stream, lambda: lat.cg(w.mass, bd, x=xd, params=prm))
+                info["wall_s"] = dt
+                res["cg"][name] = info
+            if net is not None:
+                xd = torch.zeros_like(bd)
+                prm = H.hisq_default_params(tol=1e-10, sloppy=1, recon=18)
+                (_, info), dt = solve_timed(torch, stream, lambda: net.cg_learned(lat, w.mass, bd, x=xd, params=prm))
+                info["wall_s"] = dt
+                res["cg"]["learned_fcg_f32"] = info
         return res
 
     for _ in range(args.warmup):
         step()
+    log("warm-up done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = [step() for _ in range(args.steps)]
+    results = []
+    for k in range(args.steps):
+        results.append(step())
+        log(f"step {k + 1}/{args.steps}")
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
 
@@ -180,32 +243,35 @@ def main():
 
     cg = {}
     if not args.dslash_only:
-        for name in solves:
-            infos = [r["cg"][name][0] for r in results]
-            cg[name] = {"time_s": round(float(np.median([i["wall_s"] for i in infos])), 4),
+        for name in results[0]["cg"]:
+            infos = [r["cg"][name] for r in results]
+            cg[name] = {"time_s": round(float(np.median([i["wall_s"] for i in infos])), 5),
                         "iters": infos[-1]["iters"], "reliable_updates": infos[-1]["reliable_updates"],
                         "true_residual_fp64": float(f"{infos[-1]['true_residual']:.3e}"),
                         "converged": bool(infos[-1]["converged"])}
+            if name.startswith("learned"):
+                cg[name]["fell_back"] = bool(infos[-1]["fell_back"])
+                cg[name]["training"] = train_info
 
     hbm = None
     if not args.no_hbm:
         dims = (32, 32, 32, 32)
         f2, l2 = synth.make_links(dims, 0.2, seed=1900)
-        lat2 = H.Lattice(dims, stream=H.ctypes.c_void_p(stream.cuda_stream))
+        lat2 = H.Lattice(dims, stream=sp)
         lat2.load_links(f2, l2)
         del f2, l2
         hbm = {}
         h2 = synth.volume(dims) // 2
         for p, r in formats:
             lat2.prepare_links(p, r)
-            t = timed_dslash(H, torch, lat2, p, r, h2, stream, 20)
+            t = timed_dslash(torch, lat2, p, r, h2, stream, 20)
             gbs = h2 * site_bytes(p, r) / t / 1e9
             hbm[f"{['f64', 'f32', 'f16'][p]}_r{r}"] = {"us": round(t * 1e6, 2), "GB/s": round(gbs, 1),
                                                        "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
         lat2.close()
 
     out = {
-        "metric": "Dslash GB/s (% HBM peak); CG time-to-1e-10: plain vs mixed/learned",
+        "metric": METRIC,
         "value": round(achieved, 1),
         "unit": "GB/s",
         "n_gpus": 1,
@@ -227,13 +293,199 @@ def main():
         "dslash_32^4_beyond_infinity_cache": hbm,
         "cg_time_to_1e-10": cg,
     }
-    if cg:
-        out["cg_speedup_vs_plain_f64"] = {k: round(cg["plain_f64"]["time_s"] / v["time_s"], 2)
+    if "plain_f64" in cg:
+        out["cg_speedup_vs_plain_f64"] = {k: round(cg["plain_f64"]["time_s"] / v["time_s"], 3)
                                           for k, v in cg.items()}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, fat, lng)
+        out["cpu_baseline"] = cpu_baseline(w.dims, fat, lng)
+    if net is not None:
+        net.close()
     lat.close()
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------- other workloads
+
+def run_c0(args):
+    import torch
+    from paper_1712_00143_amd import hisq as H
+    from paper_1712_00143_amd import synth
+    w = synth.C0
+    fat, lng = w.links()
+    b = w.sources()[0]
+    lat = H.Lattice(w.dims)
+    lat.load_links(fat, lng)
+    res = {}
+    for name, fl in (("eager", 0), ("graph", H.HISQ_USE_GRAPH)):
+        prm = H.hisq_default_params(tol=1e-10, sloppy=0, flags=fl)
+        lat.cg(w.mass, b, params=prm)
+        ts = []
+        for _ in range(5):
+            (_, info), dt = solve_timed(torch, None, lambda: lat.cg(w.mass, b, params=prm))
+            ts.append(dt)
+        res[name] = {"time_s": round(float(np.median(ts)), 6), "iters": info["iters"],
+                     "true_residual_fp64": float(f"{info['true_residual']:.3e}")}
+    print(json.dumps({"workload": "plain FP64 CG 4^4, eps 0.3, m 0.1, tol 1e-10", "results": res}), flush=True)
+
+
+def run_c2(args):
+    import torch
+    from paper_1712_00143_amd import hisq as H
+    from paper_1712_00143_amd import synth
+    w = synth.C2
+    fat, lng = w.links()
+    b = w.sources()
+    shifts = synth.shifts_log(12)
+    stream = torch.cuda.Stream()
+    lat = H.Lattice(w.dims, stream=H.ctypes.c_void_p(stream.cuda_stream))
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    h = synth.volume(w.dims) // 2
+    # multi-RHS Dslash throughput (4 right-hand sides share the link stream)
+    x = torch.randn(4 * 6 * h, device="cuda")
+    y = torch.empty_like(x)
+    lat.dslash(0, 1, 18, x, y, nrhs=4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(20):
+        lat.dslash(0, 1, 18, x, y, nrhs=4)
+        lat.dslash(1, 1, 18, y, x, nrhs=4)
+    e1.record(stream)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1000.0 / 40
+    mrhs_bytes = h * (16 * 18 * 4 + 4 * 2 * 24)
+    prm = H.hisq_default_params(tol=1e-8, sloppy=1, flags=H.HISQ_USE_GRAPH)
+    lat.multishift_cg(w.mass, shifts, b, params=prm)
+    (xs, infos), dt = solve_timed(torch, stream, lambda: lat.multishift_cg(w.mass, shifts, b, params=prm))
+    worst = max(i["true_residual"] for i in infos)
+    print(json.dumps({
+        "workload": "multi-shift CG 24^3x48, 12 shifts in [1e-4, 1], 4 sources, m 0.01, FP32 + FP64 recurrences, tol 1e-8",
+        "mrhs_dslash_f32_r18_nrhs4": {"us": round(t * 1e6, 2), "GB/s": round(mrhs_bytes / t / 1e9, 1),
+                                      "frac_hbm": round(mrhs_bytes / t / 1e9 / PEAK_HBM_GBS, 4)},
+        "time_s": round(dt, 4), "krylov_phase_s": round(infos[0]["t_done_s"], 4),
+        "iters_per_shift_rhs0": [i["iters"] for i in infos[:12]],
+        "worst_true_residual_fp64": float(f"{worst:.3e}"),
+        "all_converged": all(i["converged"] for i in infos)}), flush=True)
+
+
+def run_c3(args):
+    import torch
+    from paper_1712_00143_amd import hisq as H
+    from paper_1712_00143_amd import synth
+    ws = synth.batch_workload(nper=args.nper)
+    lats, bs, ms = [], [], []
+    for q, wk in enumerate(ws):
+        if q % 16 == 0:
+            log(f"generating batch problem {q}/{len(ws)}")
+        fat, lng = wk.links()
+        L = H.Lattice(wk.dims)
+        L.load_links(fat, lng)
+        L.prepare_links(1, 18)
+        lats.append(L)
+        bs.append(wk.sources()[0])
+        ms.append(wk.mass)
+    prm = H.hisq_default_params(tol=1e-10, sloppy=1, flags=H.HISQ_USE_GRAPH)
+    H.hisq_batch_cg(lats, ms, bs, params=prm)          # warm-up: tuning, graph capture
+    (xs, infos), dt = solve_timed(torch, None, lambda: H.hisq_batch_cg(lats, ms, bs, params=prm))
+    tdone = np.array([i["t_done_s"] for i in infos])
+    total_bytes = sum(i["dslash_bytes"] for i in infos)
+    # the same solves one after another, for comparison
+    t_seq = 0.0
+    for L, m, bb in zip(lats, ms, bs):
+        (_, _), d1 = solve_timed(torch, None, lambda: L.cg(m, bb, params=prm))
+        t_seq += d1
+    print(json.dumps({
+        "workload": f"batched CG: {len(ws)} solves, {args.nper} each of 8^4, 12^4, 16^4, 16^3x32; eps~U[0.1,0.4], m~logU[0.005,0.2]; FP32 + FP64 reliable, tol 1e-10",
+        "time_s": round(dt, 4), "aggregate_dslash_GB/s": round(total_bytes / dt / 1e9, 1),
+        "time_to_solution_p50_s": round(float(np.percentile(tdone, 50)), 5),
+        "time_to_solution_p99_s": round(float(np.percentile(tdone, 99)), 5),
+        "iters_min_max": [min(i["iters"] for i in infos), max(i["iters"] for i in infos)],
+        "all_converged": all(i["converged"] for i in infos),
+        "sequential_time_s": round(t_seq, 4), "batch_speedup": round(t_seq / dt, 3)}), flush=True)
+
+
+def run_c4(args):
+    import torch
+    from paper_1712_00143_amd import hisq as H
+    from paper_1712_00143_amd import synth
+    w = synth.C4
+    net, tl, t_train, losses = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, args.nfield,
+                                                    args.nsrc, args.train_steps)
+    res = {"plain_f64": [], "mixed_f32": [], "mixed_f16_r12": [], "learned_fcg": [], "untrained_fcg": []}
+    untrained = None
+    for j in range(args.nheld):
+        fat, lng = synth.make_links(w.dims, w.eps, seed=4900 + j)
+        L = H.Lattice(w.dims)
+        L.load_links(fat, lng)
+        L.prepare_links(1, 18)
+        L.prepare_links(2, 12)
+        if untrained is None:
+            untrained = H.PTC(L, (1, 4, 4, 1))
+        for s in range(2):
+            b = synth.gaussian_even(w.dims, 5400 + 10 * j + s)
+            for name, fn in (
+                    ("plain_f64", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=0, flags=H.HISQ_USE_GRAPH))),
+                    ("mixed_f32", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
+                    ("mixed_f16_r12", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH))),
+                    ("learned_fcg", lambda: net.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1))),
+                    ("untrained_fcg", lambda: untrained.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1)))):
+                (_, info), dt = solve_timed(torch, None, fn)
+                res[name].append((info["iters"], dt, info["true_residual"], info.get("fell_back", 0)))
+            log(f"held-out field {j}, source {s}: " + ", ".join(f"{k} {v[-1][0]} it {v[-1][1]:.3f}s" for k, v in res.items()))
+        L.close()
+    summ = {k: {"iters_mean": round(float(np.mean([r[0] for r in v])), 1),
+                "time_s_mean": round(float(np.mean([r[1] for r in v])), 5),
+                "worst_true_residual": float(f"{max(r[2] for r in v):.3e}"),
+                "fell_back": int(sum(r[3] for r in v))} for k, v in res.items()}
+    print(json.dumps({
+        "workload": f"learned PTC preconditioner 16^4, eps 0.25, m 0.005: trained on {args.nfield} fields x {args.nsrc} sources, tested on {args.nheld} held-out fields x 2 sources",
+        "training": {"seconds": round(t_train, 2), "steps": args.train_steps,
+                     "loss_first10": round(float(losses[:10].mean()), 4),
+                     "loss_last50": round(float(losses[-50:].mean()), 4)},
+        "solves": summ,
+        "learned_iteration_gain_vs_plain": round(summ["plain_f64"]["iters_mean"] / summ["learned_fcg"]["iters_mean"], 3),
+        "learned_time_gain_vs_plain": round(summ["plain_f64"]["time_s_mean"] / summ["learned_fcg"]["time_s_mean"], 3)}),
+        flush=True)
+
+
+def run_copy(args):
+    """Calibration for the HBM byte counters: a device-to-device copy of a
+    known size (512 MiB read + 512 MiB written per launch), three launches."""
+    import torch
+    n = 512 * 1024 * 1024 // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "device copy calibration", "bytes_read_per_launch": 4 * n,
+                      "bytes_written_per_launch": 4 * n, "launches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--reps", type=int, default=50, help="Dslash launches per parity per step")
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "copy"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the 32^4 (beyond-cache) lattice")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--dslash-only", action="store_true", help="time only the Dslash")
+    ap.add_argument("--nper", type=int, default=16, help="c3: solves per lattice size")
+    ap.add_argument("--nfield", type=int, default=32, help="c4: training fields")
+    ap.add_argument("--nsrc", type=int, default=4, help="c4: sources per training field")
+    ap.add_argument("--nheld", type=int, default=8, help="c4: held-out fields")
+    ap.add_argument("--train-steps", type=int, default=600)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU halo-exchange design is documented, not built)", file=sys.stderr)
+        sys.exit(2)
+    {"c0": run_c0, "c1": run_headline, "c2": run_c2, "c3": run_c3, "c4": run_c4,
+     "copy": run_copy}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -92,6 +92,8 @@ typedef struct {
     double t_done_s;         /* batch solves: device time from start to convergence */
     int fell_back;           /* learned solver: 1 if it handed over to plain CG */
     int fcg_iters;           /* learned solver: flexible-CG iterations before any hand-over */
+    int restarts;            /* reliable updates that restarted the search direction (p = r)
+                                because the FP64 residual exceeded twice the sloppy one */
 } hisq_solver_info;
 
 /* Fill params with defaults: tol 1e-10, maxiter 100000, F64, recon 18,
@@ -182,6 +184,9 @@ hisq_status hisq_batch_cg(int nprob, const hisq_lattice *lats, const double *mas
 /* nlayer layers (<= 8), chans[0..nlayer] channel counts (chans[0] = 1; each
  * 1, 2, 4 or 8).  Weights start at zero (M = 1). */
 hisq_status hisq_ptc_create(hisq_lattice lat, int nlayer, const int *chans, hisq_ptc *out);
+/* Frees the network and its stored pairs.  It may be called after the
+ * lattice handles are destroyed; every other network call needs the handle
+ * it was created on (and, for training, the handles the pairs came from). */
 hisq_status hisq_ptc_destroy(hisq_ptc net);
 /* Weights as complex FP64, layer by layer [Cout][Cin][9]; set writes the
  * FP32 master copy and the FP16 inference copy. */

@@ -327,6 +327,7 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
             const ProbDesc &d = S.hdesc[k];
             in.iters = st.iter;
             in.reliable_updates = st.reliable;
+            in.restarts = st.restarts;
             in.converged = st.status == ST_CONVERGED;
             in.status = sk;
             in.true_residual = st.bb > 0 ? std::sqrt(st.rr_true / st.bb) : 0.0;

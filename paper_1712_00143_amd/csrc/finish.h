@@ -130,7 +130,17 @@ __device__ __forceinline__ void run_finisher(int fin, SolveState *st, const doub
         } else if (!isfinite(rt)) {
             st->status = ST_BREAKDOWN;
         } else {
-            st->beta = rt / st->rr_old;
+            // The sloppy recursion continues from the FP64 residual.  When
+            // that residual exceeds twice the sloppy one it replaces, the
+            // sloppy operator's error dominates the search direction
+            // (16-bit links at small mass): restart from p = r instead of
+            // carrying the stale direction with a large beta.
+            if (rt > 2.0 * st->rr) {
+                st->beta = 0.0;
+                st->restarts += 1;
+            } else {
+                st->beta = rt / st->rr_old;
+            }
             st->rr = rt;
             st->maxrr = rt;
             st->status = ST_RESUME;

@@ -71,7 +71,8 @@ struct SolveState {
     unsigned int counter;  // last-tile ticket for the in-kernel reductions
     int nshift_active;
     long long t_done;      // device clock when it converged
-    int pad[2];
+    int restarts;          // reliable updates that restarted p = r
+    int pad;
 };
 
 // Multi-shift per (problem, rhs) recurrence state

@@ -41,6 +41,7 @@ struct PairBlock {
 
 struct hisq_ptc_s {
     hisq_lattice lat = nullptr;
+    int device = 0;          // kept so that destruction never touches a handle
     int nlayer = 0;
     std::vector<int> chans;
     std::vector<int> woff;   // complex offset of each layer
@@ -210,6 +211,7 @@ hisq_status hisq_ptc_create(hisq_lattice lat, int nlayer, const int *chans, hisq
     HIPCHK(lat, hipSetDevice(lat->device));
     hisq_ptc n = new hisq_ptc_s();
     n->lat = lat;
+    n->device = lat->device;
     n->nlayer = nlayer;
     n->chans.assign(chans, chans + nlayer + 1);
     int maxw = 0;
@@ -238,8 +240,9 @@ hisq_status hisq_ptc_create(hisq_lattice lat, int nlayer, const int *chans, hisq
 hisq_status hisq_ptc_destroy(hisq_ptc n)
 {
     if (!n) return HISQ_ERR_ARG;
-    (void)hipSetDevice(n->lat->device);
-    (void)hipStreamSynchronize(n->lat->s);
+    // the lattice handles may already be gone: touch only the device
+    (void)hipSetDevice(n->device);
+    (void)hipDeviceSynchronize();
     for (void *p : {(void *)n->w32, (void *)n->m, (void *)n->v, (void *)n->wa32, (void *)n->w16, (void *)n->wa16,
                     (void *)n->gw, (void *)n->gtmp, (void *)n->act, (void *)n->part, (void *)n->dloss,
                     (void *)n->dee, (void *)n->inf})
@@ -307,7 +310,7 @@ hisq_status hisq_ptc_layer_backward(hisq_ptc n, int layer, const void *in, const
         HIPCHK(lat, run_layer(lat, 2, 1, 18, false, n->wa32 + 2 * n->woff[layer], cout, cin, (const float *)gout, 0,
                               -1, (float *)gin, 0, 2, 0, 1, 1, s));
     if (gw) {
-        const size_t need = (size_t)2 * lat->ntile * 9 * cin * cout * 2;
+        const size_t need = ((size_t)2 * lat->ntile + 256) * 9 * cin * cout * 2;
         if (n->part_n < need) {
             if (n->part) (void)hipFree(n->part);
             HIPCHK(lat, hipMalloc(&n->part, need * 8));
@@ -530,7 +533,8 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
         n->wsV = V;
     }
     const size_t ntl = (size_t)((h + 63) / 64);
-    const size_t pneed = (size_t)batch * 2 * ntl * 9 * C * C * 2 + 64;
+    // weight-gradient rows plus the second-pass rows of the sum
+    const size_t pneed = ((size_t)batch * 2 * ntl + 256) * 9 * C * C * 2 + 64;
     const size_t lneed = (size_t)batch * ntl * NPART + 4 * (size_t)batch + 4;
     if (n->part_n < std::max(pneed, lneed)) {
         if (n->part) (void)hipFree(n->part);

@@ -225,6 +225,20 @@ __global__ void __launch_bounds__(576) k_ptc_wgrad(PtcLaunch a)
         }
 }
 
+// First pass of the weight-gradient sum: block b adds rows b, b + G, b + 2G,
+// ... (consecutive threads read consecutive values: coalesced) into
+// part2[b][v].  The second pass (k_ptc_wsum over the G rows) finishes in a
+// fixed order, so the result does not depend on scheduling.
+constexpr int WSUM_G = 256;
+__global__ void __launch_bounds__(256) k_ptc_wsum1(const double *partials, long long nrow, int nv, double *part2)
+{
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        double s = 0.0;
+        for (long long r = blockIdx.x; r < nrow; r += gridDim.x) s += partials[r * nv + v];
+        part2[(size_t)blockIdx.x * nv + v] = s;
+    }
+}
+
 // g_w[c][c'][k] = sum over partial rows (fixed order); one thread per value.
 __global__ void k_ptc_wsum(const double *partials, long long nrow, int cin, int cout, double *gw, int accumulate)
 {
@@ -385,7 +399,16 @@ hipError_t launch_ptc_wsum(const double *partials, long long nrow, int cin, int 
                            hipStream_t s)
 {
     const int nv = 9 * cout * cin * 2;
-    hipLaunchKernelGGL(k_ptc_wsum, dim3((nv + 255) / 256), dim3(256), 0, s, partials, nrow, cin, cout, gw, accumulate);
+    if (nrow > 4 * WSUM_G) {
+        // partials holds nrow rows followed by room for WSUM_G more
+        double *part2 = const_cast<double *>(partials) + (size_t)nrow * nv;
+        hipLaunchKernelGGL(k_ptc_wsum1, dim3(WSUM_G), dim3(256), 0, s, partials, nrow, nv, part2);
+        hipLaunchKernelGGL(k_ptc_wsum, dim3((nv + 255) / 256), dim3(256), 0, s, (const double *)part2,
+                           (long long)WSUM_G, cin, cout, gw, accumulate);
+    } else {
+        hipLaunchKernelGGL(k_ptc_wsum, dim3((nv + 255) / 256), dim3(256), 0, s, partials, nrow, cin, cout, gw,
+                           accumulate);
+    }
     return hipGetLastError();
 }
 

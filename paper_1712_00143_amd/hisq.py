@@ -52,7 +52,7 @@ class hisq_solver_info(ctypes.Structure):
                 ("true_residual", ctypes.c_double), ("time_s", ctypes.c_double),
                 ("dslash_bytes", ctypes.c_double), ("flops", ctypes.c_double),
                 ("t_done_s", ctypes.c_double), ("fell_back", ctypes.c_int),
-                ("fcg_iters", ctypes.c_int)]
+                ("fcg_iters", ctypes.c_int), ("restarts", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -132,3 +132,27 @@ def test_batch_cg_uneven():
     assert infos[0]["iters"] < infos[3]["iters"]
     for L in lats:
         L.close()
+
+
+def test_fp16_links_small_mass_restart():
+    """16^4 at m = 0.005 (condition number near 5e5): the FP16-link operator's
+    own solution leaves a true residual of about 0.1, so continuing the old
+    search direction after a reliable update stalls.  The restart rule keeps
+    the FP16 solve within 1.5x the FP64 iteration count."""
+    H = _hisq()
+    w = synth.C4
+    fat, lng = w.links()
+    b = w.sources()[0]
+    lat = H.Lattice(w.dims)
+    lat.load_links(fat, lng)
+    _, ref = lat.cg(w.mass, b, params=H.hisq_default_params(tol=1e-10))
+    lat.prepare_links(2, 12)
+    p = H.hisq_default_params(tol=1e-10, sloppy=2, recon=12, maxiter=4 * ref["iters"])
+    x, info = lat.cg(w.mass, b, params=p)
+    print("fp64", ref["iters"], "fp16 r12", info["iters"], "restarts", info["restarts"])
+    assert info["converged"] == 1
+    assert info["restarts"] >= 1
+    assert info["iters"] <= 1.5 * ref["iters"]
+    tr = oracle.true_residual(w.dims, fat, lng, w.mass, b, x)
+    assert tr <= 1e-10
+    lat.close()
