@@ -82,24 +82,72 @@ def _vec(torch, prec, h, seed):
 
 def timed_dslash(torch, lat, prec, recon, h, stream, reps):
     """Average duration (s) of one half-Dslash launch (both parities alternate),
-    from events recorded on the library's stream around 2*reps back-to-back
-    launches.  A launch takes longer on the device than on the host, so the
-    queue never drains and the figure is the kernels' own time."""
+    as (graph, eager).  The 2*reps launches are captured once in a HIP graph on
+    the library's stream and replayed there between two events, so host launch
+    gaps do not count; the same launches issued eagerly are timed too.  graph
+    is None where capture fails."""
     x = _vec(torch, prec, h, 7)
     y = torch.empty_like(x)
     torch.cuda.synchronize()
-    lat.dslash(0, prec, recon, x, y)      # tunes the block shape first
+    lat.dslash(0, prec, recon, x, y)      # tunes the block shape before any capture
     lat.dslash(1, prec, recon, y, x)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        lat.dslash(0, prec, recon, x, y)
-        lat.dslash(1, prec, recon, y, x)
-    e1.record(stream)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / 1000.0 / (2 * reps)
+
+    def body():
+        for _ in range(reps):
+            lat.dslash(0, prec, recon, x, y)
+            lat.dslash(1, prec, recon, y, x)
+
+    graph = None
+    try:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            body()
+        with torch.cuda.stream(stream):
+            graph.replay()
+        torch.cuda.synchronize()
+    except Exception as exc:   # pragma: no cover - capture not supported
+        log(f"graph capture unavailable ({exc}); timing eager launches")
+        graph = None
+    def run(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1000.0 / (2 * reps)
+
+    t_eager = run(body)
+    t_graph = run(graph.replay) if graph is not None else None
+    return t_graph, t_eager
+
+
+def timed_ceilings(torch, stream, nbytes=1 << 30, reps=10):
+    """Practical HBM ceilings on the same stream, in GB/s: a device-to-device
+    copy of nbytes (read + written bytes) and a full sum over 2*nbytes (a
+    read-only stream; the half-Dslash is 96-98 % reads)."""
+    def run(fn):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1000.0 / reps
+
+    with torch.cuda.stream(stream):
+        x = torch.ones(nbytes // 4, device="cuda")
+        y = torch.empty_like(x)
+        t_copy = run(lambda: y.copy_(x))
+        del y
+        z = torch.ones(2 * nbytes // 4, device="cuda")
+        t_read = run(lambda: z.sum())
+        del x, z
+    return 2.0 * nbytes / t_copy / 1e9, 2.0 * nbytes / t_read / 1e9
 
 
 def cpu_baseline(dims, fat, lng, budget_s=12.0):
@@ -228,17 +276,24 @@ def run_headline(args):
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
 
-    def avg(key):
-        return float(np.mean([r["dslash_s"][key] for r in results]))
+    def avg(key, which):
+        ts = [r["dslash_s"][key][which] for r in results]
+        return None if any(t is None for t in ts) else float(np.mean(ts))
+
+    def dtime(key):
+        """Graph-replay time where capture worked, else the eager time."""
+        tg = avg(key, 0)
+        return (tg, "graph") if tg is not None else (avg(key, 1), "eager")
 
     dsl = {}
     for p, r in formats:
-        t = avg((p, r))
+        t, how = dtime((p, r))
         gbs = h * site_bytes(p, r) / t / 1e9
         dsl[f"{['f64', 'f32', 'f16'][p]}_r{r}"] = {
             "us": round(t * 1e6, 3), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
-            "GFLOP/s": round(1146.0 * h / t / 1e9, 1)}
-    t32 = avg((1, 18))
+            "GFLOP/s": round(1146.0 * h / t / 1e9, 1), "timing": how,
+            "us_eager_launches": round(avg((p, r), 1) * 1e6, 3)}
+    t32, how32 = dtime((1, 18))
     achieved = h * site_bytes(1, 18) / t32 / 1e9
 
     cg = {}
@@ -253,6 +308,7 @@ def run_headline(args):
                 cg[name]["fell_back"] = bool(infos[-1]["fell_back"])
                 cg[name]["training"] = train_info
 
+    copy_gbs, read_gbs = timed_ceilings(torch, stream)
     hbm = None
     if not args.no_hbm:
         dims = (32, 32, 32, 32)
@@ -264,7 +320,8 @@ def run_headline(args):
         h2 = synth.volume(dims) // 2
         for p, r in formats:
             lat2.prepare_links(p, r)
-            t = timed_dslash(torch, lat2, p, r, h2, stream, 20)
+            tg, te = timed_dslash(torch, lat2, p, r, h2, stream, 20)
+            t = tg if tg is not None else te
             gbs = h2 * site_bytes(p, r) / t / 1e9
             hbm[f"{['f64', 'f32', 'f16'][p]}_r{r}"] = {"us": round(t * 1e6, 2), "GB/s": round(gbs, 1),
                                                        "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
@@ -288,7 +345,13 @@ def run_headline(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_entry(),
                      "kernel": "k_dslash<float,18,float,float,W,EPI_PLAIN>",
-                     "bytes_per_launch": h * site_bytes(1, 18)},
+                     "bytes_per_launch": h * site_bytes(1, 18),
+                     "launch_us": round(t32 * 1e6, 3), "timing": f"HIP events around a {how32} of "
+                     f"{2 * args.reps} launches on the library stream",
+                     "copy_ceiling": {"GB/s": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / PEAK_HBM_GBS, 4),
+                                      "what": "1 GiB device-to-device copy, read + written bytes"},
+                     "read_ceiling": {"GB/s": round(read_gbs, 1), "frac_of_peak": round(read_gbs / PEAK_HBM_GBS, 4),
+                                      "what": "sum over 2 GiB (torch reduction), bytes read"}},
         "dslash": dsl,
         "dslash_32^4_beyond_infinity_cache": hbm,
         "cg_time_to_1e-10": cg,
