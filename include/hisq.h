@@ -94,6 +94,7 @@ typedef struct {
     int fcg_iters;           /* learned solver: flexible-CG iterations before any hand-over */
     int restarts;            /* reliable updates that restarted the search direction (p = r)
                                 because the FP64 residual exceeded twice the sloppy one */
+    int refine_iters;        /* multi-shift: iterations of this shift's refinement (part of iters) */
 } hisq_solver_info;
 
 /* Fill params with defaults: tol 1e-10, maxiter 100000, F64, recon 18,
@@ -129,7 +130,9 @@ hisq_status hisq_prepare_links(hisq_lattice lat, hisq_prec prec, hisq_recon reco
  * HISQ_DEVICE_PTR, in/out are device vectors in precision prec, nrhs of them
  * back to back (nrhs > 1 uses the multi-right-hand-side kernel, FP32/FP16
  * only); without it they are host FP64 vectors, converted by the library.
- * Asynchronous on device pointers. */
+ * Asynchronous on device pointers.  The first call for a (lattice shape,
+ * precision, recon, nrhs) times the candidate block shapes synchronously
+ * (the autotuner); make it before capturing calls into a HIP graph. */
 hisq_status hisq_dslash(hisq_lattice lat, hisq_parity out_parity, hisq_prec prec,
                         hisq_recon recon, const void *in, void *out, int nrhs, int flags);
 
@@ -147,7 +150,9 @@ hisq_status hisq_cg(hisq_lattice lat, double mass, const double *b, double *x,
  * recurrences on the device), the nrhs spaces sharing one multi-RHS Dslash.
  * b: nrhs host FP64 vectors back to back; x: nrhs*nshift vectors, index
  * j*nshift + k.  Each shift stops when |zeta_k| ||r|| <= tol ||b||; shifts
- * whose FP64 true residual is above tol are then refined with mixed CG.
+ * whose FP64 true residual is above tol are then refined with mixed CG
+ * (all nrhs*nshift refinements advance together, sharing link reads; their
+ * status is checked every min(check_every, 4) iterations).
  * info: nrhs*nshift entries (or NULL). */
 hisq_status hisq_multishift_cg(hisq_lattice lat, double mass, int nshift, const double *shifts,
                                int nrhs, const double *b, double *x,

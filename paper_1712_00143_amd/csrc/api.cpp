@@ -465,6 +465,75 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     return best;
 }
 
+TuneChoice pick_shape_mrhs(hisq_lattice lat, int prec, int recon, int nr, bool no_tune)
+{
+    TuneChoice def;
+    def.W = prec == 0 ? 8 : 4;
+    def.remap = 1;
+    if (no_tune || nr < 1 || nr > 4) return def;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return def;
+    std::ostringstream ks;
+    ks << "mrhs:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << lat->ntile << ":nr" << nr;
+    std::string key = ks.str();
+    for (auto &ch : key)
+        if (ch == ' ') ch = '_';
+    TuneChoice c;
+    if (Tuner::get().lookup(key, c)) return c;
+    DVec in, out;
+    const int vprec = prec == 0 ? 0 : 1;   // FP64 vectors with FP64 links, FP32 otherwise
+    if (dvec_alloc(in, vprec, lat->h * nr) != hipSuccess || dvec_alloc(out, vprec, lat->h * nr) != hipSuccess) {
+        dvec_free(in);
+        dvec_free(out);
+        return def;
+    }
+    (void)hipMemsetAsync(in.p, 0, in.bytes, lat->s);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    TuneChoice best = def;
+    best.us = 1e30;
+    for (int W : {2, 4, 8, 16}) {
+        for (int remap = 0; remap < 2; remap++) {
+            MrhsLaunch a;
+            memset(&a, 0, sizeof a);
+            a.probs = lat->ddesc;
+            a.desc_stride = 0;
+            a.remap = remap;
+            a.lslot = prec * 2 + (recon == 12);
+            a.nrhs = nr;
+            a.vstride = lat->h;
+            a.in = in.p;
+            a.out = out.p;
+            a.epi = EPI_PLAIN;
+            bool ok = true;
+            for (int r = 0; r < 2 && ok; r++) ok = launch_dslash_mrhs(prec, recon, nr, W, a, lat->ntile, lat->s) == hipSuccess;
+            if (!ok) continue;
+            const int reps = 6;
+            (void)hipEventRecord(e0, lat->s);
+            for (int r = 0; r < reps; r++) (void)launch_dslash_mrhs(prec, recon, nr, W, a, lat->ntile, lat->s);
+            (void)hipEventRecord(e1, lat->s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double us = 1000.0 * ms / reps;
+            if (us < best.us) {
+                best.us = us;
+                best.W = W;
+                best.remap = remap;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dvec_free(in);
+    dvec_free(out);
+    (void)hipGetLastError();
+    if (best.us < 1e29) Tuner::get().store(key, best);
+    else best = def;
+    return best;
+}
+
 }  // namespace hisq
 
 extern "C" {

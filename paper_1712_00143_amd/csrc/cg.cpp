@@ -72,9 +72,14 @@ hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lat
         HIPCHK(lat0, hipHostMalloc(&S.hst, sizeof(SolveState) * n, hipHostMallocDefault));
         HIPCHK(lat0, hipMalloc(&S.dpart, sizeof(double) * NPART * ntile));
         HIPCHK(lat0, hipMemset(S.dst, 0, sizeof(SolveState) * n));
-        if (n > 1) HIPCHK(lat0, hipMemcpy(S.dt2p, t2p.data(), sizeof(int) * ntile, hipMemcpyHostToDevice));
     }
+    // the tile -> problem map depends on the order of the problems, not only
+    // on the totals compared above
+    if (n > 1) HIPCHK(lat0, hipMemcpy(S.dt2p, t2p.data(), sizeof(int) * ntile, hipMemcpyHostToDevice));
     S.hdesc = hd;
+    S.one_lattice = n > 1;
+    for (int k = 1; k < n; k++)
+        if (lats[k] != lats[0]) S.one_lattice = false;
     HIPCHK(lat0, hipMemcpyAsync(S.ddesc, hd.data(), sizeof(ProbDesc) * n, hipMemcpyHostToDevice, lat0->s));
     HIPCHK(lat0, hipStreamSynchronize(lat0->s));
     return HISQ_OK;
@@ -82,6 +87,9 @@ hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lat
 
 struct CgPlan {
     int mode, recon, slot, W, remap;
+    TuneChoice mrhs[5];   // shapes of the shared-link kernel per group size (one-lattice sets)
+    int group64 = 0;      // one-lattice sets: FP64 shared-link group size (0: per-problem kernel)
+    TuneChoice mrhs64;
 };
 
 static hipError_t enqueue_dslash(SolveSet &S, const CgPlan &pl, int prec, int lslot, int out_par, int epi,
@@ -143,17 +151,102 @@ static hipError_t enqueue_blas(SolveSet &S, int op, int mode, int want, int fin,
     return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, 1, S.nprob, s);
 }
 
+// Sloppy FP32 Dslash of a set whose problems all live on one lattice: one
+// multi-right-hand-side launch covers every problem, four per link read, so
+// the link stream is read once per four problems instead of once per problem.
+static hipError_t enqueue_dslash_shared(SolveSet &S, const CgPlan &pl, int out_par, int epi, int fin,
+                                        int want, const DVec &in, DVec &out, const DVec *aux, hipStream_t s)
+{
+    const int group = S.nprob < 4 ? S.nprob : 4;
+    const TuneChoice &tc = pl.mrhs[group];
+    MrhsLaunch a;
+    memset(&a, 0, sizeof a);
+    a.probs = S.ddesc;
+    a.desc_stride = 1;
+    a.remap = tc.remap;
+    a.out_par = out_par;
+    a.lslot = pl.slot;
+    a.nrhs = S.nprob;
+    a.vstride = S.hdesc[0].h;
+    a.in = in.p;
+    a.out = out.p;
+    a.aux = aux ? aux->p : nullptr;
+    a.partials = S.dpart;
+    a.states = S.dst;
+    a.epi = epi;
+    a.want = want;
+    hipError_t e = launch_dslash_mrhs(pl.mode, pl.recon, group, tc.W, a, S.hdesc[0].ntile, s);
+    if (e != hipSuccess || fin == FIN_NONE) return e;
+    return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, 1, S.nprob, s);
+}
+
+// FP64 recon-18 Dslash (reliable updates, initial residual) of a one-lattice
+// set through the shared-link kernel: PLAIN out = D in, or RES
+// out = b - diag x + D in with |out|^2 partials.
+static hipError_t enqueue_dslash64_shared(SolveSet &S, const CgPlan &pl, int out_par, int epi, int fin,
+                                          int want, const DVec &in, DVec &out, const DVec *x,
+                                          hipStream_t s)
+{
+    MrhsLaunch a;
+    memset(&a, 0, sizeof a);
+    a.probs = S.ddesc;
+    a.desc_stride = 1;
+    a.remap = pl.mrhs64.remap;
+    a.out_par = out_par;
+    a.lslot = 0;
+    a.nrhs = S.nprob;
+    a.vstride = S.hdesc[0].h;
+    a.in = in.p;
+    a.out = out.p;
+    a.aux = x ? x->p : nullptr;
+    a.bvec = (const double *)S.b.p;
+    a.partials = S.dpart;
+    a.states = S.dst;
+    a.epi = epi;
+    a.want = want;
+    hipError_t e = launch_dslash_mrhs(0, 18, pl.group64, pl.mrhs64.W, a, S.hdesc[0].ntile, s);
+    if (e != hipSuccess || fin == FIN_NONE) return e;
+    return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, 1, S.nprob, s);
+}
+
+// FP64 half-Dslash pair of the reliable update / initial residual:
+// t = D_oe x, r = b - diag x + D_eo t (partials of |r|^2, finisher fin).
+static hipError_t enqueue_true_residual(SolveSet &S, const CgPlan &pl, int fin, int want, hipStream_t s)
+{
+    hipError_t e;
+    if (pl.group64 > 0) {
+        if ((e = enqueue_dslash64_shared(S, pl, 1, EPI_PLAIN, FIN_NONE, want, S.xhi, S.thi, nullptr, s)) !=
+            hipSuccess)
+            return e;
+        return enqueue_dslash64_shared(S, pl, 0, EPI_RES, fin, want, S.thi, S.rhi, &S.xhi, s);
+    }
+    if ((e = enqueue_dslash(S, pl, 0, 0, 1, EPI_PLAIN, FIN_NONE, want, S.xhi, S.thi, nullptr, nullptr, 0, s)) !=
+        hipSuccess)
+        return e;
+    return enqueue_dslash(S, pl, 0, 0, 0, EPI_RES, fin, want, S.thi, S.rhi, &S.xhi, (const double *)S.b.p, 0, s);
+}
+
 static hipError_t enqueue_iters(SolveSet &S, const CgPlan &pl, int k, hipStream_t s)
 {
     const int ap_prec = pl.mode == 2 ? 1 : pl.mode;
+    const bool shared = S.one_lattice && pl.mode == 1;
     for (int j = 0; j < k; j++) {
         hipError_t e;
-        if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 1, EPI_PLAIN, FIN_NONE, ST_RUNNING, S.p, S.t,
-                                nullptr, nullptr, pl.mode, s)) != hipSuccess)
-            return e;
-        if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 0, EPI_AX, FIN_ALPHA, ST_RUNNING, S.t, S.Ap,
-                                &S.p, nullptr, ap_prec, s)) != hipSuccess)
-            return e;
+        if (shared) {
+            if ((e = enqueue_dslash_shared(S, pl, 1, EPI_PLAIN, FIN_NONE, ST_RUNNING, S.p, S.t, nullptr, s)) !=
+                hipSuccess)
+                return e;
+            if ((e = enqueue_dslash_shared(S, pl, 0, EPI_AX, FIN_ALPHA, ST_RUNNING, S.t, S.Ap, &S.p, s)) !=
+                hipSuccess)
+                return e;
+        } else {
+            if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 1, EPI_PLAIN, FIN_NONE, ST_RUNNING, S.p, S.t,
+                                    nullptr, nullptr, pl.mode, s)) != hipSuccess)
+                return e;
+            if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 0, EPI_AX, FIN_ALPHA, ST_RUNNING, S.t, S.Ap,
+                                    &S.p, nullptr, ap_prec, s)) != hipSuccess)
+                return e;
+        }
         if ((e = enqueue_blas(S, BL_RUPDATE, pl.mode, ST_RUNNING, FIN_BETA, s)) != hipSuccess) return e;
         if ((e = enqueue_blas(S, BL_PUPDATE, pl.mode, ST_RUNNING, FIN_NONE, s)) != hipSuccess) return e;
     }
@@ -164,12 +257,7 @@ static hipError_t enqueue_reliable(SolveSet &S, const CgPlan &pl, hipStream_t s)
 {
     hipError_t e;
     if ((e = enqueue_blas(S, BL_XACCUM, pl.mode, ST_RELIABLE, FIN_NONE, s)) != hipSuccess) return e;
-    if ((e = enqueue_dslash(S, pl, 0, 0, 1, EPI_PLAIN, FIN_NONE, ST_RELIABLE, S.xhi, S.thi, nullptr,
-                            nullptr, 0, s)) != hipSuccess)
-        return e;
-    if ((e = enqueue_dslash(S, pl, 0, 0, 0, EPI_RES, FIN_TRUERES, ST_RELIABLE, S.thi, S.rhi, &S.xhi,
-                            (const double *)S.b.p, 0, s)) != hipSuccess)
-        return e;
+    if ((e = enqueue_true_residual(S, pl, FIN_TRUERES, ST_RELIABLE, s)) != hipSuccess) return e;
     if ((e = enqueue_blas(S, BL_RESUME, pl.mode, ST_RESUME, FIN_NONE, s)) != hipSuccess) return e;
     return enqueue_blas(S, BL_STATUS, pl.mode, 0, FIN_NONE, s);
 }
@@ -220,19 +308,38 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
     }
     HIPCHK(lat0, hipMemcpyAsync(S.dst, S.hst, sizeof(SolveState) * S.nprob, hipMemcpyHostToDevice, s));
 
+    // one-lattice FP32 sets run their sloppy operator through the shared-link
+    // kernel; the single-problem kernel then serves only the FP64 updates,
+    // which use the default shape, so it is not tuned for them
+    const bool shared = S.one_lattice && mode == 1;
     TuneChoice tc = pick_shape(lat0, mode, recon, S.ddesc, S.dt2p, S.ntile, S.nsite, S.nprob,
-                               (prm.flags & HISQ_NO_TUNE) != 0);
-    CgPlan pl{mode, recon, slot, tc.W, tc.remap};
+                               shared || (prm.flags & HISQ_NO_TUNE) != 0);
+    CgPlan pl{mode, recon, slot, tc.W, tc.remap, {}};
+    if (shared) {
+        const int group = S.nprob < 4 ? S.nprob : 4;
+        pl.mrhs[group] = pick_shape_mrhs(lat0, mode, recon, group, (prm.flags & HISQ_NO_TUNE) != 0);
+    }
+    if (S.one_lattice) {
+        // FP64 updates: groups of 2 or 4 problems per link read, whichever the
+        // tuner finds cheaper per problem
+        const bool nt = (prm.flags & HISQ_NO_TUNE) != 0;
+        pl.group64 = S.nprob < 2 ? S.nprob : 2;
+        pl.mrhs64 = pick_shape_mrhs(lat0, 0, 18, pl.group64, nt);
+        if (S.nprob >= 4 && !nt) {
+            TuneChoice t4 = pick_shape_mrhs(lat0, 0, 18, 4, nt);
+            if (t4.us / 4 < pl.mrhs64.us / pl.group64) {
+                pl.group64 = 4;
+                pl.mrhs64 = t4;
+            }
+        }
+    }
 
     long long *dclock = nullptr;
     HIPCHK(lat0, hipMalloc(&dclock, sizeof(long long)));
     HIPCHK(lat0, launch_stamp(dclock, s));
     if (guess) {
         HIPCHK(lat0, enqueue_blas(S, BL_NORM, mode, ST_RUNNING, FIN_NORM_B, s));
-        HIPCHK(lat0, enqueue_dslash(S, pl, 0, 0, 1, EPI_PLAIN, FIN_NONE, ST_RUNNING, S.xhi, S.thi, nullptr,
-                                    nullptr, 0, s));
-        HIPCHK(lat0, enqueue_dslash(S, pl, 0, 0, 0, EPI_RES, FIN_INIT_R, ST_RUNNING, S.thi, S.rhi, &S.xhi,
-                                    (const double *)S.b.p, 0, s));
+        HIPCHK(lat0, enqueue_true_residual(S, pl, FIN_INIT_R, ST_RUNNING, s));
         HIPCHK(lat0, enqueue_blas(S, BL_START, mode, ST_RUNNING, FIN_NONE, s));
     } else {
         HIPCHK(lat0, enqueue_blas(S, BL_INIT, mode, ST_RUNNING, FIN_NORM_B, s));
@@ -252,7 +359,9 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
     const bool use_graph = (prm.flags & HISQ_USE_GRAPH) != 0;
     if (use_graph) {
         std::ostringstream ks;
-        ks << mode << ":" << recon << ":" << tc.W << ":" << tc.remap << ":" << kchunk;
+        ks << mode << ":" << recon << ":" << tc.W << ":" << tc.remap << ":" << kchunk << ":" << S.one_lattice;
+        for (int nr = 1; nr <= 4; nr++) ks << ":" << pl.mrhs[nr].W << pl.mrhs[nr].remap;
+        ks << ":" << pl.group64 << pl.mrhs64.W << pl.mrhs64.remap;
         if (S.gkey != ks.str() || !S.gexec) {
             if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
             if (S.graph) (void)hipGraphDestroy(S.graph);

@@ -32,6 +32,7 @@ struct SolveSet {
     int ntile = 0;
     long long nsite = 0;
     int mode = -1;
+    bool one_lattice = false;   // nprob > 1 problems on the same handle: vectors at q * h
     std::vector<ProbDesc> hdesc;
     ProbDesc *ddesc = nullptr;
     int *dt2p = nullptr;        // nullptr when nprob == 1

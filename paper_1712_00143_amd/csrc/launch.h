@@ -29,26 +29,31 @@ struct DslashLaunch {
 hipError_t launch_dslash(int prec, int recon, int out_prec, int epi, int W, const DslashLaunch &a,
                          int nblocks, hipStream_t s);
 
-// Multi-RHS Dslash: nrhs vectors at stride vstride sites, links read once.
+// Multi-RHS Dslash: nrhs vectors at stride vstride sites, links read once per
+// group of NR right-hand sides.  One launch covers every group: block b works
+// on group b / ntile, tile b % ntile.
 struct MrhsLaunch {
-    const ProbDesc *probs;
+    const ProbDesc *probs;  // descriptor of rhs r: probs[r * desc_stride], all on one lattice;
+                            // EPI_AX: out_r = probs[r * desc_stride].diag aux_r - D in_r
+    int desc_stride;        // 0: probs[0] for every rhs, 1: one descriptor per rhs
     int remap;
     int out_par;
     int lslot;
-    int nrhs;
-    long long vstride;     // sites between consecutive right-hand sides
+    int nrhs;               // right-hand sides in total
+    long long vstride;      // sites between consecutive right-hand sides
     const void *in;
     void *out;
-    const void *aux;       // EPI_AX: p vectors (same stride)
-    double *partials;      // [tile][NPART]: per-rhs Re(p.Ap)
-    SolveState *states;    // per-rhs states (nrhs of them), nullptr for plain
-    const int *rhs_active; // nullptr: all
+    const void *aux;        // EPI_AX: p vectors; EPI_RES: x vectors (same stride)
+    const double *bvec;     // EPI_RES: FP64 right-hand sides b (same stride)
+    double *partials;       // EPI_AX: Re(p.Ap), EPI_RES: |r|^2 of rhs r, tile t at [(r * ntile + t) * NPART]
+    SolveState *states;     // per-rhs states (nrhs of them), nullptr: all active
     int epi;
     int want;
-    double diag;           // EPI_AX: out = diag * aux - D in
 };
 
-hipError_t launch_dslash_mrhs(int prec, int recon, int nrhs, int W, const MrhsLaunch &a, int nblocks,
+// group: right-hand sides per link read (1..4); the grid is
+// ceil(nrhs / group) * ntile blocks.
+hipError_t launch_dslash_mrhs(int prec, int recon, int group, int W, const MrhsLaunch &a, int ntile,
                               hipStream_t s);
 
 // ---- packing

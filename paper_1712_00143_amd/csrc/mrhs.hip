@@ -8,9 +8,12 @@
 // the VALU ridge, so the contraction runs on the vector ALUs: staging it
 // through MFMA tiles would add register shuffles without moving the bound.
 //
-// Layout: right-hand side j of the vector arguments starts at j * vstride
-// sites; each right-hand side is a problem of the solve set (own FP64 state),
-// and its reduction partials go to tile j * ntile + tile.
+// Layout: right-hand side r of the vector arguments starts at r * vstride
+// sites; each right-hand side may be a problem of a solve set (own FP64 state
+// a.states[r], own descriptor with its diagonal term, all on the lattice of
+// a.probs[0]), and its reduction partials go to tile r * ntile + tile.  The
+// right-hand sides are processed NR at a time: block b serves group b / ntile
+// (right-hand sides NR*g .. NR*g + NR - 1) on tile b % ntile.
 #include "fields.h"
 #include "finish.h"
 #include "launch.h"
@@ -18,20 +21,29 @@
 
 namespace hisq {
 
+// Vector element type of the multi-RHS kernel: FP64 vectors with FP64 links,
+// FP32 vectors otherwise.
+template <class LT> struct MrhsVec { using type = float; using pair = float2; };
+template <> struct MrhsVec<double> { using type = double; using pair = double2; };
+
 template <class LT, int R, int W, int NR, int EPI>
 __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
 {
-    using A = float;
+    using A = typename AccOf<LT>::type;
+    using V2 = typename MrhsVec<LT>::pair;
     constexpr int DPW = 16 / W;
     using F = LinkFmt<LT, R>;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x, a.remap);
     const ProbDesc &pd = a.probs[0];
+    const int bt = xcd_tile(blockIdx.x, gridDim.x, a.remap);
+    const int grp = bt / pd.ntile;
+    const int tile = bt - grp * pd.ntile;
+    const int r0 = grp * NR;
     bool act[NR];
     bool any = false;
 #pragma unroll
     for (int j = 0; j < NR; j++) {
-        act[j] = a.states ? a.states[j].status == a.want : true;
+        act[j] = r0 + j < a.nrhs && (a.states ? a.states[r0 + j].status == a.want : true);
         any |= act[j];
     }
     if (!any) return;
@@ -42,19 +54,21 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
     const LinkSet &ls = pd.ls[a.lslot];
     const char *lbase = (const char *)ls.ptr[par];
     const int L0 = pd.L[0], L1 = pd.L[1], L2 = pd.L[2], L3 = pd.L[3];
-    const float *in = (const float *)a.in;
+    const V2 *in = (const V2 *)a.in;
 
     Cx<A> acc[NR][3];
 #pragma unroll
     for (int j = 0; j < NR; j++)
 #pragma unroll
-        for (int c = 0; c < 3; c++) acc[j][c] = {0.f, 0.f};
+        for (int c = 0; c < 3; c++) acc[j][c] = {(A)0, (A)0};
 
     if (valid) {
         const Coord co = cb_to_coord(i, par, pd.L);
         const int lex = 2 * i + (co.x[0] & 1);
         const int e1 = co.x[0] & 1, e2 = (co.x[0] + co.x[1]) & 1, e3 = (co.x[0] + co.x[1] + co.x[2]) & 1;
-        constexpr int G = NR >= 3 ? (DPW < 2 ? DPW : 2) : (DPW < 4 ? DPW : 4);
+        // links in flight per thread: fewer when the gathered vectors are many or wide
+        constexpr int GMAX = sizeof(LT) == 8 ? (NR >= 3 ? 1 : 2) : (NR >= 3 ? 2 : 4);
+        constexpr int G = DPW < GMAX ? DPW : GMAX;
 #pragma unroll
         for (int g0 = 0; g0 < DPW; g0 += G) {
             int nb[G];
@@ -82,10 +96,10 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
             for (int g = 0; g < G; g++)
 #pragma unroll
                 for (int j = 0; j < NR; j++) {
-                    const float2 *p = reinterpret_cast<const float2 *>(in) + ((long long)j * a.vstride + nb[g]) * 3;
+                    const V2 *p = in + ((long long)(r0 + j) * a.vstride + nb[g]) * 3;
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        float2 t = act[j] ? p[c] : make_float2(0.f, 0.f);
+                        V2 t = act[j] ? p[c] : V2{(A)0, (A)0};
                         v[g][j][c] = {t.x, t.y};
                     }
                 }
@@ -95,7 +109,7 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
                 const int mu = d >> 2;
                 Cx<A> u[3][3];
                 decode_link<LT, R, A>(raw[g], u);
-                A coef = 1.f;
+                A coef = (A)1;
                 if constexpr (R == 12 || sizeof(LT) == 2) {
                     const int fld = (d & 2) ? 1 : 0;
                     coef = (A)ls.a[fld];
@@ -147,34 +161,47 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
 #pragma unroll
     for (int j = 0; j < NR; j++) part[j] = 0.0;
     if (wave == 0 && valid) {
-        float *out = (float *)a.out;
+        V2 *out = (V2 *)a.out;
 #pragma unroll
         for (int j = 0; j < NR; j++) {
             if (!act[j]) continue;
-            const long long o = (long long)j * a.vstride + i;
-            float2 *po = reinterpret_cast<float2 *>(out) + o * 3;
+            const long long o = (long long)(r0 + j) * a.vstride + i;
+            V2 *po = out + o * 3;
             if constexpr (EPI == EPI_PLAIN) {
 #pragma unroll
-                for (int c = 0; c < 3; c++) po[c] = make_float2(acc[j][c].re, acc[j][c].im);
-            } else {
-                const float2 *pp = reinterpret_cast<const float2 *>(a.aux) + o * 3;
-                const float dg = (float)a.diag;
+                for (int c = 0; c < 3; c++) po[c] = V2{acc[j][c].re, acc[j][c].im};
+            } else if constexpr (EPI == EPI_AX) {
+                const V2 *pp = (const V2 *)a.aux + o * 3;
+                const A dg = (A)a.probs[(r0 + j) * a.desc_stride].diag;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    float2 p = pp[c];
-                    float vr = dg * p.x - acc[j][c].re, vi = dg * p.y - acc[j][c].im;
-                    po[c] = make_float2(vr, vi);
+                    V2 p = pp[c];
+                    A vr = dg * p.x - acc[j][c].re, vi = dg * p.y - acc[j][c].im;
+                    po[c] = V2{vr, vi};
                     part[j] += (double)p.x * (double)vr + (double)p.y * (double)vi;
+                }
+            } else {  // EPI_RES: out = b - diag x + D in, |out|^2
+                const V2 *px = (const V2 *)a.aux + o * 3;
+                const double2 *pb = reinterpret_cast<const double2 *>(a.bvec) + o * 3;
+                const A dg = (A)a.probs[(r0 + j) * a.desc_stride].diag;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    V2 x = px[c];
+                    double2 bb = pb[c];
+                    A vr = (A)bb.x - dg * x.x + acc[j][c].re, vi = (A)bb.y - dg * x.y + acc[j][c].im;
+                    po[c] = V2{vr, vi};
+                    part[j] += (double)vr * (double)vr + (double)vi * (double)vi;
                 }
             }
         }
     }
-    if constexpr (EPI == EPI_AX) {
+    if constexpr (EPI != EPI_PLAIN) {
         __shared__ double lds[16 * NR];
         block_sum<NR>(part, lds);
         if (threadIdx.x == 0) {
             const int ntile = pd.ntile;
-            for (int j = 0; j < NR; j++) a.partials[((size_t)j * ntile + tile) * NPART] = part[j];
+            for (int j = 0; j < NR; j++)
+                if (r0 + j < a.nrhs) a.partials[((size_t)(r0 + j) * ntile + tile) * NPART] = part[j];
         }
     }
 }
@@ -186,7 +213,11 @@ static hipError_t mrhs_w(int W, const MrhsLaunch &a, int nb, hipStream_t s)
     case 2: hipLaunchKernelGGL((k_dslash_mrhs<LT, R, 2, NR, EPI>), dim3(nb), dim3(128), 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_dslash_mrhs<LT, R, 4, NR, EPI>), dim3(nb), dim3(256), 0, s, a); break;
     case 8: hipLaunchKernelGGL((k_dslash_mrhs<LT, R, 8, NR, EPI>), dim3(nb), dim3(512), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_dslash_mrhs<LT, R, 16, NR, EPI>), dim3(nb), dim3(1024), 0, s, a); break;
+    case 16:
+        // the LDS reduction of 15 waves of FP64 partial vectors does not fit
+        if constexpr (sizeof(LT) == 8) return hipErrorInvalidValue;
+        else hipLaunchKernelGGL((k_dslash_mrhs<LT, R, 16, NR, EPI>), dim3(nb), dim3(1024), 0, s, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -204,25 +235,40 @@ static hipError_t mrhs_n(int nr, int W, const MrhsLaunch &a, int nb, hipStream_t
     return hipErrorInvalidValue;
 }
 
-// FP32 colour vectors; links FP32 (prec 1) or FP16 (prec 2); nrhs in 1..4
-// per launch (callers split larger counts).
-hipError_t launch_dslash_mrhs(int prec, int recon, int nrhs, int W, const MrhsLaunch &a, int nblocks,
+template <class LT, int R>
+static hipError_t mrhs_e(int epi, int nr, int W, const MrhsLaunch &a, int nb, hipStream_t s)
+{
+    switch (epi) {
+    case EPI_PLAIN: return mrhs_n<LT, R, EPI_PLAIN>(nr, W, a, nb, s);
+    case EPI_AX: return mrhs_n<LT, R, EPI_AX>(nr, W, a, nb, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Links FP64 (prec 0, FP64 vectors; recon-18, PLAIN and RES epilogues: the
+// reliable updates), FP32 (prec 1) or FP16 (prec 2) with FP32 vectors (PLAIN
+// and AX).  `nrhs` is the group size NR in 1..4; a.nrhs right-hand sides in
+// total.
+hipError_t launch_dslash_mrhs(int prec, int recon, int nrhs, int W, const MrhsLaunch &a, int ntile,
                               hipStream_t s)
 {
-    if (nblocks <= 0) return hipSuccess;
-    const bool ax = a.epi == EPI_AX;
-    if (prec == 1) {
-        if (recon == 12) return ax ? mrhs_n<float, 12, EPI_AX>(nrhs, W, a, nblocks, s)
-                                   : mrhs_n<float, 12, EPI_PLAIN>(nrhs, W, a, nblocks, s);
-        return ax ? mrhs_n<float, 18, EPI_AX>(nrhs, W, a, nblocks, s)
-                  : mrhs_n<float, 18, EPI_PLAIN>(nrhs, W, a, nblocks, s);
+    if (ntile <= 0 || a.nrhs <= 0) return hipSuccess;
+    if (nrhs < 1 || nrhs > 4 || (nrhs < 4 && a.nrhs > nrhs)) return hipErrorInvalidValue;
+    const long long nb = (long long)(a.nrhs + nrhs - 1) / nrhs * ntile;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int nblocks = (int)nb;
+    if (prec == 0) {
+        if (recon != 18) return hipErrorInvalidValue;
+        switch (a.epi) {
+        case EPI_PLAIN: return mrhs_n<double, 18, EPI_PLAIN>(nrhs, W, a, nblocks, s);
+        case EPI_RES: return mrhs_n<double, 18, EPI_RES>(nrhs, W, a, nblocks, s);
+        }
+        return hipErrorInvalidValue;
     }
-    if (prec == 2) {
-        if (recon == 12) return ax ? mrhs_n<__half, 12, EPI_AX>(nrhs, W, a, nblocks, s)
-                                   : mrhs_n<__half, 12, EPI_PLAIN>(nrhs, W, a, nblocks, s);
-        return ax ? mrhs_n<__half, 18, EPI_AX>(nrhs, W, a, nblocks, s)
-                  : mrhs_n<__half, 18, EPI_PLAIN>(nrhs, W, a, nblocks, s);
-    }
+    if (prec == 1) return recon == 12 ? mrhs_e<float, 12>(a.epi, nrhs, W, a, nblocks, s)
+                                      : mrhs_e<float, 18>(a.epi, nrhs, W, a, nblocks, s);
+    if (prec == 2) return recon == 12 ? mrhs_e<__half, 12>(a.epi, nrhs, W, a, nblocks, s)
+                                      : mrhs_e<__half, 18>(a.epi, nrhs, W, a, nblocks, s);
     return hipErrorInvalidValue;
 }
 

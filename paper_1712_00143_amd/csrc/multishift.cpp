@@ -164,31 +164,27 @@ extern "C" hisq_status hisq_multishift_cg(hisq_lattice lat, double mass, int nsh
     HIPCHK(lat, launch_ms(BL_MS_INIT, bl, ntot, s));
     HIPCHK(lat, launch_finish(W.ddesc, W.dst, W.dpart, FIN_NORM_B, ST_RUNNING, 1, nrhs, s));
 
-    TuneChoice tc = pick_shape(lat, kprec, recon, lat->ddesc, nullptr, ntile, h, 1, (prm.flags & HISQ_NO_TUNE) != 0);
-    const int Wm = std::min(std::max(tc.W, 2), 8);
+    // tuned shape of the shared-link kernel (tuning runs before any capture)
+    const int group = std::min(4, nrhs);
+    const TuneChoice tcm = pick_shape_mrhs(lat, kprec, recon, group, (prm.flags & HISQ_NO_TUNE) != 0);
     auto mrhs = [&](int out_par, int epi, const void *in, void *out, const void *aux) -> hipError_t {
-        for (int g = 0; g < nrhs; g += 4) {
-            const int nr = std::min(4, nrhs - g);
-            MrhsLaunch a;
-            memset(&a, 0, sizeof a);
-            a.probs = W.ddesc;
-            a.remap = tc.remap;
-            a.out_par = out_par;
-            a.lslot = slot;
-            a.nrhs = nr;
-            a.vstride = h;
-            a.in = (const char *)in + (size_t)g * h * 24;
-            a.out = (char *)out + (size_t)g * h * 24;
-            a.aux = aux ? (const char *)aux + (size_t)g * h * 24 : nullptr;
-            a.partials = W.dpart + (size_t)g * ntile * NPART;
-            a.states = W.dst + g;
-            a.epi = epi;
-            a.want = ST_RUNNING;
-            a.diag = 4.0 * mass * mass + sbase;
-            hipError_t e = launch_dslash_mrhs(kprec, recon, nr, Wm, a, ntile, s);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
+        MrhsLaunch a;
+        memset(&a, 0, sizeof a);
+        a.probs = W.ddesc;
+        a.desc_stride = 1;
+        a.remap = tcm.remap;
+        a.out_par = out_par;
+        a.lslot = slot;
+        a.nrhs = nrhs;
+        a.vstride = h;
+        a.in = in;
+        a.out = out;
+        a.aux = aux;
+        a.partials = W.dpart;
+        a.states = W.dst;
+        a.epi = epi;
+        a.want = ST_RUNNING;
+        return launch_dslash_mrhs(kprec, recon, group, tcm.W, a, ntile, s);
     };
     auto iterate = [&]() -> hipError_t {
         hipError_t e;
@@ -265,6 +261,10 @@ extern "C" hisq_status hisq_multishift_cg(hisq_lattice lat, double mass, int nsh
     if (st != HISQ_OK) return st;
     hisq_solver_params rp = prm;
     rp.flags = (prm.flags & (HISQ_USE_GRAPH | HISQ_NO_TUNE)) | HISQ_DEVICE_PTR | HISQ_X_IS_GUESS;
+    // warm-started refinements reach a reliable update every few iterations:
+    // short chunks keep problems from idling until the end of a long one
+    const int ce = prm.check_every > 0 ? prm.check_every : 16;
+    rp.check_every = ce < 4 ? ce : 4;
     if (rp.sloppy == HISQ_F64) rp.sloppy = HISQ_F32;
     if (!lat->ls[(int)rp.sloppy * 2 + (recon == 12)].valid) rp.recon = HISQ_RECON_18;
     if (!lat->ls[(int)rp.sloppy * 2 + (rp.recon == 12)].valid) {
@@ -284,6 +284,7 @@ extern "C" hisq_status hisq_multishift_cg(hisq_lattice lat, double mass, int nsh
                 hisq_solver_info &in = info[q];
                 in = rinfo[q];
                 in.iters = W.hms[j].iters[k] + rinfo[q].iters;
+                in.refine_iters = rinfo[q].iters;
                 in.time_s = elapsed;
                 in.t_done_s = t_krylov;   // end of the shared Krylov phase
                 const double site = (double)(link_site_bytes(kprec, recon)) / nrhs + 2.0 * 24;
@@ -303,8 +304,6 @@ hisq_status hisq_dslash_mrhs_impl(hisq_lattice lat, int out_parity, int prec, in
     const int slot = prec * 2 + (recon == 12);
     const long long h = lat->h;
     hipStream_t s = lat->s;
-    TuneChoice tc = pick_shape(lat, prec, recon, lat->ddesc, nullptr, lat->ntile, h, 1, (flags & HISQ_NO_TUNE) != 0);
-    const int Wm = std::min(std::max(tc.W, 2), 8);
     const void *din = in;
     void *dout = out;
     void *tmp = nullptr;
@@ -317,21 +316,21 @@ hisq_status hisq_dslash_mrhs_impl(hisq_lattice lat, int out_parity, int prec, in
         din = tmp;
         dout = (char *)tmp + v32;
     }
-    for (int g = 0; g < nrhs; g += 4) {
-        const int nr = std::min(4, nrhs - g);
-        MrhsLaunch a;
-        memset(&a, 0, sizeof a);
-        a.probs = lat->ddesc;
-        a.remap = tc.remap;
-        a.out_par = out_parity;
-        a.lslot = slot;
-        a.nrhs = nr;
-        a.vstride = h;
-        a.in = (const char *)din + (size_t)g * h * 24;
-        a.out = (char *)dout + (size_t)g * h * 24;
-        a.epi = EPI_PLAIN;
-        HIPCHK(lat, launch_dslash_mrhs(prec, recon, nr, Wm, a, lat->ntile, s));
-    }
+    const int group = std::min(4, nrhs);
+    const TuneChoice tc = pick_shape_mrhs(lat, prec, recon, group, (flags & HISQ_NO_TUNE) != 0);
+    MrhsLaunch a;
+    memset(&a, 0, sizeof a);
+    a.probs = lat->ddesc;
+    a.desc_stride = 0;
+    a.remap = tc.remap;
+    a.out_par = out_parity;
+    a.lslot = slot;
+    a.nrhs = nrhs;
+    a.vstride = h;
+    a.in = din;
+    a.out = dout;
+    a.epi = EPI_PLAIN;
+    HIPCHK(lat, launch_dslash_mrhs(prec, recon, group, tc.W, a, lat->ntile, s));
     if (tmp) {
         double *t64 = (double *)((char *)tmp + 2 * v32);
         HIPCHK(lat, launch_convert(dout, 1, t64, 0, (long long)nrhs * h * 3, s));

@@ -12,6 +12,9 @@ namespace hisq {
 ProbDesc lattice_desc(hisq_lattice lat);
 TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *ddesc, const int *dt2p,
                       int ntile, long long nsite, int nprob, bool no_tune);
+// Tuned launch shape of the multi-right-hand-side Dslash (nr right-hand
+// sides per launch, FP32 vectors) on lattice lat.
+TuneChoice pick_shape_mrhs(hisq_lattice lat, int prec, int recon, int nr, bool no_tune);
 
 // Describe nprob problems (one per handle) in S: descriptors, tile map,
 // states, partials.  sigma is added to every diagonal (4 m^2 + sigma).

@@ -52,7 +52,8 @@ class hisq_solver_info(ctypes.Structure):
                 ("true_residual", ctypes.c_double), ("time_s", ctypes.c_double),
                 ("dslash_bytes", ctypes.c_double), ("flops", ctypes.c_double),
                 ("t_done_s", ctypes.c_double), ("fell_back", ctypes.c_int),
-                ("fcg_iters", ctypes.c_int), ("restarts", ctypes.c_int)]
+                ("fcg_iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("refine_iters", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -214,21 +215,36 @@ class Lattice:
             _check(st, self.handle, "hisq_cg")
         return x, info.as_dict()
 
-    def multishift_cg(self, mass, shifts, b, params=None, raise_on_fail=True):
-        """b: [nrhs][h][3] host; returns x [nrhs][nshift][h][3] and info list."""
+    def multishift_cg(self, mass, shifts, b, x=None, params=None, raise_on_fail=True):
+        """b: [nrhs][h][3] complex (host array), or a device FP64 tensor of
+        nrhs*h*6 reals with x a device tensor of nrhs*nshift*h*6 reals;
+        returns (x, info list), x as [nrhs][nshift][h][3] on the host path."""
         params = params or hisq_default_params(tol=1e-8)
-        b = np.ascontiguousarray(b, dtype=np.complex128)
-        if b.ndim == 2:
-            b = b[None]
-        nrhs = b.shape[0]
         shifts = np.ascontiguousarray(shifts, dtype=np.float64)
         ns = len(shifts)
-        x = np.zeros((nrhs, ns) + b.shape[1:], dtype=np.complex128)
+        bp, bdev, k1 = _ptr(b)
+        if bdev:
+            if x is None:
+                raise ValueError("device right-hand sides need a device x")
+            nrhs = b.numel() // (self.h * 6)
+            if b.numel() != nrhs * self.h * 6 or x.numel() != nrhs * ns * self.h * 6:
+                raise ValueError("b must hold nrhs*h*6 and x nrhs*nshift*h*6 reals")
+            xp, xdev, k2 = _ptr(x)
+            if not xdev:
+                raise ValueError("x must be on the device with a device b")
+            params.flags |= HISQ_DEVICE_PTR
+        else:
+            b = np.ascontiguousarray(b, dtype=np.complex128)
+            if b.ndim == 2:
+                b = b[None]
+            nrhs = b.shape[0]
+            bp = b.ctypes.data_as(ctypes.c_void_p)
+            x = np.zeros((nrhs, ns) + b.shape[1:], dtype=np.complex128)
+            xp = x.ctypes.data_as(ctypes.c_void_p)
         infos = (hisq_solver_info * (nrhs * ns))()
         st = lib().hisq_multishift_cg(self.handle, ctypes.c_double(mass), ctypes.c_int(ns),
                                       shifts.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(nrhs),
-                                      b.ctypes.data_as(ctypes.c_void_p),
-                                      x.ctypes.data_as(ctypes.c_void_p), ctypes.byref(params), infos)
+                                      bp, xp, ctypes.byref(params), infos)
         if raise_on_fail:
             _check(st, self.handle, "hisq_multishift_cg")
         return x, [i.as_dict() for i in infos]

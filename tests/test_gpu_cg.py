@@ -156,3 +156,53 @@ def test_fp16_links_small_mass_restart():
     tr = oracle.true_residual(w.dims, fat, lng, w.mass, b, x)
     assert tr <= 1e-10
     lat.close()
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_batch_cg_one_lattice_shares_links(graph):
+    """Six problems on one handle (different masses and sources): the FP32
+    iterations go through the multi-right-hand-side kernel in groups of four
+    and two; every solution reaches the FP64 true residual, and each follows
+    the same recurrence as its lone solve."""
+    H = _hisq()
+    dims = (8, 8, 8, 12)
+    fat, lng = synth.make_links(dims, 0.2, seed=611)
+    L = H.Lattice(dims)
+    L.load_links(fat, lng)
+    L.prepare_links(1, 18)
+    ms = [0.3, 0.02, 0.1, 0.05, 0.2, 0.01]
+    bs = [synth.gaussian_even(dims, 620 + j) for j in range(len(ms))]
+    p = H.hisq_default_params(tol=1e-10, sloppy=1, flags=H.HISQ_USE_GRAPH if graph else 0)
+    xs, infos = H.hisq_batch_cg([L] * len(ms), ms, bs, params=p)
+    for j, m in enumerate(ms):
+        assert infos[j]["converged"] == 1
+        assert oracle.true_residual(dims, fat, lng, m, bs[j], xs[j]) <= 1e-10
+        _, i1 = L.cg(m, bs[j], params=H.hisq_default_params(tol=1e-10, sloppy=1))
+        assert abs(i1["iters"] - infos[j]["iters"]) <= 16, (j, i1["iters"], infos[j]["iters"])
+    assert infos[5]["iters"] > infos[0]["iters"]
+    L.close()
+
+
+def test_batch_cg_reordered_problems():
+    """Two batched calls led by the same handle, with the same sizes in a
+    different order, reuse the work set; the tile-to-problem map must follow
+    the new order."""
+    H = _hisq()
+    shapes = [(4, 4, 4, 4), (8, 8, 8, 8), (6, 6, 6, 6)]
+    lats, links = [], []
+    for j, d in enumerate(shapes):
+        fat, lng = synth.make_links(d, 0.25, seed=640 + j)
+        L = H.Lattice(d)
+        L.load_links(fat, lng)
+        L.prepare_links(1, 18)
+        lats.append(L)
+        links.append((fat, lng))
+    bs = [synth.gaussian_even(d, 650 + j) for j, d in enumerate(shapes)]
+    p = H.hisq_default_params(tol=1e-10, sloppy=1)
+    for order in ([0, 1, 2], [0, 2, 1]):
+        xs, infos = H.hisq_batch_cg([lats[k] for k in order], [0.1] * 3, [bs[k] for k in order], params=p)
+        for q, k in enumerate(order):
+            assert infos[q]["converged"] == 1
+            assert oracle.true_residual(shapes[k], *links[k], 0.1, bs[k], xs[q]) <= 1e-10
+    for L in lats:
+        L.close()

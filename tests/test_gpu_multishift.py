@@ -79,6 +79,35 @@ def test_multishift_small_vs_oracle_and_dense():
     lat.close()
 
 
+def test_multishift_device_pointers_match_host_path():
+    """Sources and solutions in device memory give the same solutions as the
+    host-pointer path (same kernels, same order: bitwise)."""
+    import torch
+    H = _hisq()
+    dims = (6, 4, 4, 6)
+    fat, lng = synth.make_links(dims, 0.2, seed=2100)
+    m = 0.02
+    shifts = synth.shifts_log(5)
+    b = synth.gaussian_even(dims, 2600, 3)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    p = H.hisq_default_params(tol=1e-9, sloppy=1)
+    xh, ih = lat.multishift_cg(m, shifts, b, params=p)
+    h = b.shape[1]
+    bd = torch.from_numpy(np.ascontiguousarray(b).view(np.float64).ravel()).cuda()
+    xd = torch.zeros(3 * 5 * h * 6, dtype=torch.float64, device="cuda")
+    _, idv = lat.multishift_cg(m, shifts, bd, x=xd, params=H.hisq_default_params(tol=1e-9, sloppy=1))
+    torch.cuda.synchronize()
+    xdh = xd.cpu().numpy().view(np.complex128).reshape(3, 5, h, 3)
+    assert np.array_equal(xdh, xh)
+    assert [i["iters"] for i in idv] == [i["iters"] for i in ih]
+    for j in range(3):
+        for k, s in enumerate(shifts):
+            assert oracle.true_residual(dims, fat, lng, m, b[j], xdh[j, k], sigma=s) <= 1e-9
+    lat.close()
+
+
 def test_multishift_fp16_recon12():
     H = _hisq()
     dims = (8, 8, 8, 8)
