@@ -232,6 +232,17 @@ hisq_status hisq_ptc_train(hisq_ptc net, int steps, int batch, double lr, unsign
 hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double mass, const double *b,
                             double *x, const hisq_solver_params *params, hisq_solver_info *info);
 
+/* ---- measurement ----
+ *
+ * Practical HBM ceilings of `device`, measured on `stream` (NULL: the null
+ * stream) with the library's own streaming kernels over a buffer of `bytes`
+ * (>= 1 MiB; two such buffers are allocated and freed): *read_gbs from a
+ * read-only pass of non-temporal 16-byte loads (the access the Dslash makes
+ * for its links), *copy_gbs from a copy (bytes read + written), each the
+ * average over `reps` launches after one warm-up.  Synchronous. */
+hisq_status hisq_stream_bandwidth(int device, void *stream, size_t bytes, int reps, double *read_gbs,
+                                  double *copy_gbs);
+
 #ifdef __cplusplus
 }
 #endif

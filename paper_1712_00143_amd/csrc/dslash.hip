@@ -86,14 +86,6 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
                 const int mu = d >> 2;
                 Cx<A> u[3][3];
                 decode_link<LT, R, A>(raw[g], u);
-                Cx<A> y[3];
-#pragma unroll
-                for (int r = 0; r < 3; r++) {
-                    Cx<A> s0 = cmul(u[r][0], v[g][0]);
-                    Cx<A> t1 = cmul(u[r][1], v[g][1]);
-                    Cx<A> t2 = cmul(u[r][2], v[g][2]);
-                    y[r] = {s0.re + t1.re + t2.re, s0.im + t1.im + t2.im};
-                }
                 if constexpr (R == 12 || sizeof(LT) == 2) {
                     const int fld = (d & 2) ? 1 : 0;
                     A coef = (A)ls.a[fld];
@@ -102,17 +94,9 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
                         const int neg = (ls.s[fld] < 0) ^ eb ^ (d & 1);
                         coef = neg ? -coef : coef;
                     }
-#pragma unroll
-                    for (int r = 0; r < 3; r++) {
-                        acc[r].re += coef * y[r].re;
-                        acc[r].im += coef * y[r].im;
-                    }
+                    matvec_acc_scaled(u, v[g], coef, acc);
                 } else {
-#pragma unroll
-                    for (int r = 0; r < 3; r++) {
-                        acc[r].re += y[r].re;
-                        acc[r].im += y[r].im;
-                    }
+                    matvec_acc(u, v[g], acc);
                 }
             }
         }

@@ -37,6 +37,55 @@ template <class A> __device__ __forceinline__ Cx<A> cconjmul(Cx<A> a, Cx<A> b)  
     return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 
+template <class A> __device__ __forceinline__ A fmaa(A a, A b, A c)
+{
+    if constexpr (sizeof(A) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
+
+// acc[r] += sum_c u[r][c] v[c]: 36 fused multiply-adds, no temporaries.
+template <class A> __device__ __forceinline__ void matvec_acc(const Cx<A> u[3][3], const Cx<A> v[3], Cx<A> acc[3])
+{
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        A re = acc[r].re, im = acc[r].im;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            re = fmaa(u[r][c].re, v[c].re, re);
+            re = fmaa(-u[r][c].im, v[c].im, re);
+            im = fmaa(u[r][c].re, v[c].im, im);
+            im = fmaa(u[r][c].im, v[c].re, im);
+        }
+        acc[r] = {re, im};
+    }
+}
+
+// acc[r] += k * sum_c u[r][c] v[c] (a scaled link: recon-12 sign, FP16 scale).
+template <class A>
+__device__ __forceinline__ void matvec_acc_scaled(const Cx<A> u[3][3], const Cx<A> v[3], A k, Cx<A> acc[3])
+{
+    Cx<A> y[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        A re = u[r][0].re * v[0].re, im = u[r][0].re * v[0].im;
+        re = fmaa(-u[r][0].im, v[0].im, re);
+        im = fmaa(u[r][0].im, v[0].re, im);
+#pragma unroll
+        for (int c = 1; c < 3; c++) {
+            re = fmaa(u[r][c].re, v[c].re, re);
+            re = fmaa(-u[r][c].im, v[c].im, re);
+            im = fmaa(u[r][c].re, v[c].im, im);
+            im = fmaa(u[r][c].im, v[c].re, im);
+        }
+        y[r] = {re, im};
+    }
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        acc[r].re = fmaa(k, y[r].re, acc[r].re);
+        acc[r].im = fmaa(k, y[r].im, acc[r].im);
+    }
+}
+
 template <class T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
 template <> __device__ __forceinline__ float to_f<__half>(__half v) { return __half2float(v); }
 

@@ -120,15 +120,10 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < NR; j++)
-#pragma unroll
-                    for (int r = 0; r < 3; r++) {
-                        Cx<A> s0 = cmul(u[r][0], v[g][j][0]);
-                        Cx<A> t1 = cmul(u[r][1], v[g][j][1]);
-                        Cx<A> t2 = cmul(u[r][2], v[g][j][2]);
-                        acc[j][r].re += coef * (s0.re + t1.re + t2.re);
-                        acc[j][r].im += coef * (s0.im + t1.im + t2.im);
-                    }
+                for (int j = 0; j < NR; j++) {
+                    if constexpr (R == 12 || sizeof(LT) == 2) matvec_acc_scaled(u, v[g][j], coef, acc[j]);
+                    else matvec_acc(u, v[g][j], acc[j]);
+                }
             }
         }
     }

@@ -37,6 +37,7 @@ EXPORTS = [
     "hisq_batch_cg", "hisq_ptc_create", "hisq_ptc_destroy", "hisq_ptc_set_weights",
     "hisq_ptc_get_weights", "hisq_ptc_layer_forward", "hisq_ptc_layer_backward", "hisq_ptc_apply",
     "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
+    "hisq_stream_bandwidth",
 ]
 
 
@@ -359,6 +360,16 @@ class PTC:
         if raise_on_fail:
             _check(st, lattice.handle, "hisq_cg_learned")
         return x, info.as_dict()
+
+
+def stream_bandwidth(device=0, stream=None, nbytes=1 << 30, reps=10):
+    """Practical HBM ceilings (read-only, copy) in GB/s from the library's
+    streaming kernels."""
+    r, c = ctypes.c_double(), ctypes.c_double()
+    st = lib().hisq_stream_bandwidth(ctypes.c_int(device), stream, ctypes.c_size_t(nbytes), ctypes.c_int(reps),
+                                     ctypes.byref(r), ctypes.byref(c))
+    _check(st, None, "hisq_stream_bandwidth")
+    return r.value, c.value
 
 
 def hisq_batch_cg(lattices, masses, bs, params=None, raise_on_fail=True):

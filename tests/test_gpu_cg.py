@@ -163,7 +163,8 @@ def test_batch_cg_one_lattice_shares_links(graph):
     """Six problems on one handle (different masses and sources): the FP32
     iterations go through the multi-right-hand-side kernel in groups of four
     and two; every solution reaches the FP64 true residual, and each follows
-    the same recurrence as its lone solve."""
+    the same recurrence as its lone solve (the two kernels round differently
+    in FP32, so the counts agree to a few per cent, not exactly)."""
     H = _hisq()
     dims = (8, 8, 8, 12)
     fat, lng = synth.make_links(dims, 0.2, seed=611)
@@ -178,7 +179,7 @@ def test_batch_cg_one_lattice_shares_links(graph):
         assert infos[j]["converged"] == 1
         assert oracle.true_residual(dims, fat, lng, m, bs[j], xs[j]) <= 1e-10
         _, i1 = L.cg(m, bs[j], params=H.hisq_default_params(tol=1e-10, sloppy=1))
-        assert abs(i1["iters"] - infos[j]["iters"]) <= 16, (j, i1["iters"], infos[j]["iters"])
+        assert abs(i1["iters"] - infos[j]["iters"]) <= 0.06 * i1["iters"] + 8, (j, i1["iters"], infos[j]["iters"])
     assert infos[5]["iters"] > infos[0]["iters"]
     L.close()
 

@@ -158,3 +158,13 @@ def test_dslash_errors():
         lat.dslash(0, 1, 12, psi, out)
     assert ei.value.status == H.HISQ_ERR_STATE     # set not prepared
     lat.close()
+
+
+def test_stream_bandwidth_probe():
+    """The ceiling probe runs and reports plausible HBM rates; bad arguments
+    are rejected."""
+    from paper_1712_00143_amd import hisq as H
+    r, c = H.stream_bandwidth(0, None, 1 << 28, 3)
+    assert 500.0 < r < 20000.0 and 500.0 < c < 20000.0
+    with pytest.raises(H.HisqError):
+        H.stream_bandwidth(0, None, 1024, 3)
