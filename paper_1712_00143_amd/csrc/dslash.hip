@@ -27,7 +27,8 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
     static_assert(16 % W == 0, "W must divide 16");
     constexpr int DPW = 16 / W;
     using F = LinkFmt<LT, R>;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index is uniform: keep it (and the direction-block bases) scalar
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = xcd_tile(blockIdx.x, gridDim.x, a.remap);
     const int prob = a.tile2prob ? a.tile2prob[tile] : 0;
     const ProbDesc &pd = a.probs[prob];
@@ -76,7 +77,7 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
             RawLink<LT, R> raw[G];
 #pragma unroll
             for (int g = 0; g < G; g++)
-                load_link_raw<LT, R>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
+                load_link_raw_wave<LT, R>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
             Cx<A> v[G][3];
 #pragma unroll
             for (int g = 0; g < G; g++) load_spinor<ST, A>(in, voff + nb[g], v[g]);

@@ -124,6 +124,34 @@ __device__ __forceinline__ void load_link_raw(const char *__restrict__ dirbase, 
     }
 }
 
+// The same loads through a buffer resource: `dirbase` must be the same for the
+// whole wavefront (one direction block), so the base and the chunk-plane
+// offsets live in scalar registers and each lane supplies only i * 16.  The
+// offsets are 32-bit: one direction block must stay below 4 GiB.
+template <class LT, int R>
+__device__ __forceinline__ void load_link_raw_wave(const char *dirbase, int i, int h, RawLink<LT, R> &raw)
+{
+    using F = LinkFmt<LT, R>;
+    constexpr int NT = 2;   // cache policy: non-temporal (links are streamed once)
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)dirbase, (short)0, h * F::BYTES, 0x00020000);
+#pragma unroll
+    for (int q = 0; q < F::NQ; q++) {
+        u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, i * 16, q * h * 16, NT));
+        raw.w[4 * q + 0] = v.x;
+        raw.w[4 * q + 1] = v.y;
+        raw.w[4 * q + 2] = v.z;
+        raw.w[4 * q + 3] = v.w;
+    }
+    if constexpr (F::REM == 8) {
+        u32x2 v = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, i * 8, F::NQ * h * 16, NT));
+        raw.w[4 * F::NQ + 0] = v.x;
+        raw.w[4 * F::NQ + 1] = v.y;
+    } else if constexpr (F::REM == 4) {
+        raw.w[4 * F::NQ] = __builtin_amdgcn_raw_buffer_load_b32(rs, i * 4, F::NQ * h * 16, NT);
+    }
+}
+
 // Unpack a raw link into a 3x3 complex matrix; recon-12 rebuilds row 2 as
 // conj(row0 x row1).
 template <class LT, int R, class A>

@@ -33,7 +33,8 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
     using V2 = typename MrhsVec<LT>::pair;
     constexpr int DPW = 16 / W;
     using F = LinkFmt<LT, R>;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index is uniform: keep it (and the direction-block bases) scalar
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const ProbDesc &pd = a.probs[0];
     const int bt = xcd_tile(blockIdx.x, gridDim.x, a.remap);
     const int grp = bt / pd.ntile;
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
             RawLink<LT, R> raw[G];
 #pragma unroll
             for (int g = 0; g < G; g++)
-                load_link_raw<LT, R>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
+                load_link_raw_wave<LT, R>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
             Cx<A> v[G][NR][3];
 #pragma unroll
             for (int g = 0; g < G; g++)
