@@ -258,6 +258,12 @@ ProbDesc lattice_desc(hisq_lattice lat)
     d.tile_begin = 0;
     d.ntile = lat->ntile;
     d.voff = 0;
+    int lmax = 0;
+    for (int k = 0; k < 3; k++) {
+        d.mdiv[k] = (unsigned)((((unsigned long long)1 << 32) + (unsigned)lat->L[k] - 1) / (unsigned)lat->L[k]);
+        lmax = lat->L[k] > lmax ? lat->L[k] : lmax;
+    }
+    d.fastdiv = (unsigned long long)lat->V * (unsigned long long)lmax <= ((unsigned long long)1 << 32);
     for (int k = 0; k < NLINKSET; k++) d.ls[k] = lat->ls[k];
     return d;
 }

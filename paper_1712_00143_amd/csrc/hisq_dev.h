@@ -44,6 +44,8 @@ struct ProbDesc {
     int h;            // sites per parity
     int tile_begin;   // first logical tile of this problem
     int ntile;        // tiles of this problem
+    int fastdiv;      // 1: mdiv[] divides every site index of this lattice exactly
+    unsigned mdiv[3]; // ceil(2^32 / L[k]): n / L[k] = umulhi(n, mdiv[k]) when n * L[k] <= 2^32
     int pad;
     long long voff;   // offset (in sites) of this problem's parity vectors
     double diag;      // 4 m^2 (+ base shift)
@@ -107,6 +109,27 @@ __device__ __forceinline__ Coord cb_to_coord(int cb, int par, const int L[4])
     r /= L[1];
     c.x[2] = r % L[2];
     c.x[3] = r / L[2];
+    c.x[0] = x0e + ((par + c.x[1] + c.x[2] + c.x[3]) & 1);
+    return c;
+}
+
+// cb_to_coord with the three divisions done as multiply-high by the
+// descriptor's reciprocals.  With m = ceil(2^32/d) = (2^32 + e)/d, 0 <= e < d,
+// n m / 2^32 = n/d + n e / (d 2^32), and the floor is exact when n e < 2^32,
+// which n d <= 2^32 guarantees; every numerator here is below V, so the host
+// sets fastdiv when V * max(L0, L1, L2) <= 2^32.
+__device__ __forceinline__ Coord cb_to_coord_pd(int cb, int par, const ProbDesc &pd)
+{
+    if (!pd.fastdiv) return cb_to_coord(cb, par, pd.L);
+    Coord c;
+    const unsigned y = 2u * (unsigned)cb;
+    const unsigned r0 = __umulhi(y, pd.mdiv[0]);
+    const int x0e = (int)(y - r0 * (unsigned)pd.L[0]);
+    const unsigned r1 = __umulhi(r0, pd.mdiv[1]);
+    c.x[1] = (int)(r0 - r1 * (unsigned)pd.L[1]);
+    const unsigned r2 = __umulhi(r1, pd.mdiv[2]);
+    c.x[2] = (int)(r1 - r2 * (unsigned)pd.L[2]);
+    c.x[3] = (int)r2;
     c.x[0] = x0e + ((par + c.x[1] + c.x[2] + c.x[3]) & 1);
     return c;
 }

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
         for (int c = 0; c < 3; c++) acc[j][c] = {(A)0, (A)0};
 
     if (valid) {
-        const Coord co = cb_to_coord(i, par, pd.L);
+        const Coord co = cb_to_coord_pd(i, par, pd);
         const int lex = 2 * i + (co.x[0] & 1);
         const int e1 = co.x[0] & 1, e2 = (co.x[0] + co.x[1]) & 1, e3 = (co.x[0] + co.x[1] + co.x[2]) & 1;
         // links in flight per thread: fewer when the gathered vectors are many or wide

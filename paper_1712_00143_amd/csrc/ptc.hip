@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(64 * W) k_ptc_layer(PtcLaunch a)
 #pragma unroll
         for (int q = 0; q < 3; q++) acc[c][q] = {0.f, 0.f};
     if (valid) {
-        const Coord co = cb_to_coord(i, par, pd.L);
+        const Coord co = cb_to_coord_pd(i, par, pd);
         const int lex = 2 * i + (co.x[0] & 1);
         constexpr int PPW = (9 + W - 1) / W;
         for (int kk = 0; kk < PPW; kk++) {
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(576) k_ptc_wgrad(PtcLaunch a)
 #pragma unroll
         for (int cp = 0; cp < CIN; cp++) acc[c][cp][0] = acc[c][cp][1] = 0.0;
     if (i < pd.h) {
-        const Coord co = cb_to_coord(i, par, pd.L);
+        const Coord co = cb_to_coord_pd(i, par, pd);
         const int lex = 2 * i + (co.x[0] & 1);
         Cx<float> v[CIN][3];
         if (transport<LT, R>(a, pd, ls, par, i, co, lex, k, in_b, CIN, v, CIN)) {

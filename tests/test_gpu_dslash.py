@@ -168,3 +168,20 @@ def test_stream_bandwidth_probe():
     assert 500.0 < r < 20000.0 and 500.0 < c < 20000.0
     with pytest.raises(H.HisqError):
         H.stream_bandwidth(0, None, 1024, 3)
+
+
+def test_dslash_long_extent_exact_division_path():
+    """32768 x 2 x 2 x 2: V * L0 = 2^33 exceeds the bound of the reciprocal
+    shortcut, so the kernels take the exact-division path; both paths must
+    give the oracle's result."""
+    from paper_1712_00143_amd import hisq as H
+    for dims in [(32768, 2, 2, 2), (2, 2, 2, 32768)]:
+        fat, lng = synth.make_links(dims, 0.2, seed=91)
+        psi = synth.gaussian_even(dims, 92)
+        lat = H.Lattice(dims)
+        lat.load_links(fat, lng)
+        out = np.zeros_like(psi)
+        lat.dslash(1, 0, 18, psi, out)
+        ref = oracle.dslash_half(dims, fat, lng, 1, psi)
+        assert _rel(out, ref) <= 1e-12, (dims, _rel(out, ref))
+        lat.close()
