@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <random>
 #include <vector>
@@ -102,11 +103,79 @@ PtcLaunch base_launch(hisq_lattice lat, int lslot)
     return a;
 }
 
+// Waves per block of the layer kernel (1, 3 or 9 of the 9 transport paths
+// each) for this geometry, channel pair, batch and link format: timed once on
+// scratch activations, then cached.  Must not run under stream capture.
+int pick_layer_waves(hisq_lattice lat, int lslot, int prec, int recon, bool w16, const void *w, int cin, int cout,
+                     int in_zero, int npar, int batch, hipStream_t stream)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return 9;
+    char key[256];
+    snprintf(key, sizeof key, "ptc:%s:t%d:p%d:r%d:w%d:%dx%d:z%d:np%d:b%d", prop.gcnArchName, lat->ntile, prec, recon,
+             (int)w16, cin, cout, in_zero, npar, batch);
+    std::string k(key);
+    for (auto &ch : k)
+        if (ch == ' ') ch = '_';
+    TuneChoice c;
+    if (Tuner::get().lookup(k, c)) return c.W;
+    const long long h = lat->h;
+    float *in = nullptr, *out = nullptr;
+    if (hipMalloc(&in, sizeof(float) * (size_t)batch * cin * 2 * h * 6) != hipSuccess ||
+        hipMalloc(&out, sizeof(float) * (size_t)batch * cout * 2 * h * 6) != hipSuccess) {
+        if (in) (void)hipFree(in);
+        return 9;
+    }
+    (void)hipMemsetAsync(in, 0, sizeof(float) * (size_t)batch * cin * 2 * h * 6, stream);
+    PtcLaunch a = base_launch(lat, lslot);
+    a.w = w;
+    a.in = in;
+    a.in_bstride = (long long)cin * 2 * h * 6;
+    a.in_zero_par = in_zero;
+    a.out = out;
+    a.out_bstride = (long long)cout * 2 * h * 6;
+    a.out_pstride = 2;
+    a.out_par0 = 0;
+    a.par_lo = 0;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    TuneChoice best;
+    best.W = 9;
+    best.us = 1e30;
+    for (int W : {1, 3, 9}) {
+        bool ok = true;
+        for (int r = 0; r < 2 && ok; r++)
+            ok = launch_ptc_layer(prec, recon, w16, cin, cout, W, a, lat->ntile * npar, batch, stream) == hipSuccess;
+        if (!ok) continue;
+        const int reps = 5;
+        (void)hipEventRecord(e0, stream);
+        for (int r = 0; r < reps; r++)
+            (void)launch_ptc_layer(prec, recon, w16, cin, cout, W, a, lat->ntile * npar, batch, stream);
+        (void)hipEventRecord(e1, stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (1000.0 * ms / reps < best.us) {
+            best.us = 1000.0 * ms / reps;
+            best.W = W;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(in);
+    (void)hipFree(out);
+    (void)hipGetLastError();
+    if (best.us < 1e29) Tuner::get().store(k, best);
+    return best.W;
+}
+
 // One layer application over output parities [plo, phi].
 hipError_t run_layer(hisq_lattice lat, int lslot, int prec, int recon, bool w16, const void *w, int cin, int cout,
                      const float *in, long long in_bs, int in_zero, float *out, long long out_bs, int out_pstride,
                      int plo, int phi, int batch, hipStream_t stream)
 {
+    const int W = pick_layer_waves(lat, lslot, prec, recon, w16, w, cin, cout, in_zero, phi - plo + 1, batch, stream);
     PtcLaunch a = base_launch(lat, lslot);
     a.w = w;
     a.in = in;
@@ -118,7 +187,7 @@ hipError_t run_layer(hisq_lattice lat, int lslot, int prec, int recon, bool w16,
     a.out_par0 = plo;
     a.par_lo = plo;
     const int nblk = lat->ntile * (phi - plo + 1);
-    return launch_ptc_layer(prec, recon, w16, cin, cout, 3, a, nblk, batch, stream);
+    return launch_ptc_layer(prec, recon, w16, cin, cout, W, a, nblk, batch, stream);
 }
 
 // Weight gradient of one layer application, summed over the output parities
@@ -136,9 +205,13 @@ hipError_t run_wgrad(hisq_ptc_s *n, hisq_lattice lat, int cin, int cout, const f
     a.g_bstride = g_bs;
     a.g_pstride = g_pstride;
     a.partials = n->part;
-    hipError_t e = launch_ptc_wgrad(cin, cout, a, lat->ntile * g_pstride, batch, s);
+    // one partial row per block; enough blocks to fill the device, at most one
+    // per work unit
+    const long long units = (long long)lat->ntile * g_pstride * batch;
+    const int nrow = (int)(units < WGRAD_ROWS ? units : WGRAD_ROWS);
+    hipError_t e = launch_ptc_wgrad(cin, cout, a, g_pstride, batch, nrow, s);
     if (e != hipSuccess) return e;
-    return launch_ptc_wsum(n->part, (long long)lat->ntile * g_pstride * batch, cin, cout, gw, accumulate, s);
+    return launch_ptc_wsum(n->part, nrow, cin, cout, gw, accumulate, s);
 }
 
 // z = M(r) for `batch` even vectors (FP32 [batch][h][3]); `ws` holds two

@@ -38,7 +38,9 @@ __device__ __forceinline__ int nb1(const Coord &co, int lex, int mu, int k, int 
 }
 
 // Transport along path k (0 identity, 1+2mu forward, 2+2mu backward) of
-// input channel c at output site (par, i); returns false if it is zero.
+// input channel c at output site (par, i); returns false if it is zero.  k
+// and par must be uniform over the wavefront (the link block is addressed
+// through a wave-uniform buffer resource).
 template <class LT, int R>
 __device__ __forceinline__ bool transport(const PtcLaunch &a, const ProbDesc &pd, const LinkSet &ls, int par,
                                           int i, const Coord &co, int lex, int k, const float *in_b, int cin,
@@ -65,7 +67,9 @@ __device__ __forceinline__ bool transport(const PtcLaunch &a, const ProbDesc &pd
     const int d = 4 * mu + (fwd ? 0 : 1);
     using F = LinkFmt<LT, R>;
     Cx<float> u[3][3];
-    load_link<LT, R, float>((const char *)ls.ptr[par] + (size_t)d * h * F::BYTES, i, (int)h, u);
+    RawLink<LT, R> raw;
+    load_link_raw_wave<LT, R>((const char *)ls.ptr[par] + (size_t)d * h * F::BYTES, i, (int)h, raw);
+    decode_link<LT, R, float>(raw, u);
     float coef = 1.f;
     if constexpr (R == 12 || sizeof(LT) == 2) {
         coef = (float)ls.a[0];
@@ -85,10 +89,8 @@ __device__ __forceinline__ bool transport(const PtcLaunch &a, const ProbDesc &pd
             s[q] = {t.x, t.y};
         }
 #pragma unroll
-        for (int r = 0; r < 3; r++) {
-            Cx<float> y0 = cmul(u[r][0], s[0]), y1 = cmul(u[r][1], s[1]), y2 = cmul(u[r][2], s[2]);
-            v[c][r] = {coef * (y0.re + y1.re + y2.re), coef * (y0.im + y1.im + y2.im)};
-        }
+        for (int r = 0; r < 3; r++) v[c][r] = {0.f, 0.f};
+        matvec_acc_scaled(u, s, coef, v[c]);
     }
     return true;
 }
@@ -97,7 +99,7 @@ __device__ __forceinline__ bool transport(const PtcLaunch &a, const ProbDesc &pd
 template <class LT, int R, class WT, int CIN, int COUT, int W>
 __global__ void __launch_bounds__(64 * W) k_ptc_layer(PtcLaunch a)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const ProbDesc &pd = a.probs[0];
     const int ntile = pd.ntile;
     const int par = a.par_lo + blockIdx.x / ntile;
@@ -116,11 +118,11 @@ __global__ void __launch_bounds__(64 * W) k_ptc_layer(PtcLaunch a)
         const Coord co = cb_to_coord_pd(i, par, pd);
         const int lex = 2 * i + (co.x[0] & 1);
         constexpr int PPW = (9 + W - 1) / W;
+#pragma unroll
         for (int kk = 0; kk < PPW; kk++) {
             const int k = wave * PPW + kk;
-            if (k >= 9) break;
             Cx<float> v[CIN][3];
-            if (!transport<LT, R>(a, pd, ls, par, i, co, lex, k, in_b, CIN, v, CIN)) continue;
+            if (k >= 9 || !transport<LT, R>(a, pd, ls, par, i, co, lex, k, in_b, CIN, v, CIN)) continue;
 #pragma unroll
             for (int c = 0; c < COUT; c++)
 #pragma unroll
@@ -167,57 +169,63 @@ __global__ void __launch_bounds__(64 * W) k_ptc_layer(PtcLaunch a)
     }
 }
 
-// Weight gradient: partial sums over this tile of (T_k in_{c'})(x)^+ g_c(x),
-// one wavefront per path k.  Partials: [block][9][COUT][CIN] complex FP64.
+// Weight gradient: sums of (T_k in_{c'})(x)^+ g_c(x) over sites and batch
+// entries, one wavefront per path k.  Block j walks the work units (batch
+// entry, output parity, tile) j, j + grid, j + 2 grid, ... accumulating in FP64
+// per lane, and reduces once at the end: partials [block][9][COUT][CIN]
+// complex FP64, in a fixed order for a given grid.
 template <class LT, int R, int CIN, int COUT>
-__global__ void __launch_bounds__(576) k_ptc_wgrad(PtcLaunch a)
+__global__ void __launch_bounds__(576) k_ptc_wgrad(PtcLaunch a, int npar, int batch)
 {
-    const int lane = threadIdx.x & 63, k = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const ProbDesc &pd = a.probs[0];
     const int ntile = pd.ntile;
-    const int par = a.par_lo + blockIdx.x / ntile;
-    const int tile = blockIdx.x % ntile;
-    const int b = blockIdx.y;
-    const int i = tile * TILE + lane;
+    const long long h = pd.h;
     const LinkSet &ls = pd.ls[a.lslot];
-    const float *in_b = a.in + (size_t)b * a.in_bstride;
-    const float *g_b = a.g + (size_t)b * a.g_bstride;
+    const long long nunit = (long long)batch * npar * ntile;
     double acc[COUT][CIN][2];
 #pragma unroll
     for (int c = 0; c < COUT; c++)
 #pragma unroll
         for (int cp = 0; cp < CIN; cp++) acc[c][cp][0] = acc[c][cp][1] = 0.0;
-    if (i < pd.h) {
+    for (long long u = blockIdx.x; u < nunit; u += gridDim.x) {
+        const int b = (int)(u / (npar * ntile));
+        const int rem = (int)(u - (long long)b * npar * ntile);
+        const int par = a.par_lo + rem / ntile;
+        const int tile = rem % ntile;
+        const int i = tile * TILE + lane;
+        if (i >= pd.h) continue;
+        const float *in_b = a.in + (size_t)b * a.in_bstride;
+        const float *g_b = a.g + (size_t)b * a.g_bstride;
         const Coord co = cb_to_coord_pd(i, par, pd);
         const int lex = 2 * i + (co.x[0] & 1);
         Cx<float> v[CIN][3];
-        if (transport<LT, R>(a, pd, ls, par, i, co, lex, k, in_b, CIN, v, CIN)) {
-            const long long h = pd.h;
+        if (!transport<LT, R>(a, pd, ls, par, i, co, lex, k, in_b, CIN, v, CIN)) continue;
 #pragma unroll
-            for (int c = 0; c < COUT; c++) {
-                const float2 *gp = reinterpret_cast<const float2 *>(g_b) + ((c * a.g_pstride + (par - a.g_par0)) * h + i) * 3;
-                float2 g[3] = {gp[0], gp[1], gp[2]};
+        for (int c = 0; c < COUT; c++) {
+            const float2 *gp = reinterpret_cast<const float2 *>(g_b) + ((c * a.g_pstride + (par - a.g_par0)) * h + i) * 3;
+            const float2 g[3] = {gp[0], gp[1], gp[2]};
 #pragma unroll
-                for (int cp = 0; cp < CIN; cp++) {
-                    float re = 0.f, im = 0.f;
+            for (int cp = 0; cp < CIN; cp++) {
+                float re = 0.f, im = 0.f;
 #pragma unroll
-                    for (int q = 0; q < 3; q++) {   // conj(v) g
-                        re += v[cp][q].re * g[q].x + v[cp][q].im * g[q].y;
-                        im += v[cp][q].re * g[q].y - v[cp][q].im * g[q].x;
-                    }
-                    acc[c][cp][0] = re;
-                    acc[c][cp][1] = im;
+                for (int q = 0; q < 3; q++) {   // conj(v) g
+                    re = fmaa(v[cp][q].re, g[q].x, re);
+                    re = fmaa(v[cp][q].im, g[q].y, re);
+                    im = fmaa(v[cp][q].re, g[q].y, im);
+                    im = fmaa(-v[cp][q].im, g[q].x, im);
                 }
+                acc[c][cp][0] += re;
+                acc[c][cp][1] += im;
             }
         }
     }
-    const size_t blk = (size_t)b * gridDim.x + blockIdx.x;
-    double *out = a.partials + (blk * 9 + k) * (COUT * CIN * 2);
+    double *out = a.partials + ((size_t)blockIdx.x * 9 + k) * (COUT * CIN * 2);
 #pragma unroll
     for (int c = 0; c < COUT; c++)
 #pragma unroll
         for (int cp = 0; cp < CIN; cp++) {
-            double re = wave_sum(acc[c][cp][0]), im = wave_sum(acc[c][cp][1]);
+            const double re = wave_sum(acc[c][cp][0]), im = wave_sum(acc[c][cp][1]);
             if (lane == 0) {
                 out[(c * CIN + cp) * 2] = re;
                 out[(c * CIN + cp) * 2 + 1] = im;
@@ -225,32 +233,24 @@ __global__ void __launch_bounds__(576) k_ptc_wgrad(PtcLaunch a)
         }
 }
 
-// First pass of the weight-gradient sum: block b adds rows b, b + G, b + 2G,
-// ... (consecutive threads read consecutive values: coalesced) into
-// part2[b][v].  The second pass (k_ptc_wsum over the G rows) finishes in a
-// fixed order, so the result does not depend on scheduling.
-constexpr int WSUM_G = 256;
-__global__ void __launch_bounds__(256) k_ptc_wsum1(const double *partials, long long nrow, int nv, double *part2)
+// g_w[c][c'][k] = sum over the partial rows: one block per value, each thread
+// summing rows t, t + 256, ... in order, then a fixed-order block sum, so the
+// result does not depend on scheduling.
+__global__ void __launch_bounds__(256) k_ptc_wsum(const double *partials, long long nrow, int cin, int cout,
+                                                  double *gw, int accumulate)
 {
-    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-        double s = 0.0;
-        for (long long r = blockIdx.x; r < nrow; r += gridDim.x) s += partials[r * nv + v];
-        part2[(size_t)blockIdx.x * nv + v] = s;
-    }
-}
-
-// g_w[c][c'][k] = sum over partial rows (fixed order); one thread per value.
-__global__ void k_ptc_wsum(const double *partials, long long nrow, int cin, int cout, double *gw, int accumulate)
-{
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;   // value index in [9][cout][cin][2]
+    __shared__ double lds[16];
+    const int v = blockIdx.x;   // value index in [9][cout][cin][2]
     const int nv = 9 * cout * cin * 2;
-    if (v >= nv) return;
-    double s = 0.0;
-    for (long long r = 0; r < nrow; r++) s += partials[r * nv + v];
-    const int ri = v & 1, q = v >> 1;
-    const int k = q / (cout * cin), c = (q / cin) % cout, cp = q % cin;
-    const int o = ((c * cin + cp) * 9 + k) * 2 + ri;
-    gw[o] = accumulate ? gw[o] + s : s;
+    double s[1] = {0.0};
+    for (long long r = threadIdx.x; r < nrow; r += blockDim.x) s[0] += partials[r * nv + v];
+    block_sum<1>(s, lds);
+    if (threadIdx.x == 0) {
+        const int ri = v & 1, q = v >> 1;
+        const int k = q / (cout * cin), c = (q / cin) % cout, cp = q % cin;
+        const int o = ((c * cin + cp) * 9 + k) * 2 + ri;
+        gw[o] = accumulate ? gw[o] + s[0] : s[0];
+    }
 }
 
 // Loss of a batch of B pairs (z_b = M r_b, e_b the target):
@@ -384,11 +384,11 @@ hipError_t launch_ptc_layer(int prec, int recon, bool w16, int cin, int cout, in
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_ptc_wgrad(int cin, int cout, const PtcLaunch &a, int nblk, int batch, hipStream_t s)
+hipError_t launch_ptc_wgrad(int cin, int cout, const PtcLaunch &a, int npar, int batch, int nrow, hipStream_t s)
 {
-    dim3 g(nblk, batch), b(576);
+    dim3 g(nrow), b(576);
 #define WG_CASE(I, O) \
-    if (cin == I && cout == O) { hipLaunchKernelGGL((k_ptc_wgrad<float, 18, I, O>), g, b, 0, s, a); return hipGetLastError(); }
+    if (cin == I && cout == O) { hipLaunchKernelGGL((k_ptc_wgrad<float, 18, I, O>), g, b, 0, s, a, npar, batch); return hipGetLastError(); }
     WG_CASE(1, 1) WG_CASE(1, 4) WG_CASE(4, 4) WG_CASE(4, 1) WG_CASE(1, 2) WG_CASE(2, 2) WG_CASE(2, 1)
     WG_CASE(2, 4) WG_CASE(4, 2) WG_CASE(1, 8) WG_CASE(8, 8) WG_CASE(8, 1)
 #undef WG_CASE
@@ -399,16 +399,7 @@ hipError_t launch_ptc_wsum(const double *partials, long long nrow, int cin, int 
                            hipStream_t s)
 {
     const int nv = 9 * cout * cin * 2;
-    if (nrow > 4 * WSUM_G) {
-        // partials holds nrow rows followed by room for WSUM_G more
-        double *part2 = const_cast<double *>(partials) + (size_t)nrow * nv;
-        hipLaunchKernelGGL(k_ptc_wsum1, dim3(WSUM_G), dim3(256), 0, s, partials, nrow, nv, part2);
-        hipLaunchKernelGGL(k_ptc_wsum, dim3((nv + 255) / 256), dim3(256), 0, s, (const double *)part2,
-                           (long long)WSUM_G, cin, cout, gw, accumulate);
-    } else {
-        hipLaunchKernelGGL(k_ptc_wsum, dim3((nv + 255) / 256), dim3(256), 0, s, partials, nrow, cin, cout, gw,
-                           accumulate);
-    }
+    hipLaunchKernelGGL(k_ptc_wsum, dim3(nv), dim3(256), 0, s, partials, nrow, cin, cout, gw, accumulate);
     return hipGetLastError();
 }
 
