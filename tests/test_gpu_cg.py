@@ -207,3 +207,33 @@ def test_batch_cg_reordered_problems():
             assert oracle.true_residual(shapes[k], *links[k], 0.1, bs[k], xs[q]) <= 1e-10
     for L in lats:
         L.close()
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (6, 6, 6, 6), (4, 4, 8, 8)])
+def test_cg_small_lattices(dims):
+    """Small lattices (1, 2, 11 and 4 tiles): the same iteration count as the
+    oracle's FP64 CG to within a few per cent (different summation order),
+    FP64 true residual below tol, the batched path (one problem) agreeing,
+    and the maxiter limit honoured."""
+    H = _hisq()
+    fat, lng = synth.make_links(dims, 0.3, seed=31)
+    b = synth.gaussian_even(dims, 32)
+    m = 0.05
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    x, info = lat.cg(m, b, params=H.hisq_default_params(tol=1e-10))
+    assert info["converged"] == 1 and info["status"] == 0
+    assert oracle.true_residual(dims, fat, lng, m, b, x) <= 1e-10
+    assert abs(info["true_residual"] - oracle.true_residual(dims, fat, lng, m, b, x)) <= 1e-3 * info["true_residual"] + 1e-15
+    _, it_o, _, _ = oracle.cg(dims, fat, lng, m, b, tol=1e-10)
+    # the three FP64 CGs sum in different orders; near kappa ~ 1e3 that moves
+    # the iteration count by a few per cent
+    assert abs(info["iters"] - it_o) <= 0.04 * it_o + 3, (info["iters"], it_o)
+    xb, ib = H.hisq_batch_cg([lat], [m], [b], params=H.hisq_default_params(tol=1e-10))
+    assert ib[0]["converged"] == 1 and abs(ib[0]["iters"] - info["iters"]) <= 0.04 * it_o + 3
+    assert oracle.true_residual(dims, fat, lng, m, b, xb[0]) <= 1e-10
+    if info["iters"] > 12:
+        x2, i2 = lat.cg(m, b, params=H.hisq_default_params(tol=1e-10, maxiter=10), raise_on_fail=False)
+        assert i2["converged"] == 0 and i2["status"] == H.HISQ_ERR_NOT_CONVERGED and 10 <= i2["iters"] <= 10 + 16
+        assert oracle.true_residual(dims, fat, lng, m, b, x2) < 1.0
+    lat.close()
