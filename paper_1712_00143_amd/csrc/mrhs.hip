@@ -130,26 +130,33 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
     }
 
     if constexpr (W > 1) {
-        __shared__ A red[(W - 1) * NR * 6 * 64];
-        if (wave > 0) {
+        // pairwise tree over the waves (W is a power of two): the upper half
+        // hands its partial vectors to the lower half through LDS, halving
+        // each round, so LDS holds W/2 waves' worth (more blocks per CU than
+        // a single round into wave 0) and the summation order is fixed
+        __shared__ A red[(W / 2) * NR * 6 * 64];
 #pragma unroll
-            for (int j = 0; j < NR; j++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    red[(((wave - 1) * NR + j) * 6 + 2 * c) * 64 + lane] = acc[j][c].re;
-                    red[(((wave - 1) * NR + j) * 6 + 2 * c + 1) * 64 + lane] = acc[j][c].im;
-                }
-        }
-        __syncthreads();
-        if (wave == 0) {
-            for (int w = 1; w < W; w++)
+        for (int half = W / 2; half >= 1; half >>= 1) {
+            if (wave >= half && wave < 2 * half) {
 #pragma unroll
                 for (int j = 0; j < NR; j++)
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        acc[j][c].re += red[(((w - 1) * NR + j) * 6 + 2 * c) * 64 + lane];
-                        acc[j][c].im += red[(((w - 1) * NR + j) * 6 + 2 * c + 1) * 64 + lane];
+                        red[(((wave - half) * NR + j) * 6 + 2 * c) * 64 + lane] = acc[j][c].re;
+                        red[(((wave - half) * NR + j) * 6 + 2 * c + 1) * 64 + lane] = acc[j][c].im;
                     }
+            }
+            __syncthreads();
+            if (wave < half) {
+#pragma unroll
+                for (int j = 0; j < NR; j++)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        acc[j][c].re += red[((wave * NR + j) * 6 + 2 * c) * 64 + lane];
+                        acc[j][c].im += red[((wave * NR + j) * 6 + 2 * c + 1) * 64 + lane];
+                    }
+            }
+            if (half > 1) __syncthreads();
         }
     }
 
