@@ -237,3 +237,28 @@ def test_cg_small_lattices(dims):
         assert i2["converged"] == 0 and i2["status"] == H.HISQ_ERR_NOT_CONVERGED and 10 <= i2["iters"] <= 10 + 16
         assert oracle.true_residual(dims, fat, lng, m, b, x2) < 1.0
     lat.close()
+
+
+def test_batch_cg_workload_sizes():
+    """The batched workload's own lattice sizes (8^4, 12^4, 16^4, 16^3x32) and
+    parameter draws, two problems of each, in one batched FP32 solve with FP64
+    reliable updates: every FP64 true residual recomputed by the oracle."""
+    H = _hisq()
+    ws = synth.batch_workload(nper=16)
+    pick = [ws[k] for k in (0, 5, 16, 21, 32, 37, 48, 53)]
+    lats, bs, links = [], [], []
+    for w in pick:
+        fat, lng = w.links()
+        L = H.Lattice(w.dims)
+        L.load_links(fat, lng)
+        L.prepare_links(1, 18)
+        lats.append(L)
+        links.append((fat, lng))
+        bs.append(w.sources()[0])
+    p = H.hisq_default_params(tol=1e-10, sloppy=1, flags=H.HISQ_USE_GRAPH)
+    xs, infos = H.hisq_batch_cg(lats, [w.mass for w in pick], bs, params=p)
+    for q, w in enumerate(pick):
+        assert infos[q]["converged"] == 1
+        assert oracle.true_residual(w.dims, *links[q], w.mass, bs[q], xs[q]) <= 1e-10, (q, w.dims, w.mass)
+    for L in lats:
+        L.close()

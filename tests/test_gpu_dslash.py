@@ -185,3 +185,23 @@ def test_dslash_long_extent_exact_division_path():
         ref = oracle.dslash_half(dims, fat, lng, 1, psi)
         assert _rel(out, ref) <= 1e-12, (dims, _rel(out, ref))
         lat.close()
+
+
+def test_dslash_32x32x32x32_beyond_cache():
+    """The 32^4 lattice the benchmark uses beyond the Infinity Cache (629 MB of
+    FP32 links per half-Dslash), FP32 recon-18 and FP16 recon-12, both
+    parities, every output against the oracle."""
+    H = _hisq()
+    dims = (32, 32, 32, 32)
+    fat, lng = synth.make_links(dims, 0.2, seed=1900)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    for par in (0, 1):
+        psi = synth.gaussian_even(dims, 1950 + par)
+        ref = oracle.dslash_half(dims, fat, lng, par, psi)
+        for p, r in [(1, 18), (2, 12)]:
+            lat.prepare_links(p, r)
+            out = np.zeros_like(psi)
+            lat.dslash(par, p, r, psi, out)
+            assert _rel(out, ref) <= TOL[p], (par, p, r, _rel(out, ref))
+    lat.close()
