@@ -66,6 +66,8 @@ void SolveSet::release()
     if (dst) (void)hipFree(dst);
     if (hst) (void)hipHostFree(hst);
     if (dpart) (void)hipFree(dpart);
+    if (dred) (void)hipFree(dred);
+    dred = nullptr;
     ddesc = nullptr;
     dt2p = nullptr;
     dst = nullptr;

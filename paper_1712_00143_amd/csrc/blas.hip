@@ -65,7 +65,22 @@ __global__ void __launch_bounds__(192) k_blas(BlasLaunch a)
     const int prob = a.tile2prob ? a.tile2prob[tile] : 0;
     const ProbDesc &pd = a.probs[prob];
     SolveState *st_ = a.states ? &a.states[prob] : nullptr;
-    if (st_ && st_->status != a.want) return;
+    const bool lead = tile == pd.tile_begin && threadIdx.x == 0;   // writes the problem's state
+    if constexpr (OP == BL_RUPDATE_F) {
+        // the state this iteration starts from, for BL_PUPDATE_F to read while
+        // its leading block writes the new one
+        if (lead) {
+            st_->snap_status = st_->status;
+            st_->snap_rr = st_->rr;
+            st_->snap_maxrr = st_->maxrr;
+            st_->snap_iter = st_->iter;
+        }
+        if (st_->status != ST_RUNNING) return;
+    } else if constexpr (OP == BL_PUPDATE_F) {
+        if (st_->snap_status != ST_RUNNING) return;
+    } else {
+        if (st_ && st_->status != a.want) return;
+    }
     const int e = threadIdx.x;
     const long long site0 = (long long)(tile - pd.tile_begin) * TILE;
     const bool ok = site0 * 3 + e < (long long)pd.h * 3;
@@ -84,6 +99,62 @@ __global__ void __launch_bounds__(192) k_blas(BlasLaunch a)
             st<R>(a.v[2], nullptr, f, make_double2(xr, xi), true, lds);
             part = (double)rr * (double)rr + (double)ri * (double)ri;
         }
+    } else if constexpr (OP == BL_RUPDATE_F) {
+        // alpha = rr / (p, Ap) from the compact tile sums of the AX Dslash
+        // (FP64, the same order in every block), then the update of BL_RUPDATE
+        const double pap = block_total(a.red, pd.tile_begin, pd.ntile);
+        if (!(pap > 0.0) || !isfinite(pap)) {
+            if (lead) {
+                st_->pAp = pap;
+                st_->alpha = 0.0;
+                st_->status = ST_BREAKDOWN;
+                st_->snap_status = ST_BREAKDOWN;
+            }
+            return;
+        }
+        const double al = st_->rr / pap;
+        if (lead) {
+            st_->pAp = pap;
+            st_->alpha = al;
+        }
+        if (ok) {
+            double2 r = ld<R>(a.v[0], a.n[0], f), q = ld<R>(a.v[1], a.n[1], f);
+            double2 x = ld<R>(a.v[2], a.n[2], f), p = ld<P>(a.v[3], a.n[3], f);
+            R rr = (R)r.x - (R)al * (R)q.x, ri = (R)r.y - (R)al * (R)q.y;
+            R xr = (R)x.x + (R)al * (R)p.x, xi = (R)x.y + (R)al * (R)p.y;
+            st<R>(a.v[0], nullptr, f, make_double2(rr, ri), true, lds);
+            st<R>(a.v[2], nullptr, f, make_double2(xr, xi), true, lds);
+            part = (double)rr * (double)rr + (double)ri * (double)ri;
+        }
+        publish_compact(part, a.red + a.ntot, tile);
+        return;
+    } else if constexpr (OP == BL_PUPDATE_F) {
+        // the scalar recurrence of the beta finisher, from the snapshot: every
+        // block decides the same way, the leading block records it
+        const double rn = block_total(a.red + a.ntot, pd.tile_begin, pd.ntile);
+        const int iter1 = st_->snap_iter + 1;
+        const double maxrr1 = rn > st_->snap_maxrr ? rn : st_->snap_maxrr;
+        const double be = rn / st_->snap_rr;
+        int stat1 = ST_RUNNING;
+        if (!isfinite(rn)) stat1 = ST_BREAKDOWN;
+        else if (rn <= st_->tol2 * st_->bb || rn < st_->delta2 * maxrr1 || iter1 >= st_->maxiter) stat1 = ST_RELIABLE;
+        if (lead) {
+            st_->iter = iter1;
+            st_->beta = be;
+            st_->rr_old = st_->snap_rr;
+            st_->rr = rn;
+            st_->maxrr = maxrr1;
+            st_->status = stat1;
+        }
+        if (stat1 != ST_RUNNING) return;   // uniform over the block
+        double2 r = make_double2(0, 0), p = make_double2(0, 0);
+        if (ok) {
+            r = ld<R>(a.v[0], a.n[0], f);
+            p = ld<P>(a.v[3], a.n[3], f);
+        }
+        R pr = (R)r.x + (R)be * (R)p.x, pi = (R)r.y + (R)be * (R)p.y;
+        st<P>(a.v[3], a.n[3], f, make_double2(pr, pi), ok, lds);
+        return;
     } else if constexpr (OP == BL_PUPDATE || OP == BL_RESUME) {
         // PUPDATE: v0 = r (R), v3 = p (P): p = r + beta p
         // RESUME:  v4 = r_hi (FP64) -> v0 = r (R); p = r + beta p
@@ -313,6 +384,8 @@ static hipError_t launch_m(int op, const BlasLaunch &a, int nt, hipStream_t s)
     case BL_COPY_D2F: hipLaunchKernelGGL((k_blas<M, BL_COPY_D2F>), g, b, 0, s, a); break;
     case BL_COPY_F2D: hipLaunchKernelGGL((k_blas<M, BL_COPY_F2D>), g, b, 0, s, a); break;
     case BL_START: hipLaunchKernelGGL((k_blas<M, BL_START>), g, b, 0, s, a); break;
+    case BL_RUPDATE_F: hipLaunchKernelGGL((k_blas<M, BL_RUPDATE_F>), g, b, 0, s, a); break;
+    case BL_PUPDATE_F: hipLaunchKernelGGL((k_blas<M, BL_PUPDATE_F>), g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -71,6 +71,7 @@ hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lat
         HIPCHK(lat0, hipMalloc(&S.dst, sizeof(SolveState) * n));
         HIPCHK(lat0, hipHostMalloc(&S.hst, sizeof(SolveState) * n, hipHostMallocDefault));
         HIPCHK(lat0, hipMalloc(&S.dpart, sizeof(double) * NPART * ntile));
+        HIPCHK(lat0, hipMalloc(&S.dred, sizeof(double) * 2 * ntile));
         HIPCHK(lat0, hipMemset(S.dst, 0, sizeof(SolveState) * n));
     }
     // the tile -> problem map depends on the order of the problems, not only
@@ -94,7 +95,7 @@ struct CgPlan {
 
 static hipError_t enqueue_dslash(SolveSet &S, const CgPlan &pl, int prec, int lslot, int out_par, int epi,
                                  int fin, int want, const DVec &in, DVec &out, const DVec *aux,
-                                 const double *bvec, int out_prec, hipStream_t s)
+                                 const double *bvec, int out_prec, hipStream_t s, double *red = nullptr)
 {
     DslashLaunch a;
     memset(&a, 0, sizeof a);
@@ -116,6 +117,7 @@ static hipError_t enqueue_dslash(SolveSet &S, const CgPlan &pl, int prec, int ls
     a.bvec = bvec;
     a.partials = S.dpart;
     a.fin = fin;
+    a.red = red;
     // the sloppy operator uses the tuned shape; the FP64 reliable-update
     // operator (slot 0: FP64 recon-18) uses the default FP64 shape
     const bool sloppy_op = lslot == pl.slot;
@@ -146,6 +148,8 @@ static hipError_t enqueue_blas(SolveSet &S, int op, int mode, int want, int fin,
     b.n[3] = S.p.n;
     b.v[4] = (op == BL_RESUME || op == BL_START) ? S.rhi.p : S.xhi.p;
     b.v[5] = S.b.p;
+    b.red = S.dred;
+    b.ntot = S.ntile;
     hipError_t e = launch_blas(op, mode, b, S.ntile, S.nprob, s);
     if (e != hipSuccess || fin == FIN_NONE) return e;
     return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, 1, S.nprob, s);
@@ -155,7 +159,8 @@ static hipError_t enqueue_blas(SolveSet &S, int op, int mode, int want, int fin,
 // multi-right-hand-side launch covers every problem, four per link read, so
 // the link stream is read once per four problems instead of once per problem.
 static hipError_t enqueue_dslash_shared(SolveSet &S, const CgPlan &pl, int out_par, int epi, int fin,
-                                        int want, const DVec &in, DVec &out, const DVec *aux, hipStream_t s)
+                                        int want, const DVec &in, DVec &out, const DVec *aux, hipStream_t s,
+                                        double *red = nullptr)
 {
     const int group = S.nprob < 4 ? S.nprob : 4;
     const TuneChoice &tc = pl.mrhs[group];
@@ -175,6 +180,7 @@ static hipError_t enqueue_dslash_shared(SolveSet &S, const CgPlan &pl, int out_p
     a.states = S.dst;
     a.epi = epi;
     a.want = want;
+    a.red = red;
     hipError_t e = launch_dslash_mrhs(pl.mode, pl.recon, group, tc.W, a, S.hdesc[0].ntile, s);
     if (e != hipSuccess || fin == FIN_NONE) return e;
     return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, 1, S.nprob, s);
@@ -226,6 +232,9 @@ static hipError_t enqueue_true_residual(SolveSet &S, const CgPlan &pl, int fin, 
     return enqueue_dslash(S, pl, 0, 0, 0, EPI_RES, fin, want, S.thi, S.rhi, &S.xhi, (const double *)S.b.p, 0, s);
 }
 
+// k CG iterations: t = D_oe p, Ap = diag p - D_eo t (p.Ap per tile, compact),
+// then the two fused vector kernels that carry the scalar recurrences
+// themselves (no separate finisher launches).
 static hipError_t enqueue_iters(SolveSet &S, const CgPlan &pl, int k, hipStream_t s)
 {
     const int ap_prec = pl.mode == 2 ? 1 : pl.mode;
@@ -236,19 +245,19 @@ static hipError_t enqueue_iters(SolveSet &S, const CgPlan &pl, int k, hipStream_
             if ((e = enqueue_dslash_shared(S, pl, 1, EPI_PLAIN, FIN_NONE, ST_RUNNING, S.p, S.t, nullptr, s)) !=
                 hipSuccess)
                 return e;
-            if ((e = enqueue_dslash_shared(S, pl, 0, EPI_AX, FIN_ALPHA, ST_RUNNING, S.t, S.Ap, &S.p, s)) !=
+            if ((e = enqueue_dslash_shared(S, pl, 0, EPI_AX, FIN_NONE, ST_RUNNING, S.t, S.Ap, &S.p, s, S.dred)) !=
                 hipSuccess)
                 return e;
         } else {
             if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 1, EPI_PLAIN, FIN_NONE, ST_RUNNING, S.p, S.t,
                                     nullptr, nullptr, pl.mode, s)) != hipSuccess)
                 return e;
-            if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 0, EPI_AX, FIN_ALPHA, ST_RUNNING, S.t, S.Ap,
-                                    &S.p, nullptr, ap_prec, s)) != hipSuccess)
+            if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 0, EPI_AX, FIN_NONE, ST_RUNNING, S.t, S.Ap,
+                                    &S.p, nullptr, ap_prec, s, S.dred)) != hipSuccess)
                 return e;
         }
-        if ((e = enqueue_blas(S, BL_RUPDATE, pl.mode, ST_RUNNING, FIN_BETA, s)) != hipSuccess) return e;
-        if ((e = enqueue_blas(S, BL_PUPDATE, pl.mode, ST_RUNNING, FIN_NONE, s)) != hipSuccess) return e;
+        if ((e = enqueue_blas(S, BL_RUPDATE_F, pl.mode, ST_RUNNING, FIN_NONE, s)) != hipSuccess) return e;
+        if ((e = enqueue_blas(S, BL_PUPDATE_F, pl.mode, ST_RUNNING, FIN_NONE, s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

@@ -157,7 +157,9 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
         }
     }
     if constexpr (EPI != EPI_PLAIN) {
-        if (a.fin != FIN_NONE) {
+        if (a.red) {
+            publish_compact(part, a.red, tile);
+        } else if (a.fin != FIN_NONE) {
             double mine[1] = {part};
             publish_partials<1>(mine, a.partials, tile);
         }

@@ -39,6 +39,7 @@ struct SolveSet {
     SolveState *dst = nullptr;
     SolveState *hst = nullptr;  // pinned host mirror
     double *dpart = nullptr;
+    double *dred = nullptr;     // compact per-tile sums of the fused CG step: [2][ntile]
     DVec b, xhi, rhi, thi, xlo, rlo, Ap, p, t;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;

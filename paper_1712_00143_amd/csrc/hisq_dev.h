@@ -75,6 +75,11 @@ struct SolveState {
     long long t_done;      // device clock when it converged
     int restarts;          // reliable updates that restarted p = r
     int pad;
+    // state at the start of the current CG iteration, copied by the fused
+    // r/x update so that the fused p update can read it while the leading
+    // block of each problem writes the new state
+    double snap_rr, snap_maxrr;
+    int snap_iter, snap_status;
 };
 
 // Multi-shift per (problem, rhs) recurrence state

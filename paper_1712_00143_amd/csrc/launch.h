@@ -24,6 +24,7 @@ struct DslashLaunch {
     double *partials;
     int fin;
     int pad;
+    double *red;            // non-null (AX/RES): block sum to red[tile] instead of partials
 };
 
 hipError_t launch_dslash(int prec, int recon, int out_prec, int epi, int W, const DslashLaunch &a,
@@ -49,6 +50,7 @@ struct MrhsLaunch {
     SolveState *states;     // per-rhs states (nrhs of them), nullptr: all active
     int epi;
     int want;
+    double *red;            // non-null: EPI_AX/RES sums to red[r * ntile + t] instead of partials
 };
 
 // group: right-hand sides per link read (1..4); the grid is
@@ -84,6 +86,9 @@ struct BlasLaunch {
     void *v[6];
     float *n[6];
     double coef;
+    double *red;   // fused CG ops: compact per-tile sums, [2][ntot]: p.Ap, then |r|^2
+    int ntot;      // tiles of the whole set
+    int pad;
 };
 enum : int {
     BL_RUPDATE = 0,   // r -= alpha Ap; x += alpha p; partial |r|^2; FIN_BETA
@@ -100,6 +105,10 @@ enum : int {
     BL_MS_UPDATE = 11,   // multi-shift: x_k += a_k p_k; p_k = z_k r + b_k p_k; p = r + beta p
     BL_MS_INIT = 12,     // multi-shift: r = p = b (FP32); p_k = b; x_k = 0; partial |b|^2
     BL_STATUS_MS = 13,   // MS_LAST -> CONVERGED (one thread per problem)
+    // The CG update with its finishers folded in: every block sums its
+    // problem's compact tile sums itself (same order, same bits in every block).
+    BL_RUPDATE_F = 14,   // snapshot the state; alpha = rr / sum(p.Ap); r -= alpha Ap; x += alpha p; |r|^2 to red
+    BL_PUPDATE_F = 15,   // beta, convergence and reliable trigger from the snapshot; new state; p = r + beta p
 };
 // vector roles for the multi-shift ops: v0 = r, v1 = Ap, v3 = p, v5 = b (FP64),
 // v2 = x_k base, v4 = p_k base ([rhs][shift][h][3] FP32); ms = per-rhs ShiftState

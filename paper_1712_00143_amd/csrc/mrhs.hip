@@ -203,8 +203,11 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
         block_sum<NR>(part, lds);
         if (threadIdx.x == 0) {
             const int ntile = pd.ntile;
-            for (int j = 0; j < NR; j++)
-                if (r0 + j < a.nrhs) a.partials[((size_t)(r0 + j) * ntile + tile) * NPART] = part[j];
+            for (int j = 0; j < NR; j++) {
+                if (r0 + j >= a.nrhs) continue;
+                if (a.red) a.red[(size_t)(r0 + j) * ntile + tile] = part[j];
+                else a.partials[((size_t)(r0 + j) * ntile + tile) * NPART] = part[j];
+            }
         }
     }
 }

@@ -44,4 +44,29 @@ __device__ __forceinline__ void publish_partials(double mine[NV], double *partia
         for (int k = 0; k < NV; k++) partials[(size_t)tile * NPART + k] = mine[k];
 }
 
+// One block-summed value per tile in a compact array (red[tile]), for kernels
+// whose consumers sum a problem's tiles themselves.
+__device__ __forceinline__ void publish_compact(double mine, double *red, int tile)
+{
+    __shared__ double lds[16];
+    double v[1] = {mine};
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) red[tile] = v[0];
+}
+
+// Sum of red[first .. first + n) in a fixed order (each thread a strided
+// subset, then the block sum), returned to every thread of the block.  Every
+// block that calls it for the same range gets the same bits.
+__device__ __forceinline__ double block_total(const double *red, int first, int n)
+{
+    __shared__ double lds[16];
+    __shared__ double tot;
+    double v[1] = {0.0};
+    for (int j = threadIdx.x; j < n; j += blockDim.x) v[0] += red[first + j];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) tot = v[0];
+    __syncthreads();
+    return tot;
+}
+
 }  // namespace hisq
