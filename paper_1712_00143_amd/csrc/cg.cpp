@@ -78,6 +78,8 @@ hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lat
     // on the totals compared above
     if (n > 1) HIPCHK(lat0, hipMemcpy(S.dt2p, t2p.data(), sizeof(int) * ntile, hipMemcpyHostToDevice));
     S.hdesc = hd;
+    S.max_ntile = 0;
+    for (const ProbDesc &d : hd) S.max_ntile = d.ntile > S.max_ntile ? d.ntile : S.max_ntile;
     S.one_lattice = n > 1;
     for (int k = 1; k < n; k++)
         if (lats[k] != lats[0]) S.one_lattice = false;
@@ -232,32 +234,49 @@ static hipError_t enqueue_true_residual(SolveSet &S, const CgPlan &pl, int fin, 
     return enqueue_dslash(S, pl, 0, 0, 0, EPI_RES, fin, want, S.thi, S.rhi, &S.xhi, (const double *)S.b.p, 0, s);
 }
 
-// k CG iterations: t = D_oe p, Ap = diag p - D_eo t (p.Ap per tile, compact),
-// then the two fused vector kernels that carry the scalar recurrences
-// themselves (no separate finisher launches).
+// Largest problem (in 64-site tiles) for which the vector kernels sum their
+// problem's tile sums themselves: every block reads ntile doubles, so the
+// redundant reads grow as ntile^2; beyond this a separate finisher launch is
+// the cheaper way (and a small share of an iteration that large).
+static constexpr int FUSE_MAX_TILES = 1024;
+
+static bool fused_step(const SolveSet &S) { return S.max_ntile <= FUSE_MAX_TILES; }
+
+// k CG iterations: t = D_oe p, Ap = diag p - D_eo t with p.Ap per tile, then
+// the r/x and p updates.  Fused (problems up to FUSE_MAX_TILES tiles): the
+// two vector kernels carry the scalar recurrences themselves from compact
+// tile sums; otherwise finisher launches compute alpha and beta in between.
 static hipError_t enqueue_iters(SolveSet &S, const CgPlan &pl, int k, hipStream_t s)
 {
     const int ap_prec = pl.mode == 2 ? 1 : pl.mode;
     const bool shared = S.one_lattice && pl.mode == 1;
+    const bool fused = fused_step(S);
+    double *red = fused ? S.dred : nullptr;
+    const int fin_a = fused ? FIN_NONE : FIN_ALPHA;
     for (int j = 0; j < k; j++) {
         hipError_t e;
         if (shared) {
             if ((e = enqueue_dslash_shared(S, pl, 1, EPI_PLAIN, FIN_NONE, ST_RUNNING, S.p, S.t, nullptr, s)) !=
                 hipSuccess)
                 return e;
-            if ((e = enqueue_dslash_shared(S, pl, 0, EPI_AX, FIN_NONE, ST_RUNNING, S.t, S.Ap, &S.p, s, S.dred)) !=
+            if ((e = enqueue_dslash_shared(S, pl, 0, EPI_AX, fin_a, ST_RUNNING, S.t, S.Ap, &S.p, s, red)) !=
                 hipSuccess)
                 return e;
         } else {
             if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 1, EPI_PLAIN, FIN_NONE, ST_RUNNING, S.p, S.t,
                                     nullptr, nullptr, pl.mode, s)) != hipSuccess)
                 return e;
-            if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 0, EPI_AX, FIN_NONE, ST_RUNNING, S.t, S.Ap,
-                                    &S.p, nullptr, ap_prec, s, S.dred)) != hipSuccess)
+            if ((e = enqueue_dslash(S, pl, pl.mode, pl.slot, 0, EPI_AX, fin_a, ST_RUNNING, S.t, S.Ap,
+                                    &S.p, nullptr, ap_prec, s, red)) != hipSuccess)
                 return e;
         }
-        if ((e = enqueue_blas(S, BL_RUPDATE_F, pl.mode, ST_RUNNING, FIN_NONE, s)) != hipSuccess) return e;
-        if ((e = enqueue_blas(S, BL_PUPDATE_F, pl.mode, ST_RUNNING, FIN_NONE, s)) != hipSuccess) return e;
+        if (fused) {
+            if ((e = enqueue_blas(S, BL_RUPDATE_F, pl.mode, ST_RUNNING, FIN_NONE, s)) != hipSuccess) return e;
+            if ((e = enqueue_blas(S, BL_PUPDATE_F, pl.mode, ST_RUNNING, FIN_NONE, s)) != hipSuccess) return e;
+        } else {
+            if ((e = enqueue_blas(S, BL_RUPDATE, pl.mode, ST_RUNNING, FIN_BETA, s)) != hipSuccess) return e;
+            if ((e = enqueue_blas(S, BL_PUPDATE, pl.mode, ST_RUNNING, FIN_NONE, s)) != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -370,7 +389,7 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
         std::ostringstream ks;
         ks << mode << ":" << recon << ":" << tc.W << ":" << tc.remap << ":" << kchunk << ":" << S.one_lattice;
         for (int nr = 1; nr <= 4; nr++) ks << ":" << pl.mrhs[nr].W << pl.mrhs[nr].remap;
-        ks << ":" << pl.group64 << pl.mrhs64.W << pl.mrhs64.remap;
+        ks << ":" << pl.group64 << pl.mrhs64.W << pl.mrhs64.remap << ":" << fused_step(S);
         if (S.gkey != ks.str() || !S.gexec) {
             if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
             if (S.graph) (void)hipGraphDestroy(S.graph);

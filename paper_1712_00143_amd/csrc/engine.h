@@ -33,6 +33,7 @@ struct SolveSet {
     long long nsite = 0;
     int mode = -1;
     bool one_lattice = false;   // nprob > 1 problems on the same handle: vectors at q * h
+    int max_ntile = 0;          // tiles of the largest problem
     std::vector<ProbDesc> hdesc;
     ProbDesc *ddesc = nullptr;
     int *dt2p = nullptr;        // nullptr when nprob == 1

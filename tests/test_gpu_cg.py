@@ -262,3 +262,22 @@ def test_batch_cg_workload_sizes():
         assert oracle.true_residual(w.dims, *links[q], w.mass, bs[q], xs[q]) <= 1e-10, (q, w.dims, w.mass)
     for L in lats:
         L.close()
+
+
+@pytest.mark.parametrize("sloppy,recon", [(0, 18), (1, 18), (2, 12)])
+def test_cg_above_fused_step_size(sloppy, recon):
+    """16^3x40 has 1280 tiles per parity, above the size where the vector
+    kernels sum the tile partials themselves: the iteration takes the
+    finisher path, and must reach the same FP64 true residual."""
+    H = _hisq()
+    dims = (16, 16, 16, 40)
+    fat, lng = synth.make_links(dims, 0.2, seed=71)
+    b = synth.gaussian_even(dims, 72)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(sloppy, recon)
+    x, info = lat.cg(0.05, b, params=H.hisq_default_params(tol=1e-10, sloppy=sloppy, recon=recon,
+                                                           flags=H.HISQ_USE_GRAPH))
+    assert info["converged"] == 1
+    assert oracle.true_residual(dims, fat, lng, 0.05, b, x) <= 1e-10
+    lat.close()
