@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(192) k_blas(BlasLaunch a)
 
 // One block per problem: fixed-order sum of the problem's tile partials, then
 // the finisher (FP64 scalar recurrences) on the totals.
-__global__ void __launch_bounds__(256) k_finish(const ProbDesc *probs, SolveState *states, const double *partials,
+__global__ void __launch_bounds__(1024) k_finish(const ProbDesc *probs, SolveState *states, const double *partials,
                                                 int fin, int want, int nv, ShiftState *ms)
 {
     __shared__ double lds[16 * NPART];
@@ -240,7 +240,8 @@ __global__ void __launch_bounds__(256) k_finish(const ProbDesc *probs, SolveStat
 hipError_t launch_finish(const ProbDesc *probs, SolveState *states, const double *partials, int fin, int want,
                          int nv, int nprob, hipStream_t s, ShiftState *ms)
 {
-    hipLaunchKernelGGL(k_finish, dim3(nprob), dim3(256), 0, s, probs, states, partials, fin, want, nv, ms);
+    // 1024 threads: a large problem's tile partials (thousands) in few loads per thread
+    hipLaunchKernelGGL(k_finish, dim3(nprob), dim3(1024), 0, s, probs, states, partials, fin, want, nv, ms);
     return hipGetLastError();
 }
 
