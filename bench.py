@@ -162,9 +162,11 @@ def solve_timed(torch, stream, fn):
 
 
 def train_preconditioner(H, synth, dims, eps, mass, seed0, nfield, nsrc, steps, chans=(1, 4, 4, 1),
-                         every=10, maxpairs=60, batch=8, lr=3e-3):
+                         every=10, maxpairs=60, batch=8, lr=3e-3, init="poly"):
     """Harvest (residual, error) pairs with the solver on nfield seeded fields
-    and train the network on the GPU.  Returns (net, lattices, seconds, losses)."""
+    and train the network on the GPU, starting from the polynomial weights
+    (init "poly") or small random ones ("random").  Returns (net, lattices,
+    seconds, losses)."""
     t0 = time.perf_counter()
     lats, net = [], None
     for j in range(nfield):
@@ -175,9 +177,13 @@ def train_preconditioner(H, synth, dims, eps, mass, seed0, nfield, nsrc, steps, 
         lats.append(L)
         if net is None:
             net = H.PTC(L, chans)
-            rng = np.random.default_rng(seed0)
-            net.set_weights([0.05 * (rng.standard_normal((b, a, 9)) + 1j * rng.standard_normal((b, a, 9)))
-                             for a, b in zip(chans[:-1], chans[1:])])
+            if init == "poly":
+                lam = net.init_polynomial(a=4.0, c=1.2)
+                log(f"polynomial start: lambda_max(-D_f^2) ~ {lam:.4f}")
+            else:
+                rng = np.random.default_rng(seed0)
+                net.set_weights([0.05 * (rng.standard_normal((b, a, 9)) + 1j * rng.standard_normal((b, a, 9)))
+                                 for a, b in zip(chans[:-1], chans[1:])])
         for s in range(nsrc):
             net.harvest(L, mass, synth.gaussian_even(dims, seed0 + j + 500 + 100 * s), every=every,
                         maxpairs=maxpairs)
@@ -220,10 +226,8 @@ def run_headline(args):
     if not args.no_learned and not args.dslash_only:
         # trained outside the timed region, on pairs from two other sources
         net = H.PTC(lat, (1, 4, 4, 1))
-        rng = np.random.default_rng(1)
-        net.set_weights([0.05 * (rng.standard_normal((bb, a, 9)) + 1j * rng.standard_normal((bb, a, 9)))
-                         for a, bb in zip((1, 4, 4), (4, 4, 1))])
         t0 = time.perf_counter()
+        net.init_polynomial(a=4.0, c=1.2)
         srcs = w.sources()
         npair = sum(net.harvest(lat, w.mass, srcs[k], every=20, maxpairs=60) for k in (1, 2))
         losses = net.train(300, batch=8, lr=3e-3, seed=1)
@@ -465,7 +469,8 @@ def run_c4(args):
     w = synth.C4
     net, tl, t_train, losses = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, args.nfield,
                                                     args.nsrc, args.train_steps)
-    res = {"plain_f64": [], "mixed_f32": [], "mixed_f16_r12": [], "learned_fcg": [], "untrained_fcg": []}
+    res = {"plain_f64": [], "mixed_f32": [], "mixed_f16_r12": [], "learned_fcg": [], "untrained_fcg": [],
+           "poly_fcg": [], "poly_fcg_121": []}
     untrained = None
     for j in range(args.nheld):
         fat, lng = synth.make_links(w.dims, w.eps, seed=4900 + j)
@@ -475,6 +480,12 @@ def run_c4(args):
         L.prepare_links(2, 12)
         if untrained is None:
             untrained = H.PTC(L, (1, 4, 4, 1))
+        # the polynomial start alone, on this field's own spectrum estimate
+        # (set up outside the timed solves)
+        poly = H.PTC(L, (1, 4, 4, 1))
+        poly.init_polynomial(a=4.0, c=1.2)
+        poly2 = H.PTC(L, (1, 2, 1))
+        poly2.init_polynomial(a=4.0, c=1.2)
         for s in range(2):
             b = synth.gaussian_even(w.dims, 5400 + 10 * j + s)
             for name, fn in (
@@ -482,10 +493,14 @@ def run_c4(args):
                     ("mixed_f32", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("mixed_f16_r12", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH))),
                     ("learned_fcg", lambda: net.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1))),
-                    ("untrained_fcg", lambda: untrained.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1)))):
+                    ("untrained_fcg", lambda: untrained.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1))),
+                    ("poly_fcg", lambda: poly.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1))),
+                    ("poly_fcg_121", lambda: poly2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1)))):
                 (_, info), dt = solve_timed(torch, None, fn)
                 res[name].append((info["iters"], dt, info["true_residual"], info.get("fell_back", 0)))
             log(f"held-out field {j}, source {s}: " + ", ".join(f"{k} {v[-1][0]} it {v[-1][1]:.3f}s" for k, v in res.items()))
+        poly.close()
+        poly2.close()
         L.close()
     summ = {k: {"iters_mean": round(float(np.mean([r[0] for r in v])), 1),
                 "time_s_mean": round(float(np.mean([r[1] for r in v])), 5),
@@ -494,6 +509,7 @@ def run_c4(args):
     print(json.dumps({
         "workload": f"learned PTC preconditioner 16^4, eps 0.25, m 0.005: trained on {args.nfield} fields x {args.nsrc} sources, tested on {args.nheld} held-out fields x 2 sources",
         "training": {"seconds": t_train, "steps": args.train_steps,
+                     "start": "polynomial K = 4 (1 + 1.2 D_f^2 / lambda), lambda from the first training field",
                      "what": "harvest_s: synthetic fields generated on the host, loaded, and plain CG to 1e-12 per source; "
                              "train_s: the Adam steps on the GPU",
                      "loss_first10": round(float(losses[:10].mean()), 4),

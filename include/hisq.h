@@ -197,6 +197,22 @@ hisq_status hisq_ptc_destroy(hisq_ptc net);
  * FP32 master copy and the FP16 inference copy. */
 hisq_status hisq_ptc_set_weights(hisq_ptc net, const double *w);
 hisq_status hisq_ptc_get_weights(hisq_ptc net, double *w);
+/* Polynomial starting weights (a starting point for training, or a
+ * preconditioner of its own): K = a (1 + c D_f^2 / lambda) on even vectors,
+ * with D_f the one-hop fat-link part of D (the PTC transports with weights
+ * +1 forward, -1 backward).  On an eigenvector of -D_f^2 with eigenvalue t,
+ * M = 1 + a^2 (1 - c t/lambda)^2: the low modes of A are enlarged up to
+ * 1 + a^2 times against the upper spectrum (c slightly above 1 puts the zero
+ * of K inside the spectrum, which lowers the condition number further;
+ * c = 1.2 is a good choice on the fields tested).  lambda, the largest
+ * eigenvalue of -D_f^2 on even sites, is estimated with `iters` power
+ * iterations on D_f^4 (FP32 transports, a fixed seeded start vector) and
+ * returned in *lambda (may be NULL).  Needs >= 2 layers and >= 2 channels
+ * after every layer but the last; all other weights are zero.  Adam state is
+ * reset.  Errors: HISQ_ERR_ARG (a <= 0, c outside (0, 4], iters outside
+ * [1, 1000], a network too small), HISQ_ERR_STATE (no links),
+ * HISQ_ERR_BREAKDOWN (no positive spectrum estimate). */
+hisq_status hisq_ptc_init_polynomial(hisq_ptc net, double a, double c, int iters, double *lambda);
 /* One layer on device FP32 activations (layout above, HISQ_DEVICE_PTR
  * required): forward out = L_l(in); backward gin = L_l^+(gout) (gin may be
  * NULL) and gw = sum_x (T_k in)^+ gout (complex FP64 [Cout][Cin][9], host). */

@@ -354,6 +354,122 @@ hisq_status hisq_ptc_get_weights(hisq_ptc n, double *w)
     return HISQ_OK;
 }
 
+// Polynomial starting point.  With D_f the one-hop (fat-link) part of D, the
+// stack is set to K = a (1 + D_f^2 / lambda): the first layer copies r into
+// channel 0 and D_f r into channel 1, the next hop layer applies D_f to
+// channel 1 once more, any further layers pass both channels through, and the
+// last layer sums a * ch0 + (a c / lambda) * ch1, i.e. K = a (1 + c D_f^2 /
+// lambda).  D_f is anti-Hermitian, so on an eigenvector of -D_f^2 with
+// eigenvalue t the preconditioner is M = 1 + a^2 (1 - c t / lambda)^2: the
+// low modes, which set the condition number of A, are enlarged up to 1 + a^2
+// times against the upper part of the spectrum.  lambda, the largest eigenvalue of -D_f^2 on even sites, is
+// estimated by power iteration on D_f^4 (a two-layer K = D_f^2 network, so
+// that M - 1 = D_f^4), with FP32 transports.
+hisq_status hisq_ptc_init_polynomial(hisq_ptc n, double a, double c, int iters, double *lambda)
+{
+    if (!n) return HISQ_ERR_ARG;
+    hisq_lattice lat = n->lat;
+    if (!(a > 0.0) || !std::isfinite(a) || !(c > 0.0) || !(c <= 4.0) || iters < 1 || iters > 1000)
+        return set_err(lat, HISQ_ERR_ARG, "polynomial start: a > 0, 0 < c <= 4 and 1 <= iters <= 1000 required");
+    if (n->nlayer < 2) return set_err(lat, HISQ_ERR_ARG, "polynomial start needs at least two layers");
+    for (int l = 1; l < n->nlayer; l++)
+        if (n->chans[l] < 2) return set_err(lat, HISQ_ERR_ARG, "polynomial start needs two inner channels");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    hisq_status st = ensure_fp32_links(lat);
+    if (st != HISQ_OK) return st;
+
+    // one hop: weight +1 on the forward paths, -1 on the backward ones
+    auto hop = [](double *w9) {
+        for (int mu = 0; mu < 4; mu++) {
+            w9[2 * (1 + 2 * mu)] = 1.0;
+            w9[2 * (2 + 2 * mu)] = -1.0;
+        }
+    };
+
+    // power iteration
+    const long long h = lat->h, nf = h * 6;
+    hisq_ptc t = nullptr;
+    const int tch[3] = {1, 1, 1};
+    st = hisq_ptc_create(lat, 2, tch, &t);
+    if (st != HISQ_OK) return st;
+    std::vector<double> tw(2 * t->nw, 0.0);
+    hop(&tw[0]);
+    hop(&tw[18]);
+    float *dv = nullptr;
+    double lam2 = 0.0;
+    st = hisq_ptc_set_weights(t, tw.data());
+    if (st == HISQ_OK && hipMalloc(&dv, sizeof(float) * 2 * nf) != hipSuccess)
+        st = set_err(lat, HISQ_ERR_OOM, "polynomial start: vector allocation failed");
+    if (st == HISQ_OK) {
+        std::vector<float> v(nf), z(nf);
+        std::mt19937_64 gen(0x9e3779b97f4a7c15ull);
+        std::normal_distribution<float> nd(0.f, 1.f);
+        for (auto &x : v) x = nd(gen);
+        for (int it = 0; it < iters && st == HISQ_OK; it++) {
+            double vv = 0.0, vz = 0.0;
+            for (long long j = 0; j < nf; j++) vv += (double)v[j] * v[j];
+            if (!(vv > 0.0)) {
+                st = set_err(lat, HISQ_ERR_BREAKDOWN, "polynomial start: power iteration reached zero");
+                break;
+            }
+            hipError_t e = hipMemcpy(dv, v.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = ptc_apply_internal(t, lat, 2, 1, 18, dv, dv + nf);
+            if (e == hipSuccess) e = hipStreamSynchronize(lat->s);
+            if (e == hipSuccess) e = hipMemcpy(z.data(), dv + nf, sizeof(float) * nf, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                st = hip_err(lat, e, "polynomial start power iteration");
+                break;
+            }
+            // M v - v = D_f^4 v; Re<v, D_f^4 v> is the Rayleigh quotient's numerator
+            const double inv = 1.0 / std::sqrt(vv);
+            for (long long j = 0; j < nf; j++) {
+                const double d = (double)z[j] - (double)v[j];
+                vz += (double)v[j] * d;
+                z[j] = (float)(d * inv);
+            }
+            lam2 = vz / vv;
+            v.swap(z);
+        }
+    }
+    if (dv) (void)hipFree(dv);
+    hisq_ptc_destroy(t);
+    if (st != HISQ_OK) return st;
+    if (!(lam2 > 0.0) || !std::isfinite(lam2))
+        return set_err(lat, HISQ_ERR_BREAKDOWN, "polynomial start: no positive spectrum estimate");
+    const double lam = std::sqrt(lam2);
+
+    std::vector<double> w(2 * n->nw, 0.0);
+    for (int l = 0; l < n->nlayer; l++) {
+        const int ci = n->chans[l], co = n->chans[l + 1];
+        double *wl = &w[2 * n->woff[l]];
+        auto at = [&](int c, int cp) { return wl + 2 * 9 * (c * ci + cp); };
+        const bool last = l == n->nlayer - 1;
+        if (l == 0) {
+            at(0, 0)[0] = 1.0;
+            hop(at(1, 0));
+        } else if (!last) {
+            at(0, 0)[0] = 1.0;
+            if (l == 1) hop(at(1, 1));
+            else at(1, 1)[0] = 1.0;
+        }
+        if (last) {
+            at(0, 0)[0] = a;
+            if (l == 1) {
+                // two layers: the second hop is taken here
+                double *p = at(0, 1);
+                hop(p);
+                for (int k = 0; k < 18; k++) p[k] *= a * c / lam;
+            } else {
+                at(0, 1)[0] = a * c / lam;
+            }
+        }
+    }
+    st = hisq_ptc_set_weights(n, w.data());
+    if (st != HISQ_OK) return st;
+    if (lambda) *lambda = lam;
+    return HISQ_OK;
+}
+
 hisq_status hisq_ptc_layer_forward(hisq_ptc n, int layer, const void *in, void *out, int flags)
 {
     if (!n || !in || !out || layer < 0 || layer >= n->nlayer) return HISQ_ERR_ARG;

@@ -37,7 +37,7 @@ EXPORTS = [
     "hisq_batch_cg", "hisq_ptc_create", "hisq_ptc_destroy", "hisq_ptc_set_weights",
     "hisq_ptc_get_weights", "hisq_ptc_layer_forward", "hisq_ptc_layer_backward", "hisq_ptc_apply",
     "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
-    "hisq_stream_bandwidth",
+    "hisq_stream_bandwidth", "hisq_ptc_init_polynomial",
 ]
 
 
@@ -285,6 +285,15 @@ class PTC:
         assert flat.size == self.nw
         self._err(lib().hisq_ptc_set_weights(self.handle, flat.ctypes.data_as(ctypes.c_void_p)),
                   "hisq_ptc_set_weights")
+
+    def init_polynomial(self, a=4.0, c=1.2, iters=30):
+        """K = a (1 + c D_f^2 / lambda): the polynomial starting point; returns
+        the estimated top eigenvalue lambda of -D_f^2 on even sites."""
+        lam = ctypes.c_double(0.0)
+        self._err(lib().hisq_ptc_init_polynomial(self.handle, ctypes.c_double(a), ctypes.c_double(c),
+                                                  ctypes.c_int(iters),
+                                                  ctypes.byref(lam)), "hisq_ptc_init_polynomial")
+        return lam.value
 
     def get_weights(self):
         flat = np.zeros(self.nw, dtype=np.complex128)

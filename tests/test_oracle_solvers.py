@@ -241,3 +241,47 @@ def test_adam_first_step_closed_form():
     for t in range(1, 20):
         q, m, v = oracle.adam_step(q, g, m, v, t, lr=1e-3)
     assert np.allclose(q, p - 19e-3 * np.sign(g), atol=1e-9)
+
+
+def _poly_weights(chans, a, lam):
+    """K = a (1 + D_f^2 / lam): r and D_f r in channels 0 and 1, one more hop
+    on channel 1, then a * ch0 + (a / lam) * ch1 (the last layer takes the
+    second hop itself when there are only two layers)."""
+    hop = np.zeros(9, complex)
+    hop[1::2], hop[2::2] = 1.0, -1.0
+    ws = []
+    n = len(chans) - 1
+    for l, (ci, co) in enumerate(zip(chans[:-1], chans[1:])):
+        w = np.zeros((co, ci, 9), complex)
+        if l == 0:
+            w[0, 0, 0] = 1.0
+            w[1, 0] = hop
+        elif l < n - 1:
+            w[0, 0, 0] = 1.0
+            w[1, 1] = hop if l == 1 else np.eye(1, 9, 0)[0]
+        if l == n - 1:
+            w[0, 0, 0] = a
+            w[0, 1] = hop * (a / lam) if l == 1 else np.eye(1, 9, 0)[0] * (a / lam)
+        ws.append(w)
+    return ws
+
+
+@pytest.mark.parametrize("chans", [(1, 4, 4, 1), (1, 2, 1), (1, 2, 2, 2, 1)])
+def test_ptc_polynomial_weights_free_field_closed_form(chans):
+    """Free field: D_f^2 = sum_mu nabla_mu^2 with nabla = T - T^-1, so an
+    even-site plane wave of momentum p is an eigenvector of -D_f^2 with
+    t = 4 sum_mu sin^2 p_mu, and the network with the polynomial weights gives
+    M = 1 + a^2 (1 - t / lam)^2 on it."""
+    dims = (4, 6, 4, 8)
+    fat, _ = synth.unit_links(dims)
+    x = synth.coords(dims)[synth.even_sites(dims)]
+    chi = np.array([0.3 - 0.2j, 1.0, -0.5j])
+    a, lam = 3.0, 16.0
+    ws = _poly_weights(chans, a, lam)
+    for n in [(1, 2, 1, 3), (0, 0, 0, 0), (2, 3, 2, 4), (1, 0, 3, 5)]:
+        p = 2 * np.pi * np.array(n) / np.array(dims)
+        v = np.exp(1j * (x @ p))[:, None] * chi[None, :]
+        t = 4 * np.sum(np.sin(p) ** 2)
+        z = oracle.ptc_apply(dims, fat, ws, v)
+        ref = (1.0 + a * a * (1.0 - t / lam) ** 2) * v
+        assert np.linalg.norm(z - ref) <= 1e-13 * np.linalg.norm(ref), (chans, n)
