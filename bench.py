@@ -247,7 +247,7 @@ def run_headline(args):
                 res["cg"][name] = info
             if net is not None:
                 xd = torch.zeros_like(bd)
-                prm = H.hisq_default_params(tol=1e-10, sloppy=1, recon=18)
+                prm = H.hisq_default_params(tol=1e-10, sloppy=1, recon=18, flags=H.HISQ_USE_GRAPH)
                 (_, info), dt = solve_timed(torch, stream, lambda: net.cg_learned(lat, w.mass, bd, x=xd, params=prm))
                 info["wall_s"] = dt
                 res["cg"]["learned_fcg_f32"] = info
@@ -492,10 +492,10 @@ def run_c4(args):
                     ("plain_f64", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=0, flags=H.HISQ_USE_GRAPH))),
                     ("mixed_f32", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("mixed_f16_r12", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH))),
-                    ("learned_fcg", lambda: net.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1))),
-                    ("untrained_fcg", lambda: untrained.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1))),
-                    ("poly_fcg", lambda: poly.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1))),
-                    ("poly_fcg_121", lambda: poly2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1)))):
+                    ("learned_fcg", lambda: net.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
+                    ("untrained_fcg", lambda: untrained.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
+                    ("poly_fcg", lambda: poly.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
+                    ("poly_fcg_121", lambda: poly2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH)))):
                 (_, info), dt = solve_timed(torch, None, fn)
                 res[name].append((info["iters"], dt, info["true_residual"], info.get("fell_back", 0)))
             log(f"held-out field {j}, source {s}: " + ", ".join(f"{k} {v[-1][0]} it {v[-1][1]:.3f}s" for k, v in res.items()))

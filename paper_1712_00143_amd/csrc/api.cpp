@@ -60,7 +60,9 @@ void SolveSet::release()
     gexec = nullptr;
     graph = nullptr;
     gkey.clear();
-    for (DVec *v : {&b, &xhi, &rhi, &thi, &xlo, &rlo, &Ap, &p, &t}) dvec_free(*v);
+    if (fred) (void)hipFree(fred);
+    fred = nullptr;
+    for (DVec *v : {&b, &xhi, &rhi, &thi, &xlo, &rlo, &Ap, &p, &t, &fz}) dvec_free(*v);
     if (ddesc) (void)hipFree(ddesc);
     if (dt2p) (void)hipFree(dt2p);
     if (dst) (void)hipFree(dst);
@@ -228,6 +230,7 @@ hisq_status hisq_destroy(hisq_lattice lat)
     lat->cg.release();
     lat->batch.release();
     lat->msref.release();
+    lat->fcg.release();
     for (auto &pp : lat->lk)
         for (auto &q : pp)
             if (q) (void)hipFree(q);

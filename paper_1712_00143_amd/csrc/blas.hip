@@ -75,7 +75,12 @@ __global__ void __launch_bounds__(192) k_blas(BlasLaunch a)
             st_->snap_maxrr = st_->maxrr;
             st_->snap_iter = st_->iter;
         }
-        if (st_->status != ST_RUNNING) return;
+        // the leading block may set a breakdown while other blocks start: one
+        // read per block keeps every thread of a block on the same path
+        __shared__ int s_status;
+        if (threadIdx.x == 0) s_status = st_->status;
+        __syncthreads();
+        if (s_status != ST_RUNNING) return;
     } else if constexpr (OP == BL_PUPDATE_F) {
         if (st_->snap_status != ST_RUNNING) return;
     } else {

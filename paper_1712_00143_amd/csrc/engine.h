@@ -45,6 +45,9 @@ struct SolveSet {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     std::string gkey;
+    // flexible CG: z = M(r) and the compact tile sums of its fused iteration
+    DVec fz;
+    double *fred = nullptr;
     ~SolveSet();
     void release();
 };
@@ -88,6 +91,7 @@ struct hisq_lattice_s {
     hisq::SolveSet cg;         // single-lattice solve workspace
     hisq::SolveSet batch;      // batched solves led by this handle
     hisq::SolveSet msref;      // multi-shift refinement (one problem per rhs x shift)
+    hisq::SolveSet fcg;        // flexible CG with the learned preconditioner
     hisq::DVec tmp_in, tmp_out, tmp64a, tmp64b;  // host-pointer Dslash staging
     hisq::ProbDesc *ddesc = nullptr;             // this lattice alone
     double *dpart = nullptr;

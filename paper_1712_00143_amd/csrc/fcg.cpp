@@ -11,7 +11,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <sstream>
+#include <string>
 
+#include "fcg_graph.h"
 #include "finish.h"
 #include "ptc.h"
 #include "solver.h"
@@ -25,7 +28,10 @@ using namespace hisq;
     } while (0)
 
 // defined in ptc.cpp
-hipError_t ptc_apply_internal(hisq_ptc n, hisq_lattice lat, int lslot, int prec, int recon, const float *r, float *z);
+hipError_t ptc_apply_internal(hisq_ptc n, hisq_lattice lat, int lslot, int prec, int recon, const float *r, float *z,
+                              const PtcFuse *fz);
+std::string ptc_graph_key(hisq_ptc n);
+FcgGraphCache &ptc_fcg_graph(hisq_ptc n);
 
 extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double mass, const double *b, double *x,
                                        const hisq_solver_params *params, hisq_solver_info *info)
@@ -57,19 +63,16 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
 
     std::vector<hisq_lattice> lats{lat};
     std::vector<double> ms{mass};
-    SolveSet &S = lat->cg;
+    SolveSet &S = lat->fcg;
     hisq_status st = build_set(lat, S, lats, ms, 0.0);
     if (st != HISQ_OK) return st;
     const long long h = lat->h;
     S.mode = -1;   // vectors below are FCG-specific
     for (DVec *v : {&S.b, &S.xhi, &S.rhi, &S.thi}) HIPCHK(lat, dvec_alloc(*v, 0, h));
-    for (DVec *v : {&S.xlo, &S.rlo, &S.Ap, &S.p, &S.t}) HIPCHK(lat, dvec_alloc(*v, 1, h));
-    DVec z;
-    HIPCHK(lat, dvec_alloc(z, 1, h));
-    struct ZG {
-        DVec &z;
-        ~ZG() { dvec_free(z); }
-    } zg{z};
+    for (DVec *v : {&S.xlo, &S.rlo, &S.Ap, &S.p, &S.t, &S.fz}) HIPCHK(lat, dvec_alloc(*v, 1, h));
+    if (!S.fred) HIPCHK(lat, hipMalloc(&S.fred, sizeof(double) * FRED_N * S.ntile));
+    DVec &z = S.fz;
+    const int nt = S.ntile;
     HIPCHK(lat, hipMemcpyAsync(S.b.p, b, (size_t)h * 48, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     SolveState &hs = S.hst[0];
     memset(&hs, 0, sizeof hs);
@@ -111,14 +114,17 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
         f.p = (float *)S.p.p;
         f.q = (float *)S.Ap.p;
         f.z = (float *)z.p;
+        f.red = S.fred;
+        f.nt = nt;
         hipError_t e = launch_fcg(f, S.ntile, s);
         if (e != hipSuccess || fin == FIN_NONE) return e;
         return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, nv, 1, s);
     };
     auto dslash = [&](int prec, int ls, int rc, int W, int par, int epi, int fin, int want, const DVec &in, DVec &out,
-                      const DVec *aux) -> hipError_t {
+                      const DVec *aux, double *red = nullptr) -> hipError_t {
         DslashLaunch a;
         memset(&a, 0, sizeof a);
+        a.red = red;
         a.probs = S.ddesc;
         a.remap = tc.remap;
         a.out_par = par;
@@ -135,24 +141,33 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
         if (e != hipSuccess || fin == FIN_NONE) return e;
         return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, 1, 1, s);
     };
-    auto precondition = [&]() -> hipError_t {
-        return ptc_apply_internal(net, lat, pslot, pprec, precon, (const float *)S.rlo.p, (float *)z.p);
+    // z = M(r); fused: gated on the status, with the (q, z) tile sums
+    auto precondition = [&](const PtcFuse *fz) -> hipError_t {
+        return ptc_apply_internal(net, lat, pslot, pprec, precon, (const float *)S.rlo.p, (float *)z.p, fz);
     };
-    auto iteration = [&](int want) -> hipError_t {
+    const PtcFuse fuse{S.dst, ST_RUNNING, (const float *)S.Ap.p, S.fred + FRED_QZ * nt, nt};
+    // one iteration, no finisher launches and no host decisions: q = A p with
+    // the (p, q) sums; alpha, x, r and the |r|^2 sums; z = M(r) with the (q, z)
+    // sums; the status decision, beta, p and the (p, r) sums
+    auto iteration = [&]() -> hipError_t {
         hipError_t e;
-        if ((e = dslash(1, slot, recon, tc.W, 1, EPI_PLAIN, FIN_NONE, want, S.p, S.t, nullptr)) != hipSuccess) return e;
-        if ((e = dslash(1, slot, recon, tc.W, 0, EPI_AX, FIN_NONE, want, S.t, S.Ap, &S.p)) != hipSuccess) return e;
-        if ((e = fcg(FCG_DOTS_A, want, FIN_FCG_ALPHA, 3)) != hipSuccess) return e;
-        if ((e = fcg(FCG_XR, want, FIN_FCG_R, 1)) != hipSuccess) return e;
-        if ((e = precondition()) != hipSuccess) return e;
-        if ((e = fcg(FCG_DOTS_B, want, FIN_FCG_BETA, 2)) != hipSuccess) return e;
-        return fcg(FCG_P, want, FIN_NONE, 0);
+        if ((e = dslash(1, slot, recon, tc.W, 1, EPI_PLAIN, FIN_NONE, ST_RUNNING, S.p, S.t, nullptr)) != hipSuccess)
+            return e;
+        if ((e = dslash(1, slot, recon, tc.W, 0, EPI_AX, FIN_NONE, ST_RUNNING, S.t, S.Ap, &S.p,
+                        S.fred + FRED_PQ * nt)) != hipSuccess)
+            return e;
+        if ((e = fcg(FCG_XR_F, ST_RUNNING, FIN_NONE, 0)) != hipSuccess) return e;
+        if ((e = precondition(&fuse)) != hipSuccess) return e;
+        return fcg(FCG_P_F, ST_RUNNING, FIN_NONE, 0);
     };
 
-    // r = b, x = 0, |b|^2; z = M(r); p = z
+    // r = b, x = 0, |b|^2; z = M(r); p = z; the (p, r) sums.  This first
+    // application also settles the layer kernels' launch shapes, before any
+    // capture.
     HIPCHK(lat, blas(BL_INIT, ST_RUNNING, FIN_NORM_B));
-    HIPCHK(lat, precondition());
+    HIPCHK(lat, precondition(nullptr));
     HIPCHK(lat, hipMemcpyAsync(S.p.p, z.p, (size_t)h * 24, hipMemcpyDeviceToDevice, s));
+    HIPCHK(lat, fcg(FCG_DOT_PR, ST_RUNNING, FIN_NONE, 0));
     HIPCHK(lat, hipMemcpyAsync(&hs, S.dst, sizeof hs, hipMemcpyDeviceToHost, s));
     HIPCHK(lat, hipStreamSynchronize(s));
     if (hs.bb == 0.0) {
@@ -166,9 +181,38 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
         return HISQ_OK;
     }
     const int kchunk = prm.check_every > 0 ? prm.check_every : 16;
+    const bool use_graph = (prm.flags & HISQ_USE_GRAPH) != 0;
+    if (use_graph) {
+        // every launch argument of the chunk: device pointers, shapes, formats
+        std::ostringstream ks;
+        ks << (const void *)lat << ":" << (const void *)lat->ddesc << ":" << S.p.p << ":" << S.t.p << ":" << S.Ap.p << ":" << S.rlo.p << ":" << S.xlo.p
+           << ":" << z.p << ":" << S.fred << ":" << S.dst << ":" << S.ddesc << ":" << S.dpart << ":" << nt << ":"
+           << slot << ":" << recon << ":" << tc.W << ":" << tc.remap << ":" << pslot << ":" << kchunk << ":"
+           << ptc_graph_key(net);
+        FcgGraphCache &G = ptc_fcg_graph(net);
+        if (G.key != ks.str() || !G.exec) {
+            G.release();
+            HIPCHK(lat, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t ce = hipSuccess;
+            for (int q = 0; q < kchunk && ce == hipSuccess; q++) ce = iteration();
+            hipGraph_t g = nullptr;
+            hipError_t ee = hipStreamEndCapture(s, &g);
+            if (ce != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_err(lat, ce, "flexible CG graph capture");
+            }
+            if (ee != hipSuccess) return hip_err(lat, ee, "hipStreamEndCapture");
+            G.graph = g;
+            HIPCHK(lat, hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0));
+            G.key = ks.str();
+        }
+    }
+    hipGraphExec_t gexec = use_graph ? ptc_fcg_graph(net).exec : nullptr;
     int fell_back = 0;
     for (;;) {
-        for (int q = 0; q < kchunk; q++) HIPCHK(lat, iteration(ST_RUNNING));
+        if (use_graph) HIPCHK(lat, hipGraphLaunch(gexec, s));
+        else
+            for (int q = 0; q < kchunk; q++) HIPCHK(lat, iteration());
         HIPCHK(lat, hipMemcpyAsync(&hs, S.dst, sizeof hs, hipMemcpyDeviceToHost, s));
         HIPCHK(lat, hipStreamSynchronize(s));
         if (hs.status == ST_RELIABLE) {
@@ -179,11 +223,13 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
             HIPCHK(lat, hipStreamSynchronize(s));
             if (hs.status == ST_RESUME) {
                 if (hs.iter >= hs.maxiter) break;
-                // continue from the true residual: r = r_hi, z = M(r), new direction
+                // continue from the true residual: r = r_hi, z = M(r), new
+                // direction, and the (p, r) sums of the next iteration
                 HIPCHK(lat, launch_convert(S.rhi.p, 0, S.rlo.p, 1, h * 3, s));
-                HIPCHK(lat, precondition());
+                HIPCHK(lat, precondition(nullptr));
                 HIPCHK(lat, fcg(FCG_DOTS_B, ST_RESUME, FIN_FCG_BETA, 2));
                 HIPCHK(lat, fcg(FCG_P, ST_RESUME, FIN_NONE, 0));
+                HIPCHK(lat, fcg(FCG_DOT_PR, ST_RESUME, FIN_NONE, 0));
                 HIPCHK(lat, blas(BL_STATUS, ST_RESUME, FIN_NONE));
                 HIPCHK(lat, hipMemcpyAsync(&hs, S.dst, sizeof hs, hipMemcpyDeviceToHost, s));
                 HIPCHK(lat, hipStreamSynchronize(s));

@@ -1,11 +1,20 @@
 // Flexible CG (truncation 1, Notay 2000) vector kernels, FP32 vectors with
-// complex FP64 scalars:
-//   DOTS_A: (p, q) and (p, r)        -> alpha = (p, r) / (p, q)
-//   XR:     x += alpha p, r -= alpha q, |r|^2
-//   DOTS_B: (q, z)                   -> beta = -(q, z) / (q, p)
-//   P:      p = z + beta p
-// with (a, b) = a^+ b.  beta makes the new direction A-orthogonal to the old
-// one; the preconditioner z = M(r) may be any (even non-Hermitian) map.
+// complex FP64 scalars, (a, b) = a^+ b:
+//   alpha = (p, r) / (p, q);  x += alpha p;  r -= alpha q;  z = M(r);
+//   beta = -(q, z) / (q, p);  p = z + beta p.
+// beta makes the new direction A-orthogonal to the old one; the
+// preconditioner may be any (even non-Hermitian) map.
+//
+// The iteration needs no finisher launch: the AX Dslash leaves the tile sums
+// of (p, q), XR_F forms alpha from them and from the (p, r) sums of the
+// previous P_F (every block sums the same tiles in the same order, so all
+// blocks agree bitwise) and leaves the |r|^2 sums, the preconditioner's last
+// layer leaves the (q, z) sums, and P_F takes the convergence /
+// reliable-update decision and beta, updates p and leaves the (p, r) sums of
+// the next iteration.  The state an iteration starts from is snapshot by XR_F
+// so that P_F reads it while its leading block writes the new one.  After a
+// reliable update the host-driven restart uses DOTS_B (with its finisher), P
+// and DOT_PR.
 #include "finish.h"
 #include "launch.h"
 #include "ptc.h"
@@ -18,23 +27,65 @@ __global__ void __launch_bounds__(192) k_fcg(FcgLaunch a)
     const int tile = blockIdx.x;
     const ProbDesc &pd = a.probs[0];
     SolveState *st = &a.states[0];
-    if (st->status != a.want) return;
+    const bool lead = tile == 0 && threadIdx.x == 0;
+    if (a.op == FCG_XR_F) {
+        if (lead) {
+            st->snap_status = st->status;
+            st->snap_rr = st->rr;
+            st->snap_maxrr = st->maxrr;
+            st->snap_iter = st->iter;
+        }
+        // XR_F's leading block may set a breakdown while other blocks start:
+        // one read per block keeps every thread of a block on the same path
+        __shared__ int s_status;
+        if (threadIdx.x == 0) s_status = st->status;
+        __syncthreads();
+        if (s_status != ST_RUNNING) return;
+    } else if (a.op == FCG_P_F) {
+        if (st->snap_status != ST_RUNNING) return;
+    } else if (st->status != a.want) {
+        return;
+    }
     const long long f = (long long)tile * TILE * 3 + threadIdx.x;
     const bool ok = f < (long long)pd.h * 3;
     double part[3] = {0.0, 0.0, 0.0};
     float2 *r = reinterpret_cast<float2 *>(a.r), *x = reinterpret_cast<float2 *>(a.x);
     float2 *p = reinterpret_cast<float2 *>(a.p), *q = reinterpret_cast<float2 *>(a.q);
     float2 *z = reinterpret_cast<float2 *>(a.z);
-    if (a.op == FCG_DOTS_A) {
+    if (a.op == FCG_DOTS_B) {
         if (ok) {
-            float2 pv = p[f], qv = q[f], rv = r[f];
-            part[0] = (double)pv.x * qv.x + (double)pv.y * qv.y;
-            part[1] = (double)pv.x * rv.x + (double)pv.y * rv.y;
-            part[2] = (double)pv.x * rv.y - (double)pv.y * rv.x;
+            float2 qv = q[f], zv = z[f];
+            part[0] = (double)qv.x * zv.x + (double)qv.y * zv.y;
+            part[1] = (double)qv.x * zv.y - (double)qv.y * zv.x;
         }
-        publish_partials<3>(part, a.partials, tile);
-    } else if (a.op == FCG_XR) {
-        const float ar = (float)st->cplx[0], ai = (float)st->cplx[1];
+        publish_partials<2>(part, a.partials, tile);
+    } else if (a.op == FCG_P) {
+        const float br = (float)st->cplx[2], bi = (float)st->cplx[3];
+        if (ok) {
+            float2 pv = p[f], zv = z[f];
+            p[f] = make_float2(zv.x + br * pv.x - bi * pv.y, zv.y + br * pv.y + bi * pv.x);
+        }
+    } else if (a.op == FCG_XR_F) {
+        const int nt = a.nt;
+        double tot[3];   // (p, q), Re (p, r), Im (p, r)
+        block_totals<3>(a.red + FRED_PQ * nt, nt, 0, nt, tot);
+        const double pq = tot[0], prr = tot[1], pri = tot[2];
+        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(prr) || !isfinite(pri)) {
+            if (lead) {
+                st->pAp = pq;
+                st->cplx[0] = st->cplx[1] = 0.0;
+                st->status = ST_BREAKDOWN;
+                st->snap_status = ST_BREAKDOWN;
+            }
+            return;
+        }
+        const double ar64 = prr / pq, ai64 = pri / pq;
+        if (lead) {
+            st->pAp = pq;
+            st->cplx[0] = ar64;
+            st->cplx[1] = ai64;
+        }
+        const float ar = (float)ar64, ai = (float)ai64;
         if (ok) {
             float2 pv = p[f], qv = q[f], rv = r[f], xv = x[f];
             xv.x += ar * pv.x - ai * pv.y;
@@ -45,20 +96,53 @@ __global__ void __launch_bounds__(192) k_fcg(FcgLaunch a)
             r[f] = rv;
             part[0] = (double)rv.x * rv.x + (double)rv.y * rv.y;
         }
-        publish_partials<1>(part, a.partials, tile);
-    } else if (a.op == FCG_DOTS_B) {
-        if (ok) {
-            float2 qv = q[f], zv = z[f];
-            part[0] = (double)qv.x * zv.x + (double)qv.y * zv.y;
-            part[1] = (double)qv.x * zv.y - (double)qv.y * zv.x;
+        publish_compact(part[0], a.red + FRED_RR * nt, tile);
+    } else if (a.op == FCG_P_F) {
+        // the decision of the |r|^2 finisher, from the snapshot; every block
+        // takes it the same way and the leading block records it
+        const int nt = a.nt;
+        double tot[3];   // |r|^2, Re (q, z), Im (q, z)
+        block_totals<3>(a.red + FRED_RR * nt, nt, 0, nt, tot);
+        const double rn = tot[0], qzr = tot[1], qzi = tot[2];
+        const int iter1 = st->snap_iter + 1;
+        const double maxrr1 = rn > st->snap_maxrr ? rn : st->snap_maxrr;
+        const double pq = st->pAp;   // written by XR_F's leading block
+        const double br64 = -qzr / pq, bi64 = -qzi / pq;
+        int stat1 = ST_RUNNING;
+        if (!isfinite(rn)) stat1 = ST_BREAKDOWN;
+        else if (rn <= st->tol2 * st->bb || rn < st->delta2 * maxrr1 || iter1 >= st->maxiter) stat1 = ST_RELIABLE;
+        else if (!isfinite(br64) || !isfinite(bi64)) stat1 = ST_BREAKDOWN;
+        if (lead) {
+            st->iter = iter1;
+            st->rr_old = st->snap_rr;
+            st->rr = rn;
+            st->maxrr = maxrr1;
+            st->cplx[2] = br64;
+            st->cplx[3] = bi64;
+            st->status = stat1;
         }
-        publish_partials<2>(part, a.partials, tile);
-    } else {
-        const float br = (float)st->cplx[2], bi = (float)st->cplx[3];
+        if (stat1 != ST_RUNNING) return;   // uniform over the grid
+        const float br = (float)br64, bi = (float)bi64;
+        double pr = 0.0, pi = 0.0;
         if (ok) {
-            float2 pv = p[f], zv = z[f];
-            p[f] = make_float2(zv.x + br * pv.x - bi * pv.y, zv.y + br * pv.y + bi * pv.x);
+            float2 pv = p[f], zv = z[f], rv = r[f];
+            pv = make_float2(zv.x + br * pv.x - bi * pv.y, zv.y + br * pv.y + bi * pv.x);
+            p[f] = pv;
+            pr = (double)pv.x * rv.x + (double)pv.y * rv.y;
+            pi = (double)pv.x * rv.y - (double)pv.y * rv.x;
         }
+        double pv2[2] = {pr, pi};
+        publish_compact_n<2>(pv2, a.red + FRED_PR * nt, nt, tile);
+    } else {   // FCG_DOT_PR: the (p, r) sums after a (re)start
+        const int nt = a.nt;
+        double pr = 0.0, pi = 0.0;
+        if (ok) {
+            float2 pv = p[f], rv = r[f];
+            pr = (double)pv.x * rv.x + (double)pv.y * rv.y;
+            pi = (double)pv.x * rv.y - (double)pv.y * rv.x;
+        }
+        double pv2[2] = {pr, pi};
+        publish_compact_n<2>(pv2, a.red + FRED_PR * nt, nt, tile);
     }
 }
 

@@ -15,8 +15,6 @@ enum : int {
     FIN_STORE = 5,      // store tot[0..NPART) into st->cplx
     FIN_INIT_R = 6,     // tot[0] = |b - A x0|^2 (warm start): initial residual
     FIN_MS = 7,         // tot[0] = |r_new|^2: base beta and every shift's zeta, alpha_k, beta_k
-    FIN_FCG_ALPHA = 8,  // tot = {(p,q), Re (p,r), Im (p,r)}: alpha = (p,r)/(p,q)
-    FIN_FCG_R = 9,      // tot[0] = |r|^2: convergence / reliable trigger
     FIN_FCG_BETA = 10,  // tot = {Re (q,z), Im (q,z)}: beta = -(q,z)/(q,p)
 };
 
@@ -64,29 +62,6 @@ __device__ __forceinline__ void run_finisher(int fin, SolveState *st, const doub
     case FIN_MS:
         ms_finish(st, ms, tot[0]);
         break;
-    case FIN_FCG_ALPHA: {
-        const double pq = tot[0];
-        st->pAp = pq;
-        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(tot[1]) || !isfinite(tot[2])) {
-            st->status = ST_BREAKDOWN;
-            st->cplx[0] = st->cplx[1] = 0.0;
-        } else {
-            st->cplx[0] = tot[1] / pq;
-            st->cplx[1] = tot[2] / pq;
-        }
-        break;
-    }
-    case FIN_FCG_R: {
-        const double rn = tot[0];
-        st->iter += 1;
-        st->rr_old = st->rr;
-        st->rr = rn;
-        if (rn > st->maxrr) st->maxrr = rn;
-        if (!isfinite(rn)) st->status = ST_BREAKDOWN;
-        else if (rn <= st->tol2 * st->bb || rn < st->delta2 * st->maxrr || st->iter >= st->maxiter)
-            st->status = ST_RELIABLE;
-        break;
-    }
     case FIN_FCG_BETA: {
         const double pq = st->pAp;
         st->cplx[2] = -tot[0] / pq;

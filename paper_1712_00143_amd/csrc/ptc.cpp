@@ -15,8 +15,10 @@
 #include <cstdio>
 #include <cstring>
 #include <random>
+#include <string>
 #include <vector>
 
+#include "fcg_graph.h"
 #include "finish.h"
 #include "ptc.h"
 #include "solver.h"
@@ -63,6 +65,7 @@ struct hisq_ptc_s {
     // inference workspace
     float *inf = nullptr;
     long long infV = 0;
+    FcgGraphCache fcg_graph;
 };
 
 namespace {
@@ -170,13 +173,27 @@ int pick_layer_waves(hisq_lattice lat, int lslot, int prec, int recon, bool w16,
     return best.W;
 }
 
-// One layer application over output parities [plo, phi].
+// One layer application over output parities [plo, phi].  fz (may be null):
+// gate the launch on the solver status; with addin, out += addin (the
+// identity term of M) and the (q, out) tile sums of the flexible CG.
 hipError_t run_layer(hisq_lattice lat, int lslot, int prec, int recon, bool w16, const void *w, int cin, int cout,
                      const float *in, long long in_bs, int in_zero, float *out, long long out_bs, int out_pstride,
-                     int plo, int phi, int batch, hipStream_t stream)
+                     int plo, int phi, int batch, hipStream_t stream, const PtcFuse *fz = nullptr,
+                     const float *addin = nullptr, long long addin_bs = 0)
 {
     const int W = pick_layer_waves(lat, lslot, prec, recon, w16, w, cin, cout, in_zero, phi - plo + 1, batch, stream);
     PtcLaunch a = base_launch(lat, lslot);
+    if (fz) {
+        a.gate = fz->gate;
+        a.gate_want = fz->want;
+    }
+    a.addin = addin;
+    a.addin_bstride = addin_bs;
+    if (fz && fz->red && addin) {
+        a.dotq = fz->q;
+        a.dotred = fz->red;
+        a.dot_nt = fz->nt;
+    }
     a.w = w;
     a.in = in;
     a.in_bstride = in_bs;
@@ -215,9 +232,10 @@ hipError_t run_wgrad(hisq_ptc_s *n, hisq_lattice lat, int cin, int cout, const f
 }
 
 // z = M(r) for `batch` even vectors (FP32 [batch][h][3]); `ws` holds two
-// full-lattice activations of cmax channels per batch entry.
+// full-lattice activations of cmax channels per batch entry.  The identity
+// term is added by the last layer.  fz: see run_layer (batch 1).
 hipError_t apply_net(hisq_ptc_s *n, hisq_lattice lat, int lslot, int prec, int recon, bool w16, const float *r,
-                     float *z, float *ws, int batch, hipStream_t s)
+                     float *z, float *ws, int batch, hipStream_t s, const PtcFuse *fz = nullptr)
 {
     const long long h = lat->h;
     const long long act = (long long)cmax(n) * 2 * h * 6;   // floats per batch entry
@@ -229,7 +247,7 @@ hipError_t apply_net(hisq_ptc_s *n, hisq_lattice lat, int lslot, int prec, int r
     for (int l = 0; l < n->nlayer; l++) {
         const void *w = w16 ? (const void *)(n->w16 + 2 * n->woff[l]) : (const void *)(n->w32 + 2 * n->woff[l]);
         hipError_t e = run_layer(lat, lslot, prec, recon, w16, w, n->chans[l], n->chans[l + 1], cur, cur_bs, cur_zero,
-                                 bufs[k], act, 2, 0, 1, batch, s);
+                                 bufs[k], act, 2, 0, 1, batch, s, fz);
         if (e != hipSuccess) return e;
         cur = bufs[k];
         cur_bs = act;
@@ -240,20 +258,22 @@ hipError_t apply_net(hisq_ptc_s *n, hisq_lattice lat, int lslot, int prec, int r
         const void *w = w16 ? (const void *)(n->wa16 + 2 * n->woff[l]) : (const void *)(n->wa32 + 2 * n->woff[l]);
         const bool last = l == 0;
         hipError_t e = last ? run_layer(lat, lslot, prec, recon, w16, w, n->chans[l + 1], n->chans[l], cur, cur_bs,
-                                        -1, z, h * 6, 1, 0, 0, batch, s)
+                                        -1, z, h * 6, 1, 0, 0, batch, s, fz, r, h * 6)
                             : run_layer(lat, lslot, prec, recon, w16, w, n->chans[l + 1], n->chans[l], cur, cur_bs,
-                                        -1, bufs[k], act, 2, 0, 1, batch, s);
+                                        -1, bufs[k], act, 2, 0, 1, batch, s, fz);
         if (e != hipSuccess) return e;
         cur = bufs[k];
         k ^= 1;
     }
-    return launch_add_f32(z, r, (long long)batch * h * 6, s);   // the identity term
+    return hipSuccess;
 }
 
 }  // namespace
 
 // z = M(r) for the flexible CG: FP16 weights, transports on link set `lslot`.
-hipError_t ptc_apply_internal(hisq_ptc n, hisq_lattice lat, int lslot, int prec, int recon, const float *r, float *z)
+// fz (may be null): the flexible CG's status gate and (q, z) tile sums.
+hipError_t ptc_apply_internal(hisq_ptc n, hisq_lattice lat, int lslot, int prec, int recon, const float *r, float *z,
+                              const PtcFuse *fz)
 {
     const long long need = (long long)cmax(n) * 2 * lat->h * 6 * 2;
     if (n->infV < need) {
@@ -262,7 +282,25 @@ hipError_t ptc_apply_internal(hisq_ptc n, hisq_lattice lat, int lslot, int prec,
         if (e != hipSuccess) return e;
         n->infV = need;
     }
-    return apply_net(n, lat, lslot, prec, recon, true, r, z, n->inf, 1, lat->s);
+    return apply_net(n, lat, lslot, prec, recon, true, r, z, n->inf, 1, lat->s, fz);
+}
+
+// Everything of the network that a captured launch of apply_net holds by
+// value: the network, its weight and workspace pointers and its shape.
+FcgGraphCache &ptc_fcg_graph(hisq_ptc n)
+{
+    return n->fcg_graph;
+}
+
+std::string ptc_graph_key(hisq_ptc n)
+{
+    std::string k;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%p:%p:%p:%p:%lld:", (const void *)n, (const void *)n->w16, (const void *)n->wa16,
+             (const void *)n->inf, n->infV);
+    k = buf;
+    for (int c : n->chans) k += std::to_string(c) + ",";
+    return k;
 }
 
 extern "C" {
@@ -316,6 +354,7 @@ hisq_status hisq_ptc_destroy(hisq_ptc n)
     // the lattice handles may already be gone: touch only the device
     (void)hipSetDevice(n->device);
     (void)hipDeviceSynchronize();
+    n->fcg_graph.release();
     for (void *p : {(void *)n->w32, (void *)n->m, (void *)n->v, (void *)n->wa32, (void *)n->w16, (void *)n->wa16,
                     (void *)n->gw, (void *)n->gtmp, (void *)n->act, (void *)n->part, (void *)n->dloss,
                     (void *)n->dee, (void *)n->inf})
@@ -413,7 +452,7 @@ hisq_status hisq_ptc_init_polynomial(hisq_ptc n, double a, double c, int iters, 
                 break;
             }
             hipError_t e = hipMemcpy(dv, v.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = ptc_apply_internal(t, lat, 2, 1, 18, dv, dv + nf);
+            if (e == hipSuccess) e = ptc_apply_internal(t, lat, 2, 1, 18, dv, dv + nf, nullptr);
             if (e == hipSuccess) e = hipStreamSynchronize(lat->s);
             if (e == hipSuccess) e = hipMemcpy(z.data(), dv + nf, sizeof(float) * nf, hipMemcpyDeviceToHost);
             if (e != hipSuccess) {
@@ -520,7 +559,7 @@ hisq_status hisq_ptc_apply(hisq_ptc n, const void *r, void *z, int flags)
     HIPCHK(lat, hipSetDevice(lat->device));
     hisq_status st = ensure_fp32_links(lat);
     if (st != HISQ_OK) return st;
-    HIPCHK(lat, ptc_apply_internal(n, lat, 2, 1, 18, (const float *)r, (float *)z));
+    HIPCHK(lat, ptc_apply_internal(n, lat, 2, 1, 18, (const float *)r, (float *)z, nullptr));
     return HISQ_OK;
 }
 

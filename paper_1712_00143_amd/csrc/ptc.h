@@ -24,6 +24,25 @@ struct PtcLaunch {
     const float *tgt;        // loss: targets [B][h][3]
     long long tgt_bstride;
     const double *ee;        // loss: |target|^2 per batch entry
+    // flexible-CG fusion (all null / unused otherwise)
+    const SolveState *gate;  // skip the launch unless gate->status == gate_want
+    int gate_want;
+    int dot_nt;              // tiles of the dot partials below
+    const float *addin;      // out += addin (same layout as out, COUT = 1, one parity)
+    long long addin_bstride;
+    const float *dotq;       // with dotred: per-tile (dotq, out) into dotred[tile], dotred[dot_nt + tile]
+    double *dotred;
+};
+
+// Fusion of the preconditioner into the flexible CG's iteration: launches are
+// skipped unless gate->status == want, and the final layer also forms the
+// per-tile partials of (q, z) (re in red[tile], im in red[nt + tile]).
+struct PtcFuse {
+    const SolveState *gate;
+    int want;
+    const float *q;
+    double *red;
+    int nt;
 };
 
 hipError_t launch_ptc_layer(int prec, int recon, bool w16, int cin, int cout, int W, const PtcLaunch &a, int nblk,
@@ -51,8 +70,13 @@ struct FcgLaunch {
     int op;
     double *partials;
     float *r, *x, *p, *q, *z;
+    double *red;   // fused ops: compact tile sums [(p,q)][Re (p,r)][Im (p,r)][|r|^2][Re (q,z)][Im (q,z)], nt each
+    int nt;
 };
-enum : int { FCG_DOTS_A = 0, FCG_XR = 1, FCG_DOTS_B = 2, FCG_P = 3 };
+enum : int { FCG_DOTS_B = 2, FCG_P = 3, FCG_XR_F = 4, FCG_P_F = 5, FCG_DOT_PR = 6 };
+// offsets of the compact sums in FcgLaunch::red, in units of nt
+// (the three sums each fused op reads are adjacent)
+enum : int { FRED_PQ = 0, FRED_PR = 1, FRED_RR = 3, FRED_QZ = 4, FRED_N = 6 };
 hipError_t launch_fcg(const FcgLaunch &a, int ntile, hipStream_t s);
 
 }  // namespace hisq

@@ -99,6 +99,7 @@ __device__ __forceinline__ bool transport(const PtcLaunch &a, const ProbDesc &pd
 template <class LT, int R, class WT, int CIN, int COUT, int W>
 __global__ void __launch_bounds__(64 * W) k_ptc_layer(PtcLaunch a)
 {
+    if (a.gate && a.gate->status != a.gate_want) return;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const ProbDesc &pd = a.probs[0];
     const int ntile = pd.ntile;
@@ -157,14 +158,44 @@ __global__ void __launch_bounds__(64 * W) k_ptc_layer(PtcLaunch a)
                         acc[c][q].im += red[(((w - 1) * COUT + c) * 6 + 2 * q + 1) * 64 + lane];
                     }
     }
-    if (wave == 0 && valid) {
-        float *out_b = a.out + (size_t)b * a.out_bstride;
-        const long long h = pd.h;
+    if (wave == 0) {
+        double dr = 0.0, di = 0.0;
+        if (valid) {
+            float *out_b = a.out + (size_t)b * a.out_bstride;
+            const long long h = pd.h;
 #pragma unroll
-        for (int c = 0; c < COUT; c++) {
-            float2 *p = reinterpret_cast<float2 *>(out_b) + ((c * a.out_pstride + (par - a.out_par0)) * h + i) * 3;
+            for (int c = 0; c < COUT; c++) {
+                const long long o = ((c * a.out_pstride + (par - a.out_par0)) * h + i) * 3;
+                float2 *p = reinterpret_cast<float2 *>(out_b) + o;
+                if (a.addin) {   // the identity term of M, added in the same rounding as a separate pass
+                    const float2 *ad = reinterpret_cast<const float2 *>(a.addin + (size_t)b * a.addin_bstride) + o;
 #pragma unroll
-            for (int q = 0; q < 3; q++) p[q] = make_float2(acc[c][q].re, acc[c][q].im);
+                    for (int q = 0; q < 3; q++) {
+                        const float2 t = ad[q];
+                        acc[c][q].re += t.x;
+                        acc[c][q].im += t.y;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 3; q++) p[q] = make_float2(acc[c][q].re, acc[c][q].im);
+            }
+            if (a.dotred) {   // (q, out) = sum conj(q) out over this tile (COUT = 1)
+                const float2 *qv = reinterpret_cast<const float2 *>(a.dotq) + (size_t)i * 3;
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    const float2 t = qv[q];
+                    dr += (double)t.x * acc[0][q].re + (double)t.y * acc[0][q].im;
+                    di += (double)t.x * acc[0][q].im - (double)t.y * acc[0][q].re;
+                }
+            }
+        }
+        if (a.dotred) {   // wave 0 covers the whole 64-site tile
+            dr = wave_sum(dr);
+            di = wave_sum(di);
+            if (lane == 0) {
+                a.dotred[tile] = dr;
+                a.dotred[a.dot_nt + tile] = di;
+            }
         }
     }
 }

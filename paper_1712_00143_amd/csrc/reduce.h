@@ -54,6 +54,18 @@ __device__ __forceinline__ void publish_compact(double mine, double *red, int ti
     if (threadIdx.x == 0) red[tile] = v[0];
 }
 
+// NV block-summed values per tile in NV compact arrays stride apart
+// (red[k * stride + tile]), with one block reduction.
+template <int NV>
+__device__ __forceinline__ void publish_compact_n(double mine[NV], double *red, int stride, int tile)
+{
+    __shared__ double lds[16 * NV];
+    block_sum<NV>(mine, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; k++) red[(size_t)k * stride + tile] = mine[k];
+}
+
 // Sum of red[first .. first + n) in a fixed order (each thread a strided
 // subset, then the block sum), returned to every thread of the block.  Every
 // block that calls it for the same range gets the same bits.
@@ -67,6 +79,30 @@ __device__ __forceinline__ double block_total(const double *red, int first, int 
     if (threadIdx.x == 0) tot = v[0];
     __syncthreads();
     return tot;
+}
+
+// NV sums at once: out[k] = sum of red[k * stride + first .. + n), each in
+// the order of block_total (so each total has the same bits as block_total's),
+// returned to every thread of the block.  One pass and one block reduction
+// instead of NV.
+template <int NV>
+__device__ __forceinline__ void block_totals(const double *red, int stride, int first, int n, double out[NV])
+{
+    __shared__ double lds[16 * NV];
+    __shared__ double tot[NV];
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) v[k] = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < NV; k++) v[k] += red[(size_t)k * stride + first + j];
+    block_sum<NV>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; k++) tot[k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; k++) out[k] = tot[k];
 }
 
 }  // namespace hisq

@@ -345,3 +345,35 @@ def test_polynomial_start_cuts_fcg_iterations():
     assert it_o - 2 <= info["iters"] <= 1.25 * it_o + 2
     net.close()
     lat.close()
+
+
+def test_fcg_graph_replay_matches_eager():
+    """The captured iteration chunk gives the eager launches' result bit for
+    bit (same kernels, same order), on two solves in a row (the second
+    replays the cached graph) and after a change of weights (read from device
+    memory by the replay)."""
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    m = 0.01
+    fat, lng = synth.make_links(dims, 0.25, seed=77)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    net = H.PTC(lat, (1, 4, 4, 1))
+    net.init_polynomial(a=4.0, c=1.2)
+    pe = H.hisq_default_params(tol=1e-10, sloppy=1)
+    pg = H.hisq_default_params(tol=1e-10, sloppy=1, flags=H.HISQ_USE_GRAPH)
+    for k, seed in enumerate([78, 79]):
+        b = synth.gaussian_even(dims, seed)
+        xe, ie = net.cg_learned(lat, m, b, params=pe)
+        xg, ig = net.cg_learned(lat, m, b, params=pg)
+        assert ie["converged"] == 1 and ig["converged"] == 1
+        assert ie["iters"] == ig["iters"] and ie["reliable_updates"] == ig["reliable_updates"]
+        assert np.array_equal(xe, xg), k
+        assert oracle.true_residual(dims, fat, lng, m, b, xg) <= 1e-10
+    net.init_polynomial(a=2.0, c=1.0)
+    b = synth.gaussian_even(dims, 80)
+    xe, ie = net.cg_learned(lat, m, b, params=pe)
+    xg, ig = net.cg_learned(lat, m, b, params=pg)
+    assert ie["iters"] == ig["iters"] and np.array_equal(xe, xg)
+    net.close()
+    lat.close()
