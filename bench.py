@@ -469,8 +469,13 @@ def run_c4(args):
     w = synth.C4
     net, tl, t_train, losses = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, args.nfield,
                                                     args.nsrc, args.train_steps)
-    res = {"plain_f64": [], "mixed_f32": [], "mixed_f16_r12": [], "learned_fcg": [], "untrained_fcg": [],
-           "poly_fcg": [], "poly_fcg_121": []}
+    # the two-layer 1 -> 2 -> 1 network (the smallest that holds the polynomial
+    # start), trained the same way on a quarter of the fields
+    net2, tl2, t_train2, losses2 = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000,
+                                                        max(1, args.nfield // 4), max(1, args.nsrc // 2),
+                                                        args.train_steps, chans=(1, 2, 1))
+    res = {"plain_f64": [], "mixed_f32": [], "mixed_f16_r12": [], "learned_fcg": [], "learned_fcg_121": [],
+           "untrained_fcg": [], "poly_fcg": [], "poly_fcg_121": []}
     untrained = None
     for j in range(args.nheld):
         fat, lng = synth.make_links(w.dims, w.eps, seed=4900 + j)
@@ -493,6 +498,7 @@ def run_c4(args):
                     ("mixed_f32", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("mixed_f16_r12", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH))),
                     ("learned_fcg", lambda: net.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
+                    ("learned_fcg_121", lambda: net2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("untrained_fcg", lambda: untrained.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("poly_fcg", lambda: poly.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("poly_fcg_121", lambda: poly2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH)))):
@@ -512,11 +518,18 @@ def run_c4(args):
                      "start": "polynomial K = 4 (1 + 1.2 D_f^2 / lambda), lambda from the first training field",
                      "what": "harvest_s: synthetic fields generated on the host, loaded, and plain CG to 1e-12 per source; "
                              "train_s: the Adam steps on the GPU",
+                     "loss": "energy norm of the error (HISQ_LOSS_ENERGY)",
                      "loss_first10": round(float(losses[:10].mean()), 4),
-                     "loss_last50": round(float(losses[-50:].mean()), 4)},
+                     "loss_last50": round(float(losses[-50:].mean()), 4),
+                     "net_121": {"seconds": t_train2, "fields": max(1, args.nfield // 4),
+                                 "sources": max(1, args.nsrc // 2),
+                                 "loss_first10": round(float(losses2[:10].mean()), 4),
+                                 "loss_last50": round(float(losses2[-50:].mean()), 4)}},
         "solves": summ,
         "learned_iteration_gain_vs_plain": round(summ["plain_f64"]["iters_mean"] / summ["learned_fcg"]["iters_mean"], 3),
-        "learned_time_gain_vs_plain": round(summ["plain_f64"]["time_s_mean"] / summ["learned_fcg"]["time_s_mean"], 3)}),
+        "learned_time_gain_vs_plain": round(summ["plain_f64"]["time_s_mean"] / summ["learned_fcg"]["time_s_mean"], 3),
+        "learned_121_time_gain_vs_plain": round(summ["plain_f64"]["time_s_mean"] / summ["learned_fcg_121"]["time_s_mean"], 3),
+        "learned_121_time_gain_vs_mixed_f32": round(summ["mixed_f32"]["time_s_mean"] / summ["learned_fcg_121"]["time_s_mean"], 3)}),
         flush=True)
 
 

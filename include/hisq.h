@@ -232,14 +232,23 @@ hisq_status hisq_ptc_harvest(hisq_ptc net, hisq_lattice lat, double mass, const 
  * even vectors r, e ([V/2][3] complex each, as stored: FP32 values). */
 hisq_status hisq_ptc_pair_count(hisq_ptc net, int *count);
 hisq_status hisq_ptc_get_pair(hisq_ptc net, int index, double *r, double *e);
+/* Training loss (hisq_ptc_set_loss).  For a minibatch of B pairs (r_b, e_b),
+ * A e_b = r_b, and z_b = M r_b, the misfit of z_b ~ c e_b with one common
+ * complex c, minimised over c and normalised (invariant to the scale of M,
+ * which the flexible CG does not see):
+ *   HISQ_LOSS_ENERGY (default): in the energy norm |v|_A^2 = <v, A v> that CG
+ *     minimises, L = 1 - |S|^2/(B Q), S = sum_b <z_b, r_b>/w_b,
+ *     Q = sum_b <z_b, A z_b>/w_b, w_b = <e_b, r_b>; each step applies the
+ *     FP32 operator of the pairs' lattice to the batch;
+ *   HISQ_LOSS_EUCLIDEAN: in the Euclidean norm, S = sum_b <z_b, e_b>/|e_b|^2,
+ *     Q = sum_b |z_b|^2/|e_b|^2.  It weights the low modes of the error by
+ *     1/lambda^2 and drifts away from good preconditioners. */
+enum { HISQ_LOSS_ENERGY = 0, HISQ_LOSS_EUCLIDEAN = 1 };
+hisq_status hisq_ptc_set_loss(hisq_ptc net, int loss);
 /* Train on the stored pairs (all from lattices whose links are those of the
  * handle each pair was harvested on): `steps` Adam steps (lr, beta1 0.9,
- * beta2 0.999, eps 1e-8) on minibatches of `batch` pairs drawn with `seed`.
- * Loss of a minibatch: L = 1 - |S|^2 / (B Q), S = sum_b <M r_b, e_b>/|e_b|^2,
- * Q = sum_b |M r_b|^2/|e_b|^2: the normalised misfit of M r_b ~ c e_b with one
- * common c (M A close to a multiple of 1 on the error directions), invariant
- * to the scale of M, which the flexible CG does not see.
- * losses: steps entries or NULL. */
+ * beta2 0.999, eps 1e-8) on minibatches of `batch` pairs of one lattice,
+ * drawn with `seed`, on the loss set above.  losses: steps entries or NULL. */
 hisq_status hisq_ptc_train(hisq_ptc net, int steps, int batch, double lr, unsigned long long seed,
                            double *losses);
 /* Flexible CG (truncation 1) with z = M(r), FP32 iteration and FP64 true

@@ -229,7 +229,7 @@ def adjoint_weights(w):
     return np.conj(np.transpose(w, (1, 0, 2))[:, :, perm])
 
 
-def ptc_loss_and_grad(dims, fat, weights, r_even_batch, e_even_batch):
+def ptc_loss_and_grad(dims, fat, weights, r_even_batch, e_even_batch, energy=None):
     """Loss of a batch of (residual, error) pairs for z_i = M(r_i),
     M = 1 + E^+ K^+ K E (K the layer stack):
         L = 1 - |S|^2 / (B Q),  S = sum_i <z_i, e_i> / |e_i|^2,
@@ -241,7 +241,14 @@ def ptc_loss_and_grad(dims, fat, weights, r_even_batch, e_even_batch):
         g_i = -2 (conj(S) e_i Q - |S|^2 z_i) / (B Q^2 |e_i|^2).
     Weight gradients follow by the layer adjoints; the adjoint half uses the
     weights W' = adjoint_weights(W), and a gradient G' with respect to W'
-    contributes adjoint_weights(G') to that of W."""
+    contributes adjoint_weights(G') to that of W.
+
+    energy = (lng, mass): the same misfit in the energy norm of A instead,
+    min_c sum_i |e_i - c z_i|_A^2 / |e_i|_A^2 with |v|_A^2 = <v, A v> -- the
+    norm CG minimises.  With A e_i = r_i and w_i = <e_i, r_i>:
+        S = sum_i <z_i, r_i> / w_i,  Q = sum_i <z_i, A z_i> / w_i,
+        L = 1 - |S|^2 / (B Q),
+        g_i = -2 (conj(S) r_i Q - |S|^2 A z_i) / (B Q^2 w_i)."""
     V = int(np.prod(dims))
     nl = len(weights)
     even = _even_lex(dims)
@@ -261,14 +268,17 @@ def ptc_loss_and_grad(dims, fat, weights, r_even_batch, e_even_batch):
         for l in range(nl, 0, -1):
             bs[l - 1] = ptc_layer(dims, fat, wadj[l - 1], bs[l])
         z = r + bs[0][0, even]          # M = 1 + E^+ K^+ K E
-        ee = float(np.vdot(e, e).real)
-        S += np.vdot(z, e) / ee
-        Q += float(np.vdot(z, z).real) / ee
-        fwd.append((acts, bs, z, e, ee))
+        if energy is None:
+            t, zw, ee = e, z, float(np.vdot(e, e).real)
+        else:
+            t, zw, ee = r, apply_A(dims, fat, energy[0], energy[1], z), float(np.vdot(e, r).real)
+        S += np.vdot(z, t) / ee
+        Q += float(np.vdot(z, zw).real) / ee
+        fwd.append((acts, bs, zw, t, ee))
     loss = 1.0 - abs(S) ** 2 / (npair * Q)
-    for acts, bs, z, e, ee in fwd:
+    for acts, bs, zw, t, ee in fwd:
         g = np.zeros((1, V, 3), dtype=np.complex128)
-        g[0, even] = -2.0 * (np.conj(S) * e * Q - abs(S) ** 2 * z) / (npair * Q * Q * ee)
+        g[0, even] = -2.0 * (np.conj(S) * t * Q - abs(S) ** 2 * zw) / (npair * Q * Q * ee)
         # adjoint half, in reverse order of application
         for l in range(1, nl + 1):
             gin, gw = ptc_layer_adj(dims, fat, wadj[l - 1], bs[l], g)

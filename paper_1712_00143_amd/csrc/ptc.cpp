@@ -35,8 +35,10 @@ namespace {
 
 struct PairBlock {
     hisq_lattice lat;
+    double mass;        // of the operator A the pairs belong to (A e_i = r_i)
     float *mem;         // [n][2][h][3] complex: r_i then e_i
-    std::vector<double> ee;
+    std::vector<double> ee;   // |e_i|^2
+    std::vector<double> er;   // <e_i, r_i> = |e_i|_A^2
     int n;
 };
 
@@ -54,6 +56,7 @@ struct hisq_ptc_s {
     __half *w16 = nullptr, *wa16 = nullptr;
     double *gw = nullptr, *gtmp = nullptr;
     int step = 0;
+    int loss = HISQ_LOSS_ENERGY;
     std::vector<PairBlock> pairs;
     // training workspace
     int wsB = 0;
@@ -621,6 +624,7 @@ hisq_status hisq_ptc_harvest(hisq_ptc n, hisq_lattice lat, double mass, const do
     const int taken = snap.taken;
     PairBlock pb;
     pb.lat = lat;
+    pb.mass = mass;
     pb.n = taken;
     HIPCHK(lat, hipMalloc(&pb.mem, (size_t)taken * 2 * h * 24));
     std::vector<double> xh((size_t)h * 6), xsh((size_t)h * 6), rh((size_t)h * 6);
@@ -634,6 +638,7 @@ hisq_status hisq_ptc_harvest(hisq_ptc n, hisq_lattice lat, double mass, const do
     HIPCHK(lat, hipMalloc(&dd, sizeof d));
     HIPCHK(lat, hipMemcpy(dd, &d, sizeof d, hipMemcpyHostToDevice));
     pb.ee.resize(taken);
+    pb.er.resize(taken);
     std::vector<double> rr(taken, 0.0);
     double b2 = 0.0;
     for (int i = 0; i < taken; i++) {
@@ -664,9 +669,11 @@ hisq_status hisq_ptc_harvest(hisq_ptc n, hisq_lattice lat, double mass, const do
         HIPCHK(lat, launch_convert(r_hi, 0, pb.mem + (size_t)2 * i * h * 6, 1, h * 3, s));
         HIPCHK(lat, hipStreamSynchronize(s));
         HIPCHK(lat, hipMemcpy(rh.data(), r_hi, (size_t)h * 48, hipMemcpyDeviceToHost));
-        double r2 = 0;
+        double r2 = 0, er = 0;
         for (double v : rh) r2 += v * v;
+        for (size_t k = 0; k < rh.size(); k++) er += xh[k] * rh[k];   // Re <e_i, r_i>
         rr[i] = r2;
+        pb.er[i] = er;
         if (i == 0) b2 = r2;   // x_0 = 0: r_0 = b
     }
     (void)hipFree(dd); (void)hipFree(t_odd); (void)hipFree(r_hi);
@@ -675,17 +682,28 @@ hisq_status hisq_ptc_harvest(hisq_ptc n, hisq_lattice lat, double mass, const do
     // (|r_i| >= 1e-9 |b|, i.e. 1e3 times |r*|), compacted in order
     int keep = 0;
     for (int i = 0; i < taken; i++) {
-        if (!(rr[i] >= 1e-18 * b2) || pb.ee[i] == 0.0) continue;
+        if (!(rr[i] >= 1e-18 * b2) || pb.ee[i] == 0.0 || !(pb.er[i] > 0.0)) continue;
         if (keep != i)
             HIPCHK(lat, hipMemcpy(pb.mem + (size_t)2 * keep * h * 6, pb.mem + (size_t)2 * i * h * 6, (size_t)h * 48,
                                   hipMemcpyDeviceToDevice));
-        pb.ee[keep++] = pb.ee[i];
+        pb.ee[keep] = pb.ee[i];
+        pb.er[keep++] = pb.er[i];
     }
     pb.n = keep;
     pb.ee.resize(keep);
+    pb.er.resize(keep);
     if (keep > 0) n->pairs.push_back(pb);
     else (void)hipFree(pb.mem);
     if (npairs) *npairs = keep;
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_set_loss(hisq_ptc n, int loss)
+{
+    if (!n) return HISQ_ERR_ARG;
+    if (loss != HISQ_LOSS_ENERGY && loss != HISQ_LOSS_EUCLIDEAN)
+        return set_err(n->lat, HISQ_ERR_ARG, "unknown training loss");
+    n->loss = loss;
     return HISQ_OK;
 }
 
@@ -749,7 +767,7 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
     // two gradient buffers (full), and z, g_{b_0}, r, e (even)
     const long long actf = (long long)C * 2 * h * 6;
     const size_t nbuf = (size_t)(2 * nl + 1);
-    const size_t need = (size_t)batch * (actf * nbuf + h * 6 * 4);
+    const size_t need = (size_t)batch * (actf * nbuf + h * 6 * 6);
     if (n->wsB != batch || n->wsV != V) {
         if (n->act) (void)hipFree(n->act);
         if (n->dee) (void)hipFree(n->dee);
@@ -780,6 +798,8 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
     float *g0 = zb + (size_t)batch * h * 6;
     float *rb = g0 + (size_t)batch * h * 6;
     float *eb = rb + (size_t)batch * h * 6;
+    float *tb = eb + (size_t)batch * h * 6;   // energy norm: D_oe z (odd sites)
+    float *ub = tb + (size_t)batch * h * 6;   // energy norm: D_eo D_oe z
     long long total = 0;
     for (auto &pb : n->pairs) total += pb.n;
     std::mt19937_64 rng(seed);
@@ -801,7 +821,7 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
                                         hipMemcpyDeviceToDevice, s));
             HIPCHK(lat0, hipMemcpyAsync(eb + (size_t)b * hl * 6, pb.mem + ((size_t)2 * i + 1) * hl * 6, hl * 24,
                                         hipMemcpyDeviceToDevice, s));
-            ee[b] = pb.ee[i];
+            ee[b] = n->loss == HISQ_LOSS_ENERGY ? pb.er[i] : pb.ee[i];
         }
         HIPCHK(lat0, hipMemcpyAsync(n->dee, ee.data(), sizeof(double) * batch, hipMemcpyHostToDevice, s));
         // forward half
@@ -823,11 +843,23 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
         }
         // z = r + E^+ b_0, then the loss and g_z = g_{b_0}
         HIPCHK(lat0, launch_add_f32(zb, rb, (long long)batch * hl * 6, s));
+        const bool energy = n->loss == HISQ_LOSS_ENERGY;
+        if (energy) {
+            // D_eo D_oe z for A z = 4 m^2 z - D_eo D_oe z, on the FP32 operator
+            // of the pairs' lattice (its own stream, ordered by the host)
+            if (lat->s != s) HIPCHK(lat0, hipStreamSynchronize(s));
+            st = hisq_dslash(lat, HISQ_ODD, HISQ_F32, HISQ_RECON_18, zb, tb, batch, HISQ_DEVICE_PTR);
+            if (st == HISQ_OK) st = hisq_dslash(lat, HISQ_EVEN, HISQ_F32, HISQ_RECON_18, tb, ub, batch, HISQ_DEVICE_PTR);
+            if (st != HISQ_OK) return st;
+            if (lat->s != s) HIPCHK(lat0, hipStreamSynchronize(lat->s));
+        }
         PtcLaunch la = base_launch(lat, 2);
         la.in = zb;
         la.in_bstride = hl * 6;
-        la.tgt = eb;
+        la.tgt = energy ? rb : eb;
         la.tgt_bstride = hl * 6;
+        la.wvec = energy ? ub : nullptr;
+        la.wdiag = 4.0 * pb.mass * pb.mass;
         la.out = g0;
         la.out_bstride = hl * 6;
         la.ee = n->dee;

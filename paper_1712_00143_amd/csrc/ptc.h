@@ -23,7 +23,9 @@ struct PtcLaunch {
     double *partials;
     const float *tgt;        // loss: targets [B][h][3]
     long long tgt_bstride;
-    const double *ee;        // loss: |target|^2 per batch entry
+    const double *ee;        // loss: normalisation per batch entry (|e|^2, or <e, r> for the energy norm)
+    const float *wvec;       // energy-norm loss: D_eo D_oe z, so that A z = wdiag z - wvec (null: Euclidean)
+    double wdiag;
     // flexible-CG fusion (all null / unused otherwise)
     const SolveState *gate;  // skip the launch unless gate->status == gate_want
     int gate_want;

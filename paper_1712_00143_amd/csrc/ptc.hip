@@ -291,6 +291,16 @@ __global__ void __launch_bounds__(256) k_ptc_wsum(const double *partials, long l
 // of M.  Passes: per-tile partials of (Re, Im <z, e>, |z|^2); per-pair totals;
 // S, Q and L; the gradient g_b = -2 (conj(S) e_b Q - |S|^2 z_b) / (B Q^2 |e_b|^2)
 // on even sites.
+// The vector the loss measures z against: z itself (Euclidean), or A z =
+// wdiag z - D_eo D_oe z (energy norm), element f of batch entry b.
+__device__ __forceinline__ float2 weighted(const PtcLaunch &a, int b, long long f, float2 z)
+{
+    if (!a.wvec) return z;
+    const float2 u = reinterpret_cast<const float2 *>(a.wvec + (size_t)b * a.in_bstride)[f];
+    const float dg = (float)a.wdiag;
+    return make_float2(dg * z.x - u.x, dg * z.y - u.y);
+}
+
 __global__ void __launch_bounds__(192) k_ptc_loss_dots(PtcLaunch a)
 {
     const ProbDesc &pd = a.probs[0];
@@ -300,9 +310,10 @@ __global__ void __launch_bounds__(192) k_ptc_loss_dots(PtcLaunch a)
     if (f < (long long)pd.h * 3) {
         const float2 z = reinterpret_cast<const float2 *>(a.in + (size_t)b * a.in_bstride)[f];
         const float2 t = reinterpret_cast<const float2 *>(a.tgt + (size_t)b * a.tgt_bstride)[f];
+        const float2 zw = weighted(a, b, f, z);
         part[0] = (double)z.x * t.x + (double)z.y * t.y;
         part[1] = (double)z.x * t.y - (double)z.y * t.x;
-        part[2] = (double)z.x * z.x + (double)z.y * z.y;
+        part[2] = (double)z.x * zw.x + (double)z.y * zw.y;
     }
     publish_partials<3>(part, a.partials, b * gridDim.x + tile);
 }
@@ -351,13 +362,15 @@ __global__ void __launch_bounds__(192) k_ptc_loss_grad(PtcLaunch a, const double
     if (f >= (long long)pd.h * 3) return;
     const double sr = pstat[4 * B], si = pstat[4 * B + 1], q = pstat[4 * B + 2];
     const double den = (double)B * q * q * a.ee[b];
-    // g = Ac e + Bc z,  Ac = -2 conj(S) Q / den,  Bc = 2 |S|^2 / den
+    // g = Ac t + Bc z_w,  Ac = -2 conj(S) Q / den,  Bc = 2 |S|^2 / den (t the
+    // target: e, or r for the energy norm; z_w = z, or A z)
     const float ar = (float)(-2.0 * sr * q / den), ai = (float)(2.0 * si * q / den);
     const float bc = (float)(2.0 * (sr * sr + si * si) / den);
     const float2 z = reinterpret_cast<const float2 *>(a.in + (size_t)b * a.in_bstride)[f];
     const float2 t = reinterpret_cast<const float2 *>(a.tgt + (size_t)b * a.tgt_bstride)[f];
+    const float2 zw = weighted(a, b, f, z);
     reinterpret_cast<float2 *>(a.out + (size_t)b * a.out_bstride)[f] =
-        make_float2(ar * t.x - ai * t.y + bc * z.x, ar * t.y + ai * t.x + bc * z.y);
+        make_float2(ar * t.x - ai * t.y + bc * zw.x, ar * t.y + ai * t.x + bc * zw.y);
 }
 
 // Adam on the FP32 master weights (complex weights as (re, im) pairs);

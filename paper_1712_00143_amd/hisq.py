@@ -18,6 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhisq.so")
 
 HISQ_OK = 0
+HISQ_LOSS_ENERGY = 0
+HISQ_LOSS_EUCLIDEAN = 1
 HISQ_ERR_ARG = -1
 HISQ_ERR_HIP = -2
 HISQ_ERR_OOM = -3
@@ -37,7 +39,7 @@ EXPORTS = [
     "hisq_batch_cg", "hisq_ptc_create", "hisq_ptc_destroy", "hisq_ptc_set_weights",
     "hisq_ptc_get_weights", "hisq_ptc_layer_forward", "hisq_ptc_layer_backward", "hisq_ptc_apply",
     "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
-    "hisq_stream_bandwidth", "hisq_ptc_init_polynomial",
+    "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss",
 ]
 
 
@@ -294,6 +296,10 @@ class PTC:
                                                   ctypes.c_int(iters),
                                                   ctypes.byref(lam)), "hisq_ptc_init_polynomial")
         return lam.value
+
+    def set_loss(self, loss):
+        """HISQ_LOSS_ENERGY (the default) or HISQ_LOSS_EUCLIDEAN."""
+        self._err(lib().hisq_ptc_set_loss(self.handle, ctypes.c_int(loss)), "hisq_ptc_set_loss")
 
     def get_weights(self):
         flat = np.zeros(self.nw, dtype=np.complex128)

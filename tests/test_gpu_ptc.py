@@ -135,7 +135,8 @@ def test_harvest_pairs_are_error_residual_pairs():
     lat.close()
 
 
-def test_one_training_step_matches_oracle():
+@pytest.mark.parametrize("loss", ["energy", "euclidean"])
+def test_one_training_step_matches_oracle(loss):
     H = _hisq()
     dims = (4, 4, 4, 6)
     fat, lng = synth.make_links(dims, 0.25, seed=4002)
@@ -150,14 +151,16 @@ def test_one_training_step_matches_oracle():
     n = net.harvest(lat, m, b, every=4, maxpairs=8)
     h = b.shape[0]
     pairs = [net.get_pair(i, h) for i in range(n)]
+    net.set_loss(H.HISQ_LOSS_ENERGY if loss == "energy" else H.HISQ_LOSS_EUCLIDEAN)
     lr = 1e-3
-    loss = net.train(1, batch=1, lr=lr, seed=11)[0]
+    got_loss = net.train(1, batch=1, lr=lr, seed=11)[0]
     w1 = net.get_weights()
     w0f = [w.astype(np.complex64).astype(np.complex128) for w in w0]
-    cands = [oracle.ptc_loss_and_grad(dims, fat, w0f, [r], [e]) for r, e in pairs]
-    k = int(np.argmin([abs(c[0] - loss) for c in cands]))
+    energy = (lng, m) if loss == "energy" else None
+    cands = [oracle.ptc_loss_and_grad(dims, fat, w0f, [r], [e], energy=energy) for r, e in pairs]
+    k = int(np.argmin([abs(c[0] - got_loss) for c in cands]))
     lo, grads = cands[k]
-    assert abs(lo - loss) <= 1e-5 * lo
+    assert abs(lo - got_loss) <= 1e-5 * lo
     for l in range(3):
         for part in ("real", "imag"):
             g = getattr(grads[l], part)

@@ -187,6 +187,49 @@ def test_ptc_loss_gradient_finite_differences():
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (l, idx, part, fd, an)
 
 
+def test_ptc_energy_loss_is_the_energy_norm_misfit_and_its_gradient():
+    """The energy-norm loss equals its definition, min over one complex c of
+    sum_b |e_b - c z_b|_A^2 / |e_b|_A^2 divided by B, with the A-norms formed
+    from the operator and c found by a numerical minimiser; and its gradient
+    matches central finite differences."""
+    from scipy.optimize import minimize
+    dims = (4, 4, 4, 4)
+    m = 0.1
+    fat, lng = synth.make_links(dims, 0.25, seed=18)
+    ws = _rand_weights([1, 2, 2, 1], 19, scale=0.3)
+    es = [synth.gaussian_even(dims, 30 + i) for i in range(3)]
+    rs = [oracle.apply_A(dims, fat, lng, m, e) for e in es]
+    loss, grads = oracle.ptc_loss_and_grad(dims, fat, ws, rs, es, energy=(lng, m))
+    zs = [oracle.ptc_apply(dims, fat, ws, r) for r in rs]
+
+    Aes = [oracle.apply_A(dims, fat, lng, m, e) for e in es]
+    Azs = [oracle.apply_A(dims, fat, lng, m, z) for z in zs]
+
+    def misfit(c):   # |e - c z|_A^2 = <e - c z, A e - c A z> (A linear)
+        cc = c[0] + 1j * c[1]
+        return sum(float(np.vdot(e - cc * z, ae - cc * az).real) / float(np.vdot(e, ae).real)
+                   for e, z, ae, az in zip(es, zs, Aes, Azs)) / len(es)
+
+    best = minimize(misfit, [0.1, 0.0], method="Nelder-Mead", options={"xatol": 1e-10, "fatol": 1e-14})
+    assert 0.0 < loss < 1.0
+    assert abs(best.fun - loss) <= 1e-8, (best.fun, loss)
+    rng = np.random.default_rng(3)
+    hstep = 1e-6
+    for trial in range(4):
+        l = int(rng.integers(0, 3))
+        idx = tuple(int(rng.integers(0, s)) for s in ws[l].shape)
+        for part, unit in ((0, 1.0), (1, 1j)):
+            wp = [w.copy() for w in ws]
+            wm = [w.copy() for w in ws]
+            wp[l][idx] += hstep * unit
+            wm[l][idx] -= hstep * unit
+            lp, _ = oracle.ptc_loss_and_grad(dims, fat, wp, rs, es, energy=(lng, m))
+            lm, _ = oracle.ptc_loss_and_grad(dims, fat, wm, rs, es, energy=(lng, m))
+            fd = (lp - lm) / (2 * hstep)
+            an = grads[l][idx].real if part == 0 else grads[l][idx].imag
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (l, idx, part, fd, an)
+
+
 def test_ptc_network_is_hermitian_psd_and_adjoint_weights():
     """M = E^+ K^+ K E is Hermitian and positive semidefinite, and the layer
     with adjoint_weights(W) is the adjoint layer of W."""
