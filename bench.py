@@ -225,13 +225,14 @@ def run_headline(args):
     train_info = None
     if not args.no_learned and not args.dslash_only:
         # trained outside the timed region, on pairs from two other sources
-        net = H.PTC(lat, (1, 4, 4, 1))
+        net = H.PTC(lat, (1, 2, 1))
         t0 = time.perf_counter()
         net.init_polynomial(a=4.0, c=1.2)
         srcs = w.sources()
         npair = sum(net.harvest(lat, w.mass, srcs[k], every=20, maxpairs=60) for k in (1, 2))
         losses = net.train(300, batch=8, lr=3e-3, seed=1)
-        train_info = {"pairs": npair, "steps": 300, "seconds": round(time.perf_counter() - t0, 3),
+        train_info = {"network": "1-2-1 PTC, polynomial start, energy-norm loss",
+                      "pairs": npair, "steps": 300, "seconds": round(time.perf_counter() - t0, 3),
                       "loss_first10": round(float(losses[:10].mean()), 4),
                       "loss_last50": round(float(losses[-50:].mean()), 4)}
 
@@ -467,15 +468,19 @@ def run_c4(args):
     from paper_1712_00143_amd import hisq as H
     from paper_1712_00143_amd import synth
     w = synth.C4
+    # the 1 -> 4 -> 4 -> 1 network, trained from small random weights
     net, tl, t_train, losses = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, args.nfield,
-                                                    args.nsrc, args.train_steps)
+                                                    args.nsrc, args.train_steps, init="random")
     # the two-layer 1 -> 2 -> 1 network (the smallest that holds the polynomial
-    # start), trained the same way on a quarter of the fields
-    net2, tl2, t_train2, losses2 = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000,
-                                                        max(1, args.nfield // 4), max(1, args.nsrc // 2),
-                                                        args.train_steps, chans=(1, 2, 1))
+    # preconditioner), on a quarter of the fields, from random weights and
+    # from the polynomial start
+    nq, sq = max(1, args.nfield // 4), max(1, args.nsrc // 2)
+    net2, tl2, t_train2, losses2 = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, nq, sq,
+                                                        args.train_steps, chans=(1, 2, 1), init="random")
+    net3, tl3, t_train3, losses3 = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, nq, sq,
+                                                        args.train_steps, chans=(1, 2, 1), init="poly")
     res = {"plain_f64": [], "mixed_f32": [], "mixed_f16_r12": [], "learned_fcg": [], "learned_fcg_121": [],
-           "untrained_fcg": [], "poly_fcg": [], "poly_fcg_121": []}
+           "learned_fcg_121_random_start": [], "untrained_fcg": [], "poly_fcg": [], "poly_fcg_121": []}
     untrained = None
     for j in range(args.nheld):
         fat, lng = synth.make_links(w.dims, w.eps, seed=4900 + j)
@@ -498,7 +503,8 @@ def run_c4(args):
                     ("mixed_f32", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("mixed_f16_r12", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH))),
                     ("learned_fcg", lambda: net.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
-                    ("learned_fcg_121", lambda: net2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
+                    ("learned_fcg_121_random_start", lambda: net2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
+                    ("learned_fcg_121", lambda: net3.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("untrained_fcg", lambda: untrained.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("poly_fcg", lambda: poly.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
                     ("poly_fcg_121", lambda: poly2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH)))):
@@ -515,16 +521,21 @@ def run_c4(args):
     print(json.dumps({
         "workload": f"learned PTC preconditioner 16^4, eps 0.25, m 0.005: trained on {args.nfield} fields x {args.nsrc} sources, tested on {args.nheld} held-out fields x 2 sources",
         "training": {"seconds": t_train, "steps": args.train_steps,
-                     "start": "polynomial K = 4 (1 + 1.2 D_f^2 / lambda), lambda from the first training field",
+                     "start": "small random weights (learned_fcg, learned_fcg_121_random_start); polynomial "
+                              "K = 4 (1 + 1.2 D_f^2 / lambda) for learned_fcg_121 and the untrained poly_* nets",
                      "what": "harvest_s: synthetic fields generated on the host, loaded, and plain CG to 1e-12 per source; "
                              "train_s: the Adam steps on the GPU",
                      "loss": "energy norm of the error (HISQ_LOSS_ENERGY)",
                      "loss_first10": round(float(losses[:10].mean()), 4),
                      "loss_last50": round(float(losses[-50:].mean()), 4),
-                     "net_121": {"seconds": t_train2, "fields": max(1, args.nfield // 4),
+                     "net_121_random_start": {"seconds": t_train2, "fields": max(1, args.nfield // 4),
                                  "sources": max(1, args.nsrc // 2),
                                  "loss_first10": round(float(losses2[:10].mean()), 4),
-                                 "loss_last50": round(float(losses2[-50:].mean()), 4)}},
+                                 "loss_last50": round(float(losses2[-50:].mean()), 4)},
+                     "net_121": {"seconds": t_train3, "fields": max(1, args.nfield // 4),
+                                            "sources": max(1, args.nsrc // 2),
+                                          "loss_first10": round(float(losses3[:10].mean()), 4),
+                                          "loss_last50": round(float(losses3[-50:].mean()), 4)}},
         "solves": summ,
         "learned_iteration_gain_vs_plain": round(summ["plain_f64"]["iters_mean"] / summ["learned_fcg"]["iters_mean"], 3),
         "learned_time_gain_vs_plain": round(summ["plain_f64"]["time_s_mean"] / summ["learned_fcg"]["time_s_mean"], 3),

@@ -231,12 +231,13 @@ def test_fcg_falls_back_on_breakdown():
 
 
 def test_training_lowers_loss_and_reports_gain():
-    """Train on fields 0..3 (pairs harvested by the solver itself), test on a
-    held-out field.  Asserted: the training loss falls, and the flexible CG
-    with the trained network reaches the FP64 true residual 1e-10 without a
-    hand-over to plain CG.  Measured and reported (not asserted, it is the
-    outcome being studied): the iteration count against the untrained network
-    (M = 1, i.e. plain CG) -- the gain of the learned part."""
+    """Train from small random weights on fields 0..3 (pairs harvested by the
+    solver itself, energy-norm loss), test on a held-out field.  Asserted: the
+    training loss falls, the flexible CG with the trained network reaches the
+    FP64 true residual 1e-10 without a hand-over to plain CG, and it needs
+    fewer iterations than the untrained network (M = 1, i.e. plain CG): the
+    network learns a preconditioner by itself (321 -> 106 iterations when
+    this was written)."""
     H = _hisq()
     dims = (8, 8, 8, 8)
     m = 0.02
@@ -267,6 +268,7 @@ def test_training_lowers_loss_and_reports_gain():
     _, i0 = untrained.cg_learned(T, m, b, params=p)
     print(f"learned-preconditioner gain: iterations {i0['iters']} (M = 1) -> {info['iters']} (trained), "
           f"ratio {i0['iters'] / info['iters']:.3f}; loss {losses[:10].mean():.4f} -> {losses[-50:].mean():.4f}")
+    assert info["iters"] <= 0.8 * i0["iters"], (info["iters"], i0["iters"])
     for L in lats + [T]:
         L.close()
 
