@@ -37,38 +37,56 @@ __device__ __forceinline__ int nb1(const Coord &co, int lex, int mu, int k, int 
     return (lex + (v - x) * Sm) >> 1;
 }
 
-// Transport along path k (0 identity, 1+2mu forward, 2+2mu backward) of
-// input channel c at output site (par, i); returns false if it is zero.  k
-// and par must be uniform over the wavefront (the link block is addressed
-// through a wave-uniform buffer resource).
-template <class LT, int R>
-__device__ __forceinline__ bool transport(const PtcLaunch &a, const ProbDesc &pd, const LinkSet &ls, int par,
-                                          int i, const Coord &co, int lex, int k, const float *in_b, int cin,
-                                          Cx<float> v[][3], int ncin)
+// Path k (0 identity, 1+2mu forward, 2+2mu backward) contributes unless the
+// input parity it reads is known to be zero.  Uniform over the wavefront.
+__device__ __forceinline__ bool path_live(const PtcLaunch &a, int par, int k)
+{
+    return k == 0 ? a.in_zero_par != par : a.in_zero_par != 1 - par;
+}
+
+// The loads of path k at output site (par, i): the input colour vectors of
+// CIN channels at the site (identity) or at its neighbour, and the packed
+// link.  k and par must be uniform over the wavefront (the link block is
+// addressed through a wave-uniform buffer resource).
+template <class LT, int R, int CIN>
+__device__ __forceinline__ void path_load(const ProbDesc &pd, const LinkSet &ls, int par, int i, const Coord &co,
+                                          int lex, int k, const float *in_b, RawLink<LT, R> &raw, float2 sv[CIN][3])
 {
     const long long h = pd.h;
-    if (k == 0) {
-        if (a.in_zero_par == par) return false;
-        for (int c = 0; c < ncin; c++) {
-            const float2 *p = reinterpret_cast<const float2 *>(in_b) + ((c * 2 + par) * h + i) * 3;
-#pragma unroll
-            for (int q = 0; q < 3; q++) {
-                float2 t = p[q];
-                v[c][q] = {t.x, t.y};
-            }
-        }
-        return true;
+    int site = i, sp = par;
+    if (k != 0) {
+        const int mu = (k - 1) >> 1;
+        const bool fwd = ((k - 1) & 1) == 0;
+        site = nb1(co, lex, mu, fwd ? 1 : -1, pd.L[0], pd.L[1], pd.L[2], pd.L[3]);
+        sp = 1 - par;
+        using F = LinkFmt<LT, R>;
+        const int d = 4 * mu + (fwd ? 0 : 1);
+        load_link_raw_wave<LT, R>((const char *)ls.ptr[par] + (size_t)d * h * F::BYTES, i, (int)h, raw);
     }
-    const int np = 1 - par;
-    if (a.in_zero_par == np) return false;
+#pragma unroll
+    for (int c = 0; c < CIN; c++) {
+        const float2 *p = reinterpret_cast<const float2 *>(in_b) + ((c * 2 + sp) * h + site) * 3;
+#pragma unroll
+        for (int q = 0; q < 3; q++) sv[c][q] = p[q];
+    }
+}
+
+// The transported colour vectors v[c] of path k from what path_load fetched.
+template <class LT, int R, int CIN>
+__device__ __forceinline__ void path_apply(const LinkSet &ls, const Coord &co, int k, const RawLink<LT, R> &raw,
+                                           const float2 sv[CIN][3], Cx<float> v[CIN][3])
+{
+    if (k == 0) {
+#pragma unroll
+        for (int c = 0; c < CIN; c++)
+#pragma unroll
+            for (int q = 0; q < 3; q++) v[c][q] = {sv[c][q].x, sv[c][q].y};
+        return;
+    }
     const int mu = (k - 1) >> 1;
     const bool fwd = ((k - 1) & 1) == 0;
-    const int n = nb1(co, lex, mu, fwd ? 1 : -1, pd.L[0], pd.L[1], pd.L[2], pd.L[3]);
     const int d = 4 * mu + (fwd ? 0 : 1);
-    using F = LinkFmt<LT, R>;
     Cx<float> u[3][3];
-    RawLink<LT, R> raw;
-    load_link_raw_wave<LT, R>((const char *)ls.ptr[par] + (size_t)d * h * F::BYTES, i, (int)h, raw);
     decode_link<LT, R, float>(raw, u);
     float coef = 1.f;
     if constexpr (R == 12 || sizeof(LT) == 2) {
@@ -80,19 +98,15 @@ __device__ __forceinline__ bool transport(const PtcLaunch &a, const ProbDesc &pd
         }
     }
     if (!fwd) coef = -coef;   // stored -F^+
-    for (int c = 0; c < ncin; c++) {
-        const float2 *p = reinterpret_cast<const float2 *>(in_b) + ((c * 2 + np) * h + n) * 3;
-        Cx<float> s[3];
 #pragma unroll
-        for (int q = 0; q < 3; q++) {
-            float2 t = p[q];
-            s[q] = {t.x, t.y};
-        }
+    for (int c = 0; c < CIN; c++) {
+        Cx<float> s3[3];
+#pragma unroll
+        for (int q = 0; q < 3; q++) s3[q] = {sv[c][q].x, sv[c][q].y};
 #pragma unroll
         for (int r = 0; r < 3; r++) v[c][r] = {0.f, 0.f};
-        matvec_acc_scaled(u, s, coef, v[c]);
+        matvec_acc_scaled(u, s3, coef, v[c]);
     }
-    return true;
 }
 
 // Forward layer (also the input-gradient layer, given the adjoint weights).
@@ -118,23 +132,37 @@ __global__ void __launch_bounds__(64 * W) k_ptc_layer(PtcLaunch a)
     if (valid) {
         const Coord co = cb_to_coord_pd(i, par, pd);
         const int lex = 2 * i + (co.x[0] & 1);
-        constexpr int PPW = (9 + W - 1) / W;
+        constexpr int PPW = (9 + W - 1) / W;   // paths of this wave
+        constexpr int G = PPW < 3 ? PPW : 3;    // paths whose loads are in flight together
 #pragma unroll
-        for (int kk = 0; kk < PPW; kk++) {
-            const int k = wave * PPW + kk;
-            Cx<float> v[CIN][3];
-            if (k >= 9 || !transport<LT, R>(a, pd, ls, par, i, co, lex, k, in_b, CIN, v, CIN)) continue;
+        for (int k0 = 0; k0 < PPW; k0 += G) {
+            RawLink<LT, R> raw[G];
+            float2 sv[G][CIN][3];
+            bool live[G];
 #pragma unroll
-            for (int c = 0; c < COUT; c++)
+            for (int g = 0; g < G; g++) {
+                const int k = wave * PPW + k0 + g;
+                live[g] = k0 + g < PPW && k < 9 && path_live(a, par, k);
+                if (live[g]) path_load<LT, R, CIN>(pd, ls, par, i, co, lex, k, in_b, raw[g], sv[g]);
+            }
 #pragma unroll
-                for (int cp = 0; cp < CIN; cp++) {
-                    const float2 w = ldw<WT>(a.w, (c * CIN + cp) * 9 + k);
+            for (int g = 0; g < G; g++) {
+                if (!live[g]) continue;
+                const int k = wave * PPW + k0 + g;
+                Cx<float> v[CIN][3];
+                path_apply<LT, R, CIN>(ls, co, k, raw[g], sv[g], v);
 #pragma unroll
-                    for (int q = 0; q < 3; q++) {
-                        acc[c][q].re += w.x * v[cp][q].re - w.y * v[cp][q].im;
-                        acc[c][q].im += w.x * v[cp][q].im + w.y * v[cp][q].re;
+                for (int c = 0; c < COUT; c++)
+#pragma unroll
+                    for (int cp = 0; cp < CIN; cp++) {
+                        const float2 w = ldw<WT>(a.w, (c * CIN + cp) * 9 + k);
+#pragma unroll
+                        for (int q = 0; q < 3; q++) {
+                            acc[c][q].re += w.x * v[cp][q].re - w.y * v[cp][q].im;
+                            acc[c][q].im += w.x * v[cp][q].im + w.y * v[cp][q].re;
+                        }
                     }
-                }
+            }
         }
     }
     if constexpr (W > 1) {
@@ -230,8 +258,12 @@ __global__ void __launch_bounds__(576) k_ptc_wgrad(PtcLaunch a, int npar, int ba
         const float *g_b = a.g + (size_t)b * a.g_bstride;
         const Coord co = cb_to_coord_pd(i, par, pd);
         const int lex = 2 * i + (co.x[0] & 1);
+        if (!path_live(a, par, k)) continue;
+        RawLink<LT, R> raw;
+        float2 sv[CIN][3];
+        path_load<LT, R, CIN>(pd, ls, par, i, co, lex, k, in_b, raw, sv);
         Cx<float> v[CIN][3];
-        if (!transport<LT, R>(a, pd, ls, par, i, co, lex, k, in_b, CIN, v, CIN)) continue;
+        path_apply<LT, R, CIN>(ls, co, k, raw, sv, v);
 #pragma unroll
         for (int c = 0; c < COUT; c++) {
             const float2 *gp = reinterpret_cast<const float2 *>(g_b) + ((c * a.g_pstride + (par - a.g_par0)) * h + i) * 3;
