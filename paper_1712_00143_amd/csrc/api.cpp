@@ -97,7 +97,7 @@ Tuner::Tuner()
         std::ifstream f(path_);
         std::string key;
         TuneChoice c;
-        while (f >> key >> c.W >> c.remap >> c.us) cache_[key] = c;
+        while (f >> key >> c.W >> c.remap >> c.cpol >> c.us) cache_[key] = c;
     }
 }
 
@@ -116,7 +116,7 @@ void Tuner::store(const std::string &key, const TuneChoice &c)
     cache_[key] = c;
     if (!path_.empty()) {
         std::ofstream f(path_, std::ios::app);
-        f << key << " " << c.W << " " << c.remap << " " << c.us << "\n";
+        f << key << " " << c.W << " " << c.remap << " " << c.cpol << " " << c.us << "\n";
     }
 }
 
@@ -416,7 +416,7 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return def;
     std::ostringstream ks;
-    ks << "dslash:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << ntile << ":n" << nprob;
+    ks << "dslash2:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << ntile << ":n" << nprob;
     std::string key = ks.str();
     for (auto &ch : key)
         if (ch == ' ') ch = '_';
@@ -433,6 +433,19 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     (void)hipEventCreate(&e1);
     TuneChoice best = def;
     best.us = 1e30;
+    // Start from a cache that holds none of these links (the packing kernels
+    // that wrote them, or another link set, may have left them in the
+    // Infinity Cache): overwrite twice its 256 MB.
+    {
+        void *junk = nullptr;
+        const size_t jb = (size_t)512 << 20;
+        if (hipMalloc(&junk, jb) == hipSuccess) {
+            (void)hipMemsetAsync(junk, 0, jb, lat->s);
+            (void)hipStreamSynchronize(lat->s);
+            (void)hipFree(junk);
+        }
+        (void)hipGetLastError();
+    }
     // every candidate shape, timed on both output parities in turn (the
     // solvers alternate them), best of three interleaved trials of 10 launches
     const int Ws[] = {1, 2, 4, 8, 16};
@@ -443,12 +456,13 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
             tbest[wi][remap] = 1e30;
             okc[wi][remap] = true;
         }
-    auto make = [&](int remap, int par) {
+    auto make = [&](int remap, int par, int cpol = 0) {
         DslashLaunch a;
         memset(&a, 0, sizeof a);
         a.probs = ddesc;
         a.tile2prob = dt2p;
         a.remap = remap;
+        a.cpol = cpol;
         a.out_par = par;
         a.lslot = prec * 2 + (recon == 12);
         a.in = in.p;
@@ -486,6 +500,36 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
                 best.W = Ws[wi];
                 best.remap = remap;
             }
+    // The link-load policy for the chosen shape: temporal loads win when both
+    // parities' links fit the Infinity Cache (they stay there between the
+    // alternating launches), non-temporal loads when they do not.  The shapes
+    // above were timed with non-temporal loads, which do not fill the cache;
+    // the temporal trials come after them, so neither measurement profits
+    // from the other's cache contents.
+    if (best.us < 1e29) {
+        double tt = 1e30;
+        const DslashLaunch t0 = make(best.remap, 0, 1), t1 = make(best.remap, 1, 1);
+        bool ok = true;
+        // a few passes first, so that the links displace whatever else the
+        // cache held (another link set applied before this one)
+        for (int r = 0; r < 6 && ok; r++)
+            ok = launch_dslash(prec, recon, prec, EPI_PLAIN, best.W, r & 1 ? t1 : t0, ntile, lat->s) == hipSuccess;
+        for (int trial = 0; trial < 3 && ok; trial++) {
+            const int reps = 10;
+            (void)hipEventRecord(e0, lat->s);
+            for (int r = 0; r < reps; r++)
+                (void)launch_dslash(prec, recon, prec, EPI_PLAIN, best.W, r & 1 ? t1 : t0, ntile, lat->s);
+            (void)hipEventRecord(e1, lat->s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tt = std::min(tt, 1000.0 * ms / reps);
+        }
+        if (ok && tt < best.us) {
+            best.cpol = 1;
+            best.us = tt;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     dvec_free(in);
@@ -505,7 +549,7 @@ TuneChoice pick_shape_mrhs(hisq_lattice lat, int prec, int recon, int nr, bool n
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return def;
     std::ostringstream ks;
-    ks << "mrhs:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << lat->ntile << ":nr" << nr;
+    ks << "mrhs2:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << lat->ntile << ":nr" << nr;
     std::string key = ks.str();
     for (auto &ch : key)
         if (ch == ' ') ch = '_';
@@ -589,6 +633,7 @@ hisq_status hisq_dslash(hisq_lattice lat, hisq_parity out_parity, hisq_prec prec
     memset(&a, 0, sizeof a);
     a.probs = lat->ddesc;
     a.remap = tc.remap;
+    a.cpol = tc.cpol;
     a.out_par = (int)out_parity;
     a.lslot = slot;
     if (flags & HISQ_DEVICE_PTR) {

@@ -89,7 +89,7 @@ hisq_status build_set(hisq_lattice lat0, SolveSet &S, const std::vector<hisq_lat
 }
 
 struct CgPlan {
-    int mode, recon, slot, W, remap;
+    int mode, recon, slot, W, remap, cpol;
     TuneChoice mrhs[5];   // shapes of the shared-link kernel per group size (one-lattice sets)
     int group64 = 0;      // one-lattice sets: FP64 shared-link group size (0: per-problem kernel)
     TuneChoice mrhs64;
@@ -125,6 +125,7 @@ static hipError_t enqueue_dslash(SolveSet &S, const CgPlan &pl, int prec, int ls
     const bool sloppy_op = lslot == pl.slot;
     const int W = sloppy_op ? pl.W : 8;
     const int recon = sloppy_op ? pl.recon : 18;
+    a.cpol = sloppy_op ? pl.cpol : 0;
     hipError_t e = launch_dslash(prec, recon, out_prec, epi, W, a, S.ntile, s);
     if (e != hipSuccess || fin == FIN_NONE) return e;
     return launch_finish(S.ddesc, S.dst, S.dpart, fin, want, 1, S.nprob, s);
@@ -342,7 +343,7 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
     const bool shared = S.one_lattice && mode == 1;
     TuneChoice tc = pick_shape(lat0, mode, recon, S.ddesc, S.dt2p, S.ntile, S.nsite, S.nprob,
                                shared || (prm.flags & HISQ_NO_TUNE) != 0);
-    CgPlan pl{mode, recon, slot, tc.W, tc.remap, {}};
+    CgPlan pl{mode, recon, slot, tc.W, tc.remap, tc.cpol, {}};
     if (shared) {
         const int group = S.nprob < 4 ? S.nprob : 4;
         pl.mrhs[group] = pick_shape_mrhs(lat0, mode, recon, group, (prm.flags & HISQ_NO_TUNE) != 0);
@@ -387,7 +388,8 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
     const bool use_graph = (prm.flags & HISQ_USE_GRAPH) != 0;
     if (use_graph) {
         std::ostringstream ks;
-        ks << mode << ":" << recon << ":" << tc.W << ":" << tc.remap << ":" << kchunk << ":" << S.one_lattice;
+        ks << mode << ":" << recon << ":" << tc.W << ":" << tc.remap << ":" << tc.cpol << ":" << kchunk << ":"
+           << S.one_lattice;
         for (int nr = 1; nr <= 4; nr++) ks << ":" << pl.mrhs[nr].W << pl.mrhs[nr].remap;
         ks << ":" << pl.group64 << pl.mrhs64.W << pl.mrhs64.remap << ":" << fused_step(S);
         if (S.gkey != ks.str() || !S.gexec) {

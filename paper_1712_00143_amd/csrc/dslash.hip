@@ -20,7 +20,7 @@
 
 namespace hisq {
 
-template <class LT, int R, class ST, class OT, int W, int EPI>
+template <class LT, int R, class ST, class OT, int W, int EPI, int CP>
 __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
 {
     using A = typename AccOf<LT>::type;
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
             RawLink<LT, R> raw[G];
 #pragma unroll
             for (int g = 0; g < G; g++)
-                load_link_raw_wave<LT, R>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
+                load_link_raw_wave<LT, R, CP>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
             Cx<A> v[G][3];
 #pragma unroll
             for (int g = 0; g < G; g++) load_spinor<ST, A>(in, voff + nb[g], v[g]);
@@ -168,18 +168,25 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
 
 // ------------------------------------------------------------- launchers
 
-template <class LT, int R, class ST, class OT, int EPI>
-static hipError_t launch_w(int W, const DslashLaunch &a, int nblocks, hipStream_t s)
+template <class LT, int R, class ST, class OT, int EPI, int CP>
+static hipError_t launch_wc(int W, const DslashLaunch &a, int nblocks, hipStream_t s)
 {
     switch (W) {
-    case 1: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 1, EPI>), dim3(nblocks), dim3(64), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 2, EPI>), dim3(nblocks), dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 4, EPI>), dim3(nblocks), dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 8, EPI>), dim3(nblocks), dim3(512), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 16, EPI>), dim3(nblocks), dim3(1024), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 1, EPI, CP>), dim3(nblocks), dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 2, EPI, CP>), dim3(nblocks), dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 4, EPI, CP>), dim3(nblocks), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 8, EPI, CP>), dim3(nblocks), dim3(512), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 16, EPI, CP>), dim3(nblocks), dim3(1024), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <class LT, int R, class ST, class OT, int EPI>
+static hipError_t launch_w(int W, const DslashLaunch &a, int nblocks, hipStream_t s)
+{
+    return a.cpol ? launch_wc<LT, R, ST, OT, EPI, 1>(W, a, nblocks, s)
+                  : launch_wc<LT, R, ST, OT, EPI, 0>(W, a, nblocks, s);
 }
 
 template <class LT, class ST, class OT, int EPI>

@@ -55,6 +55,7 @@ struct SolveSet {
 struct TuneChoice {
     int W = 4;
     int remap = 1;
+    int cpol = 0;   // Dslash link loads: 0 non-temporal, 1 temporal (DslashLaunch::cpol)
     double us = 0;
 };
 

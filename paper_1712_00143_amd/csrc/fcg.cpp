@@ -127,6 +127,7 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
         a.red = red;
         a.probs = S.ddesc;
         a.remap = tc.remap;
+        a.cpol = ls == slot ? tc.cpol : 0;   // the tuned policy belongs to the FP32 operator
         a.out_par = par;
         a.lslot = ls;
         a.want = want;
@@ -187,7 +188,7 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
         std::ostringstream ks;
         ks << (const void *)lat << ":" << (const void *)lat->ddesc << ":" << S.p.p << ":" << S.t.p << ":" << S.Ap.p << ":" << S.rlo.p << ":" << S.xlo.p
            << ":" << z.p << ":" << S.fred << ":" << S.dst << ":" << S.ddesc << ":" << S.dpart << ":" << nt << ":"
-           << slot << ":" << recon << ":" << tc.W << ":" << tc.remap << ":" << pslot << ":" << kchunk << ":"
+           << slot << ":" << recon << ":" << tc.W << ":" << tc.remap << ":" << tc.cpol << ":" << pslot << ":" << kchunk << ":"
            << ptc_graph_key(net);
         FcgGraphCache &G = ptc_fcg_graph(net);
         if (G.key != ks.str() || !G.exec) {

@@ -127,12 +127,16 @@ __device__ __forceinline__ void load_link_raw(const char *__restrict__ dirbase, 
 // The same loads through a buffer resource: `dirbase` must be the same for the
 // whole wavefront (one direction block), so the base and the chunk-plane
 // offsets live in scalar registers and each lane supplies only i * 16.  The
-// offsets are 32-bit: one direction block must stay below 4 GiB.
-template <class LT, int R>
+// offsets are 32-bit: one direction block must stay below 4 GiB.  CP = 0:
+// non-temporal loads (an operator larger than the Infinity Cache is streamed
+// once per application and should not evict the gathered vectors); CP = 1:
+// ordinary loads, so that an operator that fits the Infinity Cache stays
+// there from one application to the next.
+template <class LT, int R, int CP = 0>
 __device__ __forceinline__ void load_link_raw_wave(const char *dirbase, int i, int h, RawLink<LT, R> &raw)
 {
     using F = LinkFmt<LT, R>;
-    constexpr int NT = 2;   // cache policy: non-temporal (links are streamed once)
+    constexpr int NT = CP ? 0 : 2;   // cache-policy bits of the load
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void *)dirbase, (short)0, h * F::BYTES, 0x00020000);
 #pragma unroll

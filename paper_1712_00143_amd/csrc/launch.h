@@ -23,7 +23,8 @@ struct DslashLaunch {
     const double *bvec;
     double *partials;
     int fin;
-    int pad;
+    int cpol;               // link loads: 0 non-temporal (streamed past the caches), 1 temporal
+                            // (an operator that fits the Infinity Cache stays there between launches)
     double *red;            // non-null (AX/RES): block sum to red[tile] instead of partials
 };
 

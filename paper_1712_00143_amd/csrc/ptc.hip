@@ -61,7 +61,9 @@ __device__ __forceinline__ void path_load(const ProbDesc &pd, const LinkSet &ls,
         sp = 1 - par;
         using F = LinkFmt<LT, R>;
         const int d = 4 * mu + (fwd ? 0 : 1);
-        load_link_raw_wave<LT, R>((const char *)ls.ptr[par] + (size_t)d * h * F::BYTES, i, (int)h, raw);
+        // the fat links are re-read by every layer of every application: keep
+        // them cached (temporal loads)
+        load_link_raw_wave<LT, R, 1>((const char *)ls.ptr[par] + (size_t)d * h * F::BYTES, i, (int)h, raw);
     }
 #pragma unroll
     for (int c = 0; c < CIN; c++) {
