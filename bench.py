@@ -342,7 +342,10 @@ def run_headline(args):
                                       "what": "library streaming read of 1 GiB (non-temporal 16-byte loads)",
                                       "dslash_frac_of_read_ceiling": round(achieved / read_gbs, 4)},
                      "copy_ceiling": {"GB/s": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / PEAK_HBM_GBS, 4),
-                                      "what": "library copy of 1 GiB, read + written bytes"}},
+                                      "what": "library copy of 1 GiB, read + written bytes"},
+                     "cache": "both parities' FP32 links (151 MB) fit the 256 MB Infinity Cache; the tuner picks "
+                              "cached or streaming link loads by timing both, so part of the link stream may come "
+                              "from the cache at this size (the 32^4 line is beyond it)"},
         "dslash": dsl,
         "dslash_32^4_beyond_infinity_cache": hbm,
         "cg_time_to_1e-10": cg,
