@@ -55,7 +55,8 @@ typedef enum {
     HISQ_ERR_STATE = -4,          /* call out of order (e.g. no links loaded) */
     HISQ_ERR_RECON = -5,          /* links are not a * sign * SU(3): recon-12 impossible */
     HISQ_ERR_NOT_CONVERGED = -6,  /* maxiter reached; x and info hold the best iterate */
-    HISQ_ERR_BREAKDOWN = -7       /* non-positive p.Ap or non-finite scalar */
+    HISQ_ERR_BREAKDOWN = -7,      /* non-positive p.Ap or non-finite scalar */
+    HISQ_ERR_IO = -8              /* a file could not be written or read, or holds no matching network */
 } hisq_status;
 
 typedef enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16 = 2 } hisq_prec;
@@ -68,6 +69,10 @@ enum {
     HISQ_USE_GRAPH = 4,    /* solvers: replay captured HIP graphs of iteration chunks */
     HISQ_NO_TUNE = 8       /* use default launch shapes, skip the autotuner */
 };
+/* Environment: HISQ_TUNE=0 gives every call the default launch shapes (as
+ * HISQ_NO_TUNE does for one call); HISQ_TUNE_CACHE=<file> appends every tuned
+ * choice to a text file (one "key W remap cache-policy us" line each) and
+ * reads it back at start-up, so a later process skips the timing. */
 
 typedef struct {
     double tol;          /* target FP64 true relative residual ||b - A x|| / ||b|| */
@@ -197,6 +202,18 @@ hisq_status hisq_ptc_destroy(hisq_ptc net);
  * FP32 master copy and the FP16 inference copy. */
 hisq_status hisq_ptc_set_weights(hisq_ptc net, const double *w);
 hisq_status hisq_ptc_get_weights(hisq_ptc net, double *w);
+/* Checkpoint of a network: its shape, the FP32 master weights, the Adam
+ * moments and step count, in a small binary file (an 8-byte magic
+ * "HISQPTC1", then little-endian int32 version 1, nlayer, chans[0..nlayer],
+ * the complex weight count nw and the Adam step; then 2 nw float32 weights,
+ * 2 nw float32 first moments and 2 nw float32 second moments).  Load
+ * requires a network of the same shape, restores weights and Adam state
+ * exactly (training continues as if uninterrupted) and refreshes the FP16
+ * copies.  Stored pairs are not saved.  Errors: HISQ_ERR_ARG (null
+ * arguments), HISQ_ERR_IO (the file cannot be written or read, is not such a
+ * file, or was saved from a network of another shape). */
+hisq_status hisq_ptc_save(hisq_ptc net, const char *path);
+hisq_status hisq_ptc_load(hisq_ptc net, const char *path);
 /* Polynomial starting weights (a starting point for training, or a
  * preconditioner of its own): K = a (1 + c D_f^2 / lambda) on even vectors,
  * with D_f the one-hop fat-link part of D (the PTC transports with weights
@@ -256,6 +273,16 @@ hisq_status hisq_ptc_train(hisq_ptc net, int steps, int batch, double lr, unsign
  * iteration count exceeds params->maxiter / 2. */
 hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double mass, const double *b,
                             double *x, const hisq_solver_params *params, hisq_solver_info *info);
+
+/* FP64 true relative residuals ||b - A x|| / ||b|| at each reliable update
+ * (the last one is the final convergence check) of the last solve led by this
+ * handle: hisq_cg (problem 0), hisq_batch_cg led by it (problem = index in
+ * that call's arrays), the refinement of hisq_multishift_cg (problem = rhs *
+ * nshift + shift), or hisq_cg_learned (problem 0; after a hand-over, the plain
+ * CG that finished the solve).  Writes min(count, cap) values to out and the
+ * number recorded to *count.  Errors: HISQ_ERR_STATE (no solve yet),
+ * HISQ_ERR_ARG (problem out of range, null count, cap < 0). */
+hisq_status hisq_residual_history(hisq_lattice lat, int problem, double *out, int cap, int *count);
 
 /* ---- measurement ----
  *

@@ -79,6 +79,7 @@ void SolveSet::release()
     nsite = 0;
     mode = -1;
     hdesc.clear();
+    hist.clear();
 }
 
 SolveSet::~SolveSet() { release(); }
@@ -91,6 +92,8 @@ Tuner &Tuner::get()
 
 Tuner::Tuner()
 {
+    const char *t = getenv("HISQ_TUNE");
+    disabled_ = t && std::string(t) == "0";
     const char *p = getenv("HISQ_TUNE_CACHE");
     if (p && *p) {
         path_ = p;
@@ -168,6 +171,7 @@ const char *hisq_status_string(hisq_status s)
     case HISQ_ERR_RECON: return "links cannot be reconstructed from 12 reals";
     case HISQ_ERR_NOT_CONVERGED: return "not converged";
     case HISQ_ERR_BREAKDOWN: return "solver breakdown";
+    case HISQ_ERR_IO: return "file error";
     }
     return "unknown status";
 }
@@ -412,7 +416,7 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     TuneChoice def;
     def.W = prec == 0 ? 8 : 4;
     def.remap = 1;
-    if (no_tune) return def;
+    if (no_tune || Tuner::get().disabled()) return def;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return def;
     std::ostringstream ks;
@@ -545,7 +549,7 @@ TuneChoice pick_shape_mrhs(hisq_lattice lat, int prec, int recon, int nr, bool n
     TuneChoice def;
     def.W = prec == 0 ? 8 : 4;
     def.remap = 1;
-    if (no_tune || nr < 1 || nr > 4) return def;
+    if (no_tune || Tuner::get().disabled() || nr < 1 || nr > 4) return def;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return def;
     std::ostringstream ks;
@@ -612,6 +616,18 @@ TuneChoice pick_shape_mrhs(hisq_lattice lat, int prec, int recon, int nr, bool n
 }  // namespace hisq
 
 extern "C" {
+
+hisq_status hisq_residual_history(hisq_lattice lat, int problem, double *out, int cap, int *count)
+{
+    if (!lat || !count || cap < 0 || (cap > 0 && !out)) return set_err(lat, HISQ_ERR_ARG, "bad history arguments");
+    if (!lat->last_solve) return set_err(lat, HISQ_ERR_STATE, "no solve on this handle yet");
+    const auto &H = lat->last_solve->hist;
+    if (problem < 0 || problem >= (int)H.size()) return set_err(lat, HISQ_ERR_ARG, "problem index out of range");
+    const std::vector<double> &h = H[problem];
+    *count = (int)h.size();
+    for (int i = 0; i < cap && i < (int)h.size(); i++) out[i] = h[i];
+    return HISQ_OK;
+}
 
 hisq_status hisq_dslash(hisq_lattice lat, hisq_parity out_parity, hisq_prec prec, hisq_recon recon,
                         const void *in, void *out, int nrhs, int flags)

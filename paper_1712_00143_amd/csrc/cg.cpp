@@ -410,6 +410,15 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
     }
 
     std::vector<int> gave_up(S.nprob, 0);
+    S.hist.assign(S.nprob, std::vector<double>());
+    lat0->last_solve = &S;
+    auto record = [&]() {   // a reliable update ran: its FP64 true residual
+        for (int k = 0; k < S.nprob; k++) {
+            const SolveState &st = S.hst[k];
+            if (st.reliable > (int)S.hist[k].size() && st.bb > 0)
+                S.hist[k].push_back(std::sqrt(st.rr_true / st.bb));
+        }
+    };
     for (;;) {
         bool active = false;
         for (int k = 0; k < S.nprob; k++)
@@ -427,6 +436,7 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
             HIPCHK(lat0, enqueue_reliable(S, pl, s));
             HIPCHK(lat0, hipMemcpyAsync(S.hst, S.dst, sizeof(SolveState) * S.nprob, hipMemcpyDeviceToHost, s));
             HIPCHK(lat0, hipStreamSynchronize(s));
+            record();
         }
         for (int k = 0; k < S.nprob; k++) {
             SolveState &st = S.hst[k];

@@ -48,6 +48,9 @@ struct SolveSet {
     // flexible CG: z = M(r) and the compact tile sums of its fused iteration
     DVec fz;
     double *fred = nullptr;
+    // FP64 true relative residual of every problem at each reliable update of
+    // the last solve on this set
+    std::vector<std::vector<double>> hist;
     ~SolveSet();
     void release();
 };
@@ -67,12 +70,15 @@ class Tuner {
     static Tuner &get();
     bool lookup(const std::string &key, TuneChoice &c);
     void store(const std::string &key, const TuneChoice &c);
+    // HISQ_TUNE=0 in the environment: every launch takes its default shape
+    bool disabled() const { return disabled_; }
 
   private:
     Tuner();
     std::mutex mu_;
     std::map<std::string, TuneChoice> cache_;
     std::string path_;
+    bool disabled_ = false;
 };
 
 }  // namespace hisq
@@ -93,6 +99,7 @@ struct hisq_lattice_s {
     hisq::SolveSet batch;      // batched solves led by this handle
     hisq::SolveSet msref;      // multi-shift refinement (one problem per rhs x shift)
     hisq::SolveSet fcg;        // flexible CG with the learned preconditioner
+    hisq::SolveSet *last_solve = nullptr;   // the set of the last solve led by this handle
     hisq::DVec tmp_in, tmp_out, tmp64a, tmp64b;  // host-pointer Dslash staging
     hisq::ProbDesc *ddesc = nullptr;             // this lattice alone
     double *dpart = nullptr;

@@ -210,6 +210,8 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
     }
     hipGraphExec_t gexec = use_graph ? ptc_fcg_graph(net).exec : nullptr;
     int fell_back = 0;
+    S.hist.assign(1, std::vector<double>());
+    lat->last_solve = &S;
     for (;;) {
         if (use_graph) HIPCHK(lat, hipGraphLaunch(gexec, s));
         else
@@ -222,6 +224,7 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
             HIPCHK(lat, dslash(0, 0, 18, 8, 0, EPI_RES, FIN_TRUERES, ST_RELIABLE, S.thi, S.rhi, &S.xhi));
             HIPCHK(lat, hipMemcpyAsync(&hs, S.dst, sizeof hs, hipMemcpyDeviceToHost, s));
             HIPCHK(lat, hipStreamSynchronize(s));
+            if (hs.bb > 0) S.hist[0].push_back(std::sqrt(hs.rr_true / hs.bb));
             if (hs.status == ST_RESUME) {
                 if (hs.iter >= hs.maxiter) break;
                 // continue from the true residual: r = r_hi, z = M(r), new

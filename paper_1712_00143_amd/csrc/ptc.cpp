@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <random>
 #include <string>
@@ -125,6 +126,7 @@ int pick_layer_waves(hisq_lattice lat, int lslot, int prec, int recon, bool w16,
         if (ch == ' ') ch = '_';
     TuneChoice c;
     if (Tuner::get().lookup(k, c)) return c.W;
+    if (Tuner::get().disabled()) return 3;
     const long long h = lat->h;
     float *in = nullptr, *out = nullptr;
     if (hipMalloc(&in, sizeof(float) * (size_t)batch * cin * 2 * h * 6) != hipSuccess ||
@@ -704,6 +706,72 @@ hisq_status hisq_ptc_harvest(hisq_ptc n, hisq_lattice lat, double mass, const do
     if (keep > 0) n->pairs.push_back(pb);
     else (void)hipFree(pb.mem);
     if (npairs) *npairs = keep;
+    return HISQ_OK;
+}
+
+// Checkpoint file: magic, int32 header, then the FP32 weights and the Adam
+// moments as stored on the device (host byte order: little-endian).
+static const char PTC_MAGIC[8] = {'H', 'I', 'S', 'Q', 'P', 'T', 'C', '1'};
+
+hisq_status hisq_ptc_save(hisq_ptc n, const char *path)
+{
+    if (!n || !path) return HISQ_ERR_ARG;
+    hisq_lattice lat = n->lat;
+    const size_t nf = (size_t)2 * n->nw;
+    std::vector<float> w(nf), m(nf), v(nf);
+    HIPCHK(lat, hipSetDevice(n->device));
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    HIPCHK(lat, hipMemcpy(w.data(), n->w32, nf * 4, hipMemcpyDeviceToHost));
+    HIPCHK(lat, hipMemcpy(m.data(), n->m, nf * 4, hipMemcpyDeviceToHost));
+    HIPCHK(lat, hipMemcpy(v.data(), n->v, nf * 4, hipMemcpyDeviceToHost));
+    std::vector<int32_t> hdr{1, n->nlayer};
+    for (int c : n->chans) hdr.push_back(c);
+    hdr.push_back(n->nw);
+    hdr.push_back(n->step);
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return set_err(lat, HISQ_ERR_IO, std::string("cannot open for writing: ") + path);
+    bool ok = std::fwrite(PTC_MAGIC, 1, 8, f) == 8 &&
+              std::fwrite(hdr.data(), 4, hdr.size(), f) == hdr.size() &&
+              std::fwrite(w.data(), 4, nf, f) == nf && std::fwrite(m.data(), 4, nf, f) == nf &&
+              std::fwrite(v.data(), 4, nf, f) == nf;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return set_err(lat, HISQ_ERR_IO, std::string("write failed: ") + path);
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_load(hisq_ptc n, const char *path)
+{
+    if (!n || !path) return HISQ_ERR_ARG;
+    hisq_lattice lat = n->lat;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return set_err(lat, HISQ_ERR_IO, std::string("cannot open for reading: ") + path);
+    const size_t nf = (size_t)2 * n->nw;
+    char magic[8];
+    std::vector<int32_t> hdr((size_t)n->nlayer + 5);
+    std::vector<float> w(nf), m(nf), v(nf);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, PTC_MAGIC, 8) == 0;
+    // version and nlayer first, so that another shape is told apart before
+    // reading a header of the wrong length
+    ok = ok && std::fread(hdr.data(), 4, 2, f) == 2 && hdr[0] == 1 && hdr[1] == n->nlayer;
+    ok = ok && std::fread(hdr.data() + 2, 4, hdr.size() - 2, f) == hdr.size() - 2;
+    if (ok)
+        for (int l = 0; l <= n->nlayer; l++) ok = ok && hdr[2 + l] == n->chans[l];
+    ok = ok && hdr[3 + n->nlayer] == n->nw && hdr[4 + n->nlayer] >= 0;
+    ok = ok && std::fread(w.data(), 4, nf, f) == nf && std::fread(m.data(), 4, nf, f) == nf &&
+         std::fread(v.data(), 4, nf, f) == nf;
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;   // nothing after the moments
+    std::fclose(f);
+    if (!ok) return set_err(lat, HISQ_ERR_IO, std::string("not a checkpoint of a network of this shape: ") + path);
+    HIPCHK(lat, hipSetDevice(n->device));
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    HIPCHK(lat, hipMemcpy(n->w32, w.data(), nf * 4, hipMemcpyHostToDevice));
+    HIPCHK(lat, hipMemcpy(n->m, m.data(), nf * 4, hipMemcpyHostToDevice));
+    HIPCHK(lat, hipMemcpy(n->v, v.data(), nf * 4, hipMemcpyHostToDevice));
+    HIPCHK(lat, launch_to_half(n->w32, n->w16, (int)nf, lat->s));
+    HIPCHK(lat, refresh_adjoint(n, lat->s));
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    n->step = hdr[4 + n->nlayer];
     return HISQ_OK;
 }
 

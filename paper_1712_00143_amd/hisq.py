@@ -27,6 +27,7 @@ HISQ_ERR_STATE = -4
 HISQ_ERR_RECON = -5
 HISQ_ERR_NOT_CONVERGED = -6
 HISQ_ERR_BREAKDOWN = -7
+HISQ_ERR_IO = -8
 
 HISQ_F64, HISQ_F32, HISQ_F16 = 0, 1, 2
 HISQ_RECON_18, HISQ_RECON_12 = 18, 12
@@ -39,7 +40,8 @@ EXPORTS = [
     "hisq_batch_cg", "hisq_ptc_create", "hisq_ptc_destroy", "hisq_ptc_set_weights",
     "hisq_ptc_get_weights", "hisq_ptc_layer_forward", "hisq_ptc_layer_backward", "hisq_ptc_apply",
     "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
-    "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss",
+    "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss", "hisq_ptc_save", "hisq_ptc_load",
+    "hisq_residual_history",
 ]
 
 
@@ -218,6 +220,18 @@ class Lattice:
             _check(st, self.handle, "hisq_cg")
         return x, info.as_dict()
 
+    def residual_history(self, problem=0):
+        """FP64 true relative residuals at each reliable update of the last
+        solve led by this handle (see hisq_residual_history)."""
+        n = ctypes.c_int(0)
+        _check(lib().hisq_residual_history(self.handle, ctypes.c_int(problem), None, ctypes.c_int(0),
+                                           ctypes.byref(n)), self.handle, "hisq_residual_history")
+        out = np.zeros(max(n.value, 1), dtype=np.float64)
+        _check(lib().hisq_residual_history(self.handle, ctypes.c_int(problem),
+                                           out.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(n.value),
+                                           ctypes.byref(n)), self.handle, "hisq_residual_history")
+        return out[:n.value]
+
     def multishift_cg(self, mass, shifts, b, x=None, params=None, raise_on_fail=True):
         """b: [nrhs][h][3] complex (host array), or a device FP64 tensor of
         nrhs*h*6 reals with x a device tensor of nrhs*nshift*h*6 reals;
@@ -296,6 +310,14 @@ class PTC:
                                                   ctypes.c_int(iters),
                                                   ctypes.byref(lam)), "hisq_ptc_init_polynomial")
         return lam.value
+
+    def save(self, path):
+        """Checkpoint: shape, FP32 weights and Adam state (not the pairs)."""
+        self._err(lib().hisq_ptc_save(self.handle, os.fsencode(path)), "hisq_ptc_save")
+
+    def load(self, path):
+        """Restore a checkpoint written by save() from a network of this shape."""
+        self._err(lib().hisq_ptc_load(self.handle, os.fsencode(path)), "hisq_ptc_load")
 
     def set_loss(self, loss):
         """HISQ_LOSS_ENERGY (the default) or HISQ_LOSS_EUCLIDEAN."""

@@ -281,3 +281,46 @@ def test_cg_above_fused_step_size(sloppy, recon):
     assert info["converged"] == 1
     assert oracle.true_residual(dims, fat, lng, 0.05, b, x) <= 1e-10
     lat.close()
+
+
+def test_residual_history():
+    """The FP64 true residual of every reliable update is recorded: one per
+    reliable update, the last equal to the reported (and the oracle's) true
+    residual of the solution, the earlier ones above the target; batched
+    solves keep one history per problem."""
+    H = _hisq()
+    dims = (8, 8, 8, 12)
+    fat, lng = synth.make_links(dims, 0.2, seed=78)
+    m = 0.05
+    b = synth.gaussian_even(dims, 578)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    with pytest.raises(H.HisqError) as ei:
+        lat.residual_history()
+    assert ei.value.status == H.HISQ_ERR_STATE
+    x, info = lat.cg(m, b, params=H.hisq_default_params(tol=1e-10, sloppy=1))
+    hist = lat.residual_history()
+    assert len(hist) == info["reliable_updates"] >= 2
+    assert hist[-1] == info["true_residual"]
+    tr = oracle.true_residual(dims, fat, lng, m, b, x)
+    assert abs(hist[-1] - tr) <= 1e-6 * tr
+    assert np.all(hist[:-1] > 1e-10) and hist[-1] <= 1e-10
+    with pytest.raises(H.HisqError) as ei:
+        lat.residual_history(1)
+    assert ei.value.status == H.HISQ_ERR_ARG
+    # batched: one history per problem, on the leading handle
+    d2 = (4, 4, 4, 8)
+    f2, l2 = synth.make_links(d2, 0.3, seed=79)
+    L2 = H.Lattice(d2)
+    L2.load_links(f2, l2)
+    L2.prepare_links(1, 18)
+    b2 = synth.gaussian_even(d2, 579)
+    xs, infos = H.hisq_batch_cg([lat, L2], [m, 0.1], [b, b2], params=H.hisq_default_params(tol=1e-10, sloppy=1))
+    for k in range(2):
+        hk = lat.residual_history(k)
+        assert len(hk) == infos[k]["reliable_updates"] and hk[-1] == infos[k]["true_residual"]
+    tr2 = oracle.true_residual(d2, f2, l2, 0.1, b2, xs[1])
+    assert abs(lat.residual_history(1)[-1] - tr2) <= 1e-6 * tr2
+    L2.close()
+    lat.close()

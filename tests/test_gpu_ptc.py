@@ -382,3 +382,45 @@ def test_fcg_graph_replay_matches_eager():
     assert ie["iters"] == ig["iters"] and np.array_equal(xe, xg)
     net.close()
     lat.close()
+
+
+def test_checkpoint_save_load(tmp_path):
+    """A saved network restores exactly: the same weights, and training goes
+    on from the restored Adam state as it does in the network it came from.
+    Files of another shape, foreign files and missing files are refused."""
+    H = _hisq()
+    dims = (4, 4, 4, 6)
+    fat, lng = synth.make_links(dims, 0.25, seed=4010)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    chans = (1, 2, 2, 1)
+    b = synth.gaussian_even(dims, 4510)
+    a = H.PTC(lat, chans)
+    a.set_weights(_rand_w(chans, 9, scale=0.3))
+    a.harvest(lat, 0.1, b, every=4, maxpairs=8)
+    a.train(3, batch=2, lr=1e-3, seed=5)
+    path = str(tmp_path / "net.ptc")
+    a.save(path)
+    c = H.PTC(lat, chans)
+    c.harvest(lat, 0.1, b, every=4, maxpairs=8)
+    c.load(path)
+    for wa, wc in zip(a.get_weights(), c.get_weights()):
+        assert np.array_equal(wa, wc)
+    la = a.train(2, batch=2, lr=1e-3, seed=6)
+    lc = c.train(2, batch=2, lr=1e-3, seed=6)
+    assert np.array_equal(la, lc)
+    for wa, wc in zip(a.get_weights(), c.get_weights()):
+        assert np.array_equal(wa, wc)
+    other = H.PTC(lat, (1, 4, 4, 1))
+    for bad in [path, str(tmp_path / "missing.ptc")]:
+        with pytest.raises(H.HisqError) as ei:
+            (other if bad == path else c).load(bad)
+        assert ei.value.status == H.HISQ_ERR_IO
+    junk = tmp_path / "junk.ptc"
+    junk.write_bytes(b"HISQPTC1" + b"\x00" * 12)
+    with pytest.raises(H.HisqError) as ei:
+        c.load(str(junk))
+    assert ei.value.status == H.HISQ_ERR_IO
+    for n in (a, c, other):
+        n.close()
+    lat.close()
