@@ -67,7 +67,10 @@ enum {
     HISQ_DEVICE_PTR = 1,   /* vector / link pointers are device pointers */
     HISQ_X_IS_GUESS = 2,   /* solvers: x holds an initial guess (else cold start) */
     HISQ_USE_GRAPH = 4,    /* solvers: replay captured HIP graphs of iteration chunks */
-    HISQ_NO_TUNE = 8       /* use default launch shapes, skip the autotuner */
+    HISQ_NO_TUNE = 8,      /* use default launch shapes, skip the autotuner */
+    HISQ_STOP_STAGNATION = 16   /* CG solvers: give up (HISQ_ERR_NOT_CONVERGED, x the last
+                                   reliable update's iterate) when three reliable updates in a
+                                   row bring no FP64 true residual below the one before them */
 };
 /* Environment: HISQ_TUNE=0 gives every call the default launch shapes (as
  * HISQ_NO_TUNE does for one call); HISQ_TUNE_CACHE=<file> appends every tuned
@@ -82,7 +85,8 @@ typedef struct {
     hisq_recon recon;    /* link reconstruction of the sloppy operator */
     double delta;        /* reliable update when ||r|| < delta * max ||r|| since the last one */
     int check_every;     /* iterations per launched chunk between host status checks */
-    int flags;           /* HISQ_DEVICE_PTR | HISQ_X_IS_GUESS | HISQ_USE_GRAPH | HISQ_NO_TUNE */
+    int flags;           /* HISQ_DEVICE_PTR | HISQ_X_IS_GUESS | HISQ_USE_GRAPH | HISQ_NO_TUNE |
+                            HISQ_STOP_STAGNATION */
 } hisq_solver_params;
 
 typedef struct {

@@ -16,6 +16,7 @@
 // HIP graph) between host reads of the per-problem status.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -437,6 +438,20 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
             HIPCHK(lat0, hipMemcpyAsync(S.hst, S.dst, sizeof(SolveState) * S.nprob, hipMemcpyDeviceToHost, s));
             HIPCHK(lat0, hipStreamSynchronize(s));
             record();
+            if (prm.flags & HISQ_STOP_STAGNATION)
+                for (int k = 0; k < S.nprob; k++) {
+                    // three reliable updates in a row, none below the true
+                    // residual before them: stop with the current iterate
+                    const std::vector<double> &hk = S.hist[k];
+                    const size_t n = hk.size();
+                    if (S.hst[k].status != ST_RUNNING || n < 4) continue;
+                    if (std::min(hk[n - 1], std::min(hk[n - 2], hk[n - 3])) < hk[n - 4]) continue;
+                    int v = ST_IDLE;
+                    HIPCHK(lat0, hipMemcpyAsync(&S.dst[k].status, &v, sizeof v, hipMemcpyHostToDevice, s));
+                    HIPCHK(lat0, hipStreamSynchronize(s));
+                    S.hst[k].status = ST_IDLE;
+                    gave_up[k] = 1;
+                }
         }
         for (int k = 0; k < S.nprob; k++) {
             SolveState &st = S.hst[k];

@@ -33,6 +33,7 @@ HISQ_F64, HISQ_F32, HISQ_F16 = 0, 1, 2
 HISQ_RECON_18, HISQ_RECON_12 = 18, 12
 HISQ_EVEN, HISQ_ODD = 0, 1
 HISQ_DEVICE_PTR, HISQ_X_IS_GUESS, HISQ_USE_GRAPH, HISQ_NO_TUNE = 1, 2, 4, 8
+HISQ_STOP_STAGNATION = 16
 
 EXPORTS = [
     "hisq_default_params", "hisq_status_string", "hisq_last_error", "hisq_create", "hisq_destroy",

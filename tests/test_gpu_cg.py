@@ -324,3 +324,45 @@ def test_residual_history():
     assert abs(lat.residual_history(1)[-1] - tr2) <= 1e-6 * tr2
     L2.close()
     lat.close()
+
+
+def test_solves_are_bitwise_reproducible():
+    """No atomics and fixed reduction orders: the same solve twice gives the
+    same iterate, iteration count and residual history, bit for bit."""
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    fat, lng = synth.make_links(dims, 0.25, seed=81)
+    b = synth.gaussian_even(dims, 581)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    out = []
+    for _ in range(2):
+        x, info = lat.cg(0.02, b, params=H.hisq_default_params(tol=1e-10, sloppy=1, flags=H.HISQ_USE_GRAPH))
+        out.append((x, info["iters"], lat.residual_history()))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
+    lat.close()
+
+
+def test_stagnation_stop():
+    """With HISQ_STOP_STAGNATION an unreachable target (1e-17, below FP64
+    rounding of the true residual) ends after the true residual stops falling,
+    long before maxiter, with HISQ_ERR_NOT_CONVERGED and the last iterate,
+    which is as good as FP64 allows."""
+    H = _hisq()
+    dims = (4, 4, 4, 8)
+    fat, lng = synth.make_links(dims, 0.25, seed=82)
+    b = synth.gaussian_even(dims, 582)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    p = H.hisq_default_params(tol=1e-17, sloppy=1, flags=H.HISQ_STOP_STAGNATION)
+    p.maxiter = 50000
+    x, info = lat.cg(0.1, b, params=p, raise_on_fail=False)
+    assert info["converged"] == 0 and info["status"] == H.HISQ_ERR_NOT_CONVERGED
+    assert info["iters"] < 5000, info["iters"]
+    hist = lat.residual_history()
+    assert len(hist) >= 4 and min(hist[-3:]) >= hist[-4]
+    assert oracle.true_residual(dims, fat, lng, 0.1, b, x) <= 1e-13
+    lat.close()
