@@ -281,8 +281,8 @@ hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double mass, const d
 /* FP64 true relative residuals ||b - A x|| / ||b|| at each reliable update
  * (the last one is the final convergence check) of the last solve led by this
  * handle: hisq_cg (problem 0), hisq_batch_cg led by it (problem = index in
- * that call's arrays), the refinement of hisq_multishift_cg (problem = rhs *
- * nshift + shift), or hisq_cg_learned (problem 0; after a hand-over, the plain
+ * that call's arrays), the refinement of hisq_multishift_cg (problem = shift *
+ * nrhs + rhs), or hisq_cg_learned (problem 0; after a hand-over, the plain
  * CG that finished the solve).  Writes min(count, cap) values to out and the
  * number recorded to *count.  Errors: HISQ_ERR_STATE (no solve yet),
  * HISQ_ERR_ARG (problem out of range, null count, cap < 0). */

@@ -244,18 +244,22 @@ extern "C" hisq_status hisq_multishift_cg(hisq_lattice lat, double mass, int nsh
     HIPCHK(lat, hipStreamSynchronize(s));
     const double t_krylov = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 
-    // refinement: one batched mixed CG over all (j, k), warm start
+    // refinement: one batched mixed CG over all (j, k), warm start.  The
+    // problems are ordered shift-major (set index k * nrhs + j): the shared-
+    // link kernel groups neighbours, and one shift's sources need about the
+    // same number of iterations, so a group stops reading links when its
+    // shifts are done instead of waiting for the slowest shift of a source.
     const int nprob = nrhs * nshift;
     std::vector<hisq_lattice> lats(nprob, lat);
     std::vector<double> ms(nprob, mass), sig(nprob);
     std::vector<const double *> bp(nprob);
     std::vector<double *> xp(nprob);
-    for (int j = 0; j < nrhs; j++)
-        for (int k = 0; k < nshift; k++) {
-            const int q = j * nshift + k;
-            sig[q] = shifts[k];
-            bp[q] = W.b64 + (size_t)j * h * 6;
-            xp[q] = W.x64 + (size_t)q * h * 6;
+    for (int k = 0; k < nshift; k++)
+        for (int j = 0; j < nrhs; j++) {
+            const int pi = k * nrhs + j, q = j * nshift + k;
+            sig[pi] = shifts[k];
+            bp[pi] = W.b64 + (size_t)j * h * 6;
+            xp[pi] = W.x64 + (size_t)q * h * 6;
         }
     hisq_status st = build_set(lat, lat->msref, lats, ms, 0.0, &sig);
     if (st != HISQ_OK) return st;
@@ -265,6 +269,11 @@ extern "C" hisq_status hisq_multishift_cg(hisq_lattice lat, double mass, int nsh
     // short chunks keep problems from idling until the end of a long one
     const int ce = prm.check_every > 0 ? prm.check_every : 16;
     rp.check_every = ce < 4 ? ce : 4;
+    // A warm-started refinement has one to three decades to go: a reliable
+    // update per decade would be an FP64 multi-RHS Dslash pair (the costliest
+    // launches of the solve) each time a group of shifts crosses a decade, so
+    // the sloppy recursion is left to run two decades between them.
+    rp.delta = prm.delta < 0.01 ? prm.delta : 0.01;
     if (rp.sloppy == HISQ_F64) rp.sloppy = HISQ_F32;
     if (!lat->ls[(int)rp.sloppy * 2 + (recon == 12)].valid) rp.recon = HISQ_RECON_18;
     if (!lat->ls[(int)rp.sloppy * 2 + (rp.recon == 12)].valid) {
@@ -280,11 +289,11 @@ extern "C" hisq_status hisq_multishift_cg(hisq_lattice lat, double mass, int nsh
     if (info) {
         for (int j = 0; j < nrhs; j++)
             for (int k = 0; k < nshift; k++) {
-                const int q = j * nshift + k;
+                const int q = j * nshift + k, pi = k * nrhs + j;
                 hisq_solver_info &in = info[q];
-                in = rinfo[q];
-                in.iters = W.hms[j].iters[k] + rinfo[q].iters;
-                in.refine_iters = rinfo[q].iters;
+                in = rinfo[pi];
+                in.iters = W.hms[j].iters[k] + rinfo[pi].iters;
+                in.refine_iters = rinfo[pi].iters;
                 in.time_s = elapsed;
                 in.t_done_s = t_krylov;   // end of the shared Krylov phase
                 const double site = (double)(link_site_bytes(kprec, recon)) / nrhs + 2.0 * 24;

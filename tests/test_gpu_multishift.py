@@ -13,7 +13,7 @@ def _hisq():
     return hisq
 
 
-@pytest.mark.parametrize("nrhs", [2, 3, 4, 6])
+@pytest.mark.parametrize("nrhs", [2, 3, 4, 6, 11])
 @pytest.mark.parametrize("prec,recon,tol", [(1, 18, 5e-6), (1, 12, 5e-6), (2, 12, 2e-3)])
 def test_mrhs_dslash_matches_oracle(nrhs, prec, recon, tol):
     H = _hisq()
