@@ -34,6 +34,10 @@ def test_library_exports_every_declared_symbol():
 def test_status_strings():
     assert hisq.hisq_status_string(0) == "ok"
     assert "reconstruct" in hisq.hisq_status_string(hisq.HISQ_ERR_RECON)
+    assert "file" in hisq.hisq_status_string(hisq.HISQ_ERR_IO)
+    # every declared status has its own message
+    codes = [0, -1, -2, -3, -4, -5, -6, -7, -8]
+    assert len({hisq.hisq_status_string(c) for c in codes}) == len(codes)
 
 
 def test_create_rejects_odd_extents_without_gpu():
@@ -54,3 +58,21 @@ def test_null_handle_calls_fail_cleanly():
     L = hisq.lib()
     assert L.hisq_destroy(None) == hisq.HISQ_ERR_ARG
     assert L.hisq_prepare_links(None, 1, 18) == hisq.HISQ_ERR_ARG
+    n = ctypes.c_int(0)
+    assert L.hisq_residual_history(None, 0, None, 0, ctypes.byref(n)) == hisq.HISQ_ERR_ARG
+    assert L.hisq_ptc_save(None, b"x") == hisq.HISQ_ERR_ARG
+    assert L.hisq_ptc_load(None, b"x") == hisq.HISQ_ERR_ARG
+    assert L.hisq_ptc_set_loss(None, 0) == hisq.HISQ_ERR_ARG
+    assert L.hisq_ptc_init_polynomial(None, ctypes.c_double(4.0), ctypes.c_double(1.2), 30, None) == \
+        hisq.HISQ_ERR_ARG
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark runs on one GPU; asking for more exits with a message
+    (before it touches a GPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
