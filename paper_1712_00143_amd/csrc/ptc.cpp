@@ -110,9 +110,10 @@ PtcLaunch base_launch(hisq_lattice lat, int lslot)
     return a;
 }
 
-// Waves per block of the layer kernel (1, 3 or 9 of the 9 transport paths
-// each) for this geometry, channel pair, batch and link format: timed once on
-// scratch activations, then cached.  Must not run under stream capture.
+// Waves per block of the layer kernel (1, 3, 5 or 9, sharing the 9
+// transport paths) for this geometry, channel pair, batch and link format:
+// timed once on scratch activations, then cached.  Must not run under stream
+// capture.
 int pick_layer_waves(hisq_lattice lat, int lslot, int prec, int recon, bool w16, const void *w, int cin, int cout,
                      int in_zero, int npar, int batch, hipStream_t stream)
 {
@@ -153,15 +154,15 @@ int pick_layer_waves(hisq_lattice lat, int lslot, int prec, int recon, bool w16,
     best.us = 1e30;
     // three interleaved trials of every shape, each shape's best trial counts
     // (a single short trial is at the mercy of clock ramps and neighbours)
-    const int Ws[3] = {1, 3, 9};
-    double tbest[3] = {1e30, 1e30, 1e30};
-    bool okw[3] = {true, true, true};
-    for (int j = 0; j < 3; j++)
+    const int Ws[4] = {1, 3, 5, 9};
+    double tbest[4] = {1e30, 1e30, 1e30, 1e30};
+    bool okw[4] = {true, true, true, true};
+    for (int j = 0; j < 4; j++)
         for (int r = 0; r < 2 && okw[j]; r++)
             okw[j] = launch_ptc_layer(prec, recon, w16, cin, cout, Ws[j], a, lat->ntile * npar, batch, stream) ==
                      hipSuccess;
     for (int trial = 0; trial < 3; trial++)
-        for (int j = 0; j < 3; j++) {
+        for (int j = 0; j < 4; j++) {
             if (!okw[j]) continue;
             const int reps = 10;
             (void)hipEventRecord(e0, stream);
@@ -173,7 +174,7 @@ int pick_layer_waves(hisq_lattice lat, int lslot, int prec, int recon, bool w16,
             (void)hipEventElapsedTime(&ms, e0, e1);
             tbest[j] = std::min(tbest[j], 1000.0 * ms / reps);
         }
-    for (int j = 0; j < 3; j++)
+    for (int j = 0; j < 4; j++)
         if (okw[j] && tbest[j] < best.us) {
             best.us = tbest[j];
             best.W = Ws[j];

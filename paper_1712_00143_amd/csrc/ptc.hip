@@ -434,6 +434,7 @@ static hipError_t layer_w(int W, const PtcLaunch &a, dim3 g, hipStream_t s)
     switch (W) {
     case 1: hipLaunchKernelGGL((k_ptc_layer<LT, R, WT, CIN, COUT, 1>), g, dim3(64), 0, s, a); break;
     case 3: hipLaunchKernelGGL((k_ptc_layer<LT, R, WT, CIN, COUT, 3>), g, dim3(192), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_ptc_layer<LT, R, WT, CIN, COUT, 5>), g, dim3(320), 0, s, a); break;
     case 9: hipLaunchKernelGGL((k_ptc_layer<LT, R, WT, CIN, COUT, 9>), g, dim3(576), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
