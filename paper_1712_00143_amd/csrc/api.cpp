@@ -437,10 +437,10 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     (void)hipEventCreate(&e1);
     TuneChoice best = def;
     best.us = 1e30;
-    // Start from a cache that holds none of these links (the packing kernels
-    // that wrote them, or another link set, may have left them in the
-    // Infinity Cache): overwrite twice its 256 MB.
-    {
+    // Overwrite twice the Infinity Cache's 256 MB, so that a measurement does
+    // not start from links that the packing kernels or an earlier trial left
+    // there.
+    auto flush_cache = [&]() {
         void *junk = nullptr;
         const size_t jb = (size_t)512 << 20;
         if (hipMalloc(&junk, jb) == hipSuccess) {
@@ -449,7 +449,8 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
             (void)hipFree(junk);
         }
         (void)hipGetLastError();
-    }
+    };
+    flush_cache();
     // every candidate shape, timed on both output parities in turn (the
     // solvers alternate them), best of three interleaved trials of 10 launches
     const int Ws[] = {1, 2, 4, 8, 16};
@@ -506,32 +507,34 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
             }
     // The link-load policy for the chosen shape: temporal loads win when both
     // parities' links fit the Infinity Cache (they stay there between the
-    // alternating launches), non-temporal loads when they do not.  The shapes
-    // above were timed with non-temporal loads, which do not fill the cache;
-    // the temporal trials come after them, so neither measurement profits
-    // from the other's cache contents.
+    // alternating launches), non-temporal loads when they do not.  Each policy
+    // is timed the same way from the same start: an emptied cache, a few
+    // warm-up applications (so that whatever the policy keeps in the cache is
+    // there), then the best of three trials of 10 launches.
     if (best.us < 1e29) {
-        double tt = 1e30;
-        const DslashLaunch t0 = make(best.remap, 0, 1), t1 = make(best.remap, 1, 1);
+        double tpol[2] = {1e30, 1e30};
         bool ok = true;
-        // a few passes first, so that the links displace whatever else the
-        // cache held (another link set applied before this one)
-        for (int r = 0; r < 6 && ok; r++)
-            ok = launch_dslash(prec, recon, prec, EPI_PLAIN, best.W, r & 1 ? t1 : t0, ntile, lat->s) == hipSuccess;
-        for (int trial = 0; trial < 3 && ok; trial++) {
-            const int reps = 10;
-            (void)hipEventRecord(e0, lat->s);
-            for (int r = 0; r < reps; r++)
-                (void)launch_dslash(prec, recon, prec, EPI_PLAIN, best.W, r & 1 ? t1 : t0, ntile, lat->s);
-            (void)hipEventRecord(e1, lat->s);
-            (void)hipEventSynchronize(e1);
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            tt = std::min(tt, 1000.0 * ms / reps);
+        for (int cp = 0; cp < 2 && ok; cp++) {
+            const DslashLaunch a0 = make(best.remap, 0, cp), a1 = make(best.remap, 1, cp);
+            flush_cache();
+            for (int r = 0; r < 6 && ok; r++)
+                ok = launch_dslash(prec, recon, prec, EPI_PLAIN, best.W, r & 1 ? a1 : a0, ntile, lat->s) ==
+                     hipSuccess;
+            for (int trial = 0; trial < 3 && ok; trial++) {
+                const int reps = 10;
+                (void)hipEventRecord(e0, lat->s);
+                for (int r = 0; r < reps; r++)
+                    (void)launch_dslash(prec, recon, prec, EPI_PLAIN, best.W, r & 1 ? a1 : a0, ntile, lat->s);
+                (void)hipEventRecord(e1, lat->s);
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                tpol[cp] = std::min(tpol[cp], 1000.0 * ms / reps);
+            }
         }
-        if (ok && tt < best.us) {
-            best.cpol = 1;
-            best.us = tt;
+        if (ok) {
+            best.cpol = tpol[1] < tpol[0] ? 1 : 0;
+            best.us = std::min(tpol[0], tpol[1]);
         }
     }
     (void)hipEventDestroy(e0);
