@@ -9,6 +9,7 @@
 #include <cstring>
 #include <fstream>
 #include <sstream>
+#include <vector>
 
 #include "engine.h"
 #include "solver.h"
@@ -420,7 +421,7 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return def;
     std::ostringstream ks;
-    ks << "dslash2:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << ntile << ":n" << nprob;
+    ks << "dslash3:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << ntile << ":n" << nprob;
     std::string key = ks.str();
     for (auto &ch : key)
         if (ch == ' ') ch = '_';
@@ -505,37 +506,60 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
                 best.W = Ws[wi];
                 best.remap = remap;
             }
-    // The link-load policy for the chosen shape: temporal loads win when both
+    // The link-load policy for the chosen shape: all links cached when both
     // parities' links fit the Infinity Cache (they stay there between the
-    // alternating launches), non-temporal loads when they do not.  Each policy
-    // is timed the same way from the same start: an emptied cache, a few
-    // warm-up applications (so that whatever the policy keeps in the cache is
-    // there), then the best of three trials of 10 launches.
+    // alternating launches); when they do not, a part of the direction blocks
+    // cached (a stream larger than the cache would only evict itself) or none.
+    // Each candidate is timed the same way from the same start: an emptied
+    // cache, six warm-up applications, then the best of three trials of 10.
+    // A partly cached operator changes which block shape and tile order are
+    // best, so there every shape and order is tried with every candidate;
+    // otherwise the ones found above are kept.
     if (best.us < 1e29) {
-        double tpol[2] = {1e30, 1e30};
-        bool ok = true;
-        for (int cp = 0; cp < 2 && ok; cp++) {
-            const DslashLaunch a0 = make(best.remap, 0, cp), a1 = make(best.remap, 1, cp);
-            flush_cache();
-            for (int r = 0; r < 6 && ok; r++)
-                ok = launch_dslash(prec, recon, prec, EPI_PLAIN, best.W, r & 1 ? a1 : a0, ntile, lat->s) ==
-                     hipSuccess;
-            for (int trial = 0; trial < 3 && ok; trial++) {
-                const int reps = 10;
-                (void)hipEventRecord(e0, lat->s);
-                for (int r = 0; r < reps; r++)
-                    (void)launch_dslash(prec, recon, prec, EPI_PLAIN, best.W, r & 1 ? a1 : a0, ntile, lat->s);
-                (void)hipEventRecord(e1, lat->s);
-                (void)hipEventSynchronize(e1);
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                tpol[cp] = std::min(tpol[cp], 1000.0 * ms / reps);
+        const double op_bytes = 2.0 * (double)nsite * (double)link_site_bytes(prec, recon);
+        const bool partial = op_bytes > 200e6;
+        std::vector<int> cands{0, 16};
+        if (partial)
+            for (int c : {2, 4, 8, 12}) cands.push_back(c);
+        TuneChoice bc = best;
+        bc.us = 1e30;
+        for (int wi = 0; wi < 5; wi++)
+        for (int rm = 0; rm < 2; rm++) {
+            const int W = Ws[wi];
+            if (!okc[wi][rm] || (!partial && (W != best.W || rm != best.remap))) continue;
+            for (size_t ci = 0; ci < cands.size(); ci++) {
+                const DslashLaunch a0 = make(rm, 0, cands[ci]), a1 = make(rm, 1, cands[ci]);
+                flush_cache();
+                bool ok = true;
+                for (int r = 0; r < 6 && ok; r++)
+                    ok = launch_dslash(prec, recon, prec, EPI_PLAIN, W, r & 1 ? a1 : a0, ntile, lat->s) == hipSuccess;
+                if (!ok) continue;
+                double t = 1e30;
+                for (int trial = 0; trial < 3; trial++) {
+                    const int reps = 10;
+                    (void)hipEventRecord(e0, lat->s);
+                    for (int r = 0; r < reps; r++)
+                        (void)launch_dslash(prec, recon, prec, EPI_PLAIN, W, r & 1 ? a1 : a0, ntile, lat->s);
+                    (void)hipEventRecord(e1, lat->s);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    t = std::min(t, 1000.0 * ms / reps);
+                }
+                // an operator that fits the cache keeps it unless streaming is
+                // clearly faster: the two time within a per cent or two here,
+                // while over a long run of alternating applications the cached
+                // one holds its rate and the streamed one does not
+                const double bias = (!partial && cands[ci] == 16) ? 1.03 : 1.0;
+                if (t < bias * bc.us) {
+                    bc.us = t;
+                    bc.W = W;
+                    bc.remap = rm;
+                    bc.cpol = cands[ci];
+                }
             }
         }
-        if (ok) {
-            best.cpol = tpol[1] < tpol[0] ? 1 : 0;
-            best.us = std::min(tpol[0], tpol[1]);
-        }
+        if (bc.us < 1e29) best = bc;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

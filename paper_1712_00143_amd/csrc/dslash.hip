@@ -75,9 +75,33 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
                 nb[g] = (lex + (v - x) * Sm) >> 1;
             }
             RawLink<LT, R> raw[G];
+            if constexpr (CP < 2) {
 #pragma unroll
-            for (int g = 0; g < G; g++)
-                load_link_raw_wave<LT, R, CP>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
+                for (int g = 0; g < G; g++)
+                    load_link_raw_wave<LT, R, CP>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
+            } else {
+                // part of the operator kept in the Infinity Cache: direction
+                // blocks below a.cpol load cached, the rest stream.  The choice
+                // is made once per group (uniform over the wave) so that the
+                // group's loads still issue back to back.
+                const int dg = wave * DPW + g0;
+                if (dg + G <= a.cpol) {
+#pragma unroll
+                    for (int g = 0; g < G; g++)
+                        load_link_raw_wave<LT, R, 1>(lbase + (size_t)(dg + g) * h * F::BYTES, i, h, raw[g]);
+                } else if (dg >= a.cpol) {
+#pragma unroll
+                    for (int g = 0; g < G; g++)
+                        load_link_raw_wave<LT, R, 0>(lbase + (size_t)(dg + g) * h * F::BYTES, i, h, raw[g]);
+                } else {
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        const char *db = lbase + (size_t)(dg + g) * h * F::BYTES;
+                        if (dg + g < a.cpol) load_link_raw_wave<LT, R, 1>(db, i, h, raw[g]);
+                        else load_link_raw_wave<LT, R, 0>(db, i, h, raw[g]);
+                    }
+                }
+            }
             Cx<A> v[G][3];
 #pragma unroll
             for (int g = 0; g < G; g++) load_spinor<ST, A>(in, voff + nb[g], v[g]);
@@ -185,8 +209,11 @@ static hipError_t launch_wc(int W, const DslashLaunch &a, int nblocks, hipStream
 template <class LT, int R, class ST, class OT, int EPI>
 static hipError_t launch_w(int W, const DslashLaunch &a, int nblocks, hipStream_t s)
 {
-    return a.cpol ? launch_wc<LT, R, ST, OT, EPI, 1>(W, a, nblocks, s)
-                  : launch_wc<LT, R, ST, OT, EPI, 0>(W, a, nblocks, s);
+    // a.cpol: 0 streams every link block, 16 keeps all in the Infinity Cache,
+    // 1..15 keeps that many of the 16 direction blocks
+    return a.cpol <= 0 ? launch_wc<LT, R, ST, OT, EPI, 0>(W, a, nblocks, s)
+           : a.cpol >= 16 ? launch_wc<LT, R, ST, OT, EPI, 1>(W, a, nblocks, s)
+                          : launch_wc<LT, R, ST, OT, EPI, 2>(W, a, nblocks, s);
 }
 
 template <class LT, class ST, class OT, int EPI>

@@ -58,7 +58,7 @@ struct SolveSet {
 struct TuneChoice {
     int W = 4;
     int remap = 1;
-    int cpol = 0;   // Dslash link loads: 0 non-temporal, 1 temporal (DslashLaunch::cpol)
+    int cpol = 0;   // Dslash: link direction blocks (of 16) kept in the Infinity Cache (DslashLaunch::cpol)
     double us = 0;
 };
 

@@ -23,8 +23,8 @@ struct DslashLaunch {
     const double *bvec;
     double *partials;
     int fin;
-    int cpol;               // link loads: 0 non-temporal (streamed past the caches), 1 temporal
-                            // (an operator that fits the Infinity Cache stays there between launches)
+    int cpol;               // link direction blocks (of 16) loaded to stay in the Infinity Cache between
+                            // launches: 0 none (all streamed past the caches), 16 all, else a part
     double *red;            // non-null (AX/RES): block sum to red[tile] instead of partials
 };
 
