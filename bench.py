@@ -348,7 +348,7 @@ def run_headline(args):
                    "lattice": list(w.dims), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_entry(),
-                     "kernel": "k_dslash<float,18,float,float,W,EPI_PLAIN>",
+                     "kernel": "k_dslash<float,18,float,float,W,EPI_PLAIN,CP>",
                      "bytes_per_launch": h * site_bytes(1, 18),
                      "launch_us": round(t32 * 1e6, 3), "timing": f"HIP events around a {how32} of "
                      f"{2 * args.reps} launches on the library stream",
@@ -357,9 +357,10 @@ def run_headline(args):
                                       "dslash_frac_of_read_ceiling": round(achieved / read_gbs, 4)},
                      "copy_ceiling": {"GB/s": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / PEAK_HBM_GBS, 4),
                                       "what": "library copy of 1 GiB, read + written bytes"},
-                     "cache": "both parities' FP32 links (151 MB) fit the 256 MB Infinity Cache; the tuner picks "
-                              "cached or streaming link loads by timing both, so part of the link stream may come "
-                              "from the cache at this size (the 32^4 line is beyond it)"},
+                     "cache": "both parities' FP32 links (151 MB) fit the 256 MB Infinity Cache; the tuner times "
+                              "streamed, cached (and, beyond the cache, partly cached) link loads and keeps the "
+                              "fastest, so part of the link stream may come from the cache at this size (the 32^4 "
+                              "lines are beyond it)"},
         "dslash": dsl,
         "dslash_32^4_beyond_infinity_cache": hbm,
         "dslash_host_buffers": host_path,
