@@ -205,3 +205,76 @@ def test_dslash_32x32x32x32_beyond_cache():
             lat.dslash(par, p, r, psi, out)
             assert _rel(out, ref) <= TOL[p], (par, p, r, _rel(out, ref))
     lat.close()
+
+
+_FORCED_POLICY_CHILD = r'''
+import json, os, sys
+import numpy as np
+import torch
+import oracle
+from paper_1712_00143_amd import synth, hisq as H
+
+arch = torch.cuda.get_device_properties(0).gcnArchName.replace(" ", "_")
+path = os.environ["HISQ_TUNE_CACHE"]
+# (dims, W for FP32/FP16 or None for the default shape, cached direction blocks)
+cases = [((6, 4, 6, 4), None, 4), ((4, 4, 4, 4), None, 12), ((8, 4, 4, 4), None, 16),
+         ((4, 4, 4, 6), None, 1), ((8, 8, 8, 8), 16, 6), ((8, 8, 4, 8), 2, 10)]
+fmts = [(0, 18), (1, 18), (1, 12), (2, 12)]
+lines = []
+for dims, w, cpol in cases:
+    t = (synth.volume(dims) // 2 + 63) // 64
+    for p, r in fmts:
+        W = (8 if p == 0 else 4) if w is None or p == 0 else w
+        lines.append(f"dslash3:{arch}:p{p}:r{r}:t{t}:n1 {W} 1 {cpol} 1.0")
+with open(path, "w") as f:
+    f.write("\n".join(lines) + "\n")
+tol = {0: 1e-12, 1: 5e-6, 2: 2e-3}
+res = []
+for k, (dims, w, cpol) in enumerate(cases):
+    fat, lng = synth.make_links(dims, 0.3, seed=60 + k)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    for p, r in fmts:
+        lat.prepare_links(p, r)
+    for par in (0, 1):
+        psi = synth.gaussian_even(dims, 70 + 2 * k + par)
+        ref = oracle.dslash_half(dims, fat, lng, par, psi)
+        for p, r in fmts:
+            a = np.zeros_like(psi)
+            b = np.zeros_like(psi)
+            lat.dslash(par, p, r, psi, a)                        # shape and policy from the cache file
+            lat.dslash(par, p, r, psi, b, flags=H.HISQ_NO_TUNE)  # default shape, streamed links
+            rel = float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+            same = bool(np.array_equal(a, b))
+            res.append([list(dims), cpol, p, r, par, rel, same, w is None or p == 0])
+            assert rel <= tol[p], res[-1]
+            if w is None or p == 0:
+                assert same, res[-1]
+    lat.close()
+with open(path) as f:
+    n = sum(1 for ln in f if ln.strip())
+assert n == len(lines), "tuner added entries: a forced key did not match"
+print(json.dumps({"cases": len(res)}))
+'''
+
+
+def test_forced_link_load_policies_match_streamed_and_oracle(tmp_path):
+    """Every link-load policy (streamed, all cached, and a part of the
+    direction blocks cached, at counts that split the wave groups in different
+    places) on ragged and full-tile lattices, every storage format: the same
+    bits as the streamed default shape, and the oracle's values.  The policy
+    and shape are forced through a prefilled tuner cache in a child process,
+    since the tuner alone picks a partial count only for operators beyond the
+    Infinity Cache."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ)
+    env["HISQ_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+    env["PYTHONPATH"] = root + os.pathsep + env.get("PYTHONPATH", "")
+    print("forced link-load policy child", flush=True)
+    r = subprocess.run([sys.executable, "-c", _FORCED_POLICY_CHILD], cwd=root, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert '"cases": 48' in r.stdout, r.stdout
