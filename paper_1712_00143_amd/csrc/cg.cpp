@@ -350,18 +350,11 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
         pl.mrhs[group] = pick_shape_mrhs(lat0, mode, recon, group, (prm.flags & HISQ_NO_TUNE) != 0);
     }
     if (S.one_lattice) {
-        // FP64 updates: groups of 2 or 4 problems per link read, whichever the
-        // tuner finds cheaper per problem
+        // FP64 updates: up to four problems per link read (a group smaller
+        // than four only when it holds the whole set, as the launch requires)
         const bool nt = (prm.flags & HISQ_NO_TUNE) != 0;
-        pl.group64 = S.nprob < 2 ? S.nprob : 2;
+        pl.group64 = S.nprob < 4 ? S.nprob : 4;
         pl.mrhs64 = pick_shape_mrhs(lat0, 0, 18, pl.group64, nt);
-        if (S.nprob >= 4 && !nt) {
-            TuneChoice t4 = pick_shape_mrhs(lat0, 0, 18, 4, nt);
-            if (t4.us / 4 < pl.mrhs64.us / pl.group64) {
-                pl.group64 = 4;
-                pl.mrhs64 = t4;
-            }
-        }
     }
 
     long long *dclock = nullptr;

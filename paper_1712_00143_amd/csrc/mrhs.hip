@@ -12,8 +12,9 @@
 // sites; each right-hand side may be a problem of a solve set (own FP64 state
 // a.states[r], own descriptor with its diagonal term, all on the lattice of
 // a.probs[0]), and its reduction partials go to tile r * ntile + tile.  The
-// right-hand sides are processed NR at a time: block b serves group b / ntile
-// (right-hand sides NR*g .. NR*g + NR - 1) on tile b % ntile.
+// right-hand sides are processed NR at a time: with ng = ceil(nrhs / NR)
+// groups, logical block b serves group b % ng (right-hand sides NR*g ..
+// NR*g + NR - 1) on tile b / ng.
 #include "fields.h"
 #include "finish.h"
 #include "launch.h"
@@ -36,9 +37,13 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
     // the wave index is uniform: keep it (and the direction-block bases) scalar
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const ProbDesc &pd = a.probs[0];
+    // groups innermost: the blocks of all groups on one tile run back to back
+    // on the same XCD, so the tile's links come from that XCD's L2 after the
+    // first group instead of being streamed from HBM once per group
     const int bt = xcd_tile(blockIdx.x, gridDim.x, a.remap);
-    const int grp = bt / pd.ntile;
-    const int tile = bt - grp * pd.ntile;
+    const int ng = gridDim.x / pd.ntile;
+    const int tile = bt / ng;
+    const int grp = bt - tile * ng;
     const int r0 = grp * NR;
     bool act[NR];
     bool any = false;

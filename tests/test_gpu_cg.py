@@ -184,6 +184,31 @@ def test_batch_cg_one_lattice_shares_links(graph):
     L.close()
 
 
+@pytest.mark.parametrize("nprob,flags", [(3, 0), (5, "no_tune"), (2, 0)])
+def test_batch_cg_one_lattice_group_sizes(nprob, flags):
+    """One-lattice sets whose FP64 reliable updates run through the
+    shared-link kernel in a group smaller than four (two or three problems:
+    the whole set) or in groups of four with a ragged last group (five
+    problems, default launch shapes): every solution reaches the FP64 true
+    residual."""
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    fat, lng = synth.make_links(dims, 0.2, seed=640 + nprob)
+    L = H.Lattice(dims)
+    L.load_links(fat, lng)
+    L.prepare_links(1, 18)
+    ms = [0.3, 0.05, 0.1, 0.02, 0.2][:nprob]
+    bs = [synth.gaussian_even(dims, 650 + j) for j in range(nprob)]
+    fl = H.HISQ_NO_TUNE if flags == "no_tune" else 0
+    p = H.hisq_default_params(tol=1e-10, sloppy=1, flags=fl)
+    xs, infos = H.hisq_batch_cg([L] * nprob, ms, bs, params=p)
+    for j, m in enumerate(ms):
+        assert infos[j]["converged"] == 1, (j, infos[j])
+        assert oracle.true_residual(dims, fat, lng, m, bs[j], xs[j]) <= 1e-10
+        assert infos[j]["reliable_updates"] >= 1
+    L.close()
+
+
 def test_batch_cg_reordered_problems():
     """Two batched calls led by the same handle, with the same sizes in a
     different order, reuse the work set; the tile-to-problem map must follow
