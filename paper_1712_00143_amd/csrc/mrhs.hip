@@ -268,6 +268,14 @@ hipError_t launch_dslash_mrhs(int prec, int recon, int nrhs, int W, const MrhsLa
     const long long nb = (long long)(a.nrhs + nrhs - 1) / nrhs * ntile;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
     const int nblocks = (int)nb;
+    if (nb > ntile && !a.remap) {
+        // several groups: the XCD-contiguous order is what places the groups
+        // of one tile on one XCD to share its links through the L2 (the
+        // tuner times one group, where the order hardly matters)
+        MrhsLaunch b = a;
+        b.remap = 1;
+        return launch_dslash_mrhs(prec, recon, nrhs, W, b, ntile, s);
+    }
     if (prec == 0) {
         if (recon != 18) return hipErrorInvalidValue;
         switch (a.epi) {
