@@ -32,6 +32,28 @@ def test_mrhs_dslash_matches_oracle(nrhs, prec, recon, tol):
     lat.close()
 
 
+@pytest.mark.parametrize("no_tune", [False, True])
+def test_mrhs_dslash_many_groups_ragged_tile(no_tune):
+    """Thirteen right-hand sides (three full groups of four and a group of
+    one) on a lattice whose last tile is ragged (h = 288): every output of
+    the groups-innermost launch against the oracle, tuned and default shape."""
+    H = _hisq()
+    dims = (6, 4, 6, 4)
+    fat, lng = synth.make_links(dims, 0.3, seed=57)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    nrhs = 13
+    psi = synth.gaussian_even(dims, 58, nrhs)
+    out = np.zeros_like(psi)
+    for par in (0, 1):
+        lat.dslash(par, 1, 18, psi, out, nrhs=nrhs, flags=H.HISQ_NO_TUNE if no_tune else 0)
+        for j in range(nrhs):
+            ref = oracle.dslash_half(dims, fat, lng, par, psi[j])
+            assert np.linalg.norm(out[j] - ref) <= 5e-6 * np.linalg.norm(ref), (par, j)
+    lat.close()
+
+
 def test_mrhs_dslash_device_matches_single():
     import torch
     H = _hisq()
