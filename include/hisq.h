@@ -240,8 +240,9 @@ hisq_status hisq_ptc_init_polynomial(hisq_ptc net, double a, double c, int iters
 hisq_status hisq_ptc_layer_forward(hisq_ptc net, int layer, const void *in, void *out, int flags);
 hisq_status hisq_ptc_layer_backward(hisq_ptc net, int layer, const void *in, const void *gout,
                                     void *gin, double *gw, int flags);
-/* z = M(r) on device even vectors (FP32 complex), using the FP16 weights
- * (HISQ_DEVICE_PTR required). */
+/* z = M(r) on device even vectors (FP32 complex), using the FP16 weights and
+ * the network's transport links (hisq_ptc_set_transport; HISQ_DEVICE_PTR
+ * required). */
 hisq_status hisq_ptc_apply(hisq_ptc net, const void *r, void *z, int flags);
 /* Generate training pairs: plain FP32/FP64 CG on b (host FP64), storing the
  * residual r_i and error e_i = x* - x_i every `every` iterations, at most
@@ -266,6 +267,18 @@ hisq_status hisq_ptc_get_pair(hisq_ptc net, int index, double *r, double *e);
  *     1/lambda^2 and drifts away from good preconditioners. */
 enum { HISQ_LOSS_ENERGY = 0, HISQ_LOSS_EUCLIDEAN = 1 };
 hisq_status hisq_ptc_set_loss(hisq_ptc net, int loss);
+/* Link format of the network's transports F_mu: HISQ_F32 with HISQ_RECON_18
+ * (the default) or HISQ_F16 with HISQ_RECON_12 (fat links stored as FP16
+ * rows 1-2 over the field scale, row 3 rebuilt; requires links that are
+ * scale * sign * SU(3), else the first call that needs them returns
+ * HISQ_ERR_RECON).  Every later call of the network uses it -- the layer
+ * calls, hisq_ptc_apply, hisq_ptc_train, hisq_ptc_init_polynomial's spectrum
+ * estimate and hisq_cg_learned -- so that a network is trained and applied on
+ * the same operator; the link set is prepared on the lattice on first use.
+ * Arithmetic stays FP32.  Errors: HISQ_ERR_ARG (null net, another format).
+ * get_transport returns the current format (prec, recon). */
+hisq_status hisq_ptc_set_transport(hisq_ptc net, hisq_prec prec, hisq_recon recon);
+hisq_status hisq_ptc_get_transport(hisq_ptc net, int *prec, int *recon);
 /* Train on the stored pairs (all from lattices whose links are those of the
  * handle each pair was harvested on): `steps` Adam steps (lr, beta1 0.9,
  * beta2 0.999, eps 1e-8) on minibatches of `batch` pairs of one lattice,

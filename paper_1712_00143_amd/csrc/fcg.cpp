@@ -55,9 +55,18 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
         hisq_status ps = hisq_prepare_links(lat, HISQ_F32, HISQ_RECON_18);
         if (ps != HISQ_OK) return ps;
     }
-    // transports: FP16 recon-12 fat links when prepared, else FP32 recon-18
-    const bool p16 = lat->ls[5].valid;
-    const int pslot = p16 ? 5 : 2, pprec = p16 ? 2 : 1, precon = p16 ? 12 : 18;
+    // transports: the network's own link format (hisq_ptc_set_transport), the
+    // one it was trained with
+    int pprec = 1, precon = 18;
+    {
+        hisq_status ts = hisq_ptc_get_transport(net, &pprec, &precon);
+        if (ts != HISQ_OK) return ts;
+    }
+    const int pslot = pprec * 2 + (precon == 12);
+    if (!lat->ls[pslot].valid) {
+        hisq_status ps = hisq_prepare_links(lat, (hisq_prec)pprec, (hisq_recon)precon);
+        if (ps != HISQ_OK) return ps;
+    }
     hipStream_t s = lat->s;
     const bool dev = (prm.flags & HISQ_DEVICE_PTR) != 0;
 

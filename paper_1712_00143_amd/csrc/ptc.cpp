@@ -58,6 +58,9 @@ struct hisq_ptc_s {
     double *gw = nullptr, *gtmp = nullptr;
     int step = 0;
     int loss = HISQ_LOSS_ENERGY;
+    // link format of the transports, the same for training and inference
+    int tprec = HISQ_F32, trecon = HISQ_RECON_18;
+    int tslot() const { return tprec * 2 + (trecon == 12); }
     std::vector<PairBlock> pairs;
     // training workspace
     int wsB = 0;
@@ -81,10 +84,11 @@ int cmax(const hisq_ptc_s *n)
     return c;
 }
 
-hisq_status ensure_fp32_links(hisq_lattice lat)
+// the packed fat links the network's transports read, prepared on demand
+hisq_status ensure_transport_links(const hisq_ptc_s *n, hisq_lattice lat)
 {
-    if (lat->ls[2].valid) return HISQ_OK;
-    return hisq_prepare_links(lat, HISQ_F32, HISQ_RECON_18);
+    if (lat->ls[n->tslot()].valid) return HISQ_OK;
+    return hisq_prepare_links(lat, (hisq_prec)n->tprec, (hisq_recon)n->trecon);
 }
 
 // adjoint weights (FP32 and FP16) of every layer from the FP32 master
@@ -229,7 +233,7 @@ hipError_t run_wgrad(hisq_ptc_s *n, hisq_lattice lat, int cin, int cout, const f
                      const float *g, long long g_bs, int g_pstride, int batch, double *gw, int accumulate,
                      hipStream_t s)
 {
-    PtcLaunch a = base_launch(lat, 2);
+    PtcLaunch a = base_launch(lat, n->tslot());
     a.in = in;
     a.in_bstride = in_bs;
     a.in_zero_par = in_zero;
@@ -241,7 +245,7 @@ hipError_t run_wgrad(hisq_ptc_s *n, hisq_lattice lat, int cin, int cout, const f
     // per work unit
     const long long units = (long long)lat->ntile * g_pstride * batch;
     const int nrow = (int)(units < WGRAD_ROWS ? units : WGRAD_ROWS);
-    hipError_t e = launch_ptc_wgrad(cin, cout, a, g_pstride, batch, nrow, s);
+    hipError_t e = launch_ptc_wgrad(n->tprec, n->trecon, cin, cout, a, g_pstride, batch, nrow, s);
     if (e != hipSuccess) return e;
     return launch_ptc_wsum(n->part, nrow, cin, cout, gw, accumulate, s);
 }
@@ -429,7 +433,7 @@ hisq_status hisq_ptc_init_polynomial(hisq_ptc n, double a, double c, int iters, 
     for (int l = 1; l < n->nlayer; l++)
         if (n->chans[l] < 2) return set_err(lat, HISQ_ERR_ARG, "polynomial start needs two inner channels");
     HIPCHK(lat, hipSetDevice(lat->device));
-    hisq_status st = ensure_fp32_links(lat);
+    hisq_status st = ensure_transport_links(n, lat);
     if (st != HISQ_OK) return st;
 
     // one hop: weight +1 on the forward paths, -1 on the backward ones
@@ -467,7 +471,7 @@ hisq_status hisq_ptc_init_polynomial(hisq_ptc n, double a, double c, int iters, 
                 break;
             }
             hipError_t e = hipMemcpy(dv, v.data(), sizeof(float) * nf, hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = ptc_apply_internal(t, lat, 2, 1, 18, dv, dv + nf, nullptr);
+            if (e == hipSuccess) e = ptc_apply_internal(t, lat, n->tslot(), n->tprec, n->trecon, dv, dv + nf, nullptr);
             if (e == hipSuccess) e = hipStreamSynchronize(lat->s);
             if (e == hipSuccess) e = hipMemcpy(z.data(), dv + nf, sizeof(float) * nf, hipMemcpyDeviceToHost);
             if (e != hipSuccess) {
@@ -530,10 +534,10 @@ hisq_status hisq_ptc_layer_forward(hisq_ptc n, int layer, const void *in, void *
     hisq_lattice lat = n->lat;
     if (!(flags & HISQ_DEVICE_PTR)) return set_err(lat, HISQ_ERR_ARG, "layer calls take device pointers");
     HIPCHK(lat, hipSetDevice(lat->device));
-    hisq_status st = ensure_fp32_links(lat);
+    hisq_status st = ensure_transport_links(n, lat);
     if (st != HISQ_OK) return st;
     const int cin = n->chans[layer], cout = n->chans[layer + 1];
-    HIPCHK(lat, run_layer(lat, 2, 1, 18, false, n->w32 + 2 * n->woff[layer], cin, cout, (const float *)in, 0, -1,
+    HIPCHK(lat, run_layer(lat, n->tslot(), n->tprec, n->trecon, false, n->w32 + 2 * n->woff[layer], cin, cout, (const float *)in, 0, -1,
                           (float *)out, 0, 2, 0, 1, 1, lat->s));
     return HISQ_OK;
 }
@@ -545,12 +549,12 @@ hisq_status hisq_ptc_layer_backward(hisq_ptc n, int layer, const void *in, const
     hisq_lattice lat = n->lat;
     if (!(flags & HISQ_DEVICE_PTR)) return set_err(lat, HISQ_ERR_ARG, "layer calls take device pointers");
     HIPCHK(lat, hipSetDevice(lat->device));
-    hisq_status st = ensure_fp32_links(lat);
+    hisq_status st = ensure_transport_links(n, lat);
     if (st != HISQ_OK) return st;
     const int cin = n->chans[layer], cout = n->chans[layer + 1];
     hipStream_t s = lat->s;
     if (gin)
-        HIPCHK(lat, run_layer(lat, 2, 1, 18, false, n->wa32 + 2 * n->woff[layer], cout, cin, (const float *)gout, 0,
+        HIPCHK(lat, run_layer(lat, n->tslot(), n->tprec, n->trecon, false, n->wa32 + 2 * n->woff[layer], cout, cin, (const float *)gout, 0,
                               -1, (float *)gin, 0, 2, 0, 1, 1, s));
     if (gw) {
         const size_t need = ((size_t)2 * lat->ntile + 256) * 9 * cin * cout * 2;
@@ -572,9 +576,9 @@ hisq_status hisq_ptc_apply(hisq_ptc n, const void *r, void *z, int flags)
     hisq_lattice lat = n->lat;
     if (!(flags & HISQ_DEVICE_PTR)) return set_err(lat, HISQ_ERR_ARG, "hisq_ptc_apply takes device pointers");
     HIPCHK(lat, hipSetDevice(lat->device));
-    hisq_status st = ensure_fp32_links(lat);
+    hisq_status st = ensure_transport_links(n, lat);
     if (st != HISQ_OK) return st;
-    HIPCHK(lat, ptc_apply_internal(n, lat, 2, 1, 18, (const float *)r, (float *)z, nullptr));
+    HIPCHK(lat, ptc_apply_internal(n, lat, n->tslot(), n->tprec, n->trecon, (const float *)r, (float *)z, nullptr));
     return HISQ_OK;
 }
 
@@ -587,7 +591,7 @@ hisq_status hisq_ptc_harvest(hisq_ptc n, hisq_lattice lat, double mass, const do
     if (npairs) *npairs = 0;
     if (!lat->loaded) return set_err(lat, HISQ_ERR_STATE, "no links loaded");
     HIPCHK(lat, hipSetDevice(lat->device));
-    hisq_status st = ensure_fp32_links(lat);
+    hisq_status st = ensure_transport_links(n, lat);   // the pairs are trained on with these transports
     if (st != HISQ_OK) return st;
     const long long h = lat->h;
     hipStream_t s = lat->s;
@@ -785,6 +789,25 @@ hisq_status hisq_ptc_set_loss(hisq_ptc n, int loss)
     return HISQ_OK;
 }
 
+hisq_status hisq_ptc_set_transport(hisq_ptc n, hisq_prec prec, hisq_recon recon)
+{
+    if (!n) return HISQ_ERR_ARG;
+    const bool ok = (prec == HISQ_F32 && recon == HISQ_RECON_18) || (prec == HISQ_F16 && recon == HISQ_RECON_12);
+    if (!ok) return set_err(n->lat, HISQ_ERR_ARG, "transports: FP32 recon-18 or FP16 recon-12");
+    if (n->tprec != (int)prec || n->trecon != (int)recon) n->fcg_graph.release();
+    n->tprec = prec;
+    n->trecon = recon;
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_get_transport(hisq_ptc n, int *prec, int *recon)
+{
+    if (!n || !prec || !recon) return HISQ_ERR_ARG;
+    *prec = n->tprec;
+    *recon = n->trecon;
+    return HISQ_OK;
+}
+
 hisq_status hisq_ptc_pair_count(hisq_ptc n, int *count)
 {
     if (!n || !count) return HISQ_ERR_ARG;
@@ -888,7 +911,9 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
         while (pick >= n->pairs[g].n) pick -= n->pairs[g++].n;
         PairBlock &pb = n->pairs[g];
         hisq_lattice lat = pb.lat;
-        hisq_status st = ensure_fp32_links(lat);
+        hisq_status st = ensure_transport_links(n, lat);
+        // the energy-norm loss applies the FP32 recon-18 operator of the pairs' lattice
+        if (st == HISQ_OK && !lat->ls[2].valid) st = hisq_prepare_links(lat, HISQ_F32, HISQ_RECON_18);
         if (st != HISQ_OK) return st;
         const long long hl = lat->h;
         const long long af = (long long)C * 2 * hl * 6;
@@ -905,7 +930,7 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
         // forward half
         for (int l = 1; l <= nl; l++) {
             const bool first = l == 1;
-            HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, n->w32 + 2 * n->woff[l - 1], n->chans[l - 1], n->chans[l],
+            HIPCHK(lat0, run_layer(lat, n->tslot(), n->tprec, n->trecon, false, n->w32 + 2 * n->woff[l - 1], n->chans[l - 1], n->chans[l],
                                    first ? rb : acts[l - 1], first ? hl * 6 : af, first ? 1 : -1, acts[l], af, 2, 0, 1,
                                    batch, s));
         }
@@ -913,10 +938,10 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
         for (int l = nl; l >= 1; l--) {
             const float *w = n->wa32 + 2 * n->woff[l - 1];
             if (l == 1)
-                HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, w, n->chans[l], n->chans[l - 1], bs[1], af, -1, zb,
+                HIPCHK(lat0, run_layer(lat, n->tslot(), n->tprec, n->trecon, false, w, n->chans[l], n->chans[l - 1], bs[1], af, -1, zb,
                                        hl * 6, 1, 0, 0, batch, s));
             else
-                HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, w, n->chans[l], n->chans[l - 1], bs[l], af, -1, bs[l - 1],
+                HIPCHK(lat0, run_layer(lat, n->tslot(), n->tprec, n->trecon, false, w, n->chans[l], n->chans[l - 1], bs[l], af, -1, bs[l - 1],
                                        af, 2, 0, 1, batch, s));
         }
         // z = r + E^+ b_0, then the loss and g_z = g_{b_0}
@@ -953,7 +978,7 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
             const int ci = n->chans[l], co = n->chans[l - 1];   // the adjoint application maps ci -> co
             HIPCHK(lat0, run_wgrad(n, lat, ci, co, bs[l], af, -1, gcur, g_bs, g_pstride, batch, n->gtmp, 0, s));
             HIPCHK(lat0, launch_ptc_gadj(n->gtmp, ci, co, n->gw + 2 * n->woff[l - 1], s));
-            HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, n->w32 + 2 * n->woff[l - 1], co, ci, gcur, g_bs,
+            HIPCHK(lat0, run_layer(lat, n->tslot(), n->tprec, n->trecon, false, n->w32 + 2 * n->woff[l - 1], co, ci, gcur, g_bs,
                                    g_pstride == 1 ? 1 : -1, gbuf[k], af, 2, 0, 1, batch, s));
             gcur = gbuf[k];
             g_bs = af;
@@ -967,7 +992,7 @@ hisq_status hisq_ptc_train(hisq_ptc n, int steps, int batch, double lr, unsigned
             HIPCHK(lat0, run_wgrad(n, lat, ci, co, first ? rb : acts[l - 1], first ? hl * 6 : af, first ? 1 : -1, gcur,
                                    af, 2, batch, n->gw + 2 * n->woff[l - 1], 1, s));
             if (!first) {
-                HIPCHK(lat0, run_layer(lat, 2, 1, 18, false, n->wa32 + 2 * n->woff[l - 1], co, ci, gcur, af, -1,
+                HIPCHK(lat0, run_layer(lat, n->tslot(), n->tprec, n->trecon, false, n->wa32 + 2 * n->woff[l - 1], co, ci, gcur, af, -1,
                                        gbuf[k], af, 2, 0, 1, batch, s));
                 gcur = gbuf[k];
                 k ^= 1;

@@ -53,7 +53,8 @@ constexpr int WGRAD_ROWS = 1024;   // weight-gradient partial rows (blocks) at m
 
 // Weight-gradient partials of npar output parities x batch entries, reduced
 // into nrow rows (one per block) of [9][cout][cin] complex FP64.
-hipError_t launch_ptc_wgrad(int cin, int cout, const PtcLaunch &a, int npar, int batch, int nrow, hipStream_t s);
+hipError_t launch_ptc_wgrad(int prec, int recon, int cin, int cout, const PtcLaunch &a, int npar, int batch, int nrow,
+                           hipStream_t s);
 hipError_t launch_ptc_wsum(const double *partials, long long nrow, int cin, int cout, double *gw, int accumulate,
                            hipStream_t s);
 hipError_t launch_ptc_loss(const PtcLaunch &a, int ntile, int batch, double *loss, hipStream_t s);

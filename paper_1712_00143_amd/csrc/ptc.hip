@@ -463,14 +463,25 @@ hipError_t launch_ptc_layer(int prec, int recon, bool w16, int cin, int cout, in
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_ptc_wgrad(int cin, int cout, const PtcLaunch &a, int npar, int batch, int nrow, hipStream_t s)
+template <class LT, int R>
+static hipError_t wgrad_c(int cin, int cout, const PtcLaunch &a, int npar, int batch, dim3 g, hipStream_t s)
 {
-    dim3 g(nrow), b(576);
+    const dim3 b(576);
 #define WG_CASE(I, O) \
-    if (cin == I && cout == O) { hipLaunchKernelGGL((k_ptc_wgrad<float, 18, I, O>), g, b, 0, s, a, npar, batch); return hipGetLastError(); }
+    if (cin == I && cout == O) { hipLaunchKernelGGL((k_ptc_wgrad<LT, R, I, O>), g, b, 0, s, a, npar, batch); return hipGetLastError(); }
     WG_CASE(1, 1) WG_CASE(1, 4) WG_CASE(4, 4) WG_CASE(4, 1) WG_CASE(1, 2) WG_CASE(2, 2) WG_CASE(2, 1)
     WG_CASE(2, 4) WG_CASE(4, 2) WG_CASE(1, 8) WG_CASE(8, 8) WG_CASE(8, 1)
 #undef WG_CASE
+    return hipErrorInvalidValue;
+}
+
+// transports on FP32 recon-18 (prec 1) or FP16 recon-12 (prec 2) fat links
+hipError_t launch_ptc_wgrad(int prec, int recon, int cin, int cout, const PtcLaunch &a, int npar, int batch, int nrow,
+                            hipStream_t s)
+{
+    const dim3 g(nrow);
+    if (prec == 1 && recon == 18) return wgrad_c<float, 18>(cin, cout, a, npar, batch, g, s);
+    if (prec == 2 && recon == 12) return wgrad_c<__half, 12>(cin, cout, a, npar, batch, g, s);
     return hipErrorInvalidValue;
 }
 

@@ -42,7 +42,7 @@ EXPORTS = [
     "hisq_ptc_get_weights", "hisq_ptc_layer_forward", "hisq_ptc_layer_backward", "hisq_ptc_apply",
     "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
     "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss", "hisq_ptc_save", "hisq_ptc_load",
-    "hisq_residual_history",
+    "hisq_residual_history", "hisq_ptc_set_transport", "hisq_ptc_get_transport",
 ]
 
 
@@ -323,6 +323,18 @@ class PTC:
     def set_loss(self, loss):
         """HISQ_LOSS_ENERGY (the default) or HISQ_LOSS_EUCLIDEAN."""
         self._err(lib().hisq_ptc_set_loss(self.handle, ctypes.c_int(loss)), "hisq_ptc_set_loss")
+
+    def set_transport(self, prec, recon):
+        """Link format of the transports: (HISQ_F32, 18) or (HISQ_F16, 12);
+        used by every later call of the network, training and inference."""
+        self._err(lib().hisq_ptc_set_transport(self.handle, ctypes.c_int(prec), ctypes.c_int(recon)),
+                  "hisq_ptc_set_transport")
+
+    def get_transport(self):
+        p, r = ctypes.c_int(0), ctypes.c_int(0)
+        self._err(lib().hisq_ptc_get_transport(self.handle, ctypes.byref(p), ctypes.byref(r)),
+                  "hisq_ptc_get_transport")
+        return p.value, r.value
 
     def get_weights(self):
         flat = np.zeros(self.nw, dtype=np.complex128)

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _parity import check
 from paper_1712_00143_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -79,11 +80,11 @@ def test_layer_forward_and_backward(lat6, layer):
     out = torch.zeros(cout * 2 * h * 6, device="cuda")
     net.layer_forward(layer, _dev(_split(dims, a)), out)
     got = _unsplit(dims, _host(out, (cout, 2, h, 3)))
-    assert _rel(got, ref) <= 1e-6
+    check(got, ref, 1e-6, ("forward", layer))
     gin_ref, gw_ref = oracle.ptc_layer_adj(dims, fat, w32[layer], a, g)
     gin = torch.zeros(cin * 2 * h * 6, device="cuda")
     gw = net.layer_backward(layer, _dev(_split(dims, a)), _dev(_split(dims, g)), gin)
-    assert _rel(_unsplit(dims, _host(gin, (cin, 2, h, 3))), gin_ref) <= 1e-6
+    check(_unsplit(dims, _host(gin, (cin, 2, h, 3))), gin_ref, 1e-6, ("input gradient", layer))
     assert _rel(gw, gw_ref) <= 1e-5
     net.close()
 
@@ -105,7 +106,7 @@ def test_apply_fp16_weights_matches_oracle(lat6):
     h = r.shape[0]
     z = torch.zeros(h * 6, device="cuda")
     net.apply(_dev(r), z)
-    assert _rel(_host(z, (h, 3)), ref) <= 1e-5
+    check(_host(z, (h, 3)), ref, 1e-5)
     net.close()
 
 
@@ -266,9 +267,16 @@ def test_training_lowers_loss_and_reports_gain():
     assert oracle.true_residual(dims, fat, lng, m, b, x) <= 1e-10
     untrained = H.PTC(T, chans)          # zero weights: M = 1
     _, i0 = untrained.cg_learned(T, m, b, params=p)
-    print(f"learned-preconditioner gain: iterations {i0['iters']} (M = 1) -> {info['iters']} (trained), "
-          f"ratio {i0['iters'] / info['iters']:.3f}; loss {losses[:10].mean():.4f} -> {losses[-50:].mean():.4f}")
+    start = H.PTC(T, chans)              # the network's own starting point, untrained
+    start.set_weights(_rand_w(chans, 77, scale=0.05))
+    _, i1 = start.cg_learned(T, m, b, params=p)
+    print(f"learned-preconditioner gain: iterations {i0['iters']} (M = 1), {i1['iters']} (random start, "
+          f"untrained) -> {info['iters']} (trained), ratio {i1['iters'] / info['iters']:.3f}; "
+          f"loss {losses[:10].mean():.4f} -> {losses[-50:].mean():.4f}")
     assert info["iters"] <= 0.8 * i0["iters"], (info["iters"], i0["iters"])
+    assert info["iters"] <= 0.8 * i1["iters"], (info["iters"], i1["iters"])
+    start.close()
+    untrained.close()
     for L in lats + [T]:
         L.close()
 
@@ -423,4 +431,115 @@ def test_checkpoint_save_load(tmp_path):
     assert ei.value.status == H.HISQ_ERR_IO
     for n in (a, c, other):
         n.close()
+    lat.close()
+
+
+# ---- transports on FP16 recon-12 fat links -------------------------------
+#
+# Bars: the oracle runs on the exact FP64 links; the GPU stores each fat link
+# as two FP16 rows over the field scale (relative rounding <= 2^-11 per real)
+# and rebuilds the third row, so a transported vector carries about 2^-11
+# relative error per link, summed over the 9 paths: 2e-3 relative l2, the
+# bar of the FP16 Dslash, with the per-site bound of _parity.check.
+
+TOL16 = 2e-3
+
+
+def test_transport_format_default_and_errors(lat6):
+    H = _hisq()
+    dims, fat, lng, lat = lat6
+    net = H.PTC(lat, (1, 2, 1))
+    assert net.get_transport() == (1, 18)
+    net.set_transport(2, 12)
+    assert net.get_transport() == (2, 12)
+    for bad in [(0, 18), (1, 12), (2, 18)]:
+        with pytest.raises(H.HisqError) as ei:
+            net.set_transport(*bad)
+        assert ei.value.status == H.HISQ_ERR_ARG
+    assert net.get_transport() == (2, 12)
+    net.close()
+
+
+@pytest.mark.parametrize("layer", [0, 1, 2])
+def test_layer_fp16_transports_match_oracle(lat6, layer):
+    """Forward, input gradient and weight gradient of one layer with the
+    transports on FP16 recon-12 fat links (the format the flexible CG runs
+    on), against the oracle on the FP64 links."""
+    import torch
+    H = _hisq()
+    dims, fat, lng, lat = lat6
+    chans = (1, 4, 4, 1)
+    net = H.PTC(lat, chans)
+    net.set_transport(2, 12)
+    ws = _rand_w(chans, 40 + layer)
+    net.set_weights(ws)
+    cin, cout = chans[layer], chans[layer + 1]
+    a = synth.gaussian_full(dims, 50 + layer, cin)
+    g = synth.gaussian_full(dims, 60 + layer, cout)
+    h = synth.volume(dims) // 2
+    w32 = [w.astype(np.complex64).astype(np.complex128) for w in ws]
+    ref = oracle.ptc_layer(dims, fat, w32[layer], a)
+    out = torch.zeros(cout * 2 * h * 6, device="cuda")
+    net.layer_forward(layer, _dev(_split(dims, a)), out)
+    got = _unsplit(dims, _host(out, (cout, 2, h, 3)))
+    check(got, ref, TOL16, ("forward", layer))
+    gin_ref, gw_ref = oracle.ptc_layer_adj(dims, fat, w32[layer], a, g)
+    gin = torch.zeros(cin * 2 * h * 6, device="cuda")
+    gw = net.layer_backward(layer, _dev(_split(dims, a)), _dev(_split(dims, g)), gin)
+    check(_unsplit(dims, _host(gin, (cin, 2, h, 3))), gin_ref, TOL16, ("input gradient", layer))
+    assert _rel(gw, gw_ref) <= TOL16, ("weight gradient", layer, _rel(gw, gw_ref))
+    net.close()
+
+
+def test_apply_fp16_transports_matches_oracle(lat6):
+    """z = M(r) with FP16 weights and FP16 recon-12 transports against the
+    oracle's M on the FP16-rounded weights and the FP64 links; the same
+    network with FP32 transports stays at the FP32 bar."""
+    import torch
+    H = _hisq()
+    dims, fat, lng, lat = lat6
+    chans = (1, 4, 4, 1)
+    net = H.PTC(lat, chans)
+    ws = _rand_w(chans, 8, scale=0.3)
+    net.set_weights(ws)
+    w32 = [w.astype(np.complex64) for w in ws]
+    w16 = [(w.real.astype(np.float16).astype(np.float64) + 1j * w.imag.astype(np.float16).astype(np.float64))
+           for w in w32]
+    r = synth.gaussian_even(dims, 9)
+    ref = oracle.ptc_apply(dims, fat, w16, r)
+    h = r.shape[0]
+    z = torch.zeros(h * 6, device="cuda")
+    net.apply(_dev(r), z)
+    check(_host(z, (h, 3)), ref, 1e-5, "fp32 transports")
+    net.set_transport(2, 12)
+    net.apply(_dev(r), z)
+    check(_host(z, (h, 3)), ref, TOL16, "fp16 transports")
+    net.close()
+
+
+def test_cg_learned_fp16_transports_16x16x16x16():
+    """The learned flexible CG with FP16 recon-12 transports on a 16^4 field of
+    the learned-preconditioner workload (eps 0.25, m 0.005), polynomial start
+    trained on pairs of the same field with the same transports: the FP64
+    true residual of the solution, recomputed by the oracle, is <= 1e-10,
+    with no hand-over to plain CG."""
+    H = _hisq()
+    w = synth.C4
+    fat, lng = synth.make_links(w.dims, w.eps, seed=4000)
+    lat = H.Lattice(w.dims)
+    lat.load_links(fat, lng)
+    net = H.PTC(lat, (1, 2, 1))
+    net.set_transport(2, 12)
+    net.init_polynomial(a=4.0, c=1.2)
+    net.harvest(lat, w.mass, synth.gaussian_even(w.dims, 4500), every=20, maxpairs=30)
+    losses = net.train(60, batch=4, lr=1e-3, seed=3)
+    assert np.all(np.isfinite(losses))
+    b = synth.gaussian_even(w.dims, 4900)
+    for flags in (0, H.HISQ_USE_GRAPH):
+        x, info = net.cg_learned(lat, w.mass, b, params=H.hisq_default_params(tol=1e-10, sloppy=1, flags=flags))
+        tr = oracle.true_residual(w.dims, fat, lng, w.mass, b, x)
+        print(f"fp16-transport learned FCG, flags {flags}: {info['iters']} iterations, oracle true residual {tr:.2e}")
+        assert info["converged"] == 1 and info["fell_back"] == 0, info
+        assert tr <= 1e-10, tr
+    net.close()
     lat.close()
