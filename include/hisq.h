@@ -153,6 +153,29 @@ hisq_status hisq_dslash(hisq_lattice lat, hisq_parity out_parity, hisq_prec prec
 hisq_status hisq_cg(hisq_lattice lat, double mass, const double *b, double *x,
                     const hisq_solver_params *params, hisq_solver_info *info);
 
+/* hisq_cg for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same iteration and kernels, with every work vector, reduction partial, the
+ * solver state and the problem descriptor in one static device buffer of
+ * 64 MiB per GPU (held until the process ends), so the call performs no
+ * hipMalloc, hipFree or other allocation on the device.  The launch shape is
+ * the autotuner's cached choice for this lattice if one exists (made by an
+ * earlier hisq_cg or hisq_dslash), else the default; nothing is timed.
+ * Requirements: b and x are device FP64 vectors (HISQ_DEVICE_PTR); no
+ * HISQ_USE_GRAPH (instantiating a graph allocates); the FP64 and the sloppy
+ * link sets are already prepared (hisq_prepare_links allocates).  The buffer
+ * holds 4 FP64 vectors, 3 accumulators (FP64 plain, FP32 mixed) and 2 sloppy
+ * vectors of V/2 sites plus per-tile partials: V/2 up to about 155 000 sites
+ * in plain FP64 (16^3x32 fits, 24^4 does not), 215 000 in mixed FP32 (24^4
+ * fits, 32^4 does not), 226 000 in mixed FP16.  Every call on a GPU shares that GPU's buffer and its
+ * contents from the last call (everything a solve reads is written first by
+ * that solve); calls that overlap on one GPU, from any handle or thread, race.
+ * Errors: as hisq_cg, plus HISQ_ERR_ARG for host vectors, HISQ_USE_GRAPH or a
+ * lattice whose work set exceeds the buffer, HISQ_ERR_STATE for link sets not
+ * prepared. */
+hisq_status hisq_cg_noalloc(hisq_lattice lat, double mass, const double *b, double *x,
+                            const hisq_solver_params *params, hisq_solver_info *info);
+
 /* Multi-shift CG (Section 4.1): solve (A + shifts[k]) x_{j,k} = b_j for
  * nshift <= 64 shifts and nrhs right-hand sides with one Krylov space per
  * right-hand side (base system = smallest shift, FP64 zeta/alpha/beta

@@ -56,6 +56,23 @@ void dvec_free(DVec &v)
 
 void SolveSet::release()
 {
+    if (borrowed) {   // nothing here is owned: forget the pointers
+        for (DVec *v : {&b, &xhi, &rhi, &thi, &xlo, &rlo, &Ap, &p, &t, &fz}) *v = DVec();
+        ddesc = nullptr;
+        dt2p = nullptr;
+        dst = nullptr;
+        hst = nullptr;
+        dpart = nullptr;
+        dred = nullptr;
+        fred = nullptr;
+        dclock = nullptr;
+        nprob = ntile = 0;
+        nsite = 0;
+        mode = -1;
+        hdesc.clear();
+        hist.clear();
+        return;
+    }
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     gexec = nullptr;
@@ -410,6 +427,30 @@ hisq_status hisq_prepare_links(hisq_lattice lat, hisq_prec prec, hisq_recon reco
 
 namespace hisq {
 
+static std::string dslash_tune_key(const hipDeviceProp_t &prop, int prec, int recon, int ntile, int nprob)
+{
+    std::ostringstream ks;
+    ks << "dslash3:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << ntile << ":n" << nprob;
+    std::string key = ks.str();
+    for (auto &ch : key)
+        if (ch == ' ') ch = '_';
+    return key;
+}
+
+// The launch shape pick_shape would return, without timing anything: the
+// tuned choice if one is cached, else the default shape.
+TuneChoice lookup_shape(hisq_lattice lat, int prec, int recon, int ntile, int nprob)
+{
+    TuneChoice def;
+    def.W = prec == 0 ? 8 : 4;
+    def.remap = 1;
+    if (Tuner::get().disabled()) return def;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return def;
+    TuneChoice c;
+    return Tuner::get().lookup(dslash_tune_key(prop, prec, recon, ntile, nprob), c) ? c : def;
+}
+
 // Default and tuned launch shape of the Dslash for a geometry.
 TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *ddesc, const int *dt2p,
                       int ntile, long long nsite, int nprob, bool no_tune)
@@ -420,11 +461,7 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     if (no_tune || Tuner::get().disabled()) return def;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return def;
-    std::ostringstream ks;
-    ks << "dslash3:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << ntile << ":n" << nprob;
-    std::string key = ks.str();
-    for (auto &ch : key)
-        if (ch == ' ') ch = '_';
+    std::string key = dslash_tune_key(prop, prec, recon, ntile, nprob);
     TuneChoice c;
     if (Tuner::get().lookup(key, c)) return c;
     DVec in, out;

@@ -316,9 +316,21 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
         S.gkey.clear();
         S.mode = mode;
     }
-    for (DVec *v : {&S.b, &S.xhi, &S.rhi, &S.thi}) HIPCHK(lat0, dvec_alloc(*v, 0, S.nsite));
-    for (DVec *v : {&S.xlo, &S.rlo, &S.Ap}) HIPCHK(lat0, dvec_alloc(*v, rprec, S.nsite));
-    for (DVec *v : {&S.p, &S.t}) HIPCHK(lat0, dvec_alloc(*v, mode, S.nsite));
+    if (S.borrowed) {
+        // the caller carved every vector out of memory it owns
+        if ((prm.flags & HISQ_USE_GRAPH) || !S.dclock)
+            return set_err(lat0, HISQ_ERR_ARG, "borrowed work set: no graphs, a start stamp is required");
+        for (DVec *v : {&S.b, &S.xhi, &S.rhi, &S.thi})
+            if (!v->p || v->prec != 0 || v->sites != S.nsite) return set_err(lat0, HISQ_ERR_STATE, "work vector");
+        for (DVec *v : {&S.xlo, &S.rlo, &S.Ap})
+            if (!v->p || v->prec != rprec || v->sites != S.nsite) return set_err(lat0, HISQ_ERR_STATE, "work vector");
+        for (DVec *v : {&S.p, &S.t})
+            if (!v->p || v->prec != mode || v->sites != S.nsite) return set_err(lat0, HISQ_ERR_STATE, "work vector");
+    } else {
+        for (DVec *v : {&S.b, &S.xhi, &S.rhi, &S.thi}) HIPCHK(lat0, dvec_alloc(*v, 0, S.nsite));
+        for (DVec *v : {&S.xlo, &S.rlo, &S.Ap}) HIPCHK(lat0, dvec_alloc(*v, rprec, S.nsite));
+        for (DVec *v : {&S.p, &S.t}) HIPCHK(lat0, dvec_alloc(*v, mode, S.nsite));
+    }
 
     const bool dev = (prm.flags & HISQ_DEVICE_PTR) != 0;
     const bool guess = (prm.flags & HISQ_X_IS_GUESS) != 0;
@@ -342,8 +354,11 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
     // kernel; the single-problem kernel then serves only the FP64 updates,
     // which use the default shape, so it is not tuned for them
     const bool shared = S.one_lattice && mode == 1;
-    TuneChoice tc = pick_shape(lat0, mode, recon, S.ddesc, S.dt2p, S.ntile, S.nsite, S.nprob,
-                               shared || (prm.flags & HISQ_NO_TUNE) != 0);
+    TuneChoice tc = S.borrowed ? ((prm.flags & HISQ_NO_TUNE) ? pick_shape(lat0, mode, recon, S.ddesc, S.dt2p, S.ntile,
+                                                                          S.nsite, S.nprob, true)
+                                                             : lookup_shape(lat0, mode, recon, S.ntile, S.nprob))
+                               : pick_shape(lat0, mode, recon, S.ddesc, S.dt2p, S.ntile, S.nsite, S.nprob,
+                                            shared || (prm.flags & HISQ_NO_TUNE) != 0);
     CgPlan pl{mode, recon, slot, tc.W, tc.remap, tc.cpol, {}};
     if (shared) {
         const int group = S.nprob < 4 ? S.nprob : 4;
@@ -357,8 +372,8 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
         pl.mrhs64 = pick_shape_mrhs(lat0, 0, 18, pl.group64, nt);
     }
 
-    long long *dclock = nullptr;
-    HIPCHK(lat0, hipMalloc(&dclock, sizeof(long long)));
+    long long *dclock = S.dclock;
+    if (!dclock) HIPCHK(lat0, hipMalloc(&dclock, sizeof(long long)));
     HIPCHK(lat0, launch_stamp(dclock, s));
     if (guess) {
         HIPCHK(lat0, enqueue_blas(S, BL_NORM, mode, ST_RUNNING, FIN_NORM_B, s));
@@ -466,7 +481,7 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
                                     dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     }
     HIPCHK(lat0, hipStreamSynchronize(s));
-    (void)hipFree(dclock);
+    if (dclock != S.dclock) (void)hipFree(dclock);
     double elapsed = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int clk_khz = 100000;
     (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, lat0->device);

@@ -51,6 +51,11 @@ struct SolveSet {
     // FP64 true relative residual of every problem at each reliable update of
     // the last solve on this set
     std::vector<std::vector<double>> hist;
+    // borrowed: every device pointer above points into memory the set does not
+    // own (the static scratch of the no-allocation solver); the solver then
+    // allocates nothing, never times launch shapes and release() frees nothing
+    bool borrowed = false;
+    long long *dclock = nullptr;   // device start stamp (borrowed sets; else allocated per solve)
     ~SolveSet();
     void release();
 };

@@ -12,6 +12,8 @@ namespace hisq {
 ProbDesc lattice_desc(hisq_lattice lat);
 TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *ddesc, const int *dt2p,
                       int ntile, long long nsite, int nprob, bool no_tune);
+// pick_shape's answer without timing: the cached tuned choice or the default.
+TuneChoice lookup_shape(hisq_lattice lat, int prec, int recon, int ntile, int nprob);
 // Tuned launch shape of the multi-right-hand-side Dslash (nr right-hand
 // sides per launch, FP32 vectors) on lattice lat.
 TuneChoice pick_shape_mrhs(hisq_lattice lat, int prec, int recon, int nr, bool no_tune);

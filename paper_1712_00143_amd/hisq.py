@@ -42,7 +42,7 @@ EXPORTS = [
     "hisq_ptc_get_weights", "hisq_ptc_layer_forward", "hisq_ptc_layer_backward", "hisq_ptc_apply",
     "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
     "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss", "hisq_ptc_save", "hisq_ptc_load",
-    "hisq_residual_history", "hisq_ptc_set_transport", "hisq_ptc_get_transport",
+    "hisq_residual_history", "hisq_ptc_set_transport", "hisq_ptc_get_transport", "hisq_cg_noalloc",
 ]
 
 
@@ -219,6 +219,21 @@ class Lattice:
                            ctypes.byref(info))
         if raise_on_fail:
             _check(st, self.handle, "hisq_cg")
+        return x, info.as_dict()
+
+    def cg_noalloc(self, mass, b, x, params=None, raise_on_fail=True):
+        """hisq_cg_noalloc: b and x device FP64 tensors of V/2 * 6 reals; the
+        solver allocates no device memory.  Returns (x, info dict)."""
+        params = params or hisq_default_params()
+        bp, bdev, k1 = _ptr(b)
+        xp, xdev, k2 = _ptr(x)
+        if bdev:
+            params.flags |= HISQ_DEVICE_PTR
+        info = hisq_solver_info()
+        st = lib().hisq_cg_noalloc(self.handle, ctypes.c_double(mass), bp, xp, ctypes.byref(params),
+                                   ctypes.byref(info))
+        if raise_on_fail:
+            _check(st, self.handle, "hisq_cg_noalloc")
         return x, info.as_dict()
 
     def residual_history(self, problem=0):
