@@ -1,18 +1,27 @@
 """Benchmark of the HISQ Dslash + CG hot path on one MI355X.
 
-Default (the headline line): the 16^3x32 workload (eps 0.2, m 0.02), links
-already resident in HBM.  One step is one pass of the hot path:
-  * half-lattice Dslash D_eo and D_oe in FP32 recon-18, FP32 recon-12,
-    FP16 recon-12 and FP64 recon-18 on device vectors;
-  * CG to FP64 true residual 1e-10 from the same source: plain FP64, mixed
+Default (the headline line).  One step is one pass of the hot path on inputs
+already resident in HBM:
+  * the half-lattice Dslash D_eo / D_oe on a 32^4 lattice (eps 0.2) whose
+    links (1.2 GB per half-Dslash in FP64) are far beyond the 256 MB Infinity
+    Cache: FP64 recon-18 (the paper's precision), FP32 recon-18, FP32 recon-12
+    and FP16 recon-12 with every link streamed past the caches, and FP64 /
+    FP32 recon-18 in the autotuner's choice (part of the links may be kept in
+    the Infinity Cache: an effective rate);
+  * the 16^3x32 workload (eps 0.2, m 0.02): the half-Dslash in every format,
+    and CG to FP64 true residual 1e-10 from one source: plain FP64, mixed
     FP32 (recon-18), mixed FP16 storage (recon-12), and the flexible CG with
-    the learned preconditioner (trained before the timed region on pairs
-    the solver harvests from two other sources).
-value = FP32 recon-18 Dslash throughput in algorithmic GB/s (16 links + one
-input + one output colour vector per output site) from HIP events recorded on
-the stream the kernels run on.  Reported beside it: the other formats, a 32^4
-lattice whose links exceed the 256 MB Infinity Cache, the solver times, and
-the FP64 CPU oracle timed on the host cores over a bounded sample.
+    the learned preconditioner (trained before the timed region on pairs the
+    solver harvests from two other sources).
+value = FP64 recon-18 streamed half-Dslash throughput on 32^4 in algorithmic
+GB/s (16 links + one input + one output colour vector per output site) from
+HIP events recorded on the stream the kernels run on.  Reported beside it:
+the other formats, link load / pack times, each solve's error against the
+oracle's solution and the oracle's recomputed true residual, the practical
+HBM ceilings, and (outside the timed steps) one multi-shift solve on 24^3x48
+(12 shifts x 4 sources) and one batch of 64 uneven solves, each with oracle
+true residuals of a sample of its solutions; the FP64 CPU oracle is timed on
+the host cores over a bounded sample.
 
 Other workloads (--workload): c0 (4^4 plain FP64 CG), c2 (24^3x48
 multi-shift, 12 shifts x 4 sources), c3 (64 uneven solves in one batch),
@@ -58,9 +67,10 @@ def kernel_hash():
 
 
 def traffic_entry():
-    """Measured HBM bytes per launch from the committed counter summary, if it
-    was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "dslash_f32r18_16x16x16x32_traffic.json")
+    """Measured HBM bytes per launch of the headline kernel (FP64 recon-18,
+    streamed links, 32^4) from the committed counter summary, if it was taken
+    on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "dslash_f64r18_streamed_32x32x32x32_traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -80,23 +90,23 @@ def _vec(torch, prec, h, seed):
     return x
 
 
-def timed_dslash(torch, lat, prec, recon, h, stream, reps):
+def timed_dslash(torch, lat, prec, recon, h, stream, reps, flags=0):
     """Average duration (s) of one half-Dslash launch (both parities alternate),
     as (graph, eager).  The 2*reps launches are captured once in a HIP graph on
     the library's stream and replayed there between two events, so host launch
     gaps do not count; the same launches issued eagerly are timed too.  graph
-    is None where capture fails."""
+    is None where capture fails.  flags: hisq_dslash flags (HISQ_STREAM_LINKS)."""
     x = _vec(torch, prec, h, 7)
     y = torch.empty_like(x)
     torch.cuda.synchronize()
-    lat.dslash(0, prec, recon, x, y)      # tunes the block shape before any capture
-    lat.dslash(1, prec, recon, y, x)
+    lat.dslash(0, prec, recon, x, y, flags=flags)      # tunes the block shape before any capture
+    lat.dslash(1, prec, recon, y, x, flags=flags)
     torch.cuda.synchronize()
 
     def body():
         for _ in range(reps):
-            lat.dslash(0, prec, recon, x, y)
-            lat.dslash(1, prec, recon, y, x)
+            lat.dslash(0, prec, recon, x, y, flags=flags)
+            lat.dslash(1, prec, recon, y, x, flags=flags)
 
     graph = None
     try:
@@ -199,28 +209,80 @@ def train_preconditioner(H, synth, dims, eps, mass, seed0, nfield, nsrc, steps, 
 
 # ----------------------------------------------------------------- headline
 
+HEAD_DIMS = (32, 32, 32, 32)
+FMT_NAME = {(0, 18): "f64_r18", (1, 18): "f32_r18", (1, 12): "f32_r12", (2, 12): "f16_r12"}
+
+
+def timed_call(torch, fn):
+    """(result, seconds) of fn() between two device synchronisations."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def shape_name(prec, recon, shape):
+    W, remap, cpol = shape
+    lt = {0: "double", 1: "float", 2: "__half"}[prec]
+    st, ot = lt, lt
+    cp = 0 if cpol <= 0 else 1 if cpol >= 16 else 2
+    kern = "k_dslash_lo" if W & 256 else "k_dslash"
+    return f"{kern}<{lt},{recon},{st},{ot},{W & 255},EPI_PLAIN,{cp}>"
+
+
 def run_headline(args):
     import torch
     from paper_1712_00143_amd import hisq as H
     from paper_1712_00143_amd import synth
+    import oracle
 
+    stream = torch.cuda.Stream()
+    sp = H.ctypes.c_void_p(stream.cuda_stream)
+    formats = [(1, 18), (1, 12), (2, 12), (0, 18)]
+    setup = {}
+
+    # ---- the headline lattice, 32^4: 1.2 GB of FP64 links per half-Dslash,
+    # far beyond the 256 MB Infinity Cache
+    t0 = time.perf_counter()
+    fh, lh = synth.make_links(HEAD_DIMS, 0.2, seed=1900)
+    setup["32^4_link_generation_host_s"] = round(time.perf_counter() - t0, 2)
+    log(f"32^4 links generated in {setup['32^4_link_generation_host_s']} s")
+    latH = H.Lattice(HEAD_DIMS, stream=sp)
+    _, dt = timed_call(torch, lambda: latH.load_links(fh, lh))
+    setup["32^4_load_links_s"] = round(dt, 4)
+    del fh, lh
+    for p, r in formats[:3]:
+        _, dt = timed_call(torch, lambda: latH.prepare_links(p, r))
+        setup[f"32^4_prepare_{FMT_NAME[(p, r)]}_s"] = round(dt, 4)
+    hH = synth.volume(HEAD_DIMS) // 2
+
+    # ---- the 16^3x32 workload (eps 0.2, m 0.02): Dslash formats and solvers
     w = synth.C1
     fat, lng = w.links()
     b = w.sources()[0]
     h = synth.volume(w.dims) // 2
-    stream = torch.cuda.Stream()
-    sp = H.ctypes.c_void_p(stream.cuda_stream)
     lat = H.Lattice(w.dims, stream=sp)
-    lat.load_links(fat, lng)
-    formats = [(1, 18), (1, 12), (2, 12), (0, 18)]
-    for p, r in formats:
-        lat.prepare_links(p, r)
+    _, dt = timed_call(torch, lambda: lat.load_links(fat, lng))
+    setup["16^3x32_load_links_s"] = round(dt, 4)
+    for p, r in formats[:3]:
+        _, dt = timed_call(torch, lambda: lat.prepare_links(p, r))
+        setup[f"16^3x32_prepare_{FMT_NAME[(p, r)]}_s"] = round(dt, 4)
     bd = torch.from_numpy(b.view(np.float64)).cuda()
     solves = {
         "plain_f64": H.hisq_default_params(tol=1e-10, sloppy=0, recon=18, flags=H.HISQ_USE_GRAPH),
         "mixed_f32_r18": H.hisq_default_params(tol=1e-10, sloppy=1, recon=18, flags=H.HISQ_USE_GRAPH),
         "mixed_f16_r12": H.hisq_default_params(tol=1e-10, sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH),
     }
+    x_oracle = None
+    if not args.dslash_only:
+        # the oracle's solution of the same system, solved beyond the target,
+        # for the per-solve error (host FP64, outside the timed region)
+        t0 = time.perf_counter()
+        x_oracle, it_or, tr_or, ok_or = oracle.cg(w.dims, fat, lng, w.mass, b, tol=1e-12)
+        setup["oracle_solution"] = {"seconds": round(time.perf_counter() - t0, 2), "iters": it_or,
+                                    "true_residual": float(f"{tr_or:.3e}"), "converged": bool(ok_or)}
+        log(f"oracle solution: {it_or} iterations in {setup['oracle_solution']['seconds']} s")
     net = None
     train_info = None
     if not args.no_learned and not args.dslash_only:
@@ -231,13 +293,18 @@ def run_headline(args):
         srcs = w.sources()
         npair = sum(net.harvest(lat, w.mass, srcs[k], every=20, maxpairs=60) for k in (1, 2))
         losses = net.train(300, batch=8, lr=3e-3, seed=1)
-        train_info = {"network": "1-2-1 PTC, polynomial start, energy-norm loss",
+        train_info = {"network": "1-2-1 PTC, polynomial start, energy-norm loss, FP32 recon-18 transports",
                       "pairs": npair, "steps": 300, "seconds": round(time.perf_counter() - t0, 3),
                       "loss_first10": round(float(losses[:10].mean()), 4),
                       "loss_last50": round(float(losses[-50:].mean()), 4)}
 
+    head_fmts = [((0, 18), H.HISQ_STREAM_LINKS), ((1, 18), H.HISQ_STREAM_LINKS),
+                 ((1, 12), H.HISQ_STREAM_LINKS), ((2, 12), H.HISQ_STREAM_LINKS), ((0, 18), 0), ((1, 18), 0)]
+
     def step():
-        res = {"dslash_s": {}, "cg": {}}
+        res = {"head": {}, "dslash_s": {}, "cg": {}, "x": {}}
+        for (p, r), fl in head_fmts:
+            res["head"][(p, r, fl)] = timed_dslash(torch, latH, p, r, hH, stream, args.head_reps, fl)
         for p, r in formats:
             res["dslash_s"][(p, r)] = timed_dslash(torch, lat, p, r, h, stream, args.reps)
         if not args.dslash_only:
@@ -246,12 +313,14 @@ def run_headline(args):
                 (_, info), dt = solve_timed(torch, stream, lambda: lat.cg(w.mass, bd, x=xd, params=prm))
                 info["wall_s"] = dt
                 res["cg"][name] = info
+                res["x"][name] = xd
             if net is not None:
                 xd = torch.zeros_like(bd)
                 prm = H.hisq_default_params(tol=1e-10, sloppy=1, recon=18, flags=H.HISQ_USE_GRAPH)
                 (_, info), dt = solve_timed(torch, stream, lambda: net.cg_learned(lat, w.mass, bd, x=xd, params=prm))
                 info["wall_s"] = dt
                 res["cg"]["learned_fcg_f32"] = info
+                res["x"]["learned_fcg_f32"] = xd
         return res
 
     for _ in range(args.warmup):
@@ -266,33 +335,56 @@ def run_headline(args):
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
 
-    def avg(key, which):
-        ts = [r["dslash_s"][key][which] for r in results]
+    def avg(group, key, which):
+        ts = [r[group][key][which] for r in results]
         return None if any(t is None for t in ts) else float(np.mean(ts))
 
-    def dtime(key):
+    def dtime(group, key):
         """Graph-replay time where capture worked, else the eager time."""
-        tg = avg(key, 0)
-        return (tg, "graph") if tg is not None else (avg(key, 1), "eager")
+        tg = avg(group, key, 0)
+        return (tg, "graph") if tg is not None else (avg(group, key, 1), "eager")
+
+    # 32^4 lines
+    head = {}
+    for (p, r), fl in head_fmts:
+        t, how = dtime("head", (p, r, fl))
+        gbs = hH * site_bytes(p, r) / t / 1e9
+        shape = latH.dslash_shape(p, r, fl)
+        head[FMT_NAME[(p, r)] + ("_streamed" if fl else "_tuned")] = {
+            "us": round(t * 1e6, 3), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
+            "GFLOP/s": round(1146.0 * hH / t / 1e9, 1), "timing": how, "kernel": shape_name(p, r, shape),
+            "link_blocks_cached": shape[2],
+            "links": "all streamed past the caches (an HBM rate)" if fl else
+                     ("tuned: part of the links kept in the Infinity Cache (an effective rate, not an HBM rate)"
+                      if shape[2] else "tuned: all streamed")}
+    t64, how64 = dtime("head", (0, 18, H.HISQ_STREAM_LINKS))
+    achieved = hH * site_bytes(0, 18) / t64 / 1e9
+    shape64 = latH.dslash_shape(0, 18, H.HISQ_STREAM_LINKS)
 
     dsl = {}
     for p, r in formats:
-        t, how = dtime((p, r))
+        t, how = dtime("dslash_s", (p, r))
         gbs = h * site_bytes(p, r) / t / 1e9
-        dsl[f"{['f64', 'f32', 'f16'][p]}_r{r}"] = {
+        shape = lat.dslash_shape(p, r, 0)
+        dsl[FMT_NAME[(p, r)]] = {
             "us": round(t * 1e6, 3), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
-            "GFLOP/s": round(1146.0 * h / t / 1e9, 1), "timing": how,
-            "us_eager_launches": round(avg((p, r), 1) * 1e6, 3)}
-    t32, how32 = dtime((1, 18))
-    achieved = h * site_bytes(1, 18) / t32 / 1e9
+            "GFLOP/s": round(1146.0 * h / t / 1e9, 1), "timing": how, "kernel": shape_name(p, r, shape),
+            "link_blocks_cached": shape[2],
+            "us_eager_launches": round(avg("dslash_s", (p, r), 1) * 1e6, 3)}
 
     cg = {}
     if not args.dslash_only:
+        last = results[-1]
         for name in results[0]["cg"]:
             infos = [r["cg"][name] for r in results]
+            xh = last["x"][name].cpu().numpy().view(np.complex128).reshape(-1, 3)
+            err = float(np.linalg.norm(xh - x_oracle) / np.linalg.norm(x_oracle))
+            tr_or = oracle.true_residual(w.dims, fat, lng, w.mass, b, xh)
             cg[name] = {"time_s": round(float(np.median([i["wall_s"] for i in infos])), 5),
                         "iters": infos[-1]["iters"], "reliable_updates": infos[-1]["reliable_updates"],
                         "true_residual_fp64": float(f"{infos[-1]['true_residual']:.3e}"),
+                        "oracle_true_residual": float(f"{tr_or:.3e}"),
+                        "error_vs_oracle_solution": float(f"{err:.3e}"),
                         "converged": bool(infos[-1]["converged"])}
             if name.startswith("learned"):
                 cg[name]["fell_back"] = bool(infos[-1]["fell_back"])
@@ -311,26 +403,8 @@ def run_headline(args):
         lat.dslash(k & 1, 1, 18, psi_h, out_h)
     t_host = (time.perf_counter() - t0) / nh
     host_path = {"us": round(t_host * 1e6, 1),
-                 "what": "hisq_dslash on host FP64 vectors (copy in, convert, FP32 Dslash, convert, copy out, "
-                         "synchronised), per call"}
-    hbm = None
-    if not args.no_hbm:
-        dims = (32, 32, 32, 32)
-        f2, l2 = synth.make_links(dims, 0.2, seed=1900)
-        lat2 = H.Lattice(dims, stream=sp)
-        lat2.load_links(f2, l2)
-        del f2, l2
-        hbm = {}
-        h2 = synth.volume(dims) // 2
-        for p, r in formats:
-            lat2.prepare_links(p, r)
-            tg, te = timed_dslash(torch, lat2, p, r, h2, stream, 20)
-            t = tg if tg is not None else te
-            gbs = h2 * site_bytes(p, r) / t / 1e9
-            hbm[f"{['f64', 'f32', 'f16'][p]}_r{r}"] = {"us": round(t * 1e6, 2), "GB/s": round(gbs, 1),
-                                                       "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
-        lat2.close()
-
+                 "what": "hisq_dslash on host FP64 vectors, 16^3x32 (copy in, convert, FP32 Dslash, convert, "
+                         "copy out, synchronised), per call"}
     out = {
         "metric": METRIC,
         "value": round(achieved, 1),
@@ -342,29 +416,32 @@ def run_headline(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "HISQ even-odd Dslash (FP32 recon-18) + CG to 1e-10, 16^3x32, eps 0.2, m 0.02",
-                   "lattice": list(w.dims), "parallelism": "single GPU"},
+        "config": {"workload": "HISQ even-odd half-Dslash D_eo/D_oe in FP64 recon-18 (the paper's precision) with "
+                               "every link streamed past the caches, 32^4 (eps 0.2); in the same step the "
+                               "16^3x32 workload (eps 0.2, m 0.02): Dslash in every format and CG to FP64 true "
+                               "residual 1e-10 plain / mixed / learned",
+                   "lattice": list(HEAD_DIMS), "solver_lattice": list(w.dims), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_entry(),
-                     "kernel": "k_dslash<float,18,float,float,W,EPI_PLAIN,CP>",
-                     "bytes_per_launch": h * site_bytes(1, 18),
-                     "launch_us": round(t32 * 1e6, 3), "timing": f"HIP events around a {how32} of "
-                     f"{2 * args.reps} launches on the library stream",
+                     "kernel": shape_name(0, 18, shape64),
+                     "bytes_per_launch": hH * site_bytes(0, 18),
+                     "bytes_per_site": site_bytes(0, 18), "sites_per_launch": hH,
+                     "launch_us": round(t64 * 1e6, 3), "timing": f"HIP events around a {how64} of "
+                     f"{2 * args.head_reps} launches (parities alternating) on the library stream",
                      "read_ceiling": {"GB/s": round(read_gbs, 1), "frac_of_peak": round(read_gbs / PEAK_HBM_GBS, 4),
                                       "what": "library streaming read of 1 GiB (non-temporal 16-byte loads)",
                                       "dslash_frac_of_read_ceiling": round(achieved / read_gbs, 4)},
                      "copy_ceiling": {"GB/s": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / PEAK_HBM_GBS, 4),
                                       "what": "library copy of 1 GiB, read + written bytes"},
-                     "cache": "both parities' FP32 links (151 MB) fit the 256 MB Infinity Cache; the tuner times "
-                              "streamed, cached (and, beyond the cache, partly cached) link loads and keeps the "
-                              "fastest, so part of the link stream may come from the cache at this size (the 32^4 "
-                              "lines are beyond it)"},
-        "dslash": dsl,
-        "dslash_32^4_beyond_infinity_cache": hbm,
+                     "cache": "links streamed with non-temporal loads; both parities' FP64 links take 2.4 GB "
+                              "against a 256 MB Infinity Cache, so the rate is an HBM rate"},
+        "dslash_32^4": head,
+        "dslash_16^3x32": dsl,
         "dslash_host_buffers": host_path,
-        "cg_time_to_1e-10": cg,
+        "cg_time_to_1e-10_16^3x32": cg,
+        "setup": setup,
     }
     if "plain_f64" in cg:
         out["cg_speedup_vs_plain_f64"] = {k: round(cg["plain_f64"]["time_s"] / v["time_s"], 3)
@@ -374,6 +451,11 @@ def run_headline(args):
     if net is not None:
         net.close()
     lat.close()
+    latH.close()
+    if not args.dslash_only and not args.no_c2:
+        out["c2_multishift_24^3x48"] = c2_summary(args, oracle_sample=8)
+    if not args.dslash_only and not args.no_c3:
+        out["c3_batched_64_solves"] = c3_summary(args, oracle_sample=8)
     print(json.dumps(out), flush=True)
 
 
@@ -401,18 +483,27 @@ def run_c0(args):
     print(json.dumps({"workload": "plain FP64 CG 4^4, eps 0.3, m 0.1, tol 1e-10", "results": res}), flush=True)
 
 
-def run_c2(args):
+def c2_summary(args, oracle_sample=0):
+    """One multi-shift CG solve on the 24^3x48 workload (12 shifts in
+    [1e-4, 1], 4 sources batched through the multi-RHS Dslash, m 0.01, FP32
+    with FP64 recurrences and refinement, tol 1e-8) after one warm-up solve,
+    plus the multi-RHS Dslash rates.  oracle_sample > 0: the oracle recomputes
+    the FP64 true residual of that many solutions (both ends of the shift range
+    for each source first)."""
     import torch
     from paper_1712_00143_amd import hisq as H
     from paper_1712_00143_amd import synth
+    import oracle
     w = synth.C2
+    t0 = time.perf_counter()
     fat, lng = w.links()
+    gen_s = time.perf_counter() - t0
     b = w.sources()
     shifts = synth.shifts_log(12)
     stream = torch.cuda.Stream()
     lat = H.Lattice(w.dims, stream=H.ctypes.c_void_p(stream.cuda_stream))
-    lat.load_links(fat, lng)
-    lat.prepare_links(1, 18)
+    _, load_s = timed_call(torch, lambda: lat.load_links(fat, lng))
+    _, prep_s = timed_call(torch, lambda: lat.prepare_links(1, 18))
     h = synth.volume(w.dims) // 2
     # multi-RHS Dslash throughput (4 right-hand sides share the link stream)
     x = torch.randn(4 * 6 * h, device="cuda")
@@ -442,37 +533,65 @@ def run_c2(args):
     e1.synchronize()
     t48 = e0.elapsed_time(e1) / 1000.0 / 10
     del x48, y48
-    mrhs = {"mrhs_dslash_f32_r18_nrhs4": {"us": round(t * 1e6, 2), "GB/s": round(mrhs_bytes / t / 1e9, 1),
-                                          "frac_hbm": round(mrhs_bytes / t / 1e9 / PEAK_HBM_GBS, 4)},
-            "mrhs_dslash_f32_r18_nrhs48": {"us": round(t48 * 1e6, 2), "groups": 12,
-                                           "us_per_group": round(t48 * 1e6 / 12, 2),
-                                           "what": "one launch over 12 groups of four right-hand sides"}}
+    out = {"workload": "multi-shift CG 24^3x48, 12 shifts in [1e-4, 1], 4 sources, m 0.01, FP32 + FP64 "
+                       "recurrences, tol 1e-8",
+           "mrhs_dslash_f32_r18_nrhs4": {"us": round(t * 1e6, 2), "GB/s": round(mrhs_bytes / t / 1e9, 1),
+                                         "frac_hbm": round(mrhs_bytes / t / 1e9 / PEAK_HBM_GBS, 4)},
+           "mrhs_dslash_f32_r18_nrhs48": {"us": round(t48 * 1e6, 2), "groups": 12,
+                                          "us_per_group": round(t48 * 1e6 / 12, 2),
+                                          "what": "one launch over 12 groups of four right-hand sides"},
+           "link_generation_host_s": round(gen_s, 2), "load_links_s": round(load_s, 4),
+           "prepare_f32_r18_s": round(prep_s, 4)}
     if args.dslash_only:
-        print(json.dumps({"workload": "multi-RHS Dslash 24^3x48, FP32 recon-18", **mrhs}), flush=True)
-        return
+        lat.close()
+        return out
     prm = H.hisq_default_params(tol=1e-8, sloppy=1, flags=H.HISQ_USE_GRAPH)
     # sources and solutions resident in HBM (device pointers)
     bd = torch.from_numpy(np.ascontiguousarray(b).view(np.float64).ravel()).cuda()
     xd = torch.zeros(len(b) * len(shifts) * h * 6, dtype=torch.float64, device="cuda")
-    lat.multishift_cg(w.mass, shifts, bd, x=xd, params=prm)
+    lat.multishift_cg(w.mass, shifts, bd, x=xd, params=prm)          # warm-up: tuning, graph capture
+    xd.zero_()
     (xs, infos), dt = solve_timed(torch, stream, lambda: lat.multishift_cg(w.mass, shifts, bd, x=xd, params=prm))
     worst = max(i["true_residual"] for i in infos)
-    print(json.dumps({
-        "workload": "multi-shift CG 24^3x48, 12 shifts in [1e-4, 1], 4 sources, m 0.01, FP32 + FP64 recurrences, tol 1e-8",
-        **mrhs,
+    out.update({
         "time_s": round(dt, 4), "krylov_phase_s": round(infos[0]["t_done_s"], 4),
         "iters_per_shift_rhs0": [i["iters"] for i in infos[:12]],
         "refine_iters_per_shift_rhs0": [i["refine_iters"] for i in infos[:12]],
         "worst_true_residual_fp64": float(f"{worst:.3e}"),
-        "all_converged": all(i["converged"] for i in infos)}), flush=True)
+        "all_converged": all(i["converged"] for i in infos)})
+    if oracle_sample > 0:
+        xh = xd.cpu().numpy().view(np.complex128).reshape(len(b), len(shifts), h, 3)
+        picks = [(j, k) for j in range(len(b)) for k in (0, len(shifts) - 1)]
+        picks += [(j, k) for j in range(len(b)) for k in range(1, len(shifts) - 1)]
+        t0 = time.perf_counter()
+        checked = []
+        for j, k in picks[:oracle_sample]:
+            tr = oracle.true_residual(w.dims, fat, lng, w.mass, b[j], xh[j, k], shifts[k])
+            checked.append({"rhs": j, "shift": float(f"{shifts[k]:.4e}"), "oracle_true_residual": float(f"{tr:.3e}")})
+        out["oracle_check"] = {"solutions": checked, "all_within_tol": all(c["oracle_true_residual"] <= 1e-8
+                                                                          for c in checked),
+                               "seconds": round(time.perf_counter() - t0, 2)}
+    lat.close()
+    return out
 
 
-def run_c3(args):
+def run_c2(args):
+    print(json.dumps(c2_summary(args, oracle_sample=args.oracle_sample)), flush=True)
+
+
+def c3_summary(args, oracle_sample=0):
+    """One batch of 64 uneven solves (16 each of 8^4, 12^4, 16^4, 16^3x32,
+    eps ~ U[0.1, 0.4], m ~ logU[0.005, 0.2]; FP32 with FP64 reliable updates,
+    tol 1e-10) in one set of launches, after a warm-up batch, and the same
+    solves one after another.  oracle_sample > 0: the oracle recomputes the
+    FP64 true residual of that many solutions, spread over the four sizes."""
     import torch
     from paper_1712_00143_amd import hisq as H
     from paper_1712_00143_amd import synth
+    import oracle
     ws = synth.batch_workload(nper=args.nper)
-    lats, bs, ms = [], [], []
+    lats, bs, ms, links = [], [], [], []
+    t0 = time.perf_counter()
     for q, wk in enumerate(ws):
         if q % 16 == 0:
             log(f"generating batch problem {q}/{len(ws)}")
@@ -483,6 +602,8 @@ def run_c3(args):
         lats.append(L)
         bs.append(wk.sources()[0])
         ms.append(wk.mass)
+        links.append((wk.dims, fat, lng) if oracle_sample > 0 else None)
+    setup_s = time.perf_counter() - t0
     prm = H.hisq_default_params(tol=1e-10, sloppy=1, flags=H.HISQ_USE_GRAPH)
     H.hisq_batch_cg(lats, ms, bs, params=prm)          # warm-up: tuning, graph capture
     (xs, infos), dt = solve_timed(torch, None, lambda: H.hisq_batch_cg(lats, ms, bs, params=prm))
@@ -493,14 +614,37 @@ def run_c3(args):
     for L, m, bb in zip(lats, ms, bs):
         (_, _), d1 = solve_timed(torch, None, lambda: L.cg(m, bb, params=prm))
         t_seq += d1
-    print(json.dumps({
-        "workload": f"batched CG: {len(ws)} solves, {args.nper} each of 8^4, 12^4, 16^4, 16^3x32; eps~U[0.1,0.4], m~logU[0.005,0.2]; FP32 + FP64 reliable, tol 1e-10",
+    out = {
+        "workload": f"batched CG: {len(ws)} solves, {args.nper} each of 8^4, 12^4, 16^4, 16^3x32; eps~U[0.1,0.4], "
+                    f"m~logU[0.005,0.2]; FP32 + FP64 reliable, tol 1e-10",
         "time_s": round(dt, 4), "aggregate_dslash_GB/s": round(total_bytes / dt / 1e9, 1),
         "time_to_solution_p50_s": round(float(np.percentile(tdone, 50)), 5),
         "time_to_solution_p99_s": round(float(np.percentile(tdone, 99)), 5),
         "iters_min_max": [min(i["iters"] for i in infos), max(i["iters"] for i in infos)],
         "all_converged": all(i["converged"] for i in infos),
-        "sequential_time_s": round(t_seq, 4), "batch_speedup": round(t_seq / dt, 3)}), flush=True)
+        "worst_true_residual_fp64": float(f"{max(i['true_residual'] for i in infos):.3e}"),
+        "sequential_time_s": round(t_seq, 4), "batch_speedup": round(t_seq / dt, 3),
+        "setup_s": round(setup_s, 2)}
+    if oracle_sample > 0:
+        n = len(ws)
+        # interleave the four sizes: problems are ordered size by size
+        order = [q for k in range(args.nper) for q in range(k, n, args.nper)]
+        t0 = time.perf_counter()
+        checked = []
+        for q in order[:oracle_sample]:
+            dims, fat, lng = links[q]
+            tr = oracle.true_residual(dims, fat, lng, ms[q], bs[q], xs[q])
+            checked.append({"problem": q, "lattice": list(dims), "oracle_true_residual": float(f"{tr:.3e}")})
+        out["oracle_check"] = {"solutions": checked, "all_within_tol": all(c["oracle_true_residual"] <= 1e-10
+                                                                          for c in checked),
+                               "seconds": round(time.perf_counter() - t0, 2)}
+    for L in lats:
+        L.close()
+    return out
+
+
+def run_c3(args):
+    print(json.dumps(c3_summary(args, oracle_sample=args.oracle_sample)), flush=True)
 
 
 def run_c4(args):
@@ -602,10 +746,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--reps", type=int, default=50, help="Dslash launches per parity per step")
+    ap.add_argument("--reps", type=int, default=50, help="16^3x32 Dslash launches per parity per step")
+    ap.add_argument("--head-reps", type=int, default=20, help="32^4 Dslash launches per parity per step")
+    ap.add_argument("--no-c2", action="store_true", help="headline: skip the multi-shift summary")
+    ap.add_argument("--no-c3", action="store_true", help="headline: skip the batched-solve summary")
+    ap.add_argument("--oracle-sample", type=int, default=8, help="c2/c3: solutions checked by the oracle")
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-hbm", action="store_true", help="skip the 32^4 (beyond-cache) lattice")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--dslash-only", action="store_true", help="time only the Dslash")
     ap.add_argument("--nper", type=int, default=16, help="c3: solves per lattice size")

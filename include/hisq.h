@@ -68,14 +68,20 @@ enum {
     HISQ_X_IS_GUESS = 2,   /* solvers: x holds an initial guess (else cold start) */
     HISQ_USE_GRAPH = 4,    /* solvers: replay captured HIP graphs of iteration chunks */
     HISQ_NO_TUNE = 8,      /* use default launch shapes, skip the autotuner */
-    HISQ_STOP_STAGNATION = 16   /* CG solvers: give up (HISQ_ERR_NOT_CONVERGED, x the last
+    HISQ_STOP_STAGNATION = 16,  /* CG solvers: give up (HISQ_ERR_NOT_CONVERGED, x the last
                                    reliable update's iterate) when three reliable updates in a
                                    row bring no FP64 true residual below the one before them */
+    HISQ_STREAM_LINKS = 32      /* hisq_dslash (one right-hand side): stream every link past the
+                                   caches (no part kept in the Infinity Cache between calls), in
+                                   the block shape the autotuner found fastest that way; the rate
+                                   is then an HBM rate whatever the operator's size */
 };
 /* Environment: HISQ_TUNE=0 gives every call the default launch shapes (as
  * HISQ_NO_TUNE does for one call); HISQ_TUNE_CACHE=<file> appends every tuned
- * choice to a text file (one "key W remap cache-policy us" line each) and
- * reads it back at start-up, so a later process skips the timing. */
+ * choice to a text file (one "key W remap cache-policy us" line each; W is
+ * the waves per block, plus 256 for the variant compiled for at most two
+ * waves per SIMD) and reads it back at start-up, so a later process skips the
+ * timing. */
 
 typedef struct {
     double tol;          /* target FP64 true relative residual ||b - A x|| / ||b|| */
@@ -144,6 +150,17 @@ hisq_status hisq_prepare_links(hisq_lattice lat, hisq_prec prec, hisq_recon reco
  * (the autotuner); make it before capturing calls into a HIP graph. */
 hisq_status hisq_dslash(hisq_lattice lat, hisq_parity out_parity, hisq_prec prec,
                         hisq_recon recon, const void *in, void *out, int nrhs, int flags);
+
+/* The launch shape hisq_dslash (one right-hand side) uses for (prec, recon)
+ * on this lattice under `flags` (HISQ_STREAM_LINKS, HISQ_NO_TUNE), running
+ * the autotuner first if it has not chosen yet: *waves = wavefronts per block
+ * (1, 2, 4, 8, 16; plus 256 for the variant compiled for at most two waves
+ * per SIMD), *remap = 1 for the XCD-contiguous tile order, *cache_blocks =
+ * link direction blocks (of 16) loaded so that they stay in the Infinity
+ * Cache.  For naming the kernel a measurement profiles.  Errors: HISQ_ERR_ARG
+ * (null outputs, bad format), HISQ_ERR_STATE (no links, set not prepared). */
+hisq_status hisq_dslash_shape(hisq_lattice lat, hisq_prec prec, hisq_recon recon, int flags, int *waves,
+                              int *remap, int *cache_blocks);
 
 /* Solve (4m^2 - D_eo D_oe) x = b on even sites (host FP64 vectors, or device
  * FP64 with HISQ_DEVICE_PTR).  Plain FP64 CG when params->sloppy == HISQ_F64;

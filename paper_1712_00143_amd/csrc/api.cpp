@@ -427,10 +427,11 @@ hisq_status hisq_prepare_links(hisq_lattice lat, hisq_prec prec, hisq_recon reco
 
 namespace hisq {
 
-static std::string dslash_tune_key(const hipDeviceProp_t &prop, int prec, int recon, int ntile, int nprob)
+static std::string dslash_tune_key(const hipDeviceProp_t &prop, int prec, int recon, int ntile, int nprob,
+                                   bool streamed = false)
 {
     std::ostringstream ks;
-    ks << "dslash3:" << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << ntile << ":n" << nprob;
+    ks << (streamed ? "dslash3s:" : "dslash3:") << prop.gcnArchName << ":p" << prec << ":r" << recon << ":t" << ntile << ":n" << nprob;
     std::string key = ks.str();
     for (auto &ch : key)
         if (ch == ' ') ch = '_';
@@ -451,9 +452,11 @@ TuneChoice lookup_shape(hisq_lattice lat, int prec, int recon, int ntile, int np
     return Tuner::get().lookup(dslash_tune_key(prop, prec, recon, ntile, nprob), c) ? c : def;
 }
 
-// Default and tuned launch shape of the Dslash for a geometry.
+// Default and tuned launch shape of the Dslash for a geometry.  streamed:
+// the best shape with every link streamed (cache policy 0), else the best
+// shape and link-load policy together.  One timing run stores both.
 TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *ddesc, const int *dt2p,
-                      int ntile, long long nsite, int nprob, bool no_tune)
+                      int ntile, long long nsite, int nprob, bool no_tune, bool streamed)
 {
     TuneChoice def;
     def.W = prec == 0 ? 8 : 4;
@@ -462,8 +465,9 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return def;
     std::string key = dslash_tune_key(prop, prec, recon, ntile, nprob);
+    const std::string skey = dslash_tune_key(prop, prec, recon, ntile, nprob, true);
     TuneChoice c;
-    if (Tuner::get().lookup(key, c)) return c;
+    if (Tuner::get().lookup(streamed ? skey : key, c)) return c;
     DVec in, out;
     if (dvec_alloc(in, prec, nsite) != hipSuccess || dvec_alloc(out, prec, nsite) != hipSuccess) {
         dvec_free(in);
@@ -491,10 +495,13 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     flush_cache();
     // every candidate shape, timed on both output parities in turn (the
     // solvers alternate them), best of three interleaved trials of 10 launches
-    const int Ws[] = {1, 2, 4, 8, 16};
-    double tbest[5][2];
-    bool okc[5][2];
-    for (int wi = 0; wi < 5; wi++)
+    // waves per block, and the one- and two-wave blocks with the larger
+    // register budget (W_LOWOCC)
+    constexpr int NWS = 7;
+    const int Ws[NWS] = {1, 2, 4, 8, 16, 1 | W_LOWOCC, 2 | W_LOWOCC};
+    double tbest[NWS][2];
+    bool okc[NWS][2];
+    for (int wi = 0; wi < NWS; wi++)
         for (int remap = 0; remap < 2; remap++) {
             tbest[wi][remap] = 1e30;
             okc[wi][remap] = true;
@@ -515,7 +522,7 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
         return a;
     };
     for (int trial = 0; trial < 3; trial++)
-        for (int wi = 0; wi < 5; wi++)
+        for (int wi = 0; wi < NWS; wi++)
             for (int remap = 0; remap < 2; remap++) {
                 if (!okc[wi][remap]) continue;
                 const int W = Ws[wi];
@@ -536,13 +543,15 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
                 const double us = 1000.0 * ms / reps;
                 if (us < tbest[wi][remap]) tbest[wi][remap] = us;
             }
-    for (int wi = 0; wi < 5; wi++)
+    for (int wi = 0; wi < NWS; wi++)
         for (int remap = 0; remap < 2; remap++)
             if (okc[wi][remap] && tbest[wi][remap] < best.us) {
                 best.us = tbest[wi][remap];
                 best.W = Ws[wi];
                 best.remap = remap;
             }
+    if (best.us < 1e29) Tuner::get().store(skey, best);   // the streamed choice (cpol 0)
+    const TuneChoice best_streamed = best;
     // The link-load policy for the chosen shape: all links cached when both
     // parities' links fit the Infinity Cache (they stay there between the
     // alternating launches); when they do not, a part of the direction blocks
@@ -560,7 +569,7 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
             for (int c : {2, 4, 8, 12}) cands.push_back(c);
         TuneChoice bc = best;
         bc.us = 1e30;
-        for (int wi = 0; wi < 5; wi++)
+        for (int wi = 0; wi < NWS; wi++)
         for (int rm = 0; rm < 2; rm++) {
             const int W = Ws[wi];
             if (!okc[wi][rm] || (!partial && (W != best.W || rm != best.remap))) continue;
@@ -605,6 +614,7 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     (void)hipGetLastError();
     if (best.us < 1e29) Tuner::get().store(key, best);
     else best = def;
+    if (streamed) return best_streamed.us < 1e29 ? best_streamed : def;
     return best;
 }
 
@@ -693,6 +703,25 @@ hisq_status hisq_residual_history(hisq_lattice lat, int problem, double *out, in
     return HISQ_OK;
 }
 
+hisq_status hisq_dslash_shape(hisq_lattice lat, hisq_prec prec, hisq_recon recon, int flags, int *waves, int *remap,
+                              int *cache_blocks)
+{
+    if (!lat || !waves || !remap || !cache_blocks) return set_err(lat, HISQ_ERR_ARG, "null argument");
+    if (!lat->loaded) return set_err(lat, HISQ_ERR_STATE, "no links loaded");
+    if ((int)prec < 0 || (int)prec > 2 || (recon != 12 && recon != 18))
+        return set_err(lat, HISQ_ERR_ARG, "bad precision or reconstruction");
+    if (!lat->ls[(int)prec * 2 + (recon == 12)].valid)
+        return set_err(lat, HISQ_ERR_STATE, "link set not prepared (hisq_prepare_links)");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    const bool streamed = (flags & HISQ_STREAM_LINKS) != 0;
+    TuneChoice tc = pick_shape(lat, (int)prec, recon, lat->ddesc, nullptr, lat->ntile, lat->h, 1,
+                               (flags & HISQ_NO_TUNE) != 0, streamed);
+    *waves = tc.W;
+    *remap = tc.remap;
+    *cache_blocks = streamed ? 0 : tc.cpol;
+    return HISQ_OK;
+}
+
 hisq_status hisq_dslash(hisq_lattice lat, hisq_parity out_parity, hisq_prec prec, hisq_recon recon,
                         const void *in, void *out, int nrhs, int flags)
 {
@@ -707,13 +736,14 @@ hisq_status hisq_dslash(hisq_lattice lat, hisq_parity out_parity, hisq_prec prec
     HIPCHK(lat, hipSetDevice(lat->device));
     const int p = (int)prec;
     if (nrhs > 1) return hisq_dslash_mrhs_impl(lat, out_parity, p, recon, in, out, nrhs, flags);
+    const bool streamed = (flags & HISQ_STREAM_LINKS) != 0;
     TuneChoice tc = pick_shape(lat, p, recon, lat->ddesc, nullptr, lat->ntile, lat->h, 1,
-                               (flags & HISQ_NO_TUNE) != 0);
+                               (flags & HISQ_NO_TUNE) != 0, streamed);
     DslashLaunch a;
     memset(&a, 0, sizeof a);
     a.probs = lat->ddesc;
     a.remap = tc.remap;
-    a.cpol = tc.cpol;
+    a.cpol = streamed ? 0 : tc.cpol;
     a.out_par = (int)out_parity;
     a.lslot = slot;
     if (flags & HISQ_DEVICE_PTR) {

@@ -21,7 +21,7 @@
 namespace hisq {
 
 template <class LT, int R, class ST, class OT, int W, int EPI, int CP>
-__global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
+__device__ __forceinline__ void dslash_body(const DslashLaunch &a)
 {
     using A = typename AccOf<LT>::type;
     static_assert(16 % W == 0, "W must divide 16");
@@ -190,12 +190,34 @@ __global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
     }
 }
 
+template <class LT, int R, class ST, class OT, int W, int EPI, int CP>
+__global__ void __launch_bounds__(64 * W) k_dslash(DslashLaunch a)
+{
+    dslash_body<LT, R, ST, OT, W, EPI, CP>(a);
+}
+
+// The same kernel compiled for at most two waves per SIMD: the register
+// budget then lets a wave keep more of its link loads in flight before the
+// first arithmetic (with the default budget the compiler interleaves them),
+// which pays for the one- and two-wave blocks that walk many directions.
+template <class LT, int R, class ST, class OT, int W, int EPI, int CP>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(1, 2))) k_dslash_lo(DslashLaunch a)
+{
+    dslash_body<LT, R, ST, OT, W, EPI, CP>(a);
+}
+
 // ------------------------------------------------------------- launchers
 
 template <class LT, int R, class ST, class OT, int EPI, int CP>
 static hipError_t launch_wc(int W, const DslashLaunch &a, int nblocks, hipStream_t s)
 {
     switch (W) {
+    case 1 | W_LOWOCC:
+        hipLaunchKernelGGL((k_dslash_lo<LT, R, ST, OT, 1, EPI, CP>), dim3(nblocks), dim3(64), 0, s, a);
+        break;
+    case 2 | W_LOWOCC:
+        hipLaunchKernelGGL((k_dslash_lo<LT, R, ST, OT, 2, EPI, CP>), dim3(nblocks), dim3(128), 0, s, a);
+        break;
     case 1: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 1, EPI, CP>), dim3(nblocks), dim3(64), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 2, EPI, CP>), dim3(nblocks), dim3(128), 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_dslash<LT, R, ST, OT, 4, EPI, CP>), dim3(nblocks), dim3(256), 0, s, a); break;

@@ -6,6 +6,12 @@ namespace hisq {
 
 enum : int { EPI_PLAIN = 0, EPI_AX = 1, EPI_RES = 2 };
 
+// Launch shape code of the single-RHS Dslash: the waves per block (1, 2, 4, 8
+// or 16), or'ed with W_LOWOCC for the variant compiled for at most two waves
+// per SIMD (1 and 2 waves per block only).
+constexpr int W_LOWOCC = 0x100;
+inline int shape_waves(int W) { return W & 0xff; }
+
 struct DslashLaunch {
     const ProbDesc *probs;
     const int *tile2prob;   // nullptr: a single problem

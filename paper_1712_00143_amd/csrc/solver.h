@@ -11,7 +11,7 @@ namespace hisq {
 
 ProbDesc lattice_desc(hisq_lattice lat);
 TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *ddesc, const int *dt2p,
-                      int ntile, long long nsite, int nprob, bool no_tune);
+                      int ntile, long long nsite, int nprob, bool no_tune, bool streamed = false);
 // pick_shape's answer without timing: the cached tuned choice or the default.
 TuneChoice lookup_shape(hisq_lattice lat, int prec, int recon, int ntile, int nprob);
 // Tuned launch shape of the multi-right-hand-side Dslash (nr right-hand

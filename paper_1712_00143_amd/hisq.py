@@ -34,6 +34,7 @@ HISQ_RECON_18, HISQ_RECON_12 = 18, 12
 HISQ_EVEN, HISQ_ODD = 0, 1
 HISQ_DEVICE_PTR, HISQ_X_IS_GUESS, HISQ_USE_GRAPH, HISQ_NO_TUNE = 1, 2, 4, 8
 HISQ_STOP_STAGNATION = 16
+HISQ_STREAM_LINKS = 32
 
 EXPORTS = [
     "hisq_default_params", "hisq_status_string", "hisq_last_error", "hisq_create", "hisq_destroy",
@@ -43,6 +44,7 @@ EXPORTS = [
     "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
     "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss", "hisq_ptc_save", "hisq_ptc_load",
     "hisq_residual_history", "hisq_ptc_set_transport", "hisq_ptc_get_transport", "hisq_cg_noalloc",
+    "hisq_dslash_shape",
 ]
 
 
@@ -204,6 +206,14 @@ class Lattice:
                                ctypes.c_int(recon), ip, op, ctypes.c_int(nrhs), ctypes.c_int(flags))
         _check(st, self.handle, "hisq_dslash")
         return out
+
+    def dslash_shape(self, prec, recon, flags=0):
+        """(waves, remap, cache_blocks) of the launch hisq_dslash makes."""
+        w, r, c = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(lib().hisq_dslash_shape(self.handle, ctypes.c_int(prec), ctypes.c_int(recon), ctypes.c_int(flags),
+                                       ctypes.byref(w), ctypes.byref(r), ctypes.byref(c)),
+               self.handle, "hisq_dslash_shape")
+        return w.value, r.value, c.value
 
     def cg(self, mass, b, x=None, params=None, raise_on_fail=True):
         """Solve (4m^2 - D_eo D_oe) x = b; returns (x, info dict)."""

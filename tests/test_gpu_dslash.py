@@ -187,8 +187,9 @@ def test_dslash_long_extent_exact_division_path():
 def test_dslash_32x32x32x32_beyond_cache():
     """The 32^4 lattice the benchmark uses beyond the Infinity Cache (629 MB of
     FP32 links per half-Dslash), FP64 recon-18 (the headline format), FP32
-    recon-18 and FP16 recon-12, both parities, every output against the
-    oracle."""
+    recon-18 and FP16 recon-12, both parities, in the tuned launch and with
+    every link streamed (HISQ_STREAM_LINKS, the benchmark's headline launch),
+    every output against the oracle."""
     H = _hisq()
     dims = (32, 32, 32, 32)
     fat, lng = synth.make_links(dims, 0.2, seed=1900)
@@ -199,9 +200,10 @@ def test_dslash_32x32x32x32_beyond_cache():
         ref = oracle.dslash_half(dims, fat, lng, par, psi)
         for p, r in [(0, 18), (1, 18), (2, 12)]:
             lat.prepare_links(p, r)
-            out = np.zeros_like(psi)
-            lat.dslash(par, p, r, psi, out)
-            check(out, ref, TOL[p], (par, p, r))
+            for flags in (0, H.HISQ_STREAM_LINKS):   # tuned policy, and streamed links (the headline launch)
+                out = np.zeros_like(psi)
+                lat.dslash(par, p, r, psi, out, flags=flags)
+                check(out, ref, TOL[p], (par, p, r, flags))
     lat.close()
 
 
@@ -214,15 +216,19 @@ from paper_1712_00143_amd import synth, hisq as H
 
 arch = torch.cuda.get_device_properties(0).gcnArchName.replace(" ", "_")
 path = os.environ["HISQ_TUNE_CACHE"]
-# (dims, W for FP32/FP16 or None for the default shape, cached direction blocks)
+# (dims, shape code for every format or None for the default shape, cached
+# direction blocks); 257 and 258 are the one- and two-wave blocks compiled for
+# at most two waves per SIMD
 cases = [((6, 4, 6, 4), None, 4), ((4, 4, 4, 4), None, 12), ((8, 4, 4, 4), None, 16),
-         ((4, 4, 4, 6), None, 1), ((8, 8, 8, 8), 16, 6), ((8, 8, 4, 8), 2, 10)]
+         ((4, 4, 4, 6), None, 1), ((8, 8, 8, 8), 16, 6), ((8, 8, 4, 8), 2, 10),
+         ((8, 8, 8, 6), 257, 0), ((6, 4, 6, 6), 258, 16), ((8, 4, 4, 6), 257, 5)]
+# every case has its own tile count, so no two cases share a tuner key
 fmts = [(0, 18), (1, 18), (1, 12), (2, 12)]
 lines = []
 for dims, w, cpol in cases:
     t = (synth.volume(dims) // 2 + 63) // 64
     for p, r in fmts:
-        W = (8 if p == 0 else 4) if w is None or p == 0 else w
+        W = (8 if p == 0 else 4) if w is None else w
         lines.append(f"dslash3:{arch}:p{p}:r{r}:t{t}:n1 {W} 1 {cpol} 1.0")
 with open(path, "w") as f:
     f.write("\n".join(lines) + "\n")
@@ -244,9 +250,9 @@ for k, (dims, w, cpol) in enumerate(cases):
             lat.dslash(par, p, r, psi, b, flags=H.HISQ_NO_TUNE)  # default shape, streamed links
             rel = float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
             same = bool(np.array_equal(a, b))
-            res.append([list(dims), cpol, p, r, par, rel, same, w is None or p == 0])
+            res.append([list(dims), cpol, p, r, par, rel, same, w is None])
             assert rel <= tol[p], res[-1]
-            if w is None or p == 0:
+            if w is None:
                 assert same, res[-1]
     lat.close()
 with open(path) as f:
@@ -275,4 +281,4 @@ def test_forced_link_load_policies_match_streamed_and_oracle(tmp_path):
     r = subprocess.run([sys.executable, "-c", _FORCED_POLICY_CHILD], cwd=root, env=env,
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
-    assert '"cases": 48' in r.stdout, r.stdout
+    assert '"cases": 72' in r.stdout, r.stdout
