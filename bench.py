@@ -257,6 +257,9 @@ def run_headline(args):
         setup[f"32^4_prepare_{FMT_NAME[(p, r)]}_s"] = round(dt, 4)
     hH = synth.volume(HEAD_DIMS) // 2
 
+    if args.head_only:
+        run_head_only(args, torch, H, latH, hH, stream, setup)
+        return
     # ---- the 16^3x32 workload (eps 0.2, m 0.02): Dslash formats and solvers
     w = synth.C1
     fat, lng = w.links()
@@ -457,6 +460,34 @@ def run_headline(args):
     if not args.dslash_only and not args.no_c3:
         out["c3_batched_64_solves"] = c3_summary(args, oracle_sample=8)
     print(json.dumps(out), flush=True)
+
+
+def run_head_only(args, torch, H, latH, hH, stream, setup):
+    """Only the 32^4 headline launches (FP64 and FP32 recon-18, streamed
+    links), for profiling them alone; one JSON line."""
+    res = {}
+    for _ in range(args.warmup):
+        for p, r in ((0, 18), (1, 18)):
+            timed_dslash(torch, latH, p, r, hH, stream, args.head_reps, H.HISQ_STREAM_LINKS)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for p, r in ((0, 18), (1, 18)):
+            tg, te = timed_dslash(torch, latH, p, r, hH, stream, args.head_reps, H.HISQ_STREAM_LINKS)
+            res.setdefault((p, r), []).append(tg if tg is not None else te)
+        log(f"step {k + 1}/{args.steps}")
+    t_total = time.perf_counter() - t0
+    lines = {}
+    for (p, r), ts in res.items():
+        t = float(np.mean(ts))
+        gbs = hH * site_bytes(p, r) / t / 1e9
+        lines[FMT_NAME[(p, r)] + "_streamed"] = {
+            "us": round(t * 1e6, 3), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
+            "kernel": shape_name(p, r, latH.dslash_shape(p, r, H.HISQ_STREAM_LINKS)),
+            "launches_per_step": 2 + 6 * args.head_reps}
+    print(json.dumps({"workload": "32^4 half-Dslash, recon-18, streamed links (headline launches only)",
+                      "steps": args.steps, "ms_per_step": round(1000 * t_total / args.steps, 2),
+                      "dslash_32^4": lines, "setup": setup}), flush=True)
+    latH.close()
 
 
 # ------------------------------------------------------- other workloads
@@ -748,6 +779,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--reps", type=int, default=50, help="16^3x32 Dslash launches per parity per step")
     ap.add_argument("--head-reps", type=int, default=20, help="32^4 Dslash launches per parity per step")
+    ap.add_argument("--head-only", action="store_true", help="only the 32^4 headline launches (for profiling)")
     ap.add_argument("--no-c2", action="store_true", help="headline: skip the multi-shift summary")
     ap.add_argument("--no-c3", action="store_true", help="headline: skip the batched-solve summary")
     ap.add_argument("--oracle-sample", type=int, default=8, help="c2/c3: solutions checked by the oracle")
