@@ -171,12 +171,21 @@ def solve_timed(torch, stream, fn):
     return out, time.perf_counter() - t0
 
 
+def random_start(chans, seed, scale=0.05):
+    """Small random complex starting weights of a network (one array per layer)."""
+    rng = np.random.default_rng(seed)
+    return [scale * (rng.standard_normal((b, a, 9)) + 1j * rng.standard_normal((b, a, 9)))
+            for a, b in zip(chans[:-1], chans[1:])]
+
+
 def train_preconditioner(H, synth, dims, eps, mass, seed0, nfield, nsrc, steps, chans=(1, 4, 4, 1),
-                         every=10, maxpairs=60, batch=8, lr=3e-3, init="poly"):
+                         every=10, maxpairs=60, batch=8, lr=3e-3, init="poly", transport=(1, 18), act16=False):
     """Harvest (residual, error) pairs with the solver on nfield seeded fields
     and train the network on the GPU, starting from the polynomial weights
-    (init "poly") or small random ones ("random").  Returns (net, lattices,
-    seconds, losses)."""
+    (init "poly") or small random ones ("random", random_start(chans, seed0)).
+    transport: the network's link format, used by training and inference
+    alike; act16: FP16 activation storage at inference.  Returns (net,
+    lattices, seconds, losses)."""
     t0 = time.perf_counter()
     lats, net = [], None
     for j in range(nfield):
@@ -187,13 +196,14 @@ def train_preconditioner(H, synth, dims, eps, mass, seed0, nfield, nsrc, steps, 
         lats.append(L)
         if net is None:
             net = H.PTC(L, chans)
+            net.set_transport(*transport)
+            if act16:
+                net.set_activations(2)
             if init == "poly":
                 lam = net.init_polynomial(a=4.0, c=1.2)
                 log(f"polynomial start: lambda_max(-D_f^2) ~ {lam:.4f}")
             else:
-                rng = np.random.default_rng(seed0)
-                net.set_weights([0.05 * (rng.standard_normal((b, a, 9)) + 1j * rng.standard_normal((b, a, 9)))
-                                 for a, b in zip(chans[:-1], chans[1:])])
+                net.set_weights(random_start(chans, seed0))
         for s in range(nsrc):
             net.harvest(L, mass, synth.gaussian_even(dims, seed0 + j + 500 + 100 * s), every=every,
                         maxpairs=maxpairs)
@@ -291,12 +301,15 @@ def run_headline(args):
     if not args.no_learned and not args.dslash_only:
         # trained outside the timed region, on pairs from two other sources
         net = H.PTC(lat, (1, 2, 1))
+        net.set_transport(2, 12)       # FP16 recon-12 transports, training and inference alike
+        net.set_activations(2)         # FP16 activation storage at inference
         t0 = time.perf_counter()
         net.init_polynomial(a=4.0, c=1.2)
         srcs = w.sources()
         npair = sum(net.harvest(lat, w.mass, srcs[k], every=20, maxpairs=60) for k in (1, 2))
         losses = net.train(300, batch=8, lr=3e-3, seed=1)
-        train_info = {"network": "1-2-1 PTC, polynomial start, energy-norm loss, FP32 recon-18 transports",
+        train_info = {"network": "1-2-1 PTC, polynomial start, energy-norm loss, FP16 recon-12 transports, FP16 "
+                                 "inference activations; pairs from two other sources of the same field",
                       "pairs": npair, "steps": 300, "seconds": round(time.perf_counter() - t0, 3),
                       "loss_first10": round(float(losses[:10].mean()), 4),
                       "loss_last50": round(float(losses[-50:].mean()), 4)}
@@ -679,84 +692,119 @@ def run_c3(args):
 
 
 def run_c4(args):
+    """Learned preconditioner on 16^4 (eps 0.25, m 0.005): networks trained on
+    the GPU from pairs the solver harvests on `nfield` training fields, tested
+    against plain and mixed CG on `nheld` held-out fields x 2 sources.  Every
+    network runs its transports on FP16 recon-12 fat links (training and
+    inference) and stores its inference activations in FP16; each trained
+    network is also run from its own untrained starting weights.  Every
+    solution's FP64 true residual is recomputed by the oracle."""
     import torch
     from paper_1712_00143_amd import hisq as H
     from paper_1712_00143_amd import synth
+    import oracle
     w = synth.C4
-    # the 1 -> 4 -> 4 -> 1 network, trained from small random weights
+    fmt = dict(transport=(2, 12), act16=True)
+    chans = (1, 4, 4, 1)
+    # the specified 1 -> 4 -> 4 -> 1 network, trained from small random weights
     net, tl, t_train, losses = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, args.nfield,
-                                                    args.nsrc, args.train_steps, init="random")
+                                                    args.nsrc, args.train_steps, chans=chans, init="random", **fmt)
     # the two-layer 1 -> 2 -> 1 network (the smallest that holds the polynomial
     # preconditioner), on a quarter of the fields, from random weights and
     # from the polynomial start
     nq, sq = max(1, args.nfield // 4), max(1, args.nsrc // 2)
     net2, tl2, t_train2, losses2 = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, nq, sq,
-                                                        args.train_steps, chans=(1, 2, 1), init="random")
+                                                        args.train_steps, chans=(1, 2, 1), init="random", **fmt)
     net3, tl3, t_train3, losses3 = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, nq, sq,
-                                                        args.train_steps, chans=(1, 2, 1), init="poly")
-    res = {"plain_f64": [], "mixed_f32": [], "mixed_f16_r12": [], "learned_fcg": [], "learned_fcg_121": [],
-           "learned_fcg_121_random_start": [], "untrained_fcg": [], "poly_fcg": [], "poly_fcg_121": []}
-    untrained = None
+                                                        args.train_steps, chans=(1, 2, 1), init="poly", **fmt)
+    names = ["plain_f64", "mixed_f32", "mixed_f16_r12", "learned_fcg", "learned_fcg_untrained_start",
+             "learned_fcg_121_random", "learned_fcg_121_random_untrained_start", "learned_fcg_121_poly",
+             "poly_fcg_121_untrained", "identity_fcg"]
+    res = {k: [] for k in names}
     for j in range(args.nheld):
         fat, lng = synth.make_links(w.dims, w.eps, seed=4900 + j)
         L = H.Lattice(w.dims)
         L.load_links(fat, lng)
         L.prepare_links(1, 18)
         L.prepare_links(2, 12)
-        if untrained is None:
-            untrained = H.PTC(L, (1, 4, 4, 1))
+        nets = {}
+        for name, ch, wts in (("learned_fcg_untrained_start", chans, random_start(chans, 4000)),
+                              ("learned_fcg_121_random_untrained_start", (1, 2, 1), random_start((1, 2, 1), 4000)),
+                              ("identity_fcg", chans, None)):
+            n = H.PTC(L, ch)
+            n.set_transport(2, 12)
+            n.set_activations(2)
+            if wts is not None:
+                n.set_weights(wts)
+            nets[name] = n
         # the polynomial start alone, on this field's own spectrum estimate
         # (set up outside the timed solves)
-        poly = H.PTC(L, (1, 4, 4, 1))
+        poly = H.PTC(L, (1, 2, 1))
+        poly.set_transport(2, 12)
+        poly.set_activations(2)
         poly.init_polynomial(a=4.0, c=1.2)
-        poly2 = H.PTC(L, (1, 2, 1))
-        poly2.init_polynomial(a=4.0, c=1.2)
+        nets["poly_fcg_121_untrained"] = poly
+        nets["learned_fcg"] = net
+        nets["learned_fcg_121_random"] = net2
+        nets["learned_fcg_121_poly"] = net3
         for s in range(2):
             b = synth.gaussian_even(w.dims, 5400 + 10 * j + s)
-            for name, fn in (
-                    ("plain_f64", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=0, flags=H.HISQ_USE_GRAPH))),
-                    ("mixed_f32", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
-                    ("mixed_f16_r12", lambda: L.cg(w.mass, b, params=H.hisq_default_params(sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH))),
-                    ("learned_fcg", lambda: net.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
-                    ("learned_fcg_121_random_start", lambda: net2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
-                    ("learned_fcg_121", lambda: net3.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
-                    ("untrained_fcg", lambda: untrained.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
-                    ("poly_fcg", lambda: poly.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))),
-                    ("poly_fcg_121", lambda: poly2.cg_learned(L, w.mass, b, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH)))):
-                (_, info), dt = solve_timed(torch, None, fn)
-                res[name].append((info["iters"], dt, info["true_residual"], info.get("fell_back", 0)))
-            log(f"held-out field {j}, source {s}: " + ", ".join(f"{k} {v[-1][0]} it {v[-1][1]:.3f}s" for k, v in res.items()))
-        poly.close()
-        poly2.close()
+            bd = torch.from_numpy(b.view(np.float64)).cuda()
+            for name in names:
+                if name == "plain_f64":
+                    fn = lambda xd: L.cg(w.mass, bd, x=xd, params=H.hisq_default_params(sloppy=0, flags=H.HISQ_USE_GRAPH))
+                elif name == "mixed_f32":
+                    fn = lambda xd: L.cg(w.mass, bd, x=xd, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))
+                elif name == "mixed_f16_r12":
+                    fn = lambda xd: L.cg(w.mass, bd, x=xd,
+                                         params=H.hisq_default_params(sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH))
+                else:
+                    nn = nets[name]
+                    fn = lambda xd: nn.cg_learned(L, w.mass, bd, x=xd,
+                                                  params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))
+                xd = torch.zeros_like(bd)
+                fn(xd)                                 # warm-up: tuning, graph capture
+                xd = torch.zeros_like(bd)
+                (_, info), dt = solve_timed(torch, None, lambda: fn(xd))
+                xh = xd.cpu().numpy().view(np.complex128).reshape(-1, 3)
+                tr = oracle.true_residual(w.dims, fat, lng, w.mass, b, xh)
+                res[name].append((info["iters"], dt, tr, info.get("fell_back", 0)))
+            log(f"held-out field {j}, source {s}: " + ", ".join(f"{k} {v[-1][0]} it {v[-1][1]:.4f}s" for k, v in res.items()))
+        for name in ("learned_fcg_untrained_start", "learned_fcg_121_random_untrained_start", "identity_fcg",
+                     "poly_fcg_121_untrained"):
+            nets[name].close()
         L.close()
     summ = {k: {"iters_mean": round(float(np.mean([r[0] for r in v])), 1),
                 "time_s_mean": round(float(np.mean([r[1] for r in v])), 5),
-                "worst_true_residual": float(f"{max(r[2] for r in v):.3e}"),
+                "worst_oracle_true_residual": float(f"{max(r[2] for r in v):.3e}"),
                 "fell_back": int(sum(r[3] for r in v))} for k, v in res.items()}
+    plain = summ["plain_f64"]["time_s_mean"]
+
+    def loss_info(ls, t):
+        return {"seconds": t, "loss_first10": round(float(ls[:10].mean()), 4),
+                "loss_last50": round(float(ls[-50:].mean()), 4)}
     print(json.dumps({
-        "workload": f"learned PTC preconditioner 16^4, eps 0.25, m 0.005: trained on {args.nfield} fields x {args.nsrc} sources, tested on {args.nheld} held-out fields x 2 sources",
-        "training": {"seconds": t_train, "steps": args.train_steps,
-                     "start": "small random weights (learned_fcg, learned_fcg_121_random_start); polynomial "
-                              "K = 4 (1 + 1.2 D_f^2 / lambda) for learned_fcg_121 and the untrained poly_* nets",
-                     "what": "harvest_s: synthetic fields generated on the host, loaded, and plain CG to 1e-12 per source; "
-                             "train_s: the Adam steps on the GPU",
-                     "loss": "energy norm of the error (HISQ_LOSS_ENERGY)",
-                     "loss_first10": round(float(losses[:10].mean()), 4),
-                     "loss_last50": round(float(losses[-50:].mean()), 4),
-                     "net_121_random_start": {"seconds": t_train2, "fields": max(1, args.nfield // 4),
-                                 "sources": max(1, args.nsrc // 2),
-                                 "loss_first10": round(float(losses2[:10].mean()), 4),
-                                 "loss_last50": round(float(losses2[-50:].mean()), 4)},
-                     "net_121": {"seconds": t_train3, "fields": max(1, args.nfield // 4),
-                                            "sources": max(1, args.nsrc // 2),
-                                          "loss_first10": round(float(losses3[:10].mean()), 4),
-                                          "loss_last50": round(float(losses3[-50:].mean()), 4)}},
+        "workload": f"learned PTC preconditioner 16^4, eps 0.25, m 0.005: trained on {args.nfield} fields x "
+                    f"{args.nsrc} sources, tested on {args.nheld} held-out fields x 2 sources; FP16 recon-12 "
+                    f"transports (training and inference), FP16 inference activations, FP64 true residual 1e-10",
+        "training": {"steps": args.train_steps, "loss": "energy norm of the error (HISQ_LOSS_ENERGY)",
+                     "learned_fcg (1-4-4-1, random start)": loss_info(losses, t_train),
+                     "learned_fcg_121_random (1-2-1, random start)": loss_info(losses2, t_train2),
+                     "learned_fcg_121_poly (1-2-1, polynomial start)": loss_info(losses3, t_train3),
+                     "what": "harvest_s: synthetic fields generated on the host, loaded, and plain CG to 1e-12 per "
+                             "source; train_s: the Adam steps on the GPU"},
         "solves": summ,
-        "learned_iteration_gain_vs_plain": round(summ["plain_f64"]["iters_mean"] / summ["learned_fcg"]["iters_mean"], 3),
-        "learned_time_gain_vs_plain": round(summ["plain_f64"]["time_s_mean"] / summ["learned_fcg"]["time_s_mean"], 3),
-        "learned_121_time_gain_vs_plain": round(summ["plain_f64"]["time_s_mean"] / summ["learned_fcg_121"]["time_s_mean"], 3),
-        "learned_121_time_gain_vs_mixed_f32": round(summ["mixed_f32"]["time_s_mean"] / summ["learned_fcg_121"]["time_s_mean"], 3)}),
-        flush=True)
+        "time_gain_vs_plain_f64": {k: round(plain / v["time_s_mean"], 3) for k, v in summ.items()},
+        "iteration_gain_of_training": {
+            "1-4-4-1": round(summ["learned_fcg_untrained_start"]["iters_mean"] / summ["learned_fcg"]["iters_mean"], 3),
+            "1-2-1 random start": round(summ["learned_fcg_121_random_untrained_start"]["iters_mean"]
+                                        / summ["learned_fcg_121_random"]["iters_mean"], 3),
+            "1-2-1 polynomial start": round(summ["poly_fcg_121_untrained"]["iters_mean"]
+                                            / summ["learned_fcg_121_poly"]["iters_mean"], 3)}}), flush=True)
+    for n in (net, net2, net3):
+        n.close()
+    for L in tl + tl2 + tl3:
+        L.close()
 
 
 def run_copy(args):

@@ -319,6 +319,17 @@ hisq_status hisq_ptc_set_loss(hisq_ptc net, int loss);
  * get_transport returns the current format (prec, recon). */
 hisq_status hisq_ptc_set_transport(hisq_ptc net, hisq_prec prec, hisq_recon recon);
 hisq_status hisq_ptc_get_transport(hisq_ptc net, int *prec, int *recon);
+/* Storage precision of the activations between the layers of z = M(r) in
+ * hisq_ptc_apply and hisq_cg_learned: HISQ_F32 (the default; channel-major
+ * FP32 activations) or HISQ_F16 (site-major, channel-interleaved IEEE
+ * binary16 values over one FP32 scale per site, the site's largest |entry|;
+ * about half the activation bytes per layer).  Arithmetic stays FP32 and the
+ * input r and output z stay FP32; training keeps FP32 activations (it needs
+ * them for the gradients).  FP16 storage rounds each stored activation entry
+ * to 2^-11 of its site's scale, so M is applied to about 1e-3 relative; the
+ * flexible CG tolerates a preconditioner that inexact.  Errors: HISQ_ERR_ARG
+ * (null net, another precision). */
+hisq_status hisq_ptc_set_activations(hisq_ptc net, hisq_prec prec);
 /* Train on the stored pairs (all from lattices whose links are those of the
  * handle each pair was harvested on): `steps` Adam steps (lr, beta1 0.9,
  * beta2 0.999, eps 1e-8) on minibatches of `batch` pairs of one lattice,

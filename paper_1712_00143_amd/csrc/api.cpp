@@ -112,6 +112,8 @@ Tuner::Tuner()
 {
     const char *t = getenv("HISQ_TUNE");
     disabled_ = t && std::string(t) == "0";
+    const char *v = getenv("HISQ_TUNE_VERBOSE");
+    verbose_ = v && std::string(v) == "1";
     const char *p = getenv("HISQ_TUNE_CACHE");
     if (p && *p) {
         path_ = p;
@@ -120,6 +122,13 @@ Tuner::Tuner()
         TuneChoice c;
         while (f >> key >> c.W >> c.remap >> c.cpol >> c.us) cache_[key] = c;
     }
+}
+
+void Tuner::note(const std::string &key, int W, int remap, int cpol, double us)
+{
+    if (!verbose_) return;
+    std::lock_guard<std::mutex> g(mu_);
+    fprintf(stderr, "[hisq tune] %s W %d remap %d cpol %d: %.3f us\n", key.c_str(), W, remap, cpol, us);
 }
 
 bool Tuner::lookup(const std::string &key, TuneChoice &c)
@@ -545,6 +554,9 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
             }
     for (int wi = 0; wi < NWS; wi++)
         for (int remap = 0; remap < 2; remap++)
+            if (okc[wi][remap]) Tuner::get().note(skey, Ws[wi], remap, 0, tbest[wi][remap]);
+    for (int wi = 0; wi < NWS; wi++)
+        for (int remap = 0; remap < 2; remap++)
             if (okc[wi][remap] && tbest[wi][remap] < best.us) {
                 best.us = tbest[wi][remap];
                 best.W = Ws[wi];
@@ -596,6 +608,7 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
                 // clearly faster: the two time within a per cent or two here,
                 // while over a long run of alternating applications the cached
                 // one holds its rate and the streamed one does not
+                Tuner::get().note(key, W, rm, cands[ci], t);
                 const double bias = (!partial && cands[ci] == 16) ? 1.03 : 1.0;
                 if (t < bias * bc.us) {
                     bc.us = t;

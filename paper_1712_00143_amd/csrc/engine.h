@@ -77,6 +77,8 @@ class Tuner {
     void store(const std::string &key, const TuneChoice &c);
     // HISQ_TUNE=0 in the environment: every launch takes its default shape
     bool disabled() const { return disabled_; }
+    // HISQ_TUNE_VERBOSE=1: every timed candidate is printed to stderr
+    void note(const std::string &key, int W, int remap, int cpol, double us);
 
   private:
     Tuner();
@@ -84,6 +86,7 @@ class Tuner {
     std::map<std::string, TuneChoice> cache_;
     std::string path_;
     bool disabled_ = false;
+    bool verbose_ = false;
 };
 
 }  // namespace hisq

@@ -27,20 +27,23 @@ template <class A> struct Cx {
     A re, im;
 };
 
-template <class A> __device__ __forceinline__ Cx<A> cmul(Cx<A> a, Cx<A> b)
-{
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-
-template <class A> __device__ __forceinline__ Cx<A> cconjmul(Cx<A> a, Cx<A> b)  // conj(a) b
-{
-    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
-}
-
 template <class A> __device__ __forceinline__ A fmaa(A a, A b, A c)
 {
     if constexpr (sizeof(A) == 8) return __builtin_fma(a, b, c);
     else return __builtin_fmaf(a, b, c);
+}
+
+// Complex products with every fused multiply-add written out, so that the
+// compiler's contraction of a*b - c*d cannot differ between kernel variants
+// that share this arithmetic (they must give identical bits).
+template <class A> __device__ __forceinline__ Cx<A> cmul(Cx<A> a, Cx<A> b)
+{
+    return {fmaa(a.re, b.re, -(a.im * b.im)), fmaa(a.re, b.im, a.im * b.re)};
+}
+
+template <class A> __device__ __forceinline__ Cx<A> cconjmul(Cx<A> a, Cx<A> b)  // conj(a) b
+{
+    return {fmaa(a.re, b.re, a.im * b.im), fmaa(a.re, b.im, -(a.im * b.re))};
 }
 
 // acc[r] += sum_c u[r][c] v[c]: 36 fused multiply-adds, no temporaries.

@@ -72,6 +72,13 @@ struct hisq_ptc_s {
     // inference workspace
     float *inf = nullptr;
     long long infV = 0;
+    // activation storage of inference (hisq_ptc_set_activations): FP32
+    // [C][2][h][3] through k_ptc_layer, or FP16 [2][h][C][3] with per-site
+    // scales through k_ptc_infer
+    int aprec = HISQ_F32;
+    __half2 *inf16 = nullptr;
+    float *infsc = nullptr;
+    long long inf16V = 0;
     FcgGraphCache fcg_graph;
 };
 
@@ -178,6 +185,8 @@ int pick_layer_waves(hisq_lattice lat, int lslot, int prec, int recon, bool w16,
             (void)hipEventElapsedTime(&ms, e0, e1);
             tbest[j] = std::min(tbest[j], 1000.0 * ms / reps);
         }
+    for (int j = 0; j < 4; j++)
+        if (okw[j]) Tuner::get().note(k, Ws[j], 0, 0, tbest[j]);
     for (int j = 0; j < 4; j++)
         if (okw[j] && tbest[j] < best.us) {
             best.us = tbest[j];
@@ -289,11 +298,171 @@ hipError_t apply_net(hisq_ptc_s *n, hisq_lattice lat, int lslot, int prec, int r
 
 }  // namespace
 
+// Waves per block of the FP16-activation inference layer (1, 3 or 9, the last
+// two also with matrix-core channel mixing), timed
+// once per geometry, channel pair, input / output kind and link format on
+// scratch activations, then cached.  Must not run under stream capture.
+int pick_infer_waves(hisq_lattice lat, int lslot, int prec, int recon, const void *w16, int cin, int cout, int ik,
+                     int ok, int npar, hipStream_t stream)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, lat->device) != hipSuccess) return 3;
+    char key[256];
+    snprintf(key, sizeof key, "ptcinf:%s:t%d:p%d:r%d:%dx%d:k%d%d:np%d", prop.gcnArchName, lat->ntile, prec, recon, cin,
+             cout, ik, ok, npar);
+    std::string k(key);
+    for (auto &ch : k)
+        if (ch == ' ') ch = '_';
+    TuneChoice c;
+    if (Tuner::get().lookup(k, c)) return c.W;
+    if (Tuner::get().disabled()) return 3;
+    const long long h = lat->h;
+    const size_t act = (size_t)2 * h * 8 * 12, sc = (size_t)2 * h * 4;   // up to 8 channels
+    char *buf = nullptr;
+    if (hipMalloc(&buf, 2 * (act + sc) + (size_t)h * 48) != hipSuccess) return 3;
+    (void)hipMemsetAsync(buf, 0, 2 * (act + sc) + (size_t)h * 48, stream);
+    PtcInferLaunch a;
+    memset(&a, 0, sizeof a);
+    a.probs = lat->ddesc;
+    a.lslot = lslot;
+    a.par_lo = 0;
+    a.w = w16;
+    a.in16 = reinterpret_cast<const __half2 *>(buf);
+    a.in_scale = reinterpret_cast<const float *>(buf + act);
+    a.out16 = reinterpret_cast<__half2 *>(buf + act + sc);
+    a.out_scale = reinterpret_cast<float *>(buf + 2 * act + sc);
+    a.in32 = reinterpret_cast<const float *>(buf + 2 * (act + sc));
+    a.out32 = reinterpret_cast<float *>(buf + 2 * (act + sc));   // read and written: timing only
+    a.addin = a.in32;
+    const int nblk = lat->ntile * npar;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    // vector-ALU channel mixing with 1, 3 or 9 waves, matrix-core mixing with
+    // 3 or 9 (layers with at least as many outputs as inputs)
+    constexpr int NWI = 5;
+    const int Ws[NWI] = {1, 3, 9, 3 | PTC_MFMA, 9 | PTC_MFMA};
+    double tbest[NWI] = {1e30, 1e30, 1e30, 1e30, 1e30};
+    bool okw[NWI] = {true, true, true, cout >= cin, cout >= cin};
+    for (int j = 0; j < NWI; j++)
+        for (int r = 0; r < 2 && okw[j]; r++)
+            okw[j] = launch_ptc_infer(prec, recon, cin, cout, ik, ok, Ws[j], a, nblk, stream) == hipSuccess;
+    for (int trial = 0; trial < 3; trial++)
+        for (int j = 0; j < NWI; j++) {
+            if (!okw[j]) continue;
+            const int reps = 10;
+            (void)hipEventRecord(e0, stream);
+            for (int r = 0; r < reps; r++) (void)launch_ptc_infer(prec, recon, cin, cout, ik, ok, Ws[j], a, nblk, stream);
+            (void)hipEventRecord(e1, stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tbest[j] = std::min(tbest[j], 1000.0 * ms / reps);
+        }
+    TuneChoice best;
+    best.W = 3;
+    best.us = 1e30;
+    for (int j = 0; j < NWI; j++)
+        if (okw[j]) Tuner::get().note(k, Ws[j], 0, 0, tbest[j]);
+    for (int j = 0; j < NWI; j++)
+        if (okw[j] && tbest[j] < best.us) {
+            best.us = tbest[j];
+            best.W = Ws[j];
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    (void)hipGetLastError();
+    if (best.us < 1e29) Tuner::get().store(k, best);
+    return best.W;
+}
+
+// z = M(r) with FP16 activation storage: the forward layers from the even
+// FP32 r, the adjoint layers back, the last one writing z = r + E^+ K^+ K E r
+// in FP32 with the flexible CG's (q, z) tile sums (fz).
+hipError_t apply_net_infer16(hisq_ptc_s *n, hisq_lattice lat, int lslot, int prec, int recon, const float *r, float *z,
+                             hipStream_t s, const PtcFuse *fz)
+{
+    const long long h = lat->h;
+    const int C = cmax(n);
+    const long long act = 2 * h * C * 3;   // half2 per activation
+    if (n->inf16V < act) {
+        if (n->inf16) (void)hipFree(n->inf16);
+        if (n->infsc) (void)hipFree(n->infsc);
+        n->inf16 = nullptr;
+        n->infsc = nullptr;
+        n->inf16V = 0;
+        hipError_t e = hipMalloc(&n->inf16, sizeof(__half2) * 2 * act);
+        if (e == hipSuccess) e = hipMalloc(&n->infsc, sizeof(float) * 2 * 2 * h);
+        if (e != hipSuccess) return e;
+        n->inf16V = act;
+    }
+    __half2 *bufs[2] = {n->inf16, n->inf16 + act};
+    float *scs[2] = {n->infsc, n->infsc + 2 * h};
+    auto base = [&]() {
+        PtcInferLaunch a;
+        memset(&a, 0, sizeof a);
+        a.probs = lat->ddesc;
+        a.lslot = lslot;
+        if (fz) {
+            a.gate = fz->gate;
+            a.gate_want = fz->want;
+        }
+        return a;
+    };
+    int k = 0;
+    const int L = n->nlayer;
+    // forward layers: l = 0 reads the even r, the rest the previous activation
+    for (int l = 0; l < L; l++) {
+        const int cin = n->chans[l], cout = n->chans[l + 1], ik = l == 0 ? 0 : 1;
+        const void *w = n->w16 + 2 * n->woff[l];
+        const int W = pick_infer_waves(lat, lslot, prec, recon, w, cin, cout, ik, 0, 2, s);
+        PtcInferLaunch a = base();
+        a.w = w;
+        a.in32 = r;
+        a.in16 = bufs[k ^ 1];
+        a.in_scale = scs[k ^ 1];
+        a.out16 = bufs[k];
+        a.out_scale = scs[k];
+        hipError_t e = launch_ptc_infer(prec, recon, cin, cout, ik, 0, W, a, 2 * lat->ntile, s);
+        if (e != hipSuccess) return e;
+        k ^= 1;
+    }
+    // adjoint layers in reverse order; the last writes z on the even sites
+    for (int l = L - 1; l >= 0; l--) {
+        const int cin = n->chans[l + 1], cout = n->chans[l];
+        const bool last = l == 0;
+        const void *w = n->wa16 + 2 * n->woff[l];
+        const int W = pick_infer_waves(lat, lslot, prec, recon, w, cin, cout, 1, last ? 1 : 0, last ? 1 : 2, s);
+        PtcInferLaunch a = base();
+        a.w = w;
+        a.in16 = bufs[k ^ 1];
+        a.in_scale = scs[k ^ 1];
+        if (last) {
+            a.out32 = z;
+            a.addin = r;
+            if (fz && fz->red) {
+                a.dotq = fz->q;
+                a.dotred = fz->red;
+                a.dot_nt = fz->nt;
+            }
+        } else {
+            a.out16 = bufs[k];
+            a.out_scale = scs[k];
+        }
+        hipError_t e = launch_ptc_infer(prec, recon, cin, cout, 1, last ? 1 : 0, W, a, (last ? 1 : 2) * lat->ntile, s);
+        if (e != hipSuccess) return e;
+        k ^= 1;
+    }
+    return hipSuccess;
+}
+
 // z = M(r) for the flexible CG: FP16 weights, transports on link set `lslot`.
 // fz (may be null): the flexible CG's status gate and (q, z) tile sums.
 hipError_t ptc_apply_internal(hisq_ptc n, hisq_lattice lat, int lslot, int prec, int recon, const float *r, float *z,
                               const PtcFuse *fz)
 {
+    if (n->aprec == HISQ_F16) return apply_net_infer16(n, lat, lslot, prec, recon, r, z, lat->s, fz);
     const long long need = (long long)cmax(n) * 2 * lat->h * 6 * 2;
     if (n->infV < need) {
         if (n->inf) (void)hipFree(n->inf);
@@ -315,8 +484,9 @@ std::string ptc_graph_key(hisq_ptc n)
 {
     std::string k;
     char buf[160];
-    snprintf(buf, sizeof buf, "%p:%p:%p:%p:%lld:", (const void *)n, (const void *)n->w16, (const void *)n->wa16,
-             (const void *)n->inf, n->infV);
+    snprintf(buf, sizeof buf, "%p:%p:%p:%p:%lld:%d:%p:%p:%lld:", (const void *)n, (const void *)n->w16,
+             (const void *)n->wa16, (const void *)n->inf, n->infV, n->aprec, (const void *)n->inf16,
+             (const void *)n->infsc, n->inf16V);
     k = buf;
     for (int c : n->chans) k += std::to_string(c) + ",";
     return k;
@@ -376,7 +546,7 @@ hisq_status hisq_ptc_destroy(hisq_ptc n)
     n->fcg_graph.release();
     for (void *p : {(void *)n->w32, (void *)n->m, (void *)n->v, (void *)n->wa32, (void *)n->w16, (void *)n->wa16,
                     (void *)n->gw, (void *)n->gtmp, (void *)n->act, (void *)n->part, (void *)n->dloss,
-                    (void *)n->dee, (void *)n->inf})
+                    (void *)n->dee, (void *)n->inf, (void *)n->inf16, (void *)n->infsc})
         if (p) (void)hipFree(p);
     for (auto &pb : n->pairs)
         if (pb.mem) (void)hipFree(pb.mem);
@@ -797,6 +967,16 @@ hisq_status hisq_ptc_set_transport(hisq_ptc n, hisq_prec prec, hisq_recon recon)
     if (n->tprec != (int)prec || n->trecon != (int)recon) n->fcg_graph.release();
     n->tprec = prec;
     n->trecon = recon;
+    return HISQ_OK;
+}
+
+hisq_status hisq_ptc_set_activations(hisq_ptc n, hisq_prec prec)
+{
+    if (!n) return HISQ_ERR_ARG;
+    if (prec != HISQ_F32 && prec != HISQ_F16)
+        return set_err(n->lat, HISQ_ERR_ARG, "inference activations: FP32 or FP16");
+    if (n->aprec != (int)prec) n->fcg_graph.release();
+    n->aprec = prec;
     return HISQ_OK;
 }
 

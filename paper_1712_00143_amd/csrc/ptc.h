@@ -49,6 +49,32 @@ struct PtcFuse {
 
 hipError_t launch_ptc_layer(int prec, int recon, bool w16, int cin, int cout, int W, const PtcLaunch &a, int nblk,
                             int batch, hipStream_t s);
+
+// Inference layer with FP16 activation storage (ptc_infer.hip): activations
+// [2 parities][h][C][3] half2 plus one FP32 scale per (parity, site).
+struct PtcInferLaunch {
+    const ProbDesc *probs;
+    int lslot;
+    int par_lo;              // first output parity (grid: npar * ntile blocks)
+    const void *w;           // FP16 weights [Cout][Cin][9] complex
+    const float *in32;       // input kind 0: even FP32 vector [h][3] complex (odd parity zero)
+    const __half2 *in16;     // input kind 1: FP16 activation
+    const float *in_scale;
+    __half2 *out16;          // output kind 0: FP16 activation
+    float *out_scale;
+    float *out32;            // output kind 1: even FP32 vector z = addin + layer output
+    const float *addin;
+    const float *dotq;       // with dotred: per-tile (dotq, z) into dotred[tile], dotred[dot_nt + tile]
+    double *dotred;
+    int dot_nt;
+    int gate_want;
+    const SolveState *gate;  // skip the launch unless gate->status == gate_want
+};
+// W: 1, 3 or 9 waves per block, or'ed with PTC_MFMA (3 and 9, cout >= cin)
+// for the matrix-core channel mixing
+constexpr int PTC_MFMA = 0x100;
+hipError_t launch_ptc_infer(int prec, int recon, int cin, int cout, int ik, int ok, int W, const PtcInferLaunch &a,
+                            int nblk, hipStream_t s);
 constexpr int WGRAD_ROWS = 1024;   // weight-gradient partial rows (blocks) at most
 
 // Weight-gradient partials of npar output parities x batch entries, reduced

@@ -44,7 +44,7 @@ EXPORTS = [
     "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
     "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss", "hisq_ptc_save", "hisq_ptc_load",
     "hisq_residual_history", "hisq_ptc_set_transport", "hisq_ptc_get_transport", "hisq_cg_noalloc",
-    "hisq_dslash_shape",
+    "hisq_dslash_shape", "hisq_ptc_set_activations",
 ]
 
 
@@ -354,6 +354,10 @@ class PTC:
         used by every later call of the network, training and inference."""
         self._err(lib().hisq_ptc_set_transport(self.handle, ctypes.c_int(prec), ctypes.c_int(recon)),
                   "hisq_ptc_set_transport")
+
+    def set_activations(self, prec):
+        """Inference activation storage: HISQ_F32 (default) or HISQ_F16."""
+        self._err(lib().hisq_ptc_set_activations(self.handle, ctypes.c_int(prec)), "hisq_ptc_set_activations")
 
     def get_transport(self):
         p, r = ctypes.c_int(0), ctypes.c_int(0)

@@ -543,3 +543,147 @@ def test_cg_learned_fp16_transports_16x16x16x16():
         assert tr <= 1e-10, tr
     net.close()
     lat.close()
+
+
+# ---- FP16 activation storage of inference ---------------------------------
+#
+# Bar: each stored activation entry is rounded to 2^-11 of its site's scale,
+# three times per hidden activation chain of the 1->4->4->1 network and its
+# adjoint; 2e-3 relative l2 on M r - r (the part the layers produce), which
+# is what FP16 storage puts at stake (the identity term is added in FP32).
+
+@pytest.mark.parametrize("transport", [(1, 18), (2, 12)])
+@pytest.mark.parametrize("chans", [(1, 4, 4, 1), (1, 2, 1)])
+def test_apply_fp16_activations_matches_oracle(lat6, transport, chans):
+    import torch
+    H = _hisq()
+    dims, fat, lng, lat = lat6
+    net = H.PTC(lat, chans)
+    net.set_transport(*transport)
+    net.set_activations(2)
+    ws = _rand_w(chans, 12, scale=0.3)
+    net.set_weights(ws)
+    w32 = [w.astype(np.complex64) for w in ws]
+    w16 = [(w.real.astype(np.float16).astype(np.float64) + 1j * w.imag.astype(np.float16).astype(np.float64))
+           for w in w32]
+    r = synth.gaussian_even(dims, 13)
+    ref = oracle.ptc_apply(dims, fat, w16, r)
+    h = r.shape[0]
+    z = torch.zeros(h * 6, device="cuda")
+    net.apply(_dev(r), z)
+    got = _host(z, (h, 3))
+    check(got - r, ref - r, 2e-3, ("fp16 activations", transport, chans))
+    net.close()
+
+
+def test_cg_learned_fp16_activations_graph_and_eager():
+    """The learned flexible CG with FP16 activations and FP16 recon-12
+    transports on a 12^4 field: oracle true residual <= 1e-10 without a
+    hand-over, and the graph-captured iteration gives the eager bits."""
+    H = _hisq()
+    dims = (12, 12, 12, 12)
+    fat, lng = synth.make_links(dims, 0.25, seed=4800)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    net = H.PTC(lat, (1, 4, 4, 1))
+    net.set_transport(2, 12)
+    net.set_activations(2)
+    net.init_polynomial(a=4.0, c=1.2)
+    b = synth.gaussian_even(dims, 4801)
+    m = 0.01
+    xs = []
+    for flags in (0, H.HISQ_USE_GRAPH, H.HISQ_USE_GRAPH):
+        x, info = net.cg_learned(lat, m, b, params=H.hisq_default_params(tol=1e-10, sloppy=1, flags=flags))
+        tr = oracle.true_residual(dims, fat, lng, m, b, x)
+        assert info["converged"] == 1 and info["fell_back"] == 0 and tr <= 1e-10, (flags, info, tr)
+        xs.append(x)
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[1], xs[2])
+    net.close()
+    lat.close()
+
+
+_FORCED_INFER_CHILD = r'''
+import json, os, sys
+import numpy as np
+import torch
+import oracle
+from paper_1712_00143_amd import synth, hisq as H
+
+arch = torch.cuda.get_device_properties(0).gcnArchName.replace(" ", "_")
+W = int(sys.argv[1])
+dims = (6, 4, 4, 8)                       # h = 384: six tiles per parity
+fat, lng = synth.make_links(dims, 0.25, seed=4000)
+h = synth.volume(dims) // 2
+t = (h + 63) // 64
+path = os.environ["HISQ_TUNE_CACHE"]
+lines = []
+for p, r in ((1, 18), (2, 12)):
+    for chans in ((1, 4, 4, 1), (1, 2, 1), (1, 8, 8, 1)):
+        L = len(chans) - 1
+        def wl(cin, cout):               # matrix-core shapes only where they exist
+            return W if cout >= cin or W < 256 else W & 255
+        for l in range(L):               # forward layers, then the adjoint ones
+            ci, co = chans[l], chans[l + 1]
+            lines.append(f"ptcinf:{arch}:t{t}:p{p}:r{r}:{ci}x{co}:k{0 if l == 0 else 1}0:np2 {wl(ci, co)} 0 0 1.0")
+        for l in range(L - 1, -1, -1):
+            last = l == 0
+            ci, co = chans[l + 1], chans[l]
+            lines.append(f"ptcinf:{arch}:t{t}:p{p}:r{r}:{ci}x{co}:k1{1 if last else 0}:np{1 if last else 2} {wl(ci, co)} 0 0 1.0")
+with open(path, "w") as f:
+    f.write("\n".join(sorted(set(lines))) + "\n")
+lat = H.Lattice(dims)
+lat.load_links(fat, lng)
+rng = np.random.default_rng(3)
+worst = 0.0
+for p, r in ((1, 18), (2, 12)):
+    for chans in ((1, 4, 4, 1), (1, 2, 1), (1, 8, 8, 1)):
+        net = H.PTC(lat, chans)
+        net.set_transport(p, r)
+        net.set_activations(2)
+        ws = [0.3 * (rng.standard_normal((b, a, 9)) + 1j * rng.standard_normal((b, a, 9)))
+              for a, b in zip(chans[:-1], chans[1:])]
+        net.set_weights(ws)
+        w16 = [(w.astype(np.complex64).real.astype(np.float16).astype(np.float64)
+                + 1j * w.astype(np.complex64).imag.astype(np.float16).astype(np.float64)) for w in ws]
+        for scale in (1.0, 1e-9):        # the residual's magnitude must not matter
+            rv = scale * synth.gaussian_even(dims, 17)
+            ref = oracle.ptc_apply(dims, fat, w16, rv)
+            x = torch.from_numpy(rv.astype(np.complex64).view(np.float32).reshape(-1)).cuda()
+            z = torch.zeros_like(x)
+            net.apply(x, z)
+            torch.cuda.synchronize()
+            got = z.cpu().numpy().view(np.complex64).astype(np.complex128).reshape(-1, 3)
+            d, e = got - rv.astype(np.complex64).astype(np.complex128), ref - rv
+            rel = float(np.linalg.norm(d - e) / np.linalg.norm(e))
+            site = float(np.linalg.norm(d - e, axis=1).max() / (np.linalg.norm(e) / np.sqrt(h)))
+            worst = max(worst, rel)
+            assert rel <= 2e-3 and site <= 2e-2, (W, p, r, chans, scale, rel, site)
+        net.close()
+lat.close()
+with open(path) as f:
+    n = sum(1 for ln in f if ln.strip())
+assert n == len(set(lines)), "tuner added entries: a forced key did not match"
+print(json.dumps({"W": W, "worst": worst}))
+'''
+
+
+@pytest.mark.parametrize("W", [1, 3, 9, 259, 265])
+def test_fp16_activation_layers_every_shape(tmp_path, W):
+    """Every block shape of the FP16-activation inference layers (W = 1, 3, 9:
+    vector-ALU channel mixing; 259, 265 = 3, 9 with the matrix-core mixing,
+    used by the layers with at least as many outputs as inputs), forced
+    through a prefilled tuner cache in a child process, for 1-4-4-1, 1-2-1
+    and 1-8-8-1 networks on both transport formats and on a residual scaled
+    by 1e-9: M r - r against the oracle at the FP16-activation bar."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ)
+    env["HISQ_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+    env["PYTHONPATH"] = root + os.pathsep + env.get("PYTHONPATH", "")
+    print(f"forced inference shape child W={W}", flush=True)
+    r = subprocess.run([sys.executable, "-c", _FORCED_INFER_CHILD, str(W)], cwd=root, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert '"W": %d' % W in r.stdout, r.stdout
