@@ -659,7 +659,11 @@ TuneChoice pick_shape_mrhs(hisq_lattice lat, int prec, int recon, int nr, bool n
     (void)hipEventCreate(&e1);
     TuneChoice best = def;
     best.us = 1e30;
-    for (int W : {2, 4, 8, 16}) {
+    // the vector-ALU kernel with 2-16 waves per block, and for groups of four
+    // FP32-vector right-hand sides the matrix-core kernel
+    std::vector<int> shapes{2, 4, 8, 16};
+    if (nr == 4 && prec != 0) shapes.push_back(MRHS_MFMA);
+    for (int W : shapes) {
         for (int remap = 0; remap < 2; remap++) {
             MrhsLaunch a;
             memset(&a, 0, sizeof a);
@@ -683,6 +687,7 @@ TuneChoice pick_shape_mrhs(hisq_lattice lat, int prec, int recon, int nr, bool n
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e0, e1);
             const double us = 1000.0 * ms / reps;
+            Tuner::get().note(key, W, remap, 0, us);
             if (us < best.us) {
                 best.us = us;
                 best.W = W;

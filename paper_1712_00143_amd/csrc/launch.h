@@ -61,9 +61,13 @@ struct MrhsLaunch {
 };
 
 // group: right-hand sides per link read (1..4); the grid is
-// ceil(nrhs / group) * ntile blocks.
+// ceil(nrhs / group) * ntile blocks.  W: waves per block (2, 4, 8, 16) of the
+// vector-ALU kernel, or MRHS_MFMA for the matrix-core kernel (group 4, FP32 or
+// FP16 links, FP32 vectors, PLAIN and AX epilogues).
+constexpr int MRHS_MFMA = 0x200;
 hipError_t launch_dslash_mrhs(int prec, int recon, int group, int W, const MrhsLaunch &a, int ntile,
                               hipStream_t s);
+hipError_t launch_dslash_mrhs_mfma(int prec, int recon, const MrhsLaunch &a, int nblocks, hipStream_t s);
 
 // ---- packing
 struct PackLaunch {

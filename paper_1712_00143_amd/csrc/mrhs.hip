@@ -3,10 +3,10 @@
 // amortised NR ways.  Used by the multi-shift CG over several sources
 // (Section 4.1) and by hisq_dslash with nrhs > 1.
 //
-// Per link the work is a complex 3x3 times 3xNR product.  The kernel stays
-// bandwidth-bound even at NR = 4 (about 3.4 flop/byte in FP32), far below
-// the VALU ridge, so the contraction runs on the vector ALUs: staging it
-// through MFMA tiles would add register shuffles without moving the bound.
+// Per link the work is a complex 3x3 times 3xNR product, here on the vector
+// ALUs; mrhs_mfma.hip holds the same operator for NR = 4 on the matrix cores
+// (v_mfma_f32_4x4x1_16b_f32, one 4x4 block per site), and the autotuner times
+// both and keeps the faster.
 //
 // Layout: right-hand side r of the vector arguments starts at r * vstride
 // sites; each right-hand side may be a problem of a solve set (own FP64 state
@@ -275,6 +275,10 @@ hipError_t launch_dslash_mrhs(int prec, int recon, int nrhs, int W, const MrhsLa
         MrhsLaunch b = a;
         b.remap = 1;
         return launch_dslash_mrhs(prec, recon, nrhs, W, b, ntile, s);
+    }
+    if (W == MRHS_MFMA) {
+        if (nrhs != 4 || prec == 0) return hipErrorInvalidValue;
+        return launch_dslash_mrhs_mfma(prec, recon, a, nblocks, s);
     }
     if (prec == 0) {
         if (recon != 18) return hipErrorInvalidValue;

@@ -187,3 +187,82 @@ def test_multishift_errors():
         lat.multishift_cg(0.1, [0.1, 0.2], b)          # FP32 link set not prepared
     assert ei.value.status == H.HISQ_ERR_STATE
     lat.close()
+
+
+_FORCED_MRHS_CHILD = r'''
+import json, os, sys
+import numpy as np
+import torch
+import oracle
+from paper_1712_00143_amd import synth, hisq as H
+
+arch = torch.cuda.get_device_properties(0).gcnArchName.replace(" ", "_")
+shape = int(sys.argv[1])                  # 512: matrix-core kernel, else waves of the vector-ALU kernel
+path = os.environ["HISQ_TUNE_CACHE"]
+cases = [(6, 4, 6, 4), (8, 8, 8, 8)]      # h = 288 (ragged last tile), 2048
+lines = []
+for dims in cases:
+    t = (synth.volume(dims) // 2 + 63) // 64
+    for p, r in ((1, 18), (1, 12), (2, 12)):
+        lines.append(f"mrhs2:{arch}:p{p}:r{r}:t{t}:nr4 {shape} 1 0 1.0")
+    lines.append(f"mrhs2:{arch}:p0:r18:t{t}:nr4 8 1 0 1.0")   # the FP64 reliable updates (vector ALU)
+with open(path, "w") as f:
+    f.write("\n".join(lines) + "\n")
+tol = {1: 5e-6, 2: 2e-3}
+worst = {}
+for k, dims in enumerate(cases):
+    fat, lng = synth.make_links(dims, 0.3, seed=61 + k)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    h = synth.volume(dims) // 2
+    for p, r in ((1, 18), (1, 12), (2, 12)):
+        lat.prepare_links(p, r)
+        for nrhs in (4, 6, 13):           # full groups, and a last group of 2 or 1
+            psi = synth.gaussian_even(dims, 80 + nrhs, nrhs)
+            out = np.zeros_like(psi)
+            for par in (0, 1):
+                lat.dslash(par, p, r, psi, out, nrhs=nrhs)
+                for j in range(nrhs):
+                    ref = oracle.dslash_half(dims, fat, lng, par, psi[j])
+                    rel = float(np.linalg.norm(out[j] - ref) / np.linalg.norm(ref))
+                    site = float(np.linalg.norm(out[j] - ref, axis=1).max() / (np.linalg.norm(ref) / np.sqrt(h)))
+                    worst[(p, r)] = max(worst.get((p, r), 0.0), rel)
+                    assert rel <= tol[p] and site <= 10 * tol[p], (shape, dims, p, r, nrhs, par, j, rel, site)
+    # the shared-link CG of several problems on one lattice runs its sloppy
+    # operator (AX epilogue with the per-tile p.Ap sums) through the same launch
+    lats = [lat] * 5
+    ms = [0.1, 0.12, 0.15, 0.2, 0.25]
+    bs = [synth.gaussian_even(dims, 90 + q) for q in range(5)]
+    xs, infos = H.hisq_batch_cg(lats, ms, bs, params=H.hisq_default_params(tol=1e-10, sloppy=1))
+    for q in range(5):
+        tr = oracle.true_residual(dims, fat, lng, ms[q], bs[q], xs[q])
+        assert infos[q]["converged"] == 1 and tr <= 1e-10, (shape, dims, q, tr)
+    lat.close()
+with open(path) as f:
+    n = sum(1 for ln in f if ln.strip())
+assert n == len(lines), "tuner added entries: a forced key did not match"
+print(json.dumps({"shape": shape, "worst": {f"{k[0]}_{k[1]}": v for k, v in worst.items()}}))
+'''
+
+
+@pytest.mark.parametrize("shape", [512, 4])
+def test_mrhs_dslash_forced_matrix_core_and_vector_kernels(tmp_path, shape):
+    """The four-right-hand-side Dslash forced onto the matrix-core kernel
+    (shape 512) and onto the vector-ALU kernel with four waves, through a
+    prefilled tuner cache in a child process: FP32 recon-18 / recon-12 and
+    FP16 recon-12 links, 4, 6 and 13 right-hand sides (partial last groups),
+    a ragged last tile, every output against the oracle with the per-site
+    bound, and the shared-link batched CG (AX epilogue) to the oracle's
+    true residual 1e-10."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ)
+    env["HISQ_TUNE_CACHE"] = str(tmp_path / "tune.txt")
+    env["PYTHONPATH"] = root + os.pathsep + env.get("PYTHONPATH", "")
+    print(f"forced multi-RHS shape child {shape}", flush=True)
+    r = subprocess.run([sys.executable, "-c", _FORCED_MRHS_CHILD, str(shape)], cwd=root, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert '"shape": %d' % shape in r.stdout, r.stdout
