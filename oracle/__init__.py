@@ -1,5 +1,5 @@
 """FP64 CPU oracle for the HISQ even-odd Dslash, CG, multi-shift CG, PTC
-preconditioner and flexible CG.
+preconditioner, flexible CG and HISQ link smearing.
 
 TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
 benchmark's CPU-baseline leg, never by the library.  It shares no code with the
@@ -309,3 +309,58 @@ def adam_step(param, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8
     mhat = m / (1 - beta1 ** step)
     vhat = v / (1 - beta2 ** step)
     return param - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# ------------------------------------------------------------- link smearing
+
+HISQ_LEVEL1 = (1 / 8, 1 / 16, 1 / 64, 1 / 384, 0.0)
+HISQ_LEVEL2 = (5 / 8, 1 / 16, 1 / 64, 1 / 384, -1 / 16)
+
+
+def fat7(dims, links, coefs):
+    """Path-sum smearing of links [V][4][3][3] with coefs (c1, c3, c5, c7,
+    cLepage): one-link, 3-, 5-, 7-staples and Lepage paths, summed path by
+    path (hisq_oracle.c states the path list)."""
+    lib = _load()
+    u, up = _c(links)
+    c = (ctypes.c_double * 5)(*[float(x) for x in coefs])
+    out = np.empty_like(u)
+    lib.orc_fat7(_dims(dims), c, up, out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def unitarize(mats):
+    """Unitary polar factor V (V^+ V)^{-1/2} of every 3x3 in mats [..., 3, 3]
+    (Newton iteration).  Raises if any matrix does not converge."""
+    lib = _load()
+    m, mp = _c(mats)
+    out = np.empty_like(m)
+    n = m.size // 9
+    lib.orc_unitarize.restype = ctypes.c_int
+    bad = lib.orc_unitarize(ctypes.c_long(n), mp, out.ctypes.data_as(ctypes.c_void_p))
+    if bad:
+        raise ArithmeticError(f"polar iteration did not converge for {bad} matrices")
+    return out
+
+
+def naik_product(dims, links):
+    """W_mu(x) W_mu(x+mu) W_mu(x+2mu) for every site and direction."""
+    lib = _load()
+    u, up = _c(links)
+    out = np.empty_like(u)
+    lib.orc_naik_product(_dims(dims), up, out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def hisq_smear(dims, thin):
+    """(fat, long) HISQ links, phases folded, from thin SU(3) links."""
+    lib = _load()
+    u, up = _c(thin)
+    fat = np.empty_like(u)
+    lng = np.empty_like(u)
+    lib.orc_hisq_smear.restype = ctypes.c_int
+    bad = lib.orc_hisq_smear(_dims(dims), up, fat.ctypes.data_as(ctypes.c_void_p),
+                             lng.ctypes.data_as(ctypes.c_void_p))
+    if bad:
+        raise ArithmeticError(f"polar iteration did not converge for {bad} links")
+    return fat, lng

@@ -26,6 +26,9 @@
  *             exact adjoint (input and weight gradients).
  *   FCG       flexible CG with truncation 1 (Notay 2000) with the PTC network
  *             as preconditioner.
+ *   smearing  HISQ fat and long links from thin links: two fat7 levels
+ *             with a U(3) polar projection between, Lepage and Naik terms
+ *             at the second (stated with the code below).
  *
  * Complex numbers are C99 double complex; fields are site-major:
  *   links   [V][4][3][3]          (row-major 3x3)
@@ -471,4 +474,204 @@ int orc_fcg(const int d[4], const cplx *fat, const cplx *lng, double mass, int n
     *true_rel = orc_true_residual(d, fat, lng, mass, 0.0, b, x);
     free(r); free(z); free(p); free(q);
     return ok ? 0 : 1;
+}
+
+/* ------------------------------------------------------------ link smearing
+ *
+ * HISQ fat and long links from thin SU(3) links U (the smearing the paper's
+ * run-time breakdown lists beside the forces, Section 2; its definition is
+ * that of the HISQ action, Follana et al., hep-lat/0610092):
+ *
+ *   level 1   V = fat7(U; 1/8, 1/16, 1/64, 1/384; Lepage 0)
+ *   project   W = V (V^+ V)^{-1/2}, the unitary factor of the polar
+ *             decomposition (the nearest U(3) matrix)
+ *   level 2   X = fat7(W; 5/8, 1/16, 1/64, 1/384; Lepage -1/16)
+ *             N_mu(x) = W_mu(x) W_mu(x+mu) W_mu(x+2mu)
+ *   output    F_mu(x) = eta_mu(x) X_mu(x),  L_mu(x) = -(1/24) eta_mu(x) N_mu(x)
+ *
+ * fat7(U; c1, c3, c5, c7; cL)_mu(x) = c1 U_mu(x) + sum over the paths from x to
+ * x+mu listed below, each weighted by its class coefficient, of the product of
+ * the links along the path:
+ *   3-staples  (s nu, mu, -s nu)                           6 paths, c3
+ *   5-staples  (s nu, t rho, mu, -t rho, -s nu)            24 paths, c5
+ *   7-staples  (s nu, t rho, u sig, mu, -u sig, -t rho, -s nu)  48 paths, c7
+ *   Lepage     (s nu, s nu, mu, -s nu, -s nu)              6 paths, cL
+ * with nu, rho, sig distinct directions other than mu and s, t, u = +-1.  A
+ * step +nu from y multiplies by U_nu(y) and moves to y+nu; a step -nu moves to
+ * y-nu and multiplies by U_nu(y-nu)^+.  With unit links X = 9/8 and the Naik
+ * coefficient -1/24 makes the free derivative exact to O(p^4).
+ */
+
+/* c = a b */
+static void mm(cplx *c, const cplx *a, const cplx *b)
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cplx s = 0;
+            for (int k = 0; k < 3; k++) s += a[3 * i + k] * b[3 * k + j];
+            c[3 * i + j] = s;
+        }
+}
+
+/* Product of the links along a path of n signed steps (+(mu+1) or -(mu+1))
+ * starting at site s; P receives the 3x3 product. */
+static void path_product(const int d[4], const cplx *U, long s, const int *steps, int n, cplx *P)
+{
+    for (int i = 0; i < 9; i++) P[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    long cur = s;
+    for (int k = 0; k < n; k++) {
+        int mu = abs(steps[k]) - 1;
+        cplx M[9], T[9];
+        if (steps[k] > 0) {
+            memcpy(M, link(U, cur, mu), sizeof M);
+            cur = hop(d, cur, mu, 1);
+        } else {
+            cur = hop(d, cur, mu, -1);
+            const cplx *u = link(U, cur, mu);
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) M[3 * i + j] = conj(u[3 * j + i]);
+        }
+        mm(T, P, M);
+        memcpy(P, T, sizeof T);
+    }
+}
+
+static void acc_path(const int d[4], const cplx *U, long s, const int *steps, int n, double c, cplx *out)
+{
+    cplx P[9];
+    path_product(d, U, s, steps, n, P);
+    for (int i = 0; i < 9; i++) out[i] += c * P[i];
+}
+
+/* fat7 with coefficients c = {c1, c3, c5, c7, cL}; U, out: [V][4][3][3]. */
+void orc_fat7(const int d[4], const double c[5], const cplx *U, cplx *out)
+{
+    const long V = vol(d);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++)
+        for (int mu = 0; mu < 4; mu++) {
+            cplx *o = out + (s * 4 + mu) * 9;
+            const cplx *u = link(U, s, mu);
+            for (int i = 0; i < 9; i++) o[i] = c[0] * u[i];
+            const int M = mu + 1;
+            for (int nu = 0; nu < 4; nu++) {
+                if (nu == mu) continue;
+                for (int sn = -1; sn <= 1; sn += 2) {
+                    const int N = sn * (nu + 1);
+                    const int p3[3] = {N, M, -N};
+                    acc_path(d, U, s, p3, 3, c[1], o);
+                    const int pl[5] = {N, N, M, -N, -N};
+                    if (c[4] != 0.0) acc_path(d, U, s, pl, 5, c[4], o);
+                    for (int rho = 0; rho < 4; rho++) {
+                        if (rho == mu || rho == nu) continue;
+                        for (int sr = -1; sr <= 1; sr += 2) {
+                            const int R = sr * (rho + 1);
+                            const int p5[5] = {N, R, M, -R, -N};
+                            acc_path(d, U, s, p5, 5, c[2], o);
+                            for (int sig = 0; sig < 4; sig++) {
+                                if (sig == mu || sig == nu || sig == rho) continue;
+                                for (int ss = -1; ss <= 1; ss += 2) {
+                                    const int S = ss * (sig + 1);
+                                    const int p7[7] = {N, R, S, M, -S, -R, -N};
+                                    acc_path(d, U, s, p7, 7, c[3], o);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+}
+
+/* inverse of a 3x3 complex matrix by cofactors; returns the determinant */
+static cplx inv3(const cplx *a, cplx *r)
+{
+    cplx c[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            c[3 * i + j] = a[3 * i1 + j1] * a[3 * i2 + j2] - a[3 * i1 + j2] * a[3 * i2 + j1];
+        }
+    cplx det = a[0] * c[0] + a[1] * c[1] + a[2] * c[2];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) r[3 * i + j] = c[3 * j + i] / det;
+    return det;
+}
+
+/* Unitary polar factor of each of n 3x3 matrices by Newton's iteration
+ * X <- (X + X^{-+}) / 2 (Higham, Functions of Matrices, ch. 8), which
+ * converges quadratically to V (V^+ V)^{-1/2} for non-singular V.  Returns
+ * the number of matrices that did not converge in 100 steps (0 on success). */
+int orc_unitarize(long n, const cplx *in, cplx *out)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (long m = 0; m < n; m++) {
+        cplx X[9], Y[9];
+        memcpy(X, in + m * 9, sizeof X);
+        int ok = 0;
+        for (int it = 0; it < 100; it++) {
+            cplx det = inv3(X, Y);
+            if (cabs(det) == 0.0 || !isfinite(creal(det)) || !isfinite(cimag(det))) break;
+            double dx = 0, nx = 0;
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    cplx nxt = 0.5 * (X[3 * i + j] + conj(Y[3 * j + i]));
+                    dx += creal((nxt - X[3 * i + j]) * conj(nxt - X[3 * i + j]));
+                    nx += creal(nxt * conj(nxt));
+                    X[3 * i + j] = nxt;
+                }
+            if (dx <= 1e-30 * nx) { ok = 1; break; }
+        }
+        memcpy(out + m * 9, X, sizeof X);
+        bad += !ok;
+    }
+    return bad;
+}
+
+/* Three-link product N_mu(x) = W_mu(x) W_mu(x+mu) W_mu(x+2mu). */
+void orc_naik_product(const int d[4], const cplx *W, cplx *out)
+{
+    const long V = vol(d);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++)
+        for (int mu = 0; mu < 4; mu++) {
+            const int p[3] = {mu + 1, mu + 1, mu + 1};
+            path_product(d, W, s, p, 3, out + (s * 4 + mu) * 9);
+        }
+}
+
+/* eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}) */
+static double eta(const int d[4], long s, int mu)
+{
+    int x[4];
+    coords_of(d, s, x);
+    int k = 0;
+    for (int nu = 0; nu < mu; nu++) k += x[nu];
+    return (k & 1) ? -1.0 : 1.0;
+}
+
+/* The HISQ links (eq. above) from thin links; fat, lng: [V][4][3][3] with the
+ * phases folded in.  Returns orc_unitarize's count of failures. */
+int orc_hisq_smear(const int d[4], const cplx *thin, cplx *fat, cplx *lng)
+{
+    const long V = vol(d), n = V * 4 * 9;
+    const double lv1[5] = {1.0 / 8, 1.0 / 16, 1.0 / 64, 1.0 / 384, 0.0};
+    const double lv2[5] = {5.0 / 8, 1.0 / 16, 1.0 / 64, 1.0 / 384, -1.0 / 16};
+    cplx *Vf = malloc(sizeof(cplx) * n), *W = malloc(sizeof(cplx) * n);
+    orc_fat7(d, lv1, thin, Vf);
+    int bad = orc_unitarize(V * 4, Vf, W);
+    orc_fat7(d, lv2, W, fat);
+    orc_naik_product(d, W, lng);
+    for (long s = 0; s < V; s++)
+        for (int mu = 0; mu < 4; mu++) {
+            const double e = eta(d, s, mu);
+            for (int i = 0; i < 9; i++) {
+                fat[(s * 4 + mu) * 9 + i] *= e;
+                lng[(s * 4 + mu) * 9 + i] *= -e / 24.0;
+            }
+        }
+    free(Vf);
+    free(W);
+    return bad;
 }

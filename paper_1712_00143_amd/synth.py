@@ -93,14 +93,41 @@ def _expi_hermitian(H: np.ndarray) -> np.ndarray:
     return (v * np.exp(1j * w)[..., None, :]) @ np.conj(np.swapaxes(v, -1, -2))
 
 
-def base_links(dims, eps: float, seed: int) -> np.ndarray:
-    """Unphased F~ = 0.9 exp(i eps H) as complex128 [V][4][3][3]."""
+def _su3_field(dims, eps: float, seed: int) -> np.ndarray:
     dims = check_dims(dims)
     V = volume(dims)
     rng = np.random.default_rng(seed)
     omega = rng.standard_normal((V, 4, 8))
     H = np.einsum("sma,aij->smij", omega, _GELL_MANN / 2.0)
-    return FAT_SCALE * _expi_hermitian(eps * H)
+    return _expi_hermitian(eps * H)
+
+
+def base_links(dims, eps: float, seed: int) -> np.ndarray:
+    """Unphased F~ = 0.9 exp(i eps H) as complex128 [V][4][3][3]."""
+    return FAT_SCALE * _su3_field(dims, eps, seed)
+
+
+def thin_links(dims, eps: float, seed: int) -> np.ndarray:
+    """Thin gauge links U = exp(i eps H) in SU(3), unphased, [V][4][3][3]:
+    the input of the HISQ smearing."""
+    return _su3_field(dims, eps, seed)
+
+
+def tile_field(field: np.ndarray, dims, reps) -> np.ndarray:
+    """Periodic copy of a site-major field [V, ...] on the lattice
+    dims * reps (each extent repeated reps[mu] times)."""
+    L0, L1, L2, L3 = dims
+    f = field.reshape((L3, L2, L1, L0) + field.shape[1:])
+    f = np.tile(f, (reps[3], reps[2], reps[1], reps[0]) + (1,) * (field.ndim - 1))
+    return f.reshape((-1,) + field.shape[1:])
+
+
+def gauge_transform(links: np.ndarray, dims, g: np.ndarray) -> np.ndarray:
+    """U'_mu(x) = g(x) U_mu(x) g(x+mu)^+ for site matrices g [V][3][3]."""
+    out = np.empty_like(links)
+    for mu in range(4):
+        out[:, mu] = g @ links[:, mu] @ np.conj(np.swapaxes(_shift(g, dims, mu, 1), -1, -2))
+    return out
 
 
 def _shift(field: np.ndarray, dims, mu: int, k: int) -> np.ndarray:
