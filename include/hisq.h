@@ -71,10 +71,12 @@ enum {
     HISQ_STOP_STAGNATION = 16,  /* CG solvers: give up (HISQ_ERR_NOT_CONVERGED, x the last
                                    reliable update's iterate) when three reliable updates in a
                                    row bring no FP64 true residual below the one before them */
-    HISQ_STREAM_LINKS = 32      /* hisq_dslash (one right-hand side): stream every link past the
+    HISQ_STREAM_LINKS = 32,     /* hisq_dslash (one right-hand side): stream every link past the
                                    caches (no part kept in the Infinity Cache between calls), in
                                    the block shape the autotuner found fastest that way; the rate
                                    is then an HBM rate whatever the operator's size */
+    HISQ_LOAD_RESULT = 64       /* hisq_smear_links: the smeared links become the lattice's
+                                   links, as if passed to hisq_load_links */
 };
 /* Environment: HISQ_TUNE=0 gives every call the default launch shapes (as
  * HISQ_NO_TUNE does for one call); HISQ_TUNE_CACHE=<file> appends every tuned
@@ -351,6 +353,50 @@ hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double mass, const d
  * number recorded to *count.  Errors: HISQ_ERR_STATE (no solve yet),
  * HISQ_ERR_ARG (problem out of range, null count, cap < 0). */
 hisq_status hisq_residual_history(hisq_lattice lat, int problem, double *out, int cap, int *count);
+
+/* ---- link smearing ----
+ *
+ * The HISQ fat and long links from thin SU(3) links (the link smearing the
+ * paper's run-time breakdown reports beside the fermion and gauge forces,
+ * Section 2 and Fig. 1; the construction is that of the HISQ action,
+ * Follana et al., hep-lat/0610092):
+ *   V = fat7(U; 1/8, 1/16, 1/64, 1/384; Lepage 0)
+ *   W = V (V^+ V)^{-1/2}                         (projection onto U(3))
+ *   fat_mu(x) = eta_mu(x) fat7(W; 5/8, 1/16, 1/64, 1/384; Lepage -1/16)_mu(x)
+ *   lng_mu(x) = -(1/24) eta_mu(x) W_mu(x) W_mu(x+mu) W_mu(x+2mu)
+ * fat7(U; c1, c3, c5, c7; cL)_mu(x) is c1 U_mu(x) plus, over the directions
+ * nu, rho, sig (distinct, != mu) and both signs of each, c3 times the
+ * 3-link staples (nu, mu, -nu), c5 the 5-link staples (nu, rho, mu, -rho,
+ * -nu), c7 the 7-link staples (nu, rho, sig, mu, -sig, -rho, -nu) and cL the
+ * Lepage paths (nu, nu, mu, -nu, -nu), each the product of the links along
+ * the path (a step -nu from y multiplies by U_nu(y-nu)^+).  Unit thin links
+ * give fat = 9/8 eta, lng = -1/24 eta.
+ *
+ * Arrays use the link layout above ([V][4][3][3] complex FP64, site-major;
+ * thin links without phases), host pointers or, with HISQ_DEVICE_PTR, device
+ * pointers.  FP64 throughout; synchronous.  The library keeps a device
+ * workspace of 14 link-direction fields (22 with host outputs that are not
+ * loaded; 144 V bytes each) per lattice until hisq_destroy.
+ *
+ * hisq_smear_links: thin -> (fat, lng).  With HISQ_LOAD_RESULT the result
+ * also becomes the lattice's links (fat and lng may then be NULL), ready for
+ * the solvers; its fat links are not a scaled SU(3), so hisq_prepare_links
+ * with recon-12 returns HISQ_ERR_RECON for them.  Errors: HISQ_ERR_ARG (null
+ * arguments), HISQ_ERR_BREAKDOWN (some V^+ V singular: no projection; with
+ * HISQ_LOAD_RESULT the lattice is then left without links),
+ * HISQ_ERR_OOM / HISQ_ERR_HIP. */
+hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, double *lng, int flags);
+
+/* One fat7 level alone: out = fat7(in; coef[0..4] = c1, c3, c5, c7, cL), no
+ * phases, no projection (with the asqtad coefficients 5/8, 1/16, 1/64, 1/384,
+ * -1/16 on thin links: the asqtad fat links before their phases).  Errors:
+ * HISQ_ERR_ARG (null arguments), HISQ_ERR_OOM / HISQ_ERR_HIP. */
+hisq_status hisq_fat7(hisq_lattice lat, const double coef[5], const double *in, double *out, int flags);
+
+/* The U(3) projection alone: out = in (in^+ in)^{-1/2} for each of the 4 V
+ * links.  Errors: HISQ_ERR_ARG, HISQ_ERR_BREAKDOWN (a singular link; out
+ * still written, non-finite there). */
+hisq_status hisq_unitarize(hisq_lattice lat, const double *in, double *out, int flags);
 
 /* ---- measurement ----
  *

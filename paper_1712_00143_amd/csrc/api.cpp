@@ -270,6 +270,7 @@ hisq_status hisq_destroy(hisq_lattice lat)
     for (DVec *v : {&lat->tmp_in, &lat->tmp_out, &lat->tmp64a, &lat->tmp64b}) dvec_free(*v);
     if (lat->ddesc) (void)hipFree(lat->ddesc);
     if (lat->dpart) (void)hipFree(lat->dpart);
+    if (lat->smear_ws) (void)hipFree(lat->smear_ws);
     if (lat->own_stream && lat->s) (void)hipStreamDestroy(lat->s);
     delete lat;
     return HISQ_OK;
@@ -399,6 +400,18 @@ static hisq_status pack_set(hisq_lattice lat, int prec, int recon)
 
 }  // namespace hisq
 
+// The device FP64 copies lat->fat64 / lat->lng64 (written by the caller on
+// lat->s) become the lattice's links: every packed set and solve workspace
+// is discarded and the FP64 recon-18 operator is packed.
+hisq_status adopt_device_links(hisq_lattice lat)
+{
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    for (auto &ls : lat->ls) ls = LinkSet();
+    lat->cg.release();
+    lat->loaded = true;
+    return pack_set(lat, 0, 18);
+}
+
 extern "C" {
 
 hisq_status hisq_load_links(hisq_lattice lat, const double *fat, const double *lng, int flags)
@@ -411,11 +424,7 @@ hisq_status hisq_load_links(hisq_lattice lat, const double *fat, const double *l
     hipMemcpyKind k = (flags & HISQ_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(lat, hipMemcpyAsync(lat->fat64, fat, bytes, k, lat->s));
     HIPCHK(lat, hipMemcpyAsync(lat->lng64, lng, bytes, k, lat->s));
-    HIPCHK(lat, hipStreamSynchronize(lat->s));
-    for (auto &ls : lat->ls) ls = LinkSet();
-    lat->cg.release();
-    lat->loaded = true;
-    return pack_set(lat, 0, 18);
+    return adopt_device_links(lat);
 }
 
 hisq_status hisq_prepare_links(hisq_lattice lat, hisq_prec prec, hisq_recon recon)

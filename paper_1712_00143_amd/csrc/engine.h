@@ -111,4 +111,6 @@ struct hisq_lattice_s {
     hisq::DVec tmp_in, tmp_out, tmp64a, tmp64b;  // host-pointer Dslash staging
     hisq::ProbDesc *ddesc = nullptr;             // this lattice alone
     double *dpart = nullptr;
+    void *smear_ws = nullptr;                    // link-smearing workspace
+    size_t smear_ws_bytes = 0;
 };

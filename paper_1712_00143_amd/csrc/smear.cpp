@@ -1,0 +1,228 @@
+// HISQ link smearing: host orchestration of the staple passes and the C-ABI
+// entry points hisq_smear_links, hisq_fat7 and hisq_unitarize.
+//
+// fat7(U; c1, c3, c5, c7; cL) for output direction mu is built with staple
+// reuse: for each nu != mu the 3-staple field T1 = staple(U_mu, nu) is formed
+// once and every 5-staple through nu is a staple of T1 (T2 = staple(T1,
+// rho)), every 7-staple a staple of T2 through the one remaining direction.
+// 15 passes per direction instead of one kernel per path; each pass adds its
+// contribution to the accumulated output field in place.
+#include <vector>
+
+#include "smear.h"
+#include "solver.h"
+
+using namespace hisq;
+
+#define HIPCHK(lat, x)                                     \
+    do {                                                   \
+        hipError_t e_ = (x);                               \
+        if (e_ != hipSuccess) return hip_err(lat, e_, #x); \
+    } while (0)
+
+namespace {
+
+constexpr double LV1[5] = {1.0 / 8, 1.0 / 16, 1.0 / 64, 1.0 / 384, 0.0};
+constexpr double LV2[5] = {5.0 / 8, 1.0 / 16, 1.0 / 64, 1.0 / 384, -1.0 / 16};
+constexpr double NAIK = -1.0 / 24;
+
+SmearGeom geom_of(hisq_lattice lat)
+{
+    SmearGeom g;
+    g.V = lat->V;
+    for (int k = 0; k < 4; k++) g.L[k] = lat->L[k];
+    g.S[0] = 1;
+    g.S[1] = lat->L[0];
+    g.S[2] = lat->L[0] * lat->L[1];
+    g.S[3] = lat->L[0] * lat->L[1] * lat->L[2];
+    return g;
+}
+
+// Workspace: nf one-direction planar fields (9 V double2 each) and a
+// 256-byte tail for the projection's failure counter.
+struct Work {
+    double2 *f = nullptr;   // field k at f + k * 9 V
+    int *bad = nullptr;
+    size_t fsz = 0;         // double2 per field
+    double2 *field(int k) const { return f + (size_t)k * fsz; }
+};
+
+hisq_status get_work(hisq_lattice lat, int nf, Work &w)
+{
+    w.fsz = (size_t)9 * lat->V;
+    const size_t need = (size_t)nf * w.fsz * sizeof(double2) + 256;
+    if (lat->smear_ws_bytes < need) {
+        if (lat->smear_ws) {
+            HIPCHK(lat, hipStreamSynchronize(lat->s));
+            HIPCHK(lat, hipFree(lat->smear_ws));
+            lat->smear_ws = nullptr;
+            lat->smear_ws_bytes = 0;
+        }
+        HIPCHK(lat, hipMalloc(&lat->smear_ws, need));
+        lat->smear_ws_bytes = need;
+    }
+    w.f = (double2 *)lat->smear_ws;
+    w.bad = (int *)((char *)lat->smear_ws + (size_t)nf * w.fsz * sizeof(double2));
+    return HISQ_OK;
+}
+
+// out (4 planar fields) = fat7(U (4 planar fields)); T1, T2 one field each.
+hipError_t run_fat7(const SmearGeom &g, const double2 *U, double2 *out, double2 *T1, double2 *T2,
+                    const double c[5], size_t fsz, hipStream_t s)
+{
+    const bool need5 = c[2] != 0.0 || c[3] != 0.0, need7 = c[3] != 0.0;
+    for (int mu = 0; mu < 4; mu++) {
+        int perp[3], np = 0;
+        for (int d = 0; d < 4; d++)
+            if (d != mu) perp[np++] = d;
+        double2 *F = out + (size_t)mu * fsz;
+        const double2 *Umu = U + (size_t)mu * fsz;
+        for (int i = 0; i < 3; i++) {
+            const int nu = perp[i];
+            StapleArgs a{U + (size_t)nu * fsz, Umu, F, need5 ? T1 : nullptr, c[0], c[1], c[4], i == 0, mu, nu};
+            hipError_t e = launch_smear_staple(g, a, s);
+            if (e != hipSuccess) return e;
+            if (!need5) continue;
+            for (int j = 0; j < 3; j++) {
+                const int rho = perp[j];
+                if (rho == nu) continue;
+                StapleArgs b{U + (size_t)rho * fsz, T1, F, need7 ? T2 : nullptr, 0.0, c[2], 0.0, 0, mu, rho};
+                if ((e = launch_smear_staple(g, b, s)) != hipSuccess) return e;
+                if (!need7) continue;
+                const int sig = perp[0] + perp[1] + perp[2] - nu - rho;
+                StapleArgs t{U + (size_t)sig * fsz, T2, F, nullptr, 0.0, c[3], 0.0, 0, mu, sig};
+                if ((e = launch_smear_staple(g, t, s)) != hipSuccess) return e;
+            }
+        }
+    }
+    return hipSuccess;
+}
+
+size_t link_array_bytes(hisq_lattice lat) { return (size_t)lat->V * 4 * 18 * sizeof(double); }
+
+// Bring a [V][4][3][3] array onto the device: its own pointer with
+// HISQ_DEVICE_PTR, else a copy into `stage` (at least link_array_bytes).
+hisq_status stage_in(hisq_lattice lat, const double *src, int flags, double2 *stage, const double2 **dev)
+{
+    if (flags & HISQ_DEVICE_PTR) {
+        *dev = (const double2 *)src;
+        return HISQ_OK;
+    }
+    HIPCHK(lat, hipMemcpyAsync(stage, src, link_array_bytes(lat), hipMemcpyHostToDevice, lat->s));
+    *dev = stage;
+    return HISQ_OK;
+}
+
+hisq_status check_projection(hisq_lattice lat, const int *bad)
+{
+    int h = 0;
+    HIPCHK(lat, hipMemcpyAsync(&h, bad, sizeof h, hipMemcpyDeviceToHost, lat->s));
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    if (h) return set_err(lat, HISQ_ERR_BREAKDOWN, std::to_string(h) + " links have no U(3) projection (V^+ V singular or not finite)");
+    return HISQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hisq_status hisq_fat7(hisq_lattice lat, const double coef[5], const double *in, double *out, int flags)
+{
+    if (!lat || !coef || !in || !out) return set_err(lat, HISQ_ERR_ARG, "null argument");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    Work w;
+    hisq_status st = get_work(lat, 14, w);   // U 0-3, result 4-7, staging 8-11, T1 12, T2 13
+    if (st != HISQ_OK) return st;
+    const SmearGeom g = geom_of(lat);
+    const double2 *src;
+    if ((st = stage_in(lat, in, flags, w.field(8), &src)) != HISQ_OK) return st;
+    HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(13), coef, w.fsz, lat->s));
+    if (flags & HISQ_DEVICE_PTR) {
+        HIPCHK(lat, launch_smear_from_planar(g, w.field(4), (double2 *)out, lat->s));
+    } else {
+        HIPCHK(lat, launch_smear_from_planar(g, w.field(4), w.field(8), lat->s));
+        HIPCHK(lat, hipMemcpyAsync(out, w.field(8), link_array_bytes(lat), hipMemcpyDeviceToHost, lat->s));
+    }
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    return HISQ_OK;
+}
+
+hisq_status hisq_unitarize(hisq_lattice lat, const double *in, double *out, int flags)
+{
+    if (!lat || !in || !out) return set_err(lat, HISQ_ERR_ARG, "null argument");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    Work w;
+    hisq_status st = get_work(lat, 8, w);   // planar 0-3, staging 4-7
+    if (st != HISQ_OK) return st;
+    const SmearGeom g = geom_of(lat);
+    const double2 *src;
+    if ((st = stage_in(lat, in, flags, w.field(4), &src)) != HISQ_OK) return st;
+    HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
+    HIPCHK(lat, hipMemsetAsync(w.bad, 0, sizeof(int), lat->s));
+    HIPCHK(lat, launch_smear_unitarize(g, w.field(0), w.bad, lat->s));
+    if (flags & HISQ_DEVICE_PTR) {
+        HIPCHK(lat, launch_smear_from_planar(g, w.field(0), (double2 *)out, lat->s));
+    } else {
+        HIPCHK(lat, launch_smear_from_planar(g, w.field(0), w.field(4), lat->s));
+        HIPCHK(lat, hipMemcpyAsync(out, w.field(4), link_array_bytes(lat), hipMemcpyDeviceToHost, lat->s));
+    }
+    return check_projection(lat, w.bad);
+}
+
+hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, double *lng, int flags)
+{
+    const bool load = (flags & HISQ_LOAD_RESULT) != 0;
+    if (!lat || !thin || (!load && (!fat || !lng)) || (!fat != !lng))
+        return set_err(lat, HISQ_ERR_ARG, "null argument");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
+    // fields: thin U 0-3, level 1 / projected W 4-7, level 2 X 8-11 (also the
+    // host input staging), T1 12, T2 13, output staging 14-21 for host
+    // outputs that are not loaded
+    const bool stage_out = !dev && !load;
+    Work w;
+    hisq_status st = get_work(lat, stage_out ? 22 : 14, w);
+    if (st != HISQ_OK) return st;
+    const SmearGeom g = geom_of(lat);
+    const double2 *src;
+    if ((st = stage_in(lat, thin, flags, w.field(8), &src)) != HISQ_OK) return st;
+    HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(13), LV1, w.fsz, lat->s));
+    HIPCHK(lat, hipMemsetAsync(w.bad, 0, sizeof(int), lat->s));
+    HIPCHK(lat, launch_smear_unitarize(g, w.field(4), w.bad, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(4), w.field(8), w.field(12), w.field(13), LV2, w.fsz, lat->s));
+    double2 *of, *ol;
+    if (load) {
+        const size_t bytes = link_array_bytes(lat);
+        if (!lat->fat64) HIPCHK(lat, hipMalloc(&lat->fat64, bytes));
+        if (!lat->lng64) HIPCHK(lat, hipMalloc(&lat->lng64, bytes));
+        of = (double2 *)lat->fat64;
+        ol = (double2 *)lat->lng64;
+    } else if (dev) {
+        of = (double2 *)fat;
+        ol = (double2 *)lng;
+    } else {
+        of = w.field(14);
+        ol = w.field(18);
+    }
+    HIPCHK(lat, launch_smear_output(g, w.field(8), w.field(4), NAIK, of, ol, lat->s));
+    if ((st = check_projection(lat, w.bad)) != HISQ_OK) {
+        if (load) {   // the FP64 copies no longer match any packed set
+            for (auto &ls : lat->ls) ls = LinkSet();
+            lat->cg.release();
+            lat->loaded = false;
+        }
+        return st;
+    }
+    if (fat && (load || !dev)) {
+        const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        HIPCHK(lat, hipMemcpyAsync(fat, of, link_array_bytes(lat), k, lat->s));
+        HIPCHK(lat, hipMemcpyAsync(lng, ol, link_array_bytes(lat), k, lat->s));
+    }
+    if (load) return adopt_device_links(lat);
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    return HISQ_OK;
+}
+
+}  // extern "C"

@@ -6,6 +6,9 @@
 
 hisq_status set_err(hisq_lattice lat, hisq_status st, const std::string &msg);
 hisq_status hip_err(hisq_lattice lat, hipError_t e, const char *what);
+// Make the device FP64 copies lat->fat64 / lat->lng64 the lattice's links
+// (drops packed sets and solve workspaces, packs FP64 recon-18).
+hisq_status adopt_device_links(hisq_lattice lat);
 
 namespace hisq {
 

@@ -35,6 +35,7 @@ HISQ_EVEN, HISQ_ODD = 0, 1
 HISQ_DEVICE_PTR, HISQ_X_IS_GUESS, HISQ_USE_GRAPH, HISQ_NO_TUNE = 1, 2, 4, 8
 HISQ_STOP_STAGNATION = 16
 HISQ_STREAM_LINKS = 32
+HISQ_LOAD_RESULT = 64
 
 EXPORTS = [
     "hisq_default_params", "hisq_status_string", "hisq_last_error", "hisq_create", "hisq_destroy",
@@ -44,7 +45,7 @@ EXPORTS = [
     "hisq_ptc_harvest", "hisq_ptc_train", "hisq_cg_learned", "hisq_ptc_pair_count", "hisq_ptc_get_pair",
     "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss", "hisq_ptc_save", "hisq_ptc_load",
     "hisq_residual_history", "hisq_ptc_set_transport", "hisq_ptc_get_transport", "hisq_cg_noalloc",
-    "hisq_dslash_shape", "hisq_ptc_set_activations",
+    "hisq_dslash_shape", "hisq_ptc_set_activations", "hisq_smear_links", "hisq_fat7", "hisq_unitarize",
 ]
 
 
@@ -214,6 +215,48 @@ class Lattice:
                                        ctypes.byref(w), ctypes.byref(r), ctypes.byref(c)),
                self.handle, "hisq_dslash_shape")
         return w.value, r.value, c.value
+
+    def _link_out(self, like, dev):
+        if dev:
+            import torch
+            return torch.empty_like(like)
+        return np.empty((self.V, 4, 3, 3), dtype=np.complex128)
+
+    def smear_links(self, thin, load=False, outputs=True):
+        """hisq_smear_links: (fat, lng) HISQ links from thin links (numpy
+        [V][4][3][3] complex128, or a device tensor of the same bytes).  load:
+        the result also becomes this lattice's links; outputs=False (with
+        load) returns nothing."""
+        tp, tdev, k0 = _ptr(thin)
+        flags = (HISQ_DEVICE_PTR if tdev else 0) | (HISQ_LOAD_RESULT if load else 0)
+        if not outputs and not load:
+            raise ValueError("outputs=False needs load=True")
+        fat = self._link_out(thin, tdev) if outputs else None
+        lng = self._link_out(thin, tdev) if outputs else None
+        fp, _, k1 = _ptr(fat)
+        lp, _, k2 = _ptr(lng)
+        _check(lib().hisq_smear_links(self.handle, tp, fp, lp, ctypes.c_int(flags)), self.handle,
+               "hisq_smear_links")
+        return (fat, lng) if outputs else None
+
+    def fat7(self, coefs, links):
+        """hisq_fat7: one smearing level with (c1, c3, c5, c7, cLepage)."""
+        ip, idev, k0 = _ptr(links)
+        out = self._link_out(links, idev)
+        op, _, k1 = _ptr(out)
+        c = (ctypes.c_double * 5)(*[float(x) for x in coefs])
+        _check(lib().hisq_fat7(self.handle, c, ip, op, ctypes.c_int(HISQ_DEVICE_PTR if idev else 0)),
+               self.handle, "hisq_fat7")
+        return out
+
+    def unitarize(self, links):
+        """hisq_unitarize: U(3) polar factor of each of the 4 V links."""
+        ip, idev, k0 = _ptr(links)
+        out = self._link_out(links, idev)
+        op, _, k1 = _ptr(out)
+        _check(lib().hisq_unitarize(self.handle, ip, op, ctypes.c_int(HISQ_DEVICE_PTR if idev else 0)),
+               self.handle, "hisq_unitarize")
+        return out
 
     def cg(self, mass, b, x=None, params=None, raise_on_fail=True):
         """Solve (4m^2 - D_eo D_oe) x = b; returns (x, info dict)."""

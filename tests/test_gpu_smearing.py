@@ -1,0 +1,159 @@
+"""GPU parity of the HISQ link smearing (hisq_fat7, hisq_unitarize,
+hisq_smear_links) against the FP64 oracle, link by link.
+
+Bar: FP64, 1e-13 relative l2 over the links and 1e-12 per link (the
+per-link factor of tests/_parity.py).  Derived from the arithmetic: a link is
+a sum of 85 path products of at most seven 3x3 factors of norm about 1, each
+product rounded in about 20 operations at 2^-53, and the projection is
+well conditioned for these fields (the singular values of the level-1 sum
+lie near 1), so the accumulated rounding stays near 1e-15 and 1e-13 leaves
+two orders of margin while catching any wrong path (an O(1/384) change).
+
+At 32^4 the oracle cannot smear the whole lattice in seconds, so the input
+is an 8^4 random field tiled 4 times along each axis and then rotated by a
+random (not periodic) gauge transformation g: the smearing is gauge
+covariant and translation invariant, so the exact answer is g (tiled oracle
+links) g^+, compared on every link.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from _parity import check
+from paper_1712_00143_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-13
+
+
+def _hisq():
+    from paper_1712_00143_amd import hisq
+    return hisq
+
+
+def _links(a):
+    return np.asarray(a).reshape(-1, 9)
+
+
+def _dag(m):
+    return np.conj(np.swapaxes(m, -1, -2))
+
+
+@pytest.mark.parametrize("dims", [(6, 4, 6, 10), (2, 4, 2, 6), (4, 4, 4, 4)])
+def test_fat7_and_projection_stages(dims):
+    H = _hisq()
+    lat = H.Lattice(dims)
+    U = synth.thin_links(dims, 0.4, 60)
+    for seed in (61, 62):
+        c = tuple(np.random.default_rng(seed).uniform(-1.0, 1.0, 5))
+        check(_links(lat.fat7(c, U)), _links(oracle.fat7(dims, U, c)), TOL, ("fat7", dims, seed))
+    for lv in (oracle.HISQ_LEVEL1, oracle.HISQ_LEVEL2):
+        check(_links(lat.fat7(lv, U)), _links(oracle.fat7(dims, U, lv)), TOL, ("fat7 level", dims))
+    v = oracle.fat7(dims, U, oracle.HISQ_LEVEL1)
+    check(_links(lat.unitarize(v)), _links(oracle.unitarize(v)), TOL, ("unitarize", dims))
+    # general complex matrices (far from unitary): the closed form against Newton's iteration
+    A = (np.random.default_rng(63).standard_normal(U.shape)
+         + 1j * np.random.default_rng(64).standard_normal(U.shape))
+    check(_links(lat.unitarize(A)), _links(oracle.unitarize(A)), 1e-11, ("unitarize generic", dims))
+    lat.close()
+
+
+@pytest.mark.parametrize("dims", [(6, 4, 6, 10), (2, 4, 2, 6), (8, 8, 8, 8)])
+def test_smear_links_host_pointers(dims):
+    H = _hisq()
+    lat = H.Lattice(dims)
+    U = synth.thin_links(dims, 0.4, 70)
+    fat_ref, lng_ref = oracle.hisq_smear(dims, U)
+    fat, lng = lat.smear_links(U)
+    check(_links(fat), _links(fat_ref), TOL, ("fat", dims))
+    check(_links(lng), _links(lng_ref), TOL, ("long", dims))
+    # a second call on the same workspace gives the same bits
+    fat2, lng2 = lat.smear_links(U)
+    assert np.array_equal(fat, fat2) and np.array_equal(lng, lng2)
+    lat.close()
+
+
+def test_smear_links_device_pointers_and_free_field():
+    import torch
+    H = _hisq()
+    dims = (16, 16, 16, 32)
+    lat = H.Lattice(dims)
+    fb, _ = synth.unit_links(dims, phased=False)
+    t = torch.from_numpy(fb.view(np.float64).copy()).cuda()
+    fat, lng = lat.smear_links(t)
+    eta = synth.staggered_phases(dims)[:, :, None, None]
+    f = fat.cpu().numpy().view(np.complex128).reshape(fb.shape)
+    l = lng.cpu().numpy().view(np.complex128).reshape(fb.shape)
+    assert np.abs(f - 9 / 8 * eta * np.eye(3)).max() < 1e-14
+    assert np.abs(l + 1 / 24 * eta * np.eye(3)).max() < 1e-15
+    lat.close()
+
+
+def test_smear_links_32x32x32x32_tiled_and_gauge_rotated():
+    import torch
+    H = _hisq()
+    small, reps = (8, 8, 8, 8), (4, 4, 4, 4)
+    dims = (32, 32, 32, 32)
+    U8 = synth.thin_links(small, 0.4, 80)
+    fat8, lng8 = oracle.hisq_smear(small, U8)
+    g = synth.random_su3(synth.volume(dims), 81)
+    U = synth.gauge_transform(synth.tile_field(U8, small, reps), dims, g)
+    fat_ref = synth.gauge_transform(synth.tile_field(fat8, small, reps), dims, g)
+    lng_t = synth.tile_field(lng8, small, reps)
+    lng_ref = np.empty_like(lng_t)
+    for mu in range(4):
+        lng_ref[:, mu] = g @ lng_t[:, mu] @ _dag(synth._shift(g, dims, mu, 3))
+    del lng_t
+    lat = H.Lattice(dims)
+    t = torch.from_numpy(U.view(np.float64)).cuda()
+    del U
+    fat, lng = lat.smear_links(t)
+    check(_links(fat.cpu().numpy().view(np.complex128)), _links(fat_ref), TOL, "fat 32^4")
+    check(_links(lng.cpu().numpy().view(np.complex128)), _links(lng_ref), TOL, "long 32^4")
+    lat.close()
+
+
+def test_solvers_on_smeared_links():
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    U = synth.thin_links(dims, 0.4, 90)
+    fat_ref, lng_ref = oracle.hisq_smear(dims, U)
+    lat = H.Lattice(dims)
+    assert lat.smear_links(U, load=True, outputs=False) is None
+    b = synth.gaussian_even(dims, 91)
+    mass = 0.05
+    lat.prepare_links(1, 18)
+    for sloppy in (0, 1):
+        p = H.hisq_default_params(tol=1e-10, sloppy=sloppy, recon=18)
+        x, info = lat.cg(mass, b, params=p)
+        assert info["converged"]
+        # judged on the oracle's own smeared links
+        assert oracle.true_residual(dims, fat_ref, lng_ref, mass, b, x) <= 1.5e-10
+    # the Dslash on the loaded links
+    psi = synth.gaussian_even(dims, 92)
+    out = np.zeros_like(psi)
+    lat.dslash(0, 0, 18, psi, out)
+    check(out, oracle.dslash_half(dims, fat_ref, lng_ref, 0, psi), 1e-12, "dslash on smeared links")
+    # smeared fat links are not a scaled SU(3): recon-12 must refuse them
+    with pytest.raises(H.HisqError) as e:
+        lat.prepare_links(1, 12)
+    assert e.value.status == H.HISQ_ERR_RECON
+    lat.close()
+
+
+def test_singular_level_one_is_reported():
+    H = _hisq()
+    dims = (4, 4, 4, 4)
+    lat = H.Lattice(dims)
+    fb, lb = synth.unit_links(dims)
+    lat.load_links(fb, lb)
+    zero = np.zeros((synth.volume(dims), 4, 3, 3), dtype=np.complex128)
+    with pytest.raises(H.HisqError) as e:
+        lat.smear_links(zero, load=True, outputs=False)
+    assert e.value.status == H.HISQ_ERR_BREAKDOWN
+    # the lattice has no links any more
+    with pytest.raises(H.HisqError) as e:
+        lat.cg(0.1, synth.gaussian_even(dims, 1))
+    assert e.value.status == H.HISQ_ERR_STATE
+    lat.close()
