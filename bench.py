@@ -472,7 +472,57 @@ def run_headline(args):
         out["c2_multishift_24^3x48"] = c2_summary(args, oracle_sample=8)
     if not args.dslash_only and not args.no_c3:
         out["c3_batched_64_solves"] = c3_summary(args, oracle_sample=8)
+    if not args.dslash_only and not args.no_smear:
+        out["smear_32^4"] = smear_summary(args)
     print(json.dumps(out), flush=True)
+
+
+def smear_summary(args):
+    """HISQ link smearing at 32^4: thin links are a 16^4 random SU(3) field
+    (eps 0.4, plaquette about 0.65) repeated twice along each axis, so that
+    the oracle's smearing of the 16^4 field, repeated the same way, is the
+    exact answer for every link; a sample of links is compared."""
+    import torch
+    import oracle
+    from paper_1712_00143_amd import hisq as H
+    from paper_1712_00143_amd import synth
+    small, dims = (16, 16, 16, 16), (32, 32, 32, 32)
+    u16 = synth.thin_links(small, 0.4, 7000)
+    t0 = time.perf_counter()
+    fat_ref, lng_ref = oracle.hisq_smear(small, u16)
+    t_oracle = time.perf_counter() - t0
+    thin = torch.from_numpy(synth.tile_field(u16, small, (2, 2, 2, 2)).view(np.float64)).cuda()
+    lat = H.Lattice(dims)
+    fat = torch.empty_like(thin)
+    lng = torch.empty_like(thin)
+    lat.smear_links(thin)                      # workspace allocation
+    times = []
+    for _ in range(max(3, args.steps)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fat, lng = lat.smear_links(thin)       # synchronous
+        times.append(time.perf_counter() - t1)
+    t = float(np.median(times))
+    V = synth.volume(dims)
+    rng = np.random.default_rng(7001)
+    idx = rng.choice(V, 4096, replace=False)
+    c = synth.coords(dims)[idx] % 16
+    j = c[:, 0] + 16 * (c[:, 1] + 16 * (c[:, 2] + 16 * c[:, 3]))
+    sel = torch.from_numpy(idx).cuda()
+    f = fat.view(V, 4, 3, 6)[sel].cpu().numpy().view(np.complex128).reshape(-1, 4, 3, 3)
+    l = lng.view(V, 4, 3, 6)[sel].cpu().numpy().view(np.complex128).reshape(-1, 4, 3, 3)
+    err = max(float(np.abs(f - fat_ref[j]).max() / np.abs(fat_ref).max()),
+              float(np.abs(l - lng_ref[j]).max() / np.abs(lng_ref).max()))
+    lat.close()
+    return {"ms": round(t * 1e3, 3), "links_per_s": round(4 * V / t, 1),
+            "what": "hisq_smear_links on device arrays, 32^4: fat7 level 1, U(3) projection, fat7 level 2 "
+                    "with Lepage, Naik, phases; synchronous call, median of the timed calls",
+            "sample_max_rel_error_vs_oracle": float(f"{err:.3e}"), "sample_links": 4 * len(idx),
+            "oracle_s_16^4": round(t_oracle, 2)}
+
+
+def run_smear(args):
+    print(json.dumps({"smear_32^4": smear_summary(args)}), flush=True)
 
 
 def run_head_only(args, torch, H, latH, hH, stream, setup):
@@ -830,8 +880,9 @@ def main():
     ap.add_argument("--head-only", action="store_true", help="only the 32^4 headline launches (for profiling)")
     ap.add_argument("--no-c2", action="store_true", help="headline: skip the multi-shift summary")
     ap.add_argument("--no-c3", action="store_true", help="headline: skip the batched-solve summary")
+    ap.add_argument("--no-smear", action="store_true", help="headline: skip the link-smearing summary")
     ap.add_argument("--oracle-sample", type=int, default=8, help="c2/c3: solutions checked by the oracle")
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "copy"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "copy", "smear"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--dslash-only", action="store_true", help="time only the Dslash")
@@ -846,7 +897,7 @@ def main():
               "(the multi-GPU halo-exchange design is documented, not built)", file=sys.stderr)
         sys.exit(2)
     {"c0": run_c0, "c1": run_headline, "c2": run_c2, "c3": run_c3, "c4": run_c4,
-     "copy": run_copy}[args.workload](args)
+     "copy": run_copy, "smear": run_smear}[args.workload](args)
 
 
 if __name__ == "__main__":

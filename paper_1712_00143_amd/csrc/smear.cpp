@@ -2,11 +2,10 @@
 // entry points hisq_smear_links, hisq_fat7 and hisq_unitarize.
 //
 // fat7(U; c1, c3, c5, c7; cL) for output direction mu is built with staple
-// reuse: for each nu != mu the 3-staple field T1 = staple(U_mu, nu) is formed
-// once and every 5-staple through nu is a staple of T1 (T2 = staple(T1,
-// rho)), every 7-staple a staple of T2 through the one remaining direction.
-// 15 passes per direction instead of one kernel per path; each pass adds its
-// contribution to the accumulated output field in place.
+// reuse: the three 3-staple fields T1_nu are formed once, every 5-staple is
+// a staple of one of them and every 7-staple a staple of the 5-staples,
+// summed over the two orders of its transverse steps before the last
+// staple is taken (the staple is linear in the field it transports).
 #include <vector>
 
 #include "smear.h"
@@ -66,33 +65,40 @@ hisq_status get_work(hisq_lattice lat, int nf, Work &w)
     return HISQ_OK;
 }
 
-// out (4 planar fields) = fat7(U (4 planar fields)); T1, T2 one field each.
+// out (4 planar fields) = fat7(U (4 planar fields)); T1: three fields, T2:
+// one.  Per output direction: pass 1 (3-staples, Lepage, one-link term),
+// then for each sig != mu pass 2 (the 5-staples avoiding sig) and pass 3
+// (their c5 share and the 7-staples through sig): 7 passes instead of one
+// kernel per path class and pair.
 hipError_t run_fat7(const SmearGeom &g, const double2 *U, double2 *out, double2 *T1, double2 *T2,
                     const double c[5], size_t fsz, hipStream_t s)
 {
-    const bool need5 = c[2] != 0.0 || c[3] != 0.0, need7 = c[3] != 0.0;
+    const bool need5 = c[2] != 0.0 || c[3] != 0.0;
     for (int mu = 0; mu < 4; mu++) {
         int perp[3], np = 0;
         for (int d = 0; d < 4; d++)
             if (d != mu) perp[np++] = d;
         double2 *F = out + (size_t)mu * fsz;
-        const double2 *Umu = U + (size_t)mu * fsz;
-        for (int i = 0; i < 3; i++) {
-            const int nu = perp[i];
-            StapleArgs a{U + (size_t)nu * fsz, Umu, F, need5 ? T1 : nullptr, c[0], c[1], c[4], i == 0, mu, nu};
-            hipError_t e = launch_smear_staple(g, a, s);
+        Pass1Args p1{U, F, {nullptr, nullptr, nullptr}, c[0], c[1], c[4], mu, {perp[0], perp[1], perp[2]}, {}};
+        if (need5)
+            for (int k = 0; k < 3; k++) p1.T1[k] = T1 + (size_t)k * fsz;
+        smear_order(perp, 0, p1.ord);
+        hipError_t e = launch_smear_pass1(g, p1, s);
+        if (e != hipSuccess || !need5) {
             if (e != hipSuccess) return e;
-            if (!need5) continue;
-            for (int j = 0; j < 3; j++) {
-                const int rho = perp[j];
-                if (rho == nu) continue;
-                StapleArgs b{U + (size_t)rho * fsz, T1, F, need7 ? T2 : nullptr, 0.0, c[2], 0.0, 0, mu, rho};
-                if ((e = launch_smear_staple(g, b, s)) != hipSuccess) return e;
-                if (!need7) continue;
-                const int sig = perp[0] + perp[1] + perp[2] - nu - rho;
-                StapleArgs t{U + (size_t)sig * fsz, T2, F, nullptr, 0.0, c[3], 0.0, 0, mu, sig};
-                if ((e = launch_smear_staple(g, t, s)) != hipSuccess) return e;
-            }
+            continue;
+        }
+        for (int k = 0; k < 3; k++) {
+            const int sig = perp[k], inu = (k + 1) % 3, irho = (k + 2) % 3;
+            const int nu = perp[inu], rho = perp[irho];
+            Pass2Args p2{U, T1 + (size_t)inu * fsz, T1 + (size_t)irho * fsz, T2, mu, nu, rho, {}};
+            const int f2[3] = {nu, rho, mu};
+            smear_order(f2, 3, p2.ord);
+            if ((e = launch_smear_pass2(g, p2, s)) != hipSuccess) return e;
+            Pass3Args p3{U, T2, F, c[2], c[3], mu, sig, {}};
+            const int f3[2] = {sig, mu};
+            smear_order(f3, 2, p3.ord);
+            if ((e = launch_smear_pass3(g, p3, s)) != hipSuccess) return e;
         }
     }
     return hipSuccess;
@@ -131,13 +137,13 @@ hisq_status hisq_fat7(hisq_lattice lat, const double coef[5], const double *in, 
     if (!lat || !coef || !in || !out) return set_err(lat, HISQ_ERR_ARG, "null argument");
     HIPCHK(lat, hipSetDevice(lat->device));
     Work w;
-    hisq_status st = get_work(lat, 14, w);   // U 0-3, result 4-7, staging 8-11, T1 12, T2 13
+    hisq_status st = get_work(lat, 16, w);   // U 0-3, result 4-7, staging 8-11, T1 12-14, T2 15
     if (st != HISQ_OK) return st;
     const SmearGeom g = geom_of(lat);
     const double2 *src;
     if ((st = stage_in(lat, in, flags, w.field(8), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(13), coef, w.fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(15), coef, w.fsz, lat->s));
     if (flags & HISQ_DEVICE_PTR) {
         HIPCHK(lat, launch_smear_from_planar(g, w.field(4), (double2 *)out, lat->s));
     } else {
@@ -178,20 +184,20 @@ hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, 
     HIPCHK(lat, hipSetDevice(lat->device));
     const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
     // fields: thin U 0-3, level 1 / projected W 4-7, level 2 X 8-11 (also the
-    // host input staging), T1 12, T2 13, output staging 14-21 for host
+    // host input staging), T1 12-14, T2 15, output staging 16-23 for host
     // outputs that are not loaded
     const bool stage_out = !dev && !load;
     Work w;
-    hisq_status st = get_work(lat, stage_out ? 22 : 14, w);
+    hisq_status st = get_work(lat, stage_out ? 24 : 16, w);
     if (st != HISQ_OK) return st;
     const SmearGeom g = geom_of(lat);
     const double2 *src;
     if ((st = stage_in(lat, thin, flags, w.field(8), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(13), LV1, w.fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(15), LV1, w.fsz, lat->s));
     HIPCHK(lat, hipMemsetAsync(w.bad, 0, sizeof(int), lat->s));
     HIPCHK(lat, launch_smear_unitarize(g, w.field(4), w.bad, lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(4), w.field(8), w.field(12), w.field(13), LV2, w.fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(4), w.field(8), w.field(12), w.field(15), LV2, w.fsz, lat->s));
     double2 *of, *ol;
     if (load) {
         const size_t bytes = link_array_bytes(lat);
@@ -203,8 +209,8 @@ hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, 
         of = (double2 *)fat;
         ol = (double2 *)lng;
     } else {
-        of = w.field(14);
-        ol = w.field(18);
+        of = w.field(16);
+        ol = w.field(20);
     }
     HIPCHK(lat, launch_smear_output(g, w.field(8), w.field(4), NAIK, of, ol, lat->s));
     if ((st = check_projection(lat, w.bad)) != HISQ_OK) {

@@ -16,21 +16,50 @@ struct SmearGeom {
     int S[4];   // lex strides 1, L0, L0 L1, L0 L1 L2
 };
 
-// One staple pass for output direction mu through direction nu:
-//   T(x) = U_nu(x) M(x+nu) U_nu(x+mu)^+ + U_nu(x-nu)^+ M(x-nu) U_nu(x-nu+mu)
-//   F(x) = (init ? cM M(x) : F(x)) + cT T(x) [+ cL * the two-step (Lepage) staple]
-// T is stored when T_out is not null.  Un, M, F, T_out: one-direction planar fields.
-struct StapleArgs {
-    const double2 *Un;
-    const double2 *M;
+// fat7(U; c1, c3, c5, c7; cL) of output direction mu in three kinds of
+// pass over planar fields (U: the four-direction input):
+//   pass 1       F = c1 U_mu + sum over nu != mu of (c3 T1_nu + cL Lep_nu),
+//                T1_nu = U_nu(x) U_mu(x+nu) U_nu(x+mu)^+ + (the -nu staple)
+//                stored for passes 2 (Lep_nu: the two-step staple);
+//   pass 2 (sig) T2 = staple of T1_nu through rho + staple of T1_rho through
+//                nu, {nu, rho} the two directions other than mu and sig
+//                (all 5-link staples whose steps avoid sig);
+//   pass 3 (sig) F += c5 T2 + c7 (staple of T2 through sig) (the 7-link
+//                staples through sig).
+// ord: the site visiting order, an axis permutation with ord[0] = 0 (x
+// fastest); the directions a pass steps along come next.
+struct Pass1Args {
+    const double2 *U;
     double2 *F;
-    double2 *T_out;
-    double cM, cT, cL;
-    int init;
-    int mu, nu;
+    double2 *T1[3];   // null: not stored
+    double c1, c3, cL;
+    int mu;
+    int perp[3];
+    int ord[4];
+};
+struct Pass2Args {
+    const double2 *U;
+    const double2 *T1nu, *T1rho;
+    double2 *T2;
+    int mu, nu, rho;
+    int ord[4];
+};
+struct Pass3Args {
+    const double2 *U;
+    const double2 *T2;
+    double2 *F;
+    double c5, c7;
+    int mu, sig;
+    int ord[4];
 };
 
-hipError_t launch_smear_staple(const SmearGeom &g, const StapleArgs &a, hipStream_t s);
+hipError_t launch_smear_pass1(const SmearGeom &g, const Pass1Args &a, hipStream_t s);
+hipError_t launch_smear_pass2(const SmearGeom &g, const Pass2Args &a, hipStream_t s);
+hipError_t launch_smear_pass3(const SmearGeom &g, const Pass3Args &a, hipStream_t s);
+
+// Visiting order x, then the directions of `first` (in that order, skipping
+// x and repeats), then the rest.
+void smear_order(const int *first, int n, int ord[4]);
 
 // [V][4][3][3] complex (site-major) -> four-direction planar field.
 hipError_t launch_smear_to_planar(const SmearGeom &g, const double2 *aos, double2 *pl, hipStream_t s);

@@ -128,58 +128,133 @@ __device__ __forceinline__ int pick(const int v[4], int d)
     return d == 0 ? v[0] : d == 1 ? v[1] : d == 2 ? v[2] : v[3];
 }
 
-template <bool LEP, bool WT>
-__global__ void __launch_bounds__(256) k_smear_staple(SmearGeom g, StapleArgs a)
+// Sites are visited in the order of the axis permutation o (o[0] = 0, x
+// fastest, so that a wavefront's loads stay contiguous): the host puts the
+// directions a pass steps along right after x, so that a site's neighbours
+// along them are visited, and held in L2 / the Infinity Cache, soon after it.
+// Returns lex(x) for visit index i and the coordinates c[k] along o[k].
+__device__ __forceinline__ long long walk(unsigned i, const SmearGeom &g, const int o[4], int c[4])
 {
-    const long long s = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
-    if (s >= g.V) return;
+    const unsigned L0 = (unsigned)pick(g.L, o[0]), L1 = (unsigned)pick(g.L, o[1]), L2 = (unsigned)pick(g.L, o[2]);
+    c[0] = (int)(i % L0);
+    i /= L0;
+    c[1] = (int)(i % L1);
+    i /= L1;
+    c[2] = (int)(i % L2);
+    c[3] = (int)(i / L2);
+    return (long long)c[0] * pick(g.S, o[0]) + (long long)c[1] * pick(g.S, o[1]) + (long long)c[2] * pick(g.S, o[2]) +
+           (long long)c[3] * pick(g.S, o[3]);
+}
+
+__device__ __forceinline__ int coord(const int c[4], const int o[4], int d)
+{
+    return o[0] == d ? c[0] : o[1] == d ? c[1] : o[2] == d ? c[2] : c[3];
+}
+
+// One-step staple of field M through direction (S, L) at site y, whose
+// coordinates along that direction and along mu are yd and ym:
+// U(y) M(y+d) U(y+mu)^+ + U(y-d)^+ M(y-d) U(y-d+mu).
+__device__ __forceinline__ M3 staple_at(const double2 *__restrict__ U, const double2 *__restrict__ M, size_t V,
+                                        long long y, int yd, int S, int L, int ym, int Sm, int Lm)
+{
+    const long long pd = shift(y, yd, S, L, 1), md = shift(y, yd, S, L, -1);
+    const long long pm = shift(y, ym, Sm, Lm, 1), md_pm = shift(md, ym, Sm, Lm, 1);
+    M3 T = mul_na(mul_nn(ld(U, V, y), ld(M, V, pd)), ld(U, V, pm));
+    const M3 Q = mul_nn(mul_an(ld(U, V, md), ld(M, V, md)), ld(U, V, md_pm));
+#pragma unroll
+    for (int i = 0; i < 9; i++) T.e[i] = make_double2(T.e[i].x + Q.e[i].x, T.e[i].y + Q.e[i].y);
+    return T;
+}
+
+// Two-step (Lepage) staple of M through direction (S, L) at y:
+// U(y) U(y+d) M(y+2d) U(y+d+mu)^+ U(y+mu)^+ + U(y-d)^+ U(y-2d)^+ M(y-2d) U(y-2d+mu) U(y-d+mu).
+__device__ __forceinline__ M3 lepage_at(const double2 *__restrict__ U, const double2 *__restrict__ M, size_t V,
+                                        long long y, int yd, int S, int L, int ym, int Sm, int Lm)
+{
+    const long long pd = shift(y, yd, S, L, 1), md = shift(y, yd, S, L, -1);
+    const long long p2d = shift(y, yd, S, L, 2), m2d = shift(y, yd, S, L, -2);
+    const long long pm = shift(y, ym, Sm, Lm, 1), pd_pm = shift(pd, ym, Sm, Lm, 1);
+    const long long md_pm = shift(md, ym, Sm, Lm, 1), m2d_pm = shift(m2d, ym, Sm, Lm, 1);
+    M3 P = mul_nn(ld(U, V, y), ld(U, V, pd));
+    P = mul_nn(P, ld(M, V, p2d));
+    P = mul_na(P, ld(U, V, pd_pm));
+    M3 T = mul_na(P, ld(U, V, pm));
+    P = mul_nn(ld(U, V, m2d), ld(U, V, md));
+    P = mul_an(P, ld(M, V, m2d));
+    P = mul_nn(P, ld(U, V, m2d_pm));
+    const M3 Q = mul_nn(P, ld(U, V, md_pm));
+#pragma unroll
+    for (int i = 0; i < 9; i++) T.e[i] = make_double2(T.e[i].x + Q.e[i].x, T.e[i].y + Q.e[i].y);
+    return T;
+}
+
+// Pass 1 of output direction mu: the 3-link staples through all three nu
+// != mu, stored as T1[i] when WT, and
+//   F = c1 U_mu + sum_nu (c3 T1_nu + cL Lepage_nu).
+template <bool LEP, bool WT>
+__global__ void __launch_bounds__(256) k_smear_pass1(SmearGeom g, Pass1Args a)
+{
+    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
+    if (vi >= g.V) return;
     const size_t V = (size_t)g.V;
-    const int Sm = pick(g.S, a.mu), Lm = pick(g.L, a.mu), Sn = pick(g.S, a.nu), Ln = pick(g.L, a.nu);
-    const unsigned su = (unsigned)s;   // V <= 2^31
-    const int xm = (int)((su / (unsigned)Sm) % (unsigned)Lm), xn = (int)((su / (unsigned)Sn) % (unsigned)Ln);
-    const long long pn = shift(s, xn, Sn, Ln, 1), mn = shift(s, xn, Sn, Ln, -1);
-    const long long pm = shift(s, xm, Sm, Lm, 1), mn_pm = shift(mn, xm, Sm, Lm, 1);
-    M3 T;
-    {
-        const M3 P = mul_nn(ld(a.Un, V, s), ld(a.M, V, pn));
-        T = mul_na(P, ld(a.Un, V, pm));
-    }
-    {
-        const M3 P = mul_an(ld(a.Un, V, mn), ld(a.M, V, mn));
-        const M3 Q = mul_nn(P, ld(a.Un, V, mn_pm));
+    int c[4];
+    const long long s = walk((unsigned)vi, g, a.ord, c);   // V <= 2^31
+    const int mu = a.mu;
+    const int Sm = pick(g.S, mu), Lm = pick(g.L, mu), xm = coord(c, a.ord, mu);
+    const double2 *Umu = a.U + (size_t)mu * 9 * V;
+    M3 F = ld(Umu, V, s);
 #pragma unroll
-        for (int i = 0; i < 9; i++) T.e[i] = make_double2(T.e[i].x + Q.e[i].x, T.e[i].y + Q.e[i].y);
-    }
-    M3 F;
-    if (a.init) {
-        F = ld(a.M, V, s);
-#pragma unroll
-        for (int i = 0; i < 9; i++) F.e[i] = make_double2(a.cM * F.e[i].x, a.cM * F.e[i].y);
-    } else {
-        F = ld(a.F, V, s);
-    }
-    axpy(F, a.cT, T);
-    if constexpr (LEP) {
-        // two steps out along nu, across mu, two steps back
-        const long long p2n = shift(s, xn, Sn, Ln, 2), m2n = shift(s, xn, Sn, Ln, -2);
-        const long long pn_pm = shift(pn, xm, Sm, Lm, 1), m2n_pm = shift(m2n, xm, Sm, Lm, 1);
-        {
-            M3 P = mul_nn(ld(a.Un, V, s), ld(a.Un, V, pn));
-            P = mul_nn(P, ld(a.M, V, p2n));
-            P = mul_na(P, ld(a.Un, V, pn_pm));
-            P = mul_na(P, ld(a.Un, V, pm));
-            axpy(F, a.cL, P);
-        }
-        {
-            M3 P = mul_nn(ld(a.Un, V, m2n), ld(a.Un, V, mn));
-            P = mul_an(P, ld(a.M, V, m2n));
-            P = mul_nn(P, ld(a.Un, V, m2n_pm));
-            P = mul_nn(P, ld(a.Un, V, mn_pm));
-            axpy(F, a.cL, P);
-        }
+    for (int i = 0; i < 9; i++) F.e[i] = make_double2(a.c1 * F.e[i].x, a.c1 * F.e[i].y);
+    // one direction at a time: unrolled, the three staples' loads are all
+    // hoisted and spill
+#pragma unroll 1
+    for (int k = 0; k < 3; k++) {
+        const int nu = a.perp[k];
+        const int Sn = pick(g.S, nu), Ln = pick(g.L, nu), xn = coord(c, a.ord, nu);
+        const double2 *Un = a.U + (size_t)nu * 9 * V;
+        const M3 T = staple_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm);
+        axpy(F, a.c3, T);
+        if constexpr (WT) st(k == 0 ? a.T1[0] : k == 1 ? a.T1[1] : a.T1[2], V, s, T);
+        if constexpr (LEP) axpy(F, a.cL, lepage_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm));
     }
     st(a.F, V, s, F);
-    if constexpr (WT) st(a.T_out, V, s, T);
+}
+
+// Pass 2 of (mu, sig): the 5-link staples whose transverse steps are the two
+// directions nu, rho other than mu and sig, in both orders:
+//   T2 = staple(T1_nu through rho) + staple(T1_rho through nu).
+__global__ void __launch_bounds__(256) k_smear_pass2(SmearGeom g, Pass2Args a)
+{
+    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
+    if (vi >= g.V) return;
+    const size_t V = (size_t)g.V;
+    int c[4];
+    const long long s = walk((unsigned)vi, g, a.ord, c);
+    const int Sm = pick(g.S, a.mu), Lm = pick(g.L, a.mu), xm = coord(c, a.ord, a.mu);
+    const int Sn = pick(g.S, a.nu), Ln = pick(g.L, a.nu), xn = coord(c, a.ord, a.nu);
+    const int Sr = pick(g.S, a.rho), Lr = pick(g.L, a.rho), xr = coord(c, a.ord, a.rho);
+    M3 T = staple_at(a.U + (size_t)a.rho * 9 * V, a.T1nu, V, s, xr, Sr, Lr, xm, Sm, Lm);
+    const M3 Q = staple_at(a.U + (size_t)a.nu * 9 * V, a.T1rho, V, s, xn, Sn, Ln, xm, Sm, Lm);
+#pragma unroll
+    for (int i = 0; i < 9; i++) T.e[i] = make_double2(T.e[i].x + Q.e[i].x, T.e[i].y + Q.e[i].y);
+    st(a.T2, V, s, T);
+}
+
+// Pass 3 of (mu, sig): F += c5 T2 + c7 staple(T2 through sig), the
+// 7-link staples being the staples of the 5-link ones.
+__global__ void __launch_bounds__(256) k_smear_pass3(SmearGeom g, Pass3Args a)
+{
+    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
+    if (vi >= g.V) return;
+    const size_t V = (size_t)g.V;
+    int c[4];
+    const long long s = walk((unsigned)vi, g, a.ord, c);
+    const int Sm = pick(g.S, a.mu), Lm = pick(g.L, a.mu), xm = coord(c, a.ord, a.mu);
+    const int Ss = pick(g.S, a.sig), Ls = pick(g.L, a.sig), xs = coord(c, a.ord, a.sig);
+    M3 F = ld(a.F, V, s);
+    axpy(F, a.c5, ld(a.T2, V, s));
+    axpy(F, a.c7, staple_at(a.U + (size_t)a.sig * 9 * V, a.T2, V, s, xs, Ss, Ls, xm, Sm, Lm));
+    st(a.F, V, s, F);
 }
 
 // Blocks of 64 sites x 4 directions; the [64][4][9] slab of the site-major
@@ -302,14 +377,40 @@ __global__ void __launch_bounds__(256) k_smear_unitarize(SmearGeom g, double2 *_
 
 }  // namespace
 
-hipError_t launch_smear_staple(const SmearGeom &g, const StapleArgs &a, hipStream_t s)
+void smear_order(const int *first, int n, int ord[4])
+{
+    bool used[4] = {true, false, false, false};
+    int k = 0;
+    ord[k++] = 0;
+    for (int i = 0; i < n; i++)
+        if (first[i] > 0 && first[i] < 4 && !used[first[i]]) {
+            used[first[i]] = true;
+            ord[k++] = first[i];
+        }
+    for (int d = 1; d < 4; d++)
+        if (!used[d]) ord[k++] = d;
+}
+
+hipError_t launch_smear_pass1(const SmearGeom &g, const Pass1Args &a, hipStream_t s)
 {
     const dim3 grid((unsigned)((g.V + 255) / 256)), blk(256);
-    const bool lep = a.cL != 0.0, wt = a.T_out != nullptr;
-    if (lep && wt) hipLaunchKernelGGL((k_smear_staple<true, true>), grid, blk, 0, s, g, a);
-    else if (lep) hipLaunchKernelGGL((k_smear_staple<true, false>), grid, blk, 0, s, g, a);
-    else if (wt) hipLaunchKernelGGL((k_smear_staple<false, true>), grid, blk, 0, s, g, a);
-    else hipLaunchKernelGGL((k_smear_staple<false, false>), grid, blk, 0, s, g, a);
+    const bool lep = a.cL != 0.0, wt = a.T1[0] != nullptr;
+    if (lep && wt) hipLaunchKernelGGL((k_smear_pass1<true, true>), grid, blk, 0, s, g, a);
+    else if (lep) hipLaunchKernelGGL((k_smear_pass1<true, false>), grid, blk, 0, s, g, a);
+    else if (wt) hipLaunchKernelGGL((k_smear_pass1<false, true>), grid, blk, 0, s, g, a);
+    else hipLaunchKernelGGL((k_smear_pass1<false, false>), grid, blk, 0, s, g, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_smear_pass2(const SmearGeom &g, const Pass2Args &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_smear_pass2, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, s, g, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_smear_pass3(const SmearGeom &g, const Pass3Args &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_smear_pass3, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, s, g, a);
     return hipGetLastError();
 }
 
