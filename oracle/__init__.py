@@ -364,3 +364,30 @@ def hisq_smear(dims, thin):
     if bad:
         raise ArithmeticError(f"polar iteration did not converge for {bad} links")
     return fat, lng
+
+
+# --------------------------------------------------------------- gauge force
+
+def gauge_force(dims, links, beta, coefs):
+    """Symanzik gauge force F [V][4][3][3] (traceless anti-Hermitian) of thin
+    links; coefs = (plaquette, rectangle, parallelogram) weights."""
+    lib = _load()
+    u, up = _c(links)
+    c = (ctypes.c_double * 3)(*[float(x) for x in coefs])
+    out = np.empty_like(u)
+    lib.orc_gauge_force.restype = ctypes.c_int
+    if lib.orc_gauge_force(_dims(dims), up, ctypes.c_double(beta), c, out.ctypes.data_as(ctypes.c_void_p)):
+        raise ValueError("the gauge force needs every extent >= 4")
+    return out
+
+
+def gauge_action(dims, links, beta, coefs):
+    """S = beta sum_loops c (1 - Re Tr U_loop / 3)."""
+    lib = _load()
+    u, up = _c(links)
+    c = (ctypes.c_double * 3)(*[float(x) for x in coefs])
+    lib.orc_gauge_action.restype = ctypes.c_double
+    s = lib.orc_gauge_action(_dims(dims), up, ctypes.c_double(beta), c)
+    if np.isnan(s):
+        raise ValueError("the gauge action needs every extent >= 4")
+    return float(s)

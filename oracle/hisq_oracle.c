@@ -29,6 +29,8 @@
  *   smearing  HISQ fat and long links from thin links: two fat7 levels
  *             with a U(3) polar projection between, Lepage and Naik terms
  *             at the second (stated with the code below).
+ *   gauge     Symanzik-improved (plaquette, rectangle, parallelogram)
+ *   force     gauge action and its force (stated with the code below).
  *
  * Complex numbers are C99 double complex; fields are site-major:
  *   links   [V][4][3][3]          (row-major 3x3)
@@ -674,4 +676,124 @@ int orc_hisq_smear(const int d[4], const cplx *thin, cplx *fat, cplx *lng)
     free(Vf);
     free(W);
     return bad;
+}
+
+/* --------------------------------------------------------- gauge force
+ *
+ * Symanzik-improved gauge action and its force (the gauge-field part of the
+ * HISQ RHMC step, Section 4.2).  The paper does not write the action out;
+ * it is the Luescher-Weisz action, a sum over three loop shapes:
+ *
+ *   S = beta sum over loops L of c_L (1 - Re Tr U_L / 3)
+ *
+ * with c_L = c[0] for the 1x1 plaquettes, c[1] for the 1x2 and 2x1
+ * rectangles and c[2] for the six-link parallelograms (mu, a, b, -mu, -a,
+ * -b: three orthogonal signed steps and back), each loop counted once.
+ *
+ * The force on the link U_mu(x) is
+ *   F_mu(x) = (beta/3) TA[ U_mu(x) A_mu(x) ],   TA(M) = (M - M^+)/2 - Tr(M - M^+)/6,
+ * A_mu(x) = sum over the loops through the link of c_L times the product of
+ * the loop's other links, from x+mu back to x.  For U_mu(x) -> exp(eps X)
+ * U_mu(x) with X traceless anti-Hermitian, dS/deps = -Re Tr(X F_mu(x)).
+ * The loops through (x, mu), written as the steps after the first (+mu):
+ *   plaquette     (s nu, -mu, -s nu)                          6
+ *   rectangle     (s nu, s nu, -mu, -s nu, -s nu)             6
+ *                 (mu, s nu, -mu, -mu, -s nu)                 6
+ *                 (s nu, -mu, -mu, -s nu, mu)                 6
+ *   parallelogram (a, b, -mu, -a, -b)                        24
+ * (nu != mu, s = +-1; a, b signed steps along two distinct axes other
+ * than mu).  Every loop through the link appears exactly once when all
+ * extents are >= 4, which the functions below require.
+ */
+
+static int gf_rest(int mu, int cls, int k, int *st)
+{
+    /* the k-th loop of class cls through (x, mu): writes its steps after the
+     * first and returns their number, or 0 past the end of the class */
+    const int M = mu + 1;
+    int ax[3], na = 0;
+    for (int d = 0; d < 4; d++)
+        if (d != mu) ax[na++] = d + 1;
+    if (cls == 0) {
+        if (k >= 6) return 0;
+        const int N = (k & 1 ? -1 : 1) * ax[k >> 1];
+        st[0] = N; st[1] = -M; st[2] = -N;
+        return 3;
+    }
+    if (cls == 1) {
+        if (k >= 18) return 0;
+        const int N = (k & 1 ? -1 : 1) * ax[(k >> 1) % 3], shape = k / 6;
+        if (shape == 0) { st[0] = N; st[1] = N; st[2] = -M; st[3] = -N; st[4] = -N; }
+        else if (shape == 1) { st[0] = M; st[1] = N; st[2] = -M; st[3] = -M; st[4] = -N; }
+        else { st[0] = N; st[1] = -M; st[2] = -M; st[3] = -N; st[4] = M; }
+        return 5;
+    }
+    if (k >= 24) return 0;
+    /* ordered pair of distinct transverse axes (6) x signs (4) */
+    const int pair = k >> 2, sa = (k & 1) ? -1 : 1, sb = (k & 2) ? -1 : 1;
+    const int ia = pair >> 1, ib = (ia + 1 + (pair & 1)) % 3;
+    const int A = sa * ax[ia], B = sb * ax[ib];
+    st[0] = A; st[1] = B; st[2] = -M; st[3] = -A; st[4] = -B;
+    return 5;
+}
+
+static int gf_extents_ok(const int d[4])
+{
+    return d[0] >= 4 && d[1] >= 4 && d[2] >= 4 && d[3] >= 4;
+}
+
+/* A_mu(x) for class weights w[3] */
+static void gf_staple_sum(const int d[4], const cplx *U, long s, int mu, const double w[3], cplx *A)
+{
+    for (int i = 0; i < 9; i++) A[i] = 0;
+    const long s1 = hop(d, s, mu, 1);
+    int st[5];
+    for (int cls = 0; cls < 3; cls++) {
+        if (w[cls] == 0.0) continue;
+        int n;
+        for (int k = 0; (n = gf_rest(mu, cls, k, st)) > 0; k++) acc_path(d, U, s1, st, n, w[cls], A);
+    }
+}
+
+/* F: [V][4][3][3] traceless anti-Hermitian.  Returns 1 (F untouched) if an
+ * extent is below 4. */
+int orc_gauge_force(const int d[4], const cplx *U, double beta, const double c[3], cplx *F)
+{
+    if (!gf_extents_ok(d)) return 1;
+    const long V = vol(d);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++)
+        for (int mu = 0; mu < 4; mu++) {
+            cplx A[9], M[9];
+            gf_staple_sum(d, U, s, mu, c, A);
+            mm(M, link(U, s, mu), A);
+            cplx tr = 0;
+            for (int i = 0; i < 3; i++) tr += M[4 * i] - conj(M[4 * i]);
+            cplx *f = F + (s * 4 + mu) * 9;
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++)
+                    f[3 * i + j] = (beta / 3.0) * (0.5 * (M[3 * i + j] - conj(M[3 * j + i])) - (i == j ? tr / 6.0 : 0.0));
+        }
+    return 0;
+}
+
+/* S (the definition above): every loop is met once per link it contains,
+ * so summing Re Tr U_mu(x) A_mu(x) with the class weights divided by the
+ * loop lengths (4, 6, 6) counts each loop once; there are 6, 12 and 16
+ * loops of the three classes per site.  Returns NaN if an extent is below 4. */
+double orc_gauge_action(const int d[4], const cplx *U, double beta, const double c[3])
+{
+    if (!gf_extents_ok(d)) return NAN;
+    const long V = vol(d);
+    const double w[3] = {c[0] / 4.0, c[1] / 6.0, c[2] / 6.0};
+    double re = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : re)
+    for (long s = 0; s < V; s++)
+        for (int mu = 0; mu < 4; mu++) {
+            cplx A[9], M[9];
+            gf_staple_sum(d, U, s, mu, w, A);
+            mm(M, link(U, s, mu), A);
+            re += creal(M[0] + M[4] + M[8]);
+        }
+    return beta * ((double)V * (6.0 * c[0] + 12.0 * c[1] + 16.0 * c[2]) - re / 3.0);
 }
