@@ -474,6 +474,7 @@ def run_headline(args):
         out["c3_batched_64_solves"] = c3_summary(args, oracle_sample=8)
     if not args.dslash_only and not args.no_smear:
         out["smear_32^4"] = smear_summary(args)
+        out["gauge_force_32^4"] = gforce_summary(args)
     print(json.dumps(out), flush=True)
 
 
@@ -523,6 +524,67 @@ def smear_summary(args):
 
 def run_smear(args):
     print(json.dumps({"smear_32^4": smear_summary(args)}), flush=True)
+
+
+GF_FLOP_PER_LINK = 145 * 198 + 60   # 3x3 complex products per link (see gforce.hip) and the projection
+
+
+def one_loop_coefs(u0):
+    """Tadpole-improved one-loop Luescher-Weisz weights (plaquette,
+    rectangle, parallelogram) for the mean link u0."""
+    a_s = -4.0 * math.log(u0) / 3.0684
+    return (1.0, -(1.0 + 0.4805 * a_s) / (20.0 * u0 * u0), -0.03325 * a_s / (u0 * u0))
+
+
+def gforce_summary(args):
+    """Symanzik gauge force and action at 32^4 on a 16^4 random field
+    (eps 0.5) repeated twice per axis; a sample of force links and the
+    action (16 times the 16^4 value) are compared with the oracle."""
+    import torch
+    import oracle
+    from paper_1712_00143_amd import hisq as H
+    from paper_1712_00143_amd import synth
+    small, dims = (16, 16, 16, 16), (32, 32, 32, 32)
+    u16 = synth.thin_links(small, 0.5, 7100)
+    # tadpole factor u0 = (mean plaquette)^(1/4), the plaquette from the
+    # plaquette-only action: S = sum over the 6 V plaquettes of 1 - Re Tr / 3
+    plaq = 1.0 - oracle.gauge_action(small, u16, 1.0, (1.0, 0.0, 0.0)) / (6 * synth.volume(small))
+    beta, coefs = 6.0, one_loop_coefs(plaq ** 0.25)
+    t0 = time.perf_counter()
+    f_ref = oracle.gauge_force(small, u16, beta, coefs)
+    t_oracle = time.perf_counter() - t0
+    s_ref = 16 * oracle.gauge_action(small, u16, beta, coefs)
+    thin = torch.from_numpy(synth.tile_field(u16, small, (2, 2, 2, 2)).view(np.float64)).cuda()
+    lat = H.Lattice(dims)
+    F = lat.gauge_force(thin, beta, coefs)
+    times = []
+    for _ in range(max(3, args.steps)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        F = lat.gauge_force(thin, beta, coefs)
+        times.append(time.perf_counter() - t1)
+    t = float(np.median(times))
+    S = lat.gauge_action(thin, beta, coefs)
+    V = synth.volume(dims)
+    idx = np.random.default_rng(7101).choice(V, 4096, replace=False)
+    c = synth.coords(dims)[idx] % 16
+    j = c[:, 0] + 16 * (c[:, 1] + 16 * (c[:, 2] + 16 * c[:, 3]))
+    f = F.view(V, 4, 3, 6)[torch.from_numpy(idx).cuda()].cpu().numpy().view(np.complex128).reshape(-1, 4, 3, 3)
+    err = float(np.abs(f - f_ref[j]).max() / np.abs(f_ref).max())
+    lat.close()
+    gflops = 4 * V * GF_FLOP_PER_LINK / t / 1e9
+    return {"ms": round(t * 1e3, 3), "GFLOP/s": round(gflops, 1), "frac_fp64_peak": round(gflops / 78600.0, 4),
+            "flop_per_link": GF_FLOP_PER_LINK, "beta": beta, "plaquette": round(plaq, 5),
+            "coefs": [round(x, 6) for x in coefs],
+            "what": "hisq_gauge_force on device arrays, 32^4 (plaquette, rectangle and parallelogram loops); "
+                    "synchronous call incl. the layout conversions, median of the timed calls",
+            "sample_max_rel_error_vs_oracle": float(f"{err:.3e}"), "sample_links": 4 * len(idx),
+            "action_rel_error_vs_oracle": float(f"{abs(S - s_ref) / abs(s_ref):.3e}"),
+            "oracle_s_16^4": round(t_oracle, 2)}
+
+
+def run_gforce(args):
+    print(json.dumps({"gauge_force_32^4": gforce_summary(args)}), flush=True)
 
 
 def run_head_only(args, torch, H, latH, hH, stream, setup):
@@ -880,9 +942,9 @@ def main():
     ap.add_argument("--head-only", action="store_true", help="only the 32^4 headline launches (for profiling)")
     ap.add_argument("--no-c2", action="store_true", help="headline: skip the multi-shift summary")
     ap.add_argument("--no-c3", action="store_true", help="headline: skip the batched-solve summary")
-    ap.add_argument("--no-smear", action="store_true", help="headline: skip the link-smearing summary")
+    ap.add_argument("--no-smear", action="store_true", help="headline: skip the smearing and gauge-force summaries")
     ap.add_argument("--oracle-sample", type=int, default=8, help="c2/c3: solutions checked by the oracle")
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "copy", "smear"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "copy", "smear", "gforce"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--dslash-only", action="store_true", help="time only the Dslash")
@@ -897,7 +959,7 @@ def main():
               "(the multi-GPU halo-exchange design is documented, not built)", file=sys.stderr)
         sys.exit(2)
     {"c0": run_c0, "c1": run_headline, "c2": run_c2, "c3": run_c3, "c4": run_c4,
-     "copy": run_copy, "smear": run_smear}[args.workload](args)
+     "copy": run_copy, "smear": run_smear, "gforce": run_gforce}[args.workload](args)
 
 
 if __name__ == "__main__":

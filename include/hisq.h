@@ -398,6 +398,33 @@ hisq_status hisq_fat7(hisq_lattice lat, const double coef[5], const double *in, 
  * still written, non-finite there). */
 hisq_status hisq_unitarize(hisq_lattice lat, const double *in, double *out, int flags);
 
+/* ---- gauge force ----
+ *
+ * The Symanzik-improved gauge action and force, the gauge-field part of the
+ * RHMC molecular-dynamics step (the paper's second benchmark, Section 4.2):
+ *   S = beta sum over loops L of c_L (1 - Re Tr U_L / 3)
+ * over the 1x1 plaquettes (c_L = coef[0]), the 1x2 and 2x1 rectangles
+ * (coef[1]) and the six-link parallelograms mu, a, b, -mu, -a, -b around 3-cubes
+ * (coef[2]), each loop once.  (The tadpole-improved one-loop choice is
+ * coef = {1, -(1 + 0.4805 alpha_s) / (20 u0^2), -0.03325 alpha_s / u0^2}.)
+ * Thin links U in the link layout above, no phases; host pointers or, with
+ * HISQ_DEVICE_PTR, device pointers.  FP64, synchronous; every extent must be
+ * >= 4 (HISQ_ERR_ARG otherwise; on smaller extents loops wrap onto
+ * themselves).
+ *
+ * hisq_gauge_force: F_mu(x) = (beta/3) TA[U_mu(x) A_mu(x)], the traceless
+ * anti-Hermitian part TA(M) = (M - M^+)/2 - Tr(M - M^+)/6, A_mu(x) the sum
+ * over the loops through the link of c_L times the product of its other
+ * links from x+mu back to x; so that U_mu(x) -> exp(eps X) U_mu(x) (X in
+ * su(3)) changes S at the rate -Re Tr(X F_mu(x)).  F: [V][4][3][3]. */
+hisq_status hisq_gauge_force(hisq_lattice lat, const double *U, double beta, const double coef[3], double *F,
+                             int flags);
+
+/* hisq_gauge_action: *S (a host double) as defined above; the site sums
+ * are reduced in a fixed order (the same bits on every call). */
+hisq_status hisq_gauge_action(hisq_lattice lat, const double *U, double beta, const double coef[3], double *S,
+                              int flags);
+
 /* ---- measurement ----
  *
  * Practical HBM ceilings of `device`, measured on `stream` (NULL: the null

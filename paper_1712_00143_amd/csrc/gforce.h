@@ -1,0 +1,25 @@
+// Launcher of the Symanzik gauge force / action kernel (FP64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "smear.h"
+
+namespace hisq {
+
+// U: four-direction planar thin links (see smear.h).  mode 0: F (four
+// planar fields) = scale * TA[U_mu(x) B_mu(x)^+], B the sum of the loop-
+// closing paths from x to x+mu weighted cp (plaquettes), cr (rectangles),
+// cg (parallelograms).  mode 1: part[mu * nblk + blk] = sum over the block's
+// links of Re Tr U_mu(x) B_mu(x)^+ (nblk = ceil(V / 256)).  Every extent
+// must be >= 4.
+struct GForceArgs {
+    const double2 *U;
+    double2 *F;
+    double *part;
+    double cp, cr, cg;
+    double scale;
+};
+
+hipError_t launch_gauge_force(const SmearGeom &g, const GForceArgs &a, int mode, hipStream_t s);
+
+}  // namespace hisq

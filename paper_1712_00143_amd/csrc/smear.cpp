@@ -1,5 +1,6 @@
-// HISQ link smearing: host orchestration of the staple passes and the C-ABI
-// entry points hisq_smear_links, hisq_fat7 and hisq_unitarize.
+// HISQ link smearing and the Symanzik gauge force: host orchestration of
+// the link kernels and the C-ABI entry points hisq_smear_links, hisq_fat7,
+// hisq_unitarize, hisq_gauge_force and hisq_gauge_action.
 //
 // fat7(U; c1, c3, c5, c7; cL) for output direction mu is built with staple
 // reuse: the three 3-staple fields T1_nu are formed once, every 5-staple is
@@ -8,6 +9,7 @@
 // staple is taken (the staple is linear in the field it transports).
 #include <vector>
 
+#include "gforce.h"
 #include "smear.h"
 #include "solver.h"
 
@@ -37,19 +39,20 @@ SmearGeom geom_of(hisq_lattice lat)
     return g;
 }
 
-// Workspace: nf one-direction planar fields (9 V double2 each) and a
-// 256-byte tail for the projection's failure counter.
+// Workspace: nf one-direction planar fields (9 V double2 each), a 256-byte
+// slot for the projection's failure counter and `extra` bytes of partials.
 struct Work {
     double2 *f = nullptr;   // field k at f + k * 9 V
     int *bad = nullptr;
+    double *part = nullptr;
     size_t fsz = 0;         // double2 per field
     double2 *field(int k) const { return f + (size_t)k * fsz; }
 };
 
-hisq_status get_work(hisq_lattice lat, int nf, Work &w)
+hisq_status get_work(hisq_lattice lat, int nf, Work &w, size_t extra = 0)
 {
     w.fsz = (size_t)9 * lat->V;
-    const size_t need = (size_t)nf * w.fsz * sizeof(double2) + 256;
+    const size_t need = (size_t)nf * w.fsz * sizeof(double2) + 256 + extra;
     if (lat->smear_ws_bytes < need) {
         if (lat->smear_ws) {
             HIPCHK(lat, hipStreamSynchronize(lat->s));
@@ -62,6 +65,7 @@ hisq_status get_work(hisq_lattice lat, int nf, Work &w)
     }
     w.f = (double2 *)lat->smear_ws;
     w.bad = (int *)((char *)lat->smear_ws + (size_t)nf * w.fsz * sizeof(double2));
+    w.part = (double *)((char *)w.bad + 256);
     return HISQ_OK;
 }
 
@@ -228,6 +232,64 @@ hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, 
     }
     if (load) return adopt_device_links(lat);
     HIPCHK(lat, hipStreamSynchronize(lat->s));
+    return HISQ_OK;
+}
+
+static hisq_status gauge_args(hisq_lattice lat, const double *U, const double coef[3], const void *out)
+{
+    if (!lat || !U || !coef || !out) return set_err(lat, HISQ_ERR_ARG, "null argument");
+    for (int k = 0; k < 4; k++)
+        if (lat->L[k] < 4) return set_err(lat, HISQ_ERR_ARG, "the gauge force and action need every extent >= 4");
+    return HISQ_OK;
+}
+
+hisq_status hisq_gauge_force(hisq_lattice lat, const double *U, double beta, const double coef[3], double *F,
+                             int flags)
+{
+    hisq_status st = gauge_args(lat, U, coef, F);
+    if (st != HISQ_OK) return st;
+    HIPCHK(lat, hipSetDevice(lat->device));
+    Work w;
+    if ((st = get_work(lat, 12, w)) != HISQ_OK) return st;   // U 0-3, F 4-7, staging 8-11
+    const SmearGeom g = geom_of(lat);
+    const double2 *src;
+    if ((st = stage_in(lat, U, flags, w.field(8), &src)) != HISQ_OK) return st;
+    HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
+    GForceArgs a{w.field(0), w.field(4), nullptr, coef[0], coef[1], coef[2], beta / 3.0};
+    HIPCHK(lat, launch_gauge_force(g, a, 0, lat->s));
+    if (flags & HISQ_DEVICE_PTR) {
+        HIPCHK(lat, launch_smear_from_planar(g, w.field(4), (double2 *)F, lat->s));
+    } else {
+        HIPCHK(lat, launch_smear_from_planar(g, w.field(4), w.field(8), lat->s));
+        HIPCHK(lat, hipMemcpyAsync(F, w.field(8), link_array_bytes(lat), hipMemcpyDeviceToHost, lat->s));
+    }
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    return HISQ_OK;
+}
+
+hisq_status hisq_gauge_action(hisq_lattice lat, const double *U, double beta, const double coef[3], double *S,
+                              int flags)
+{
+    hisq_status st = gauge_args(lat, U, coef, S);
+    if (st != HISQ_OK) return st;
+    HIPCHK(lat, hipSetDevice(lat->device));
+    const size_t nblk = (size_t)((lat->V + 255) / 256);
+    Work w;
+    if ((st = get_work(lat, 8, w, 4 * nblk * sizeof(double))) != HISQ_OK) return st;   // U 0-3, staging 4-7
+    const SmearGeom g = geom_of(lat);
+    const double2 *src;
+    if ((st = stage_in(lat, U, flags, w.field(4), &src)) != HISQ_OK) return st;
+    HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
+    // each loop is met once per link it holds: weights over the loop lengths
+    GForceArgs a{w.field(0), nullptr, w.part, coef[0] / 4.0, coef[1] / 6.0, coef[2] / 6.0, 1.0};
+    HIPCHK(lat, launch_gauge_force(g, a, 1, lat->s));
+    std::vector<double> part(4 * nblk);
+    HIPCHK(lat, hipMemcpyAsync(part.data(), w.part, part.size() * sizeof(double), hipMemcpyDeviceToHost, lat->s));
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    double re = 0.0;
+    for (double v : part) re += v;   // fixed order: the same bits every call
+    const double V = (double)lat->V;
+    *S = beta * (V * (6.0 * coef[0] + 12.0 * coef[1] + 16.0 * coef[2]) - re / 3.0);
     return HISQ_OK;
 }
 

@@ -11,122 +11,13 @@
 // bound by HBM traffic (about 1.1 flop per byte), not by the FP64 units.
 #include "hisq_dev.h"
 #include "smear.h"
+#include "su3.h"
 
 namespace hisq {
 
+using namespace su3;
+
 namespace {
-
-struct M3 {
-    double2 e[9];
-};
-
-__device__ __forceinline__ M3 ld(const double2 *__restrict__ f, size_t V, long long s)
-{
-    M3 m;
-#pragma unroll
-    for (int i = 0; i < 9; i++) m.e[i] = f[i * V + s];
-    return m;
-}
-
-__device__ __forceinline__ void st(double2 *__restrict__ f, size_t V, long long s, const M3 &m)
-{
-#pragma unroll
-    for (int i = 0; i < 9; i++) f[i * V + s] = m.e[i];
-}
-
-// c = a b
-__device__ __forceinline__ M3 mul_nn(const M3 &a, const M3 &b)
-{
-    M3 c;
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            double re = 0.0, im = 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                const double2 x = a.e[3 * i + k], y = b.e[3 * k + j];
-                re = __builtin_fma(x.x, y.x, re);
-                re = __builtin_fma(-x.y, y.y, re);
-                im = __builtin_fma(x.x, y.y, im);
-                im = __builtin_fma(x.y, y.x, im);
-            }
-            c.e[3 * i + j] = make_double2(re, im);
-        }
-    return c;
-}
-
-// c = a b^+
-__device__ __forceinline__ M3 mul_na(const M3 &a, const M3 &b)
-{
-    M3 c;
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            double re = 0.0, im = 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                const double2 x = a.e[3 * i + k], y = b.e[3 * j + k];
-                re = __builtin_fma(x.x, y.x, re);
-                re = __builtin_fma(x.y, y.y, re);
-                im = __builtin_fma(x.y, y.x, im);
-                im = __builtin_fma(-x.x, y.y, im);
-            }
-            c.e[3 * i + j] = make_double2(re, im);
-        }
-    return c;
-}
-
-// c = a^+ b
-__device__ __forceinline__ M3 mul_an(const M3 &a, const M3 &b)
-{
-    M3 c;
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            double re = 0.0, im = 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                const double2 x = a.e[3 * k + i], y = b.e[3 * k + j];
-                re = __builtin_fma(x.x, y.x, re);
-                re = __builtin_fma(x.y, y.y, re);
-                im = __builtin_fma(x.x, y.y, im);
-                im = __builtin_fma(-x.y, y.x, im);
-            }
-            c.e[3 * i + j] = make_double2(re, im);
-        }
-    return c;
-}
-
-// acc += c m
-__device__ __forceinline__ void axpy(M3 &acc, double c, const M3 &m)
-{
-#pragma unroll
-    for (int i = 0; i < 9; i++)
-        acc.e[i] = make_double2(__builtin_fma(c, m.e[i].x, acc.e[i].x), __builtin_fma(c, m.e[i].y, acc.e[i].y));
-}
-
-__device__ __forceinline__ int wrap(int v, int L)
-{
-    v -= v >= L ? L : 0;
-    v -= v >= L ? L : 0;
-    v += v < 0 ? L : 0;
-    v += v < 0 ? L : 0;
-    return v;
-}
-
-// site x + k * dir, for x's coordinate xd along dir (|k| <= 2 L)
-__device__ __forceinline__ long long shift(long long s, int xd, int S, int L, int k)
-{
-    return s + (long long)(wrap(xd + k, L) - xd) * S;
-}
-
-__device__ __forceinline__ int pick(const int v[4], int d)
-{
-    return d == 0 ? v[0] : d == 1 ? v[1] : d == 2 ? v[2] : v[3];
-}
 
 // Sites are visited in the order of the axis permutation o (o[0] = 0, x
 // fastest, so that a wavefront's loads stay contiguous): the host puts the

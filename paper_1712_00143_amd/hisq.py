@@ -46,6 +46,7 @@ EXPORTS = [
     "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss", "hisq_ptc_save", "hisq_ptc_load",
     "hisq_residual_history", "hisq_ptc_set_transport", "hisq_ptc_get_transport", "hisq_cg_noalloc",
     "hisq_dslash_shape", "hisq_ptc_set_activations", "hisq_smear_links", "hisq_fat7", "hisq_unitarize",
+    "hisq_gauge_force", "hisq_gauge_action",
 ]
 
 
@@ -257,6 +258,26 @@ class Lattice:
         _check(lib().hisq_unitarize(self.handle, ip, op, ctypes.c_int(HISQ_DEVICE_PTR if idev else 0)),
                self.handle, "hisq_unitarize")
         return out
+
+    def gauge_force(self, links, beta, coefs):
+        """hisq_gauge_force: Symanzik force [V][4][3][3] of thin links (coefs:
+        plaquette, rectangle, parallelogram weights)."""
+        ip, idev, k0 = _ptr(links)
+        out = self._link_out(links, idev)
+        op, _, k1 = _ptr(out)
+        c = (ctypes.c_double * 3)(*[float(x) for x in coefs])
+        _check(lib().hisq_gauge_force(self.handle, ip, ctypes.c_double(beta), c, op,
+                                      ctypes.c_int(HISQ_DEVICE_PTR if idev else 0)), self.handle, "hisq_gauge_force")
+        return out
+
+    def gauge_action(self, links, beta, coefs):
+        """hisq_gauge_action: the Symanzik action of thin links."""
+        ip, idev, k0 = _ptr(links)
+        c = (ctypes.c_double * 3)(*[float(x) for x in coefs])
+        s = ctypes.c_double(0.0)
+        _check(lib().hisq_gauge_action(self.handle, ip, ctypes.c_double(beta), c, ctypes.byref(s),
+                                       ctypes.c_int(HISQ_DEVICE_PTR if idev else 0)), self.handle, "hisq_gauge_action")
+        return s.value
 
     def cg(self, mass, b, x=None, params=None, raise_on_fail=True):
         """Solve (4m^2 - D_eo D_oe) x = b; returns (x, info dict)."""
