@@ -391,3 +391,114 @@ def gauge_action(dims, links, beta, coefs):
     if np.isnan(s):
         raise ValueError("the gauge action needs every extent >= 4")
     return float(s)
+
+
+# ------------------------------------------------------------- fermion force
+#
+# Q(U) = sum_k alpha_k X_k^+ A X_k, A = 4 m^2 - D_eo D_oe on the links
+# smeared from the thin links U, for fixed even vectors X_k (in the RHMD step
+# the multi-shift solutions X_k = (A + sigma_k)^-1 Phi; the pseudofermion
+# action's derivative is then -dQ).  The force is F_mu(x) = TA[U_mu(x)
+# G_mu(x)] with G the gradient dQ = sum Re Tr(dU_mu(x) G_mu(x)), so that
+# U_mu(x) -> exp(eps X) U_mu(x), X in su(3), changes Q at the rate
+# Re Tr(X F_mu(x)).
+
+
+def _dag(m):
+    return np.conj(np.swapaxes(m, -1, -2))
+
+
+def _shift_sites(field, dims, mu, k):
+    L0, L1, L2, L3 = dims
+    f = field.reshape((L3, L2, L1, L0) + field.shape[1:])
+    return np.roll(f, -k, axis=3 - mu).reshape(field.shape)
+
+
+def fermion_force_links(dims, fat, lng, alphas, xs):
+    """Gradients (OF, OL) [V][4][3][3] of Q with respect to the (phased) fat
+    and long links: dQ = sum Re Tr(dF_mu(x) OF_mu(x) + dL_mu(x) OL_mu(x)).
+    With Y = D_oe X on odd sites and Psi = (X, Y), eps(x) = +1 (-1) on even
+    (odd) sites, dQ = -sum_k alpha_k (Psi'^+ dD Psi), Psi' = eps Psi, so
+      OF_mu(x) = -2 eps(x) sum_k alpha_k Psi_k(x+mu) Psi_k(x)^+
+      OL_mu(x) = -2 eps(x) sum_k alpha_k Psi_k(x+3mu) Psi_k(x)^+."""
+    V = int(np.prod(dims))
+    c = np.stack(np.meshgrid(*[np.arange(n) for n in dims[::-1]], indexing="ij")[::-1], -1).reshape(-1, 4)
+    par = c.sum(axis=1) % 2
+    eps = np.where(par == 0, 1.0, -1.0)
+    OF = np.zeros((V, 4, 3, 3), dtype=np.complex128)
+    OL = np.zeros_like(OF)
+    for a, x in zip(alphas, xs):
+        y = dslash_half(dims, fat, lng, 1, x)
+        psi = np.zeros((V, 3), dtype=np.complex128)
+        psi[par == 0] = x
+        psi[par == 1] = y
+        for mu in range(4):
+            p1 = _shift_sites(psi, dims, mu, 1)
+            p3 = _shift_sites(psi, dims, mu, 3)
+            OF[:, mu] += -2.0 * a * eps[:, None, None] * (p1[:, :, None] * np.conj(psi)[:, None, :])
+            OL[:, mu] += -2.0 * a * eps[:, None, None] * (p3[:, :, None] * np.conj(psi)[:, None, :])
+    return OF, OL
+
+
+def fat7_adjoint(dims, links, coefs, G):
+    """Gradient with respect to links of sum Re Tr(fat7(links)_mu(x) G_mu(x))."""
+    lib = _load()
+    u, up = _c(links)
+    g, gp = _c(G)
+    c = (ctypes.c_double * 5)(*[float(x) for x in coefs])
+    out = np.zeros_like(u)
+    lib.orc_fat7_adjoint(_dims(dims), c, up, gp, out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def naik_adjoint(dims, links, G):
+    """Gradient with respect to W of sum Re Tr(N_mu(x) G_mu(x)), N = W W W."""
+    lib = _load()
+    u, up = _c(links)
+    g, gp = _c(G)
+    out = np.zeros_like(u)
+    lib.orc_naik_adjoint(_dims(dims), up, gp, out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def unitarize_adjoint(V, G):
+    """Gradient with respect to V of Re Tr(W(V) G), W = V (V^+ V)^{-1/2}, from
+    the singular values: V = A S B^+, W = A B^+, dW = A Om B^+ with
+    Om_ij = (K_ij - conj(K_ji)) / (s_i + s_j), K = A^+ dV B; so the gradient
+    is B M A^+ with M = (C - C^+) / (s_i + s_j), C = B^+ G A."""
+    a, s, bh = np.linalg.svd(V)
+    C = bh @ G @ a
+    M = (C - _dag(C)) / (s[..., :, None] + s[..., None, :])
+    return _dag(bh) @ M @ _dag(a)
+
+
+def _ta(M):
+    A = 0.5 * (M - _dag(M))
+    return A - np.trace(A, axis1=-2, axis2=-1)[..., None, None] / 3.0 * np.eye(3)
+
+
+def hisq_fermion_force(dims, thin, alphas, xs):
+    """F_mu(x) = TA[U_mu(x) G_mu(x)] (see above) for thin links U, weights
+    alphas and even vectors xs: the chain rule through the Naik product, the
+    second fat7 level, the U(3) projection and the first fat7 level."""
+    Vl = fat7(dims, thin, HISQ_LEVEL1)
+    W = unitarize(Vl)
+    fat, lng = hisq_smear(dims, thin)
+    OF, OL = fermion_force_links(dims, fat, lng, alphas, xs)
+    eta = np.ones((int(np.prod(dims)), 4))
+    c = np.stack(np.meshgrid(*[np.arange(n) for n in dims[::-1]], indexing="ij")[::-1], -1).reshape(-1, 4)
+    for mu in range(1, 4):
+        eta[:, mu] = (-1.0) ** (c[:, :mu].sum(axis=1) % 2)
+    GX = eta[:, :, None, None] * OF
+    GN = -eta[:, :, None, None] / 24.0 * OL
+    GW = fat7_adjoint(dims, W, HISQ_LEVEL2, GX) + naik_adjoint(dims, W, GN)
+    GV = unitarize_adjoint(Vl, GW)
+    GU = fat7_adjoint(dims, thin, HISQ_LEVEL1, GV)
+    return _ta(thin @ GU)
+
+
+def fermion_force_objective(dims, thin, alphas, xs, mass=0.1):
+    """Q(U) = sum_k alpha_k Re(X_k^+ A X_k) on the links smeared from U (the
+    mass only adds a constant)."""
+    fat, lng = hisq_smear(dims, thin)
+    return float(sum(a * np.vdot(x, apply_A(dims, fat, lng, mass, x)).real for a, x in zip(alphas, xs)))

@@ -31,6 +31,9 @@
  *             at the second (stated with the code below).
  *   gauge     Symanzik-improved (plaquette, rectangle, parallelogram)
  *   force     gauge action and its force (stated with the code below).
+ *   fermion   adjoints (link gradients) of fat7 and of the Naik product
+ *   force     for the chain rule of the HISQ fermion force; the rest of that
+ *             force is composed in the Python module.
  *
  * Complex numbers are C99 double complex; fields are site-major:
  *   links   [V][4][3][3]          (row-major 3x3)
@@ -796,4 +799,103 @@ double orc_gauge_action(const int d[4], const cplx *U, double beta, const double
             re += creal(M[0] + M[4] + M[8]);
         }
     return beta * ((double)V * (6.0 * c[0] + 12.0 * c[1] + 16.0 * c[2]) - re / 3.0);
+}
+
+/* ------------------------------------------------------- fermion force
+ *
+ * Chain rule of the HISQ fermion force (Section 4.2's fermion force, the
+ * derivative of the pseudofermion action through the link smearing).  For a
+ * scalar Q of the smeared links with gradient G (dQ = sum Re Tr(dY G) over
+ * every output link Y), the gradient with respect to the input links of a
+ * path sum Y = sum_P c_P L_1 ... L_n follows link by link:
+ *   Re Tr(L_1 .. dL_k .. L_n G) = Re Tr(dL_k R_k),  R_k = L_{k+1}..L_n G L_1..L_{k-1},
+ * and a link met daggered (L_k = U^+) receives R_k^+.  The functions below
+ * walk the same path lists as orc_fat7 and orc_naik_product.
+ */
+
+static void adj_path(const int d[4], const cplx *U, long s, const int *steps, int n, double c, const cplx *G,
+                     cplx *GU)
+{
+    cplx L[7][9], pre[8][9], suf[8][9];
+    long addr[7];
+    int dg[7];
+    long cur = s;
+    for (int k = 0; k < n; k++) {
+        const int mu = abs(steps[k]) - 1;
+        if (steps[k] > 0) {
+            memcpy(L[k], link(U, cur, mu), sizeof L[k]);
+            addr[k] = cur * 4 + mu;
+            dg[k] = 0;
+            cur = hop(d, cur, mu, 1);
+        } else {
+            cur = hop(d, cur, mu, -1);
+            const cplx *u = link(U, cur, mu);
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) L[k][3 * i + j] = conj(u[3 * j + i]);
+            addr[k] = cur * 4 + mu;
+            dg[k] = 1;
+        }
+    }
+    for (int i = 0; i < 9; i++) pre[0][i] = suf[n][i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int k = 0; k < n; k++) mm(pre[k + 1], pre[k], L[k]);            /* pre[k] = L_1..L_k */
+    for (int k = n - 1; k >= 0; k--) mm(suf[k], L[k], suf[k + 1]);       /* suf[k] = L_{k+1}..L_n (0-based) */
+    for (int k = 0; k < n; k++) {
+        cplx T[9], R[9];
+        mm(T, suf[k + 1], G);
+        mm(R, T, pre[k]);
+        cplx *g = GU + addr[k] * 9;
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) g[3 * i + j] += c * (dg[k] ? conj(R[3 * j + i]) : R[3 * i + j]);
+    }
+}
+
+/* GU += gradient of sum Re Tr(fat7(U; c)_mu(x) G_mu(x)) with respect to U
+ * (the path list of orc_fat7).  Serial: contributions scatter to links. */
+void orc_fat7_adjoint(const int d[4], const double c[5], const cplx *U, const cplx *G, cplx *GU)
+{
+    const long V = vol(d);
+    for (long s = 0; s < V; s++)
+        for (int mu = 0; mu < 4; mu++) {
+            const cplx *g = G + (s * 4 + mu) * 9;
+            cplx *gu = GU + (s * 4 + mu) * 9;
+            for (int i = 0; i < 9; i++) gu[i] += c[0] * g[i];
+            const int M = mu + 1;
+            for (int nu = 0; nu < 4; nu++) {
+                if (nu == mu) continue;
+                for (int sn = -1; sn <= 1; sn += 2) {
+                    const int N = sn * (nu + 1);
+                    const int p3[3] = {N, M, -N};
+                    adj_path(d, U, s, p3, 3, c[1], g, GU);
+                    const int pl[5] = {N, N, M, -N, -N};
+                    if (c[4] != 0.0) adj_path(d, U, s, pl, 5, c[4], g, GU);
+                    for (int rho = 0; rho < 4; rho++) {
+                        if (rho == mu || rho == nu) continue;
+                        for (int sr = -1; sr <= 1; sr += 2) {
+                            const int R = sr * (rho + 1);
+                            const int p5[5] = {N, R, M, -R, -N};
+                            adj_path(d, U, s, p5, 5, c[2], g, GU);
+                            for (int sig = 0; sig < 4; sig++) {
+                                if (sig == mu || sig == nu || sig == rho) continue;
+                                for (int ss = -1; ss <= 1; ss += 2) {
+                                    const int S = ss * (sig + 1);
+                                    const int p7[7] = {N, R, S, M, -S, -R, -N};
+                                    adj_path(d, U, s, p7, 7, c[3], g, GU);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+}
+
+/* GW += gradient of sum Re Tr(N_mu(x) G_mu(x)), N = W_mu(x) W_mu(x+mu) W_mu(x+2mu). */
+void orc_naik_adjoint(const int d[4], const cplx *W, const cplx *G, cplx *GW)
+{
+    const long V = vol(d);
+    for (long s = 0; s < V; s++)
+        for (int mu = 0; mu < 4; mu++) {
+            const int p[3] = {mu + 1, mu + 1, mu + 1};
+            adj_path(d, W, s, p, 3, 1.0, G + (s * 4 + mu) * 9, GW);
+        }
 }
