@@ -425,6 +425,40 @@ hisq_status hisq_gauge_force(hisq_lattice lat, const double *U, double beta, con
 hisq_status hisq_gauge_action(hisq_lattice lat, const double *U, double beta, const double coef[3], double *S,
                               int flags);
 
+/* ---- fermion force ----
+ *
+ * The HISQ fermion force of the RHMD step (Section 4.2), for the rational
+ * pseudofermion action S = Phi^+ (a0 + sum_k alpha_k (A + sigma_k)^-1) Phi
+ * with the multi-shift solutions X_k = (A + sigma_k)^-1 Phi: at fixed X_k
+ * dS = -dQ, where
+ *   Q = sum_k alpha_k X_k^+ A X_k,   A = 4 m^2 - D_eo D_oe
+ * (n terms, 1 <= n <= 64; X: n even FP64 vectors back to back, [n][V/2][3]
+ * complex; alpha: n host doubles).  Gradients are taken in the sense
+ * dQ = sum Re Tr(dY_mu(x) G_mu(x)) over the links Y; arrays in the link
+ * layout above, host pointers or, with HISQ_DEVICE_PTR, device pointers
+ * (alpha is always a host array).  FP64, synchronous.
+ *
+ * hisq_fermion_force_links: the gradients OF, OL of Q with respect to the
+ * lattice's loaded (phased) fat and long links:
+ *   OF_mu(x) = -2 eps(x) sum_k alpha_k Psi_k(x+mu) Psi_k(x)^+,
+ *   OL_mu(x) = -2 eps(x) sum_k alpha_k Psi_k(x+3mu) Psi_k(x)^+,
+ * Psi_k = X_k on even and D_oe X_k on odd sites, eps = +1 (-1) on even (odd)
+ * sites.  Errors: HISQ_ERR_ARG, HISQ_ERR_STATE (no links loaded). */
+hisq_status hisq_fermion_force_links(hisq_lattice lat, int n, const double *alpha, const double *X, double *OF,
+                                     double *OL, int flags);
+
+/* hisq_fermion_force: the force on the thin links U of the HISQ links
+ * (hisq_smear_links), F_mu(x) = TA[U_mu(x) G_mu(x)], G the gradient of Q with
+ * respect to U, so that U_mu(x) -> exp(eps X) U_mu(x) (X in su(3)) changes Q
+ * at the rate Re Tr(X F_mu(x)) (and S at minus that rate).  The chain rule
+ * runs through the Naik product, the second fat7 level, the U(3) projection
+ * and the first level.  U is smeared first and the result loaded as the
+ * lattice's links (as hisq_smear_links with HISQ_LOAD_RESULT).  Workspace: 46
+ * link-direction fields (144 V bytes each) and 2 n V/2 vectors, kept until
+ * hisq_destroy.  Errors: as hisq_smear_links, HISQ_ERR_ARG. */
+hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const double *alpha, const double *X,
+                               double *F, int flags);
+
 /* ---- measurement ----
  *
  * Practical HBM ceilings of `device`, measured on `stream` (NULL: the null

@@ -1,0 +1,66 @@
+// Launchers of the HISQ fermion-force kernels (FP64).  Fields are the
+// site-planar link fields of smear.h; gradients G of a real scalar Q with
+// respect to a link field Y are fields with dQ = sum Re Tr(dY_mu(x) G_mu(x)).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "smear.h"
+
+namespace hisq {
+
+// Gradients of Q = sum_k alpha_k X_k^+ A X_k with respect to the fat and long
+// links, from the even vectors X_k and Y_k = D_oe X_k ([n][h][3] complex
+// each): with Psi = (X on even, Y on odd sites) and eps = +1 / -1 on even /
+// odd sites,
+//   OF_mu(x) = -2 eps(x) sum_k alpha_k Psi_k(x+mu) Psi_k(x)^+,
+//   OL_mu(x) = -2 eps(x) sum_k alpha_k Psi_k(x+3mu) Psi_k(x)^+.
+// fold: write eta_mu(x) OF and cN eta_mu(x) OL instead (the gradients with
+// respect to the unphased level-2 sum and the Naik product).
+struct OuterArgs {
+    const double2 *X, *Y;
+    const double *alpha;
+    int n;
+    long long h;
+    double2 *OF, *OL;   // four planar fields each
+    int fold;
+    double cN;
+};
+hipError_t launch_ff_outer(const SmearGeom &g, const OuterArgs &a, hipStream_t s);
+
+// Adjoint of the staple of M through direction d for output direction mu,
+//   T(x) = sum_{s in signs} L_s(x) M(x+s) L_s(x+mu)^+   (L_{+d}(x) = U_d(x),
+//                                                       L_{-d}(x) = U_d(x-d)^+),
+// for the gradient G of T, scaled by c:
+//   GM  (= or +=)  the gradient with respect to M,
+//   GUd +=         the gradient with respect to the links U_d.
+// Either output may be null; signs: 1 = +d only, 2 = -d only, 3 = both.
+struct StapleAdjArgs {
+    const double2 *Ud, *M, *G;
+    double2 *GM, *GUd;
+    double c;
+    int mu, d, signs, gm_init;
+    int ord[4];
+};
+hipError_t launch_staple_adjoint(const SmearGeom &g, const StapleAdjArgs &a, hipStream_t s);
+
+// Single-sign staples of U_mu through nu: Hp = U_nu(x) U_mu(x+nu) U_nu(x+mu)^+,
+// Hm = U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu).
+hipError_t launch_ff_halves(const SmearGeom &g, const double2 *U, int mu, int nu, double2 *Hp, double2 *Hm,
+                            hipStream_t s);
+
+// GW += gradient of sum Re Tr(N_mu(x) GN_mu(x)), N_mu(x) = W_mu(x) W_mu(x+mu) W_mu(x+2mu)
+// (four-direction planar fields).
+hipError_t launch_ff_naik_adjoint(const SmearGeom &g, const double2 *W, const double2 *GN, double2 *GW,
+                                  hipStream_t s);
+
+// In place: G <- gradient with respect to V of Re Tr(W(V) G), W = V (V^+ V)^{-1/2},
+// four-direction planar fields.
+hipError_t launch_ff_unitarize_adjoint(const SmearGeom &g, const double2 *V, double2 *G, hipStream_t s);
+
+// out = a * out + b * in over n double2 (a = 0: out = b * in, out not read).
+hipError_t launch_field_axpby(double2 *out, double a, const double2 *in, double b, size_t n, hipStream_t s);
+
+// F_mu(x) = TA[U_mu(x) G_mu(x)] (four-direction planar fields; F may alias G).
+hipError_t launch_ff_project(const SmearGeom &g, const double2 *U, const double2 *G, double2 *F, hipStream_t s);
+
+}  // namespace hisq

@@ -1,6 +1,7 @@
-// HISQ link smearing and the Symanzik gauge force: host orchestration of
-// the link kernels and the C-ABI entry points hisq_smear_links, hisq_fat7,
-// hisq_unitarize, hisq_gauge_force and hisq_gauge_action.
+// HISQ link smearing, the Symanzik gauge force and the HISQ fermion force:
+// host orchestration of the link kernels and the C-ABI entry points
+// hisq_smear_links, hisq_fat7, hisq_unitarize, hisq_gauge_force,
+// hisq_gauge_action, hisq_fermion_force_links and hisq_fermion_force.
 //
 // fat7(U; c1, c3, c5, c7; cL) for output direction mu is built with staple
 // reuse: the three 3-staple fields T1_nu are formed once, every 5-staple is
@@ -9,6 +10,9 @@
 // staple is taken (the staple is linear in the field it transports).
 #include <vector>
 
+#include <cmath>
+
+#include "fforce.h"
 #include "gforce.h"
 #include "smear.h"
 #include "solver.h"
@@ -291,6 +295,189 @@ hisq_status hisq_gauge_action(hisq_lattice lat, const double *U, double beta, co
     const double V = (double)lat->V;
     *S = beta * (V * (6.0 * coef[0] + 12.0 * coef[1] + 16.0 * coef[2]) - re / 3.0);
     return HISQ_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ fermion force
+
+namespace {
+
+// Gradient of sum Re Tr(fat7(Ul; c)_mu(x) G_mu(x)) with respect to Ul, added
+// to GU (four planar fields each): the forward intermediates of each output
+// direction are rebuilt (3-staples T1, 5-staples T2, the single-sign
+// 3-staples H+- of the Lepage term) and every pass is undone by its
+// gather-form adjoint.  sc: 18 scratch fields.
+hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5], const double2 *G, double2 *GU,
+                        double2 *sc, size_t fsz, hipStream_t s)
+{
+    double2 *T1 = sc, *T2 = sc + 3 * fsz, *Hp = sc + 6 * fsz, *Hm = sc + 9 * fsz, *GT1 = sc + 12 * fsz;
+    double2 *GT2 = sc + 15 * fsz, *GHp = sc + 16 * fsz, *GHm = sc + 17 * fsz;
+    double2 *Fdummy = GT2;   // pass 1's own sum, not used here
+    const bool need5 = c[2] != 0.0 || c[3] != 0.0, lep = c[4] != 0.0;
+    hipError_t e;
+    auto U_ = [&](int d) { return Ul + (size_t)d * fsz; };
+    auto GU_ = [&](int d) { return GU + (size_t)d * fsz; };
+    auto adj = [&](int mu, int d, int signs, const double2 *M, const double2 *Gin, double2 *GM, int gm_init,
+                   double2 *GUd, double coef) {
+        StapleAdjArgs a{U_(d), M, Gin, GM, GUd, coef, mu, d, signs, gm_init, {}};
+        const int f[2] = {d, mu};
+        smear_order(f, 2, a.ord);
+        return launch_staple_adjoint(g, a, s);
+    };
+    for (int mu = 0; mu < 4; mu++) {
+        int perp[3], np = 0;
+        for (int d = 0; d < 4; d++)
+            if (d != mu) perp[np++] = d;
+        const double2 *Gmu = G + (size_t)mu * fsz;
+        // forward intermediates
+        Pass1Args p1{Ul, Fdummy, {T1, T1 + fsz, T1 + 2 * fsz}, 0.0, 0.0, 0.0, mu, {perp[0], perp[1], perp[2]}, {}};
+        smear_order(perp, 0, p1.ord);
+        if ((e = launch_smear_pass1(g, p1, s)) != hipSuccess) return e;
+        if (lep)
+            for (int k = 0; k < 3; k++)
+                if ((e = launch_ff_halves(g, Ul, mu, perp[k], Hp + k * fsz, Hm + k * fsz, s)) != hipSuccess) return e;
+        if (need5)
+            for (int k = 0; k < 3; k++) {
+                const int inu = (k + 1) % 3, irho = (k + 2) % 3;
+                Pass2Args p2{Ul, T1 + inu * fsz, T1 + irho * fsz, T2 + k * fsz, mu, perp[inu], perp[irho], {}};
+                const int f2[3] = {perp[inu], perp[irho], mu};
+                smear_order(f2, 3, p2.ord);
+                if ((e = launch_smear_pass2(g, p2, s)) != hipSuccess) return e;
+            }
+        // reverse
+        if ((e = launch_field_axpby(GU_(mu), 1.0, Gmu, c[0], fsz, s)) != hipSuccess) return e;
+        for (int k = 0; k < 3; k++)
+            if ((e = launch_field_axpby(GT1 + k * fsz, 0.0, Gmu, c[1], fsz, s)) != hipSuccess) return e;
+        if (need5)
+            for (int k = 0; k < 3; k++) {
+                const int sig = perp[k], inu = (k + 1) % 3, irho = (k + 2) % 3;
+                const int nu = perp[inu], rho = perp[irho];
+                if ((e = launch_field_axpby(GT2, 0.0, Gmu, c[2], fsz, s)) != hipSuccess) return e;
+                if (c[3] != 0.0 && (e = adj(mu, sig, 3, T2 + k * fsz, Gmu, GT2, 0, GU_(sig), c[3])) != hipSuccess)
+                    return e;
+                if ((e = adj(mu, rho, 3, T1 + inu * fsz, GT2, GT1 + inu * fsz, 0, GU_(rho), 1.0)) != hipSuccess) return e;
+                if ((e = adj(mu, nu, 3, T1 + irho * fsz, GT2, GT1 + irho * fsz, 0, GU_(nu), 1.0)) != hipSuccess) return e;
+            }
+        for (int k = 0; k < 3; k++) {
+            const int nu = perp[k];
+            if ((e = adj(mu, nu, 3, U_(mu), GT1 + k * fsz, GU_(mu), 0, GU_(nu), 1.0)) != hipSuccess) return e;
+            if (!lep) continue;
+            // Lepage = S+(H+) + S-(H-), S+- the single-sign staples through nu
+            if ((e = adj(mu, nu, 1, Hp + k * fsz, Gmu, GHp, 1, GU_(nu), c[4])) != hipSuccess) return e;
+            if ((e = adj(mu, nu, 2, Hm + k * fsz, Gmu, GHm, 1, GU_(nu), c[4])) != hipSuccess) return e;
+            if ((e = adj(mu, nu, 1, U_(mu), GHp, GU_(mu), 0, GU_(nu), 1.0)) != hipSuccess) return e;
+            if ((e = adj(mu, nu, 2, U_(mu), GHm, GU_(mu), 0, GU_(nu), 1.0)) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hisq_status ff_check(hisq_lattice lat, int n, const double *alpha, const double *X, const void *out)
+{
+    if (!lat || !alpha || !X || !out) return set_err(lat, HISQ_ERR_ARG, "null argument");
+    if (n < 1 || n > 64) return set_err(lat, HISQ_ERR_ARG, "the number of terms must be in [1, 64]");
+    for (int k = 0; k < n; k++)
+        if (!std::isfinite(alpha[k])) return set_err(lat, HISQ_ERR_ARG, "non-finite weight");
+    return HISQ_OK;
+}
+
+// Y_k = D_oe X_k on the lattice's FP64 links; X, Y device [n][h][3] complex.
+hisq_status ff_solutions_odd(hisq_lattice lat, int n, const double2 *X, double2 *Y)
+{
+    for (int k = 0; k < n; k++) {
+        hisq_status st = hisq_dslash(lat, HISQ_ODD, HISQ_F64, HISQ_RECON_18, X + (size_t)k * lat->h * 3,
+                                     Y + (size_t)k * lat->h * 3, 1, HISQ_DEVICE_PTR);
+        if (st != HISQ_OK) return st;
+    }
+    return HISQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hisq_status hisq_fermion_force_links(hisq_lattice lat, int n, const double *alpha, const double *X, double *OF,
+                                     double *OL, int flags)
+{
+    hisq_status st = ff_check(lat, n, alpha, X, OF);
+    if (st != HISQ_OK) return st;
+    if (!OL) return set_err(lat, HISQ_ERR_ARG, "null argument");
+    if (!lat->loaded) return set_err(lat, HISQ_ERR_STATE, "no links loaded");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    const size_t vb = (size_t)n * lat->h * 3 * sizeof(double2);
+    Work w;
+    if ((st = get_work(lat, 12, w, 2 * vb + 64 * sizeof(double))) != HISQ_OK) return st;   // OF 0-3, OL 4-7, staging 8-11
+    double2 *Xd = (double2 *)w.part, *Yd = Xd + (size_t)n * lat->h * 3;
+    double *ad = (double *)(Yd + (size_t)n * lat->h * 3);
+    const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
+    HIPCHK(lat, hipMemcpyAsync(Xd, X, vb, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, lat->s));
+    HIPCHK(lat, hipMemcpyAsync(ad, alpha, n * sizeof(double), hipMemcpyHostToDevice, lat->s));
+    if ((st = ff_solutions_odd(lat, n, Xd, Yd)) != HISQ_OK) return st;
+    const SmearGeom g = geom_of(lat);
+    OuterArgs oa{Xd, Yd, ad, n, lat->h, w.field(0), w.field(4), 0, 0.0};
+    HIPCHK(lat, launch_ff_outer(g, oa, lat->s));
+    double *outs[2] = {OF, OL};
+    for (int k = 0; k < 2; k++) {
+        if (dev) {
+            HIPCHK(lat, launch_smear_from_planar(g, w.field(4 * k), (double2 *)outs[k], lat->s));
+        } else {
+            HIPCHK(lat, launch_smear_from_planar(g, w.field(4 * k), w.field(8), lat->s));
+            HIPCHK(lat, hipMemcpyAsync(outs[k], w.field(8), link_array_bytes(lat), hipMemcpyDeviceToHost, lat->s));
+        }
+    }
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    return HISQ_OK;
+}
+
+hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const double *alpha, const double *X,
+                               double *F, int flags)
+{
+    hisq_status st = ff_check(lat, n, alpha, X, F);
+    if (st != HISQ_OK) return st;
+    if (!U) return set_err(lat, HISQ_ERR_ARG, "null argument");
+    // the smeared links become the lattice's links (the Dslash of Y = D_oe X)
+    if ((st = hisq_smear_links(lat, U, nullptr, nullptr, (flags & HISQ_DEVICE_PTR) | HISQ_LOAD_RESULT)) != HISQ_OK)
+        return st;
+    HIPCHK(lat, hipSetDevice(lat->device));
+    const size_t vb = (size_t)n * lat->h * 3 * sizeof(double2);
+    // fields: U 0-3, level-1 sum 4-7, W 8-11, GX 12-15, GN 16-19, GW 20-23,
+    // GU 24-27 (also the input and output staging), scratch 28-45
+    Work w;
+    if ((st = get_work(lat, 46, w, 2 * vb + 64 * sizeof(double))) != HISQ_OK) return st;
+    const size_t fsz = w.fsz;
+    double2 *Xd = (double2 *)w.part, *Yd = Xd + (size_t)n * lat->h * 3;
+    double *ad = (double *)(Yd + (size_t)n * lat->h * 3);
+    const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
+    HIPCHK(lat, hipMemcpyAsync(Xd, X, vb, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, lat->s));
+    HIPCHK(lat, hipMemcpyAsync(ad, alpha, n * sizeof(double), hipMemcpyHostToDevice, lat->s));
+    if ((st = ff_solutions_odd(lat, n, Xd, Yd)) != HISQ_OK) return st;
+    const SmearGeom g = geom_of(lat);
+    const double2 *src;
+    if ((st = stage_in(lat, U, flags, w.field(24), &src)) != HISQ_OK) return st;
+    HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
+    // forward: level-1 sum V and its projection W
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(28), w.field(31), LV1, fsz, lat->s));
+    HIPCHK(lat, launch_field_axpby(w.field(8), 0.0, w.field(4), 1.0, 4 * fsz, lat->s));
+    HIPCHK(lat, hipMemsetAsync(w.bad, 0, sizeof(int), lat->s));
+    HIPCHK(lat, launch_smear_unitarize(g, w.field(8), w.bad, lat->s));
+    // gradients with respect to the level-2 sum (phases folded) and the Naik product
+    OuterArgs oa{Xd, Yd, ad, n, lat->h, w.field(12), w.field(16), 1, NAIK};
+    HIPCHK(lat, launch_ff_outer(g, oa, lat->s));
+    HIPCHK(lat, hipMemsetAsync(w.field(20), 0, 4 * fsz * sizeof(double2), lat->s));
+    HIPCHK(lat, launch_ff_naik_adjoint(g, w.field(8), w.field(16), w.field(20), lat->s));
+    HIPCHK(lat, fat7_adjoint(g, w.field(8), LV2, w.field(12), w.field(20), w.field(28), fsz, lat->s));
+    HIPCHK(lat, launch_ff_unitarize_adjoint(g, w.field(4), w.field(20), lat->s));
+    HIPCHK(lat, hipMemsetAsync(w.field(24), 0, 4 * fsz * sizeof(double2), lat->s));
+    HIPCHK(lat, fat7_adjoint(g, w.field(0), LV1, w.field(20), w.field(24), w.field(28), fsz, lat->s));
+    HIPCHK(lat, launch_ff_project(g, w.field(0), w.field(24), w.field(24), lat->s));
+    if (dev) {
+        HIPCHK(lat, launch_smear_from_planar(g, w.field(24), (double2 *)F, lat->s));
+    } else {
+        HIPCHK(lat, launch_smear_from_planar(g, w.field(24), w.field(12), lat->s));
+        HIPCHK(lat, hipMemcpyAsync(F, w.field(12), link_array_bytes(lat), hipMemcpyDeviceToHost, lat->s));
+    }
+    return check_projection(lat, w.bad);
 }
 
 }  // extern "C"

@@ -19,29 +19,6 @@ using namespace su3;
 
 namespace {
 
-// Sites are visited in the order of the axis permutation o (o[0] = 0, x
-// fastest, so that a wavefront's loads stay contiguous): the host puts the
-// directions a pass steps along right after x, so that a site's neighbours
-// along them are visited, and held in L2 / the Infinity Cache, soon after it.
-// Returns lex(x) for visit index i and the coordinates c[k] along o[k].
-__device__ __forceinline__ long long walk(unsigned i, const SmearGeom &g, const int o[4], int c[4])
-{
-    const unsigned L0 = (unsigned)pick(g.L, o[0]), L1 = (unsigned)pick(g.L, o[1]), L2 = (unsigned)pick(g.L, o[2]);
-    c[0] = (int)(i % L0);
-    i /= L0;
-    c[1] = (int)(i % L1);
-    i /= L1;
-    c[2] = (int)(i % L2);
-    c[3] = (int)(i / L2);
-    return (long long)c[0] * pick(g.S, o[0]) + (long long)c[1] * pick(g.S, o[1]) + (long long)c[2] * pick(g.S, o[2]) +
-           (long long)c[3] * pick(g.S, o[3]);
-}
-
-__device__ __forceinline__ int coord(const int c[4], const int o[4], int d)
-{
-    return o[0] == d ? c[0] : o[1] == d ? c[1] : o[2] == d ? c[2] : c[3];
-}
-
 // One-step staple of field M through direction (S, L) at site y, whose
 // coordinates along that direction and along mu are yd and ym:
 // U(y) M(y+d) U(y+mu)^+ + U(y-d)^+ M(y-d) U(y-d+mu).

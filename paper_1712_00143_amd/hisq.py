@@ -46,7 +46,7 @@ EXPORTS = [
     "hisq_stream_bandwidth", "hisq_ptc_init_polynomial", "hisq_ptc_set_loss", "hisq_ptc_save", "hisq_ptc_load",
     "hisq_residual_history", "hisq_ptc_set_transport", "hisq_ptc_get_transport", "hisq_cg_noalloc",
     "hisq_dslash_shape", "hisq_ptc_set_activations", "hisq_smear_links", "hisq_fat7", "hisq_unitarize",
-    "hisq_gauge_force", "hisq_gauge_action",
+    "hisq_gauge_force", "hisq_gauge_action", "hisq_fermion_force_links", "hisq_fermion_force",
 ]
 
 
@@ -278,6 +278,55 @@ class Lattice:
         _check(lib().hisq_gauge_action(self.handle, ip, ctypes.c_double(beta), c, ctypes.byref(s),
                                        ctypes.c_int(HISQ_DEVICE_PTR if idev else 0)), self.handle, "hisq_gauge_action")
         return s.value
+
+    def _ff_vectors(self, xs, n):
+        try:
+            import torch
+            if isinstance(xs, torch.Tensor):
+                if xs.numel() != n * self.h * 6 or xs.dtype != torch.float64:
+                    raise ValueError("vectors: n * V/2 * 3 complex FP64 values expected")
+                return xs
+        except ImportError:
+            pass
+        return np.ascontiguousarray(np.asarray(xs, dtype=np.complex128).reshape(n, self.h, 3))
+
+    def fermion_force_links(self, alphas, xs):
+        """hisq_fermion_force_links: (OF, OL) gradients of sum alpha_k X_k^+ A X_k
+        with respect to the loaded fat and long links; xs: [n][V/2][3] complex
+        (numpy, or a device tensor of the same bytes)."""
+        n = len(alphas)
+        xa = self._ff_vectors(xs, n)
+        al = (ctypes.c_double * n)(*[float(a) for a in alphas])
+        xp, xdev, k0 = _ptr(xa)
+        if xdev:
+            import torch
+            OF = torch.empty((self.V, 4, 3, 6), dtype=torch.float64, device=xa.device)
+            OL = torch.empty_like(OF)
+        else:
+            OF, OL = self._link_out(None, False), self._link_out(None, False)
+        fp, _, k1 = _ptr(OF)
+        lp, _, k2 = _ptr(OL)
+        _check(lib().hisq_fermion_force_links(self.handle, ctypes.c_int(n), al, xp, fp, lp,
+                                              ctypes.c_int(HISQ_DEVICE_PTR if xdev else 0)),
+               self.handle, "hisq_fermion_force_links")
+        return OF, OL
+
+    def fermion_force(self, links, alphas, xs):
+        """hisq_fermion_force: force [V][4][3][3] on the thin links (which are
+        smeared and loaded as this lattice's links first)."""
+        n = len(alphas)
+        ip, idev, k0 = _ptr(links)
+        xa = self._ff_vectors(xs, n)
+        al = (ctypes.c_double * n)(*[float(a) for a in alphas])
+        xp, xdev, k1 = _ptr(xa)
+        if idev != xdev:
+            raise ValueError("links and vectors must both be host or both device arrays")
+        out = self._link_out(links, idev)
+        op, _, k2 = _ptr(out)
+        _check(lib().hisq_fermion_force(self.handle, ip, ctypes.c_int(n), al, xp, op,
+                                        ctypes.c_int(HISQ_DEVICE_PTR if idev else 0)),
+               self.handle, "hisq_fermion_force")
+        return out
 
     def cg(self, mass, b, x=None, params=None, raise_on_fail=True):
         """Solve (4m^2 - D_eo D_oe) x = b; returns (x, info dict)."""
