@@ -475,6 +475,7 @@ def run_headline(args):
     if not args.dslash_only and not args.no_smear:
         out["smear_32^4"] = smear_summary(args)
         out["gauge_force_32^4"] = gforce_summary(args)
+        out["fermion_force_32^4"] = fforce_summary(args)
     print(json.dumps(out), flush=True)
 
 
@@ -581,6 +582,63 @@ def gforce_summary(args):
             "sample_max_rel_error_vs_oracle": float(f"{err:.3e}"), "sample_links": 4 * len(idx),
             "action_rel_error_vs_oracle": float(f"{abs(S - s_ref) / abs(s_ref):.3e}"),
             "oracle_s_16^4": round(t_oracle, 2)}
+
+
+FF_TERMS = 12   # rational-approximation terms of the RHMD pseudofermion action
+
+
+def fforce_summary(args):
+    """HISQ fermion force at 32^4 for FF_TERMS solution vectors: an 8^4
+    random field and 8^4 Gaussian vectors (standing in for the multi-shift
+    solutions) repeated 4 times per axis, so that the oracle's force on the
+    8^4 field, repeated, is the exact answer; a sample of links is compared.
+    The call includes the smearing (the force smears and loads the links)."""
+    import torch
+    import oracle
+    from paper_1712_00143_amd import hisq as H
+    from paper_1712_00143_amd import synth
+    small, dims, reps = (8, 8, 8, 8), (32, 32, 32, 32), (4, 4, 4, 4)
+    u8 = synth.thin_links(small, 0.4, 7200)
+    alphas = list(np.random.default_rng(7201).uniform(0.01, 1.0, FF_TERMS))
+    xs8 = [synth.gaussian_even(small, 7300 + k) for k in range(FF_TERMS)]
+    t0 = time.perf_counter()
+    f_ref = oracle.hisq_fermion_force(small, u8, alphas, xs8)
+    t_oracle = time.perf_counter() - t0
+    ev8, ev = synth.even_sites(small), synth.even_sites(dims)
+    xs = np.empty((FF_TERMS, len(ev), 3), dtype=np.complex128)
+    for k, x8 in enumerate(xs8):
+        full = np.zeros((synth.volume(small), 3), dtype=np.complex128)
+        full[ev8] = x8
+        xs[k] = synth.tile_field(full, small, reps)[ev]
+    thin = torch.from_numpy(synth.tile_field(u8, small, reps).view(np.float64)).cuda()
+    xt = torch.from_numpy(xs.view(np.float64)).cuda()
+    del xs
+    lat = H.Lattice(dims)
+    F = lat.fermion_force(thin, alphas, xt)
+    times = []
+    for _ in range(max(3, args.steps)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        F = lat.fermion_force(thin, alphas, xt)
+        times.append(time.perf_counter() - t1)
+    t = float(np.median(times))
+    V = synth.volume(dims)
+    idx = np.random.default_rng(7202).choice(V, 4096, replace=False)
+    c = synth.coords(dims)[idx] % 8
+    j = c[:, 0] + 8 * (c[:, 1] + 8 * (c[:, 2] + 8 * c[:, 3]))
+    f = F.view(V, 4, 3, 6)[torch.from_numpy(idx).cuda()].cpu().numpy().view(np.complex128).reshape(-1, 4, 3, 3)
+    err = float(np.abs(f - f_ref[j]).max() / np.abs(f_ref).max())
+    lat.close()
+    return {"ms": round(t * 1e3, 3), "terms": FF_TERMS,
+            "what": "hisq_fermion_force on device arrays, 32^4, 12 solution vectors: smearing and loading the links, "
+                    "D_oe of each vector, outer products, Naik / fat7 level 2 / projection / fat7 level 1 adjoints, "
+                    "projection onto su(3); synchronous call, median of the timed calls",
+            "sample_max_rel_error_vs_oracle": float(f"{err:.3e}"), "sample_links": 4 * len(idx),
+            "oracle_s_8^4": round(t_oracle, 2)}
+
+
+def run_fforce(args):
+    print(json.dumps({"fermion_force_32^4": fforce_summary(args)}), flush=True)
 
 
 def run_gforce(args):
@@ -942,9 +1000,9 @@ def main():
     ap.add_argument("--head-only", action="store_true", help="only the 32^4 headline launches (for profiling)")
     ap.add_argument("--no-c2", action="store_true", help="headline: skip the multi-shift summary")
     ap.add_argument("--no-c3", action="store_true", help="headline: skip the batched-solve summary")
-    ap.add_argument("--no-smear", action="store_true", help="headline: skip the smearing and gauge-force summaries")
+    ap.add_argument("--no-smear", action="store_true", help="headline: skip the smearing, gauge- and fermion-force summaries")
     ap.add_argument("--oracle-sample", type=int, default=8, help="c2/c3: solutions checked by the oracle")
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "copy", "smear", "gforce"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "copy", "smear", "gforce", "fforce"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--dslash-only", action="store_true", help="time only the Dslash")
@@ -959,7 +1017,7 @@ def main():
               "(the multi-GPU halo-exchange design is documented, not built)", file=sys.stderr)
         sys.exit(2)
     {"c0": run_c0, "c1": run_headline, "c2": run_c2, "c3": run_c3, "c4": run_c4,
-     "copy": run_copy, "smear": run_smear, "gforce": run_gforce}[args.workload](args)
+     "copy": run_copy, "smear": run_smear, "gforce": run_gforce, "fforce": run_fforce}[args.workload](args)
 
 
 if __name__ == "__main__":
