@@ -9,9 +9,9 @@ namespace hisq {
 // U: four-direction planar thin links (see smear.h).  mode 0: F (four
 // planar fields) = scale * TA[U_mu(x) B_mu(x)^+], B the sum of the loop-
 // closing paths from x to x+mu weighted cp (plaquettes), cr (rectangles),
-// cg (parallelograms).  mode 1: part[mu * nblk + blk] = sum over the block's
-// links of Re Tr U_mu(x) B_mu(x)^+ (nblk = ceil(V / 256)).  Every extent
-// must be >= 4.
+// cg (parallelograms).  mode 1: part[blk] = sum over the block's links (the
+// four directions of 64 sites) of Re Tr U_mu(x) B_mu(x)^+ (ceil(V / 64)
+// blocks).  Every extent must be >= 4.
 struct GForceArgs {
     const double2 *U;
     double2 *F;

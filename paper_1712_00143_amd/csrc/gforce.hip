@@ -6,7 +6,7 @@
 // the force on U_mu(x) is (beta/3) TA[U_mu(x) B^+], B the weighted sum of
 // the paths from x to x+mu that close each loop through the link.
 //
-// One thread per link (blockIdx.y = mu), the whole staple sum in registers:
+// One thread per link, the whole staple sum in registers:
 // 6 signed transverse steps n, each giving the plaquette and the three
 // rectangles (11 products with the shared prefix and suffix factored out),
 // and 24 parallelograms (b, a, mu, -b, -a), summed over b before the common
@@ -125,10 +125,13 @@ __device__ __forceinline__ void parallelograms(const SmearGeom &g, const Geo &q,
 template <int MODE>   // 0: force, 1: action partials
 __global__ void __launch_bounds__(256) k_gauge_force(SmearGeom g, GForceArgs a)
 {
-    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
+    // a block holds the four links of 64 sites (one wave per direction), so
+    // the neighbour links one direction's staples fetch serve the others
+    // from L1 / L2
+    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 64 + (threadIdx.x & 63);
     const bool valid = vi < g.V;
     const size_t V = (size_t)g.V;
-    const int mu = blockIdx.y;
+    const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Geo q;
     q.s = valid ? vi : 0;
     {
@@ -177,8 +180,7 @@ __global__ void __launch_bounds__(256) k_gauge_force(SmearGeom g, GForceArgs a)
         __shared__ double red[4];
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
         __syncthreads();
-        if (threadIdx.x == 0)
-            a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+        if (threadIdx.x == 0) a.part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
     }
 }
 
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(256) k_gauge_force(SmearGeom g, GForceArgs a)
 
 hipError_t launch_gauge_force(const SmearGeom &g, const GForceArgs &a, int mode, hipStream_t s)
 {
-    const dim3 grid((unsigned)((g.V + 255) / 256), 4), blk(256);
+    const dim3 grid((unsigned)((g.V + 63) / 64)), blk(256);
     if (mode == 0) hipLaunchKernelGGL((k_gauge_force<0>), grid, blk, 0, s, g, a);
     else hipLaunchKernelGGL((k_gauge_force<1>), grid, blk, 0, s, g, a);
     return hipGetLastError();

@@ -277,9 +277,9 @@ hisq_status hisq_gauge_action(hisq_lattice lat, const double *U, double beta, co
     hisq_status st = gauge_args(lat, U, coef, S);
     if (st != HISQ_OK) return st;
     HIPCHK(lat, hipSetDevice(lat->device));
-    const size_t nblk = (size_t)((lat->V + 255) / 256);
+    const size_t nblk = (size_t)((lat->V + 63) / 64);
     Work w;
-    if ((st = get_work(lat, 8, w, 4 * nblk * sizeof(double))) != HISQ_OK) return st;   // U 0-3, staging 4-7
+    if ((st = get_work(lat, 8, w, nblk * sizeof(double))) != HISQ_OK) return st;   // U 0-3, staging 4-7
     const SmearGeom g = geom_of(lat);
     const double2 *src;
     if ((st = stage_in(lat, U, flags, w.field(4), &src)) != HISQ_OK) return st;
@@ -287,7 +287,7 @@ hisq_status hisq_gauge_action(hisq_lattice lat, const double *U, double beta, co
     // each loop is met once per link it holds: weights over the loop lengths
     GForceArgs a{w.field(0), nullptr, w.part, coef[0] / 4.0, coef[1] / 6.0, coef[2] / 6.0, 1.0};
     HIPCHK(lat, launch_gauge_force(g, a, 1, lat->s));
-    std::vector<double> part(4 * nblk);
+    std::vector<double> part(nblk);
     HIPCHK(lat, hipMemcpyAsync(part.data(), w.part, part.size() * sizeof(double), hipMemcpyDeviceToHost, lat->s));
     HIPCHK(lat, hipStreamSynchronize(lat->s));
     double re = 0.0;
