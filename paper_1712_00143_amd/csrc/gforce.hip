@@ -125,25 +125,34 @@ __device__ __forceinline__ void parallelograms(const SmearGeom &g, const Geo &q,
 template <int MODE>   // 0: force, 1: action partials
 __global__ void __launch_bounds__(256) k_gauge_force(SmearGeom g, GForceArgs a)
 {
-    // a block holds the four links of 64 sites (one wave per direction), so
-    // the neighbour links one direction's staples fetch serve the others
-    // from L1 / L2
-    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 64 + (threadIdx.x & 63);
-    const bool valid = vi < g.V;
+    // A block holds the four links (one wave per direction) of 64 sites of
+    // one x-y-z slab and walks a run of tch time slices: the links one
+    // direction's staples fetch serve the other directions, and those of the
+    // next slices, from L1 / L2 (the t neighbours are the block's own recent
+    // loads instead of a lattice-volume stride away).
+    const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
+    const int chunk = lb / a.ntile, tile = lb - chunk * a.ntile;
+    const long long nxyz = (long long)g.L[0] * g.L[1] * g.L[2];
+    const long long i = (long long)tile * 64 + (threadIdx.x & 63);
+    const bool valid = i < nxyz;
     const size_t V = (size_t)g.V;
     const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Geo q;
-    q.s = valid ? vi : 0;
     {
-        unsigned r = (unsigned)q.s;   // V <= 2^31
+        unsigned r = valid ? (unsigned)i : 0u;
         q.x[0] = (int)(r % (unsigned)g.L[0]);
         r /= (unsigned)g.L[0];
         q.x[1] = (int)(r % (unsigned)g.L[1]);
-        r /= (unsigned)g.L[1];
-        q.x[2] = (int)(r % (unsigned)g.L[2]);
-        q.x[3] = (int)(r / (unsigned)g.L[2]);
+        q.x[2] = (int)(r / (unsigned)g.L[1]);
     }
+    const long long ixyz = valid ? i : 0;
+    const int t0 = chunk * a.tch, t1 = t0 + a.tch < g.L[3] ? t0 + a.tch : g.L[3];
     const int perp[3] = {mu == 0 ? 1 : 0, mu <= 1 ? 2 : 1, mu <= 2 ? 3 : 2};
+    double v = 0.0;
+#pragma unroll 1
+    for (int t = t0; t < t1; t++) {
+        q.x[3] = t;
+        q.s = ixyz + (long long)t * g.S[3];
     M3 B = zero3();
 #pragma unroll 1
     for (int k = 0; k < 3; k++) {
@@ -162,33 +171,53 @@ __global__ void __launch_bounds__(256) k_gauge_force(SmearGeom g, GForceArgs a)
     }
     const M3 M = mul_na(ld(a.U + (size_t)mu * 9 * V, V, q.s), B);
     if constexpr (MODE == 0) {
-        if (!valid) return;
-        const double im3 = (M.e[0].y + M.e[4].y + M.e[8].y) * (1.0 / 3.0);
-        M3 F;
+        if (valid) {
+            const double im3 = (M.e[0].y + M.e[4].y + M.e[8].y) * (1.0 / 3.0);
+            M3 F;
 #pragma unroll
-        for (int i = 0; i < 3; i++)
+            for (int i2 = 0; i2 < 3; i2++)
 #pragma unroll
-            for (int j = 0; j < 3; j++) {
-                const double2 p = M.e[3 * i + j], r = M.e[3 * j + i];
-                F.e[3 * i + j] = make_double2(a.scale * 0.5 * (p.x - r.x), a.scale * (0.5 * (p.y + r.y) - (i == j ? im3 : 0.0)));
-            }
-        st(a.F + (size_t)mu * 9 * V, V, q.s, F);
+                for (int j = 0; j < 3; j++) {
+                    const double2 p = M.e[3 * i2 + j], r = M.e[3 * j + i2];
+                    F.e[3 * i2 + j] = make_double2(a.scale * 0.5 * (p.x - r.x),
+                                                   a.scale * (0.5 * (p.y + r.y) - (i2 == j ? im3 : 0.0)));
+                }
+            st(a.F + (size_t)mu * 9 * V, V, q.s, F);
+        }
     } else {
-        double v = valid ? M.e[0].x + M.e[4].x + M.e[8].x : 0.0;
+        if (valid) v += M.e[0].x + M.e[4].x + M.e[8].x;
+    }
+    }
+    if constexpr (MODE == 1) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         __shared__ double red[4];
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
         __syncthreads();
-        if (threadIdx.x == 0) a.part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+        if (threadIdx.x == 0) a.part[lb] = ((red[0] + red[1]) + red[2]) + red[3];
     }
 }
 
 }  // namespace
 
-hipError_t launch_gauge_force(const SmearGeom &g, const GForceArgs &a, int mode, hipStream_t s)
+void gauge_force_grid(const SmearGeom &g, int *ntile, int *tch, int *nblocks)
 {
-    const dim3 grid((unsigned)((g.V + 63) / 64)), blk(256);
+    const long long nxyz = (long long)g.L[0] * g.L[1] * g.L[2];
+    *ntile = (int)((nxyz + 63) / 64);
+    // enough blocks to fill the chip (about 2048), each with a run of slices
+    int nchunk = (int)((2048 + *ntile - 1) / *ntile);
+    nchunk = nchunk < 1 ? 1 : (nchunk > g.L[3] ? g.L[3] : nchunk);
+    *tch = (g.L[3] + nchunk - 1) / nchunk;
+    nchunk = (g.L[3] + *tch - 1) / *tch;
+    *nblocks = *ntile * nchunk;
+}
+
+hipError_t launch_gauge_force(const SmearGeom &g, const GForceArgs &a0, int mode, hipStream_t s)
+{
+    GForceArgs a = a0;
+    int nb;
+    gauge_force_grid(g, &a.ntile, &a.tch, &nb);
+    const dim3 grid((unsigned)nb), blk(256);
     if (mode == 0) hipLaunchKernelGGL((k_gauge_force<0>), grid, blk, 0, s, g, a);
     else hipLaunchKernelGGL((k_gauge_force<1>), grid, blk, 0, s, g, a);
     return hipGetLastError();

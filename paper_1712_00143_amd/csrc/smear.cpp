@@ -259,7 +259,7 @@ hisq_status hisq_gauge_force(hisq_lattice lat, const double *U, double beta, con
     const double2 *src;
     if ((st = stage_in(lat, U, flags, w.field(8), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    GForceArgs a{w.field(0), w.field(4), nullptr, coef[0], coef[1], coef[2], beta / 3.0};
+    GForceArgs a{w.field(0), w.field(4), nullptr, coef[0], coef[1], coef[2], beta / 3.0, 0, 0};
     HIPCHK(lat, launch_gauge_force(g, a, 0, lat->s));
     if (flags & HISQ_DEVICE_PTR) {
         HIPCHK(lat, launch_smear_from_planar(g, w.field(4), (double2 *)F, lat->s));
@@ -277,7 +277,9 @@ hisq_status hisq_gauge_action(hisq_lattice lat, const double *U, double beta, co
     hisq_status st = gauge_args(lat, U, coef, S);
     if (st != HISQ_OK) return st;
     HIPCHK(lat, hipSetDevice(lat->device));
-    const size_t nblk = (size_t)((lat->V + 63) / 64);
+    int ntile, tch, nb;
+    gauge_force_grid(geom_of(lat), &ntile, &tch, &nb);
+    const size_t nblk = (size_t)nb;
     Work w;
     if ((st = get_work(lat, 8, w, nblk * sizeof(double))) != HISQ_OK) return st;   // U 0-3, staging 4-7
     const SmearGeom g = geom_of(lat);
@@ -285,7 +287,7 @@ hisq_status hisq_gauge_action(hisq_lattice lat, const double *U, double beta, co
     if ((st = stage_in(lat, U, flags, w.field(4), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
     // each loop is met once per link it holds: weights over the loop lengths
-    GForceArgs a{w.field(0), nullptr, w.part, coef[0] / 4.0, coef[1] / 6.0, coef[2] / 6.0, 1.0};
+    GForceArgs a{w.field(0), nullptr, w.part, coef[0] / 4.0, coef[1] / 6.0, coef[2] / 6.0, 1.0, 0, 0};
     HIPCHK(lat, launch_gauge_force(g, a, 1, lat->s));
     std::vector<double> part(nblk);
     HIPCHK(lat, hipMemcpyAsync(part.data(), w.part, part.size() * sizeof(double), hipMemcpyDeviceToHost, lat->s));
