@@ -28,17 +28,22 @@ struct OuterArgs {
 hipError_t launch_ff_outer(const SmearGeom &g, const OuterArgs &a, hipStream_t s);
 
 // Adjoint of the staple of M through direction d for output direction mu,
-//   T(x) = sum_{s in signs} L_s(x) M(x+s) L_s(x+mu)^+   (L_{+d}(x) = U_d(x),
-//                                                       L_{-d}(x) = U_d(x-d)^+),
-// for the gradient G of T, scaled by c:
-//   GM  (= or +=)  the gradient with respect to M,
-//   GUd +=         the gradient with respect to the links U_d.
-// Either output may be null; signs: 1 = +d only, 2 = -d only, 3 = both.
+//   T(x) = sum_s L_s(x) M_s(x+s) L_s(x+mu)^+   (s = +d, -d; L_{+d}(x) = U_d(x),
+//                                              L_{-d}(x) = U_d(x-d)^+),
+// for the gradient G_s of T (each sign its own field, the sum of G[s][0]
+// and, if not null, G[s][1]), scaled by c:
+//   GM[s] (= or +=)  the gradient with respect to M_s (GM[0] may equal GM[1]),
+//   GUd +=           the gradient with respect to the links U_d.
+// Sign index 0 is +d, 1 is -d; M[s] null leaves that sign out; GM[s] and
+// GUd may be null.
 struct StapleAdjArgs {
-    const double2 *Ud, *M, *G;
-    double2 *GM, *GUd;
+    const double2 *Ud;
+    const double2 *M[2];
+    const double2 *G[2][2];
+    double2 *GM[2];
+    double2 *GUd;
     double c;
-    int mu, d, signs, gm_init;
+    int mu, d, gm_init;
     int ord[4];
 };
 hipError_t launch_staple_adjoint(const SmearGeom &g, const StapleAdjArgs &a, hipStream_t s);

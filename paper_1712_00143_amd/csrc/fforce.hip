@@ -93,6 +93,13 @@ __global__ void __launch_bounds__(256) k_ff_outer(SmearGeom g, OuterArgs a)
     }
 }
 
+__device__ __forceinline__ M3 ld_grad(const double2 *const G[2], size_t V, long long s)
+{
+    M3 m = ld(G[0], V, s);
+    if (G[1]) m = add(m, ld(G[1], V, s));
+    return m;
+}
+
 __global__ void __launch_bounds__(256) k_staple_adjoint(SmearGeom g, StapleAdjArgs a)
 {
     const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
@@ -105,15 +112,27 @@ __global__ void __launch_bounds__(256) k_staple_adjoint(SmearGeom g, StapleAdjAr
     const long long pd = shift(s, xd, Sd, Ld, 1), md = shift(s, xd, Sd, Ld, -1);
     const long long pm = shift(s, xm, Sm, Lm, 1), mm = shift(s, xm, Sm, Lm, -1);
     const long long md_pm = shift(md, xm, Sm, Lm, 1), mm_pd = shift(mm, xd, Sd, Ld, 1);
-    const bool plus = a.signs & 1, minus = a.signs & 2;
-    if (a.GM) {
-        // staple output at x = y - d (sign +) and x = y + d (sign -) holds M(y)
-        M3 acc = zero3();
-        if (plus) acc = add(acc, mul_nn(mul_an(ld(a.Ud, V, md_pm), ld(a.G, V, md)), ld(a.Ud, V, md)));
-        if (minus) acc = add(acc, mul_na(mul_nn(ld(a.Ud, V, pm), ld(a.G, V, pd)), ld(a.Ud, V, s)));
-        M3 out = a.gm_init ? zero3() : ld(a.GM, V, s);
-        axpy(out, a.c, acc);
-        st(a.GM, V, s, out);
+    const bool plus = a.M[0] != nullptr, minus = a.M[1] != nullptr;
+    // gradient with respect to M_s(y): the + staple at x = y - d and the -
+    // staple at x = y + d read it
+    if (a.GM[0] || a.GM[1]) {
+        M3 gp = zero3(), gmn = zero3();
+        if (plus && a.GM[0]) gp = mul_nn(mul_an(ld(a.Ud, V, md_pm), ld_grad(a.G[0], V, md)), ld(a.Ud, V, md));
+        if (minus && a.GM[1]) gmn = mul_na(mul_nn(ld(a.Ud, V, pm), ld_grad(a.G[1], V, pd)), ld(a.Ud, V, s));
+        if (a.GM[0] == a.GM[1]) {
+            M3 out = a.gm_init ? zero3() : ld(a.GM[0], V, s);
+            axpy(out, a.c, add(gp, gmn));
+            st(a.GM[0], V, s, out);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                double2 *gm = a.GM[k];
+                if (!gm || !(k == 0 ? plus : minus)) continue;
+                M3 out = a.gm_init ? zero3() : ld(gm, V, s);
+                axpy(out, a.c, k == 0 ? gp : gmn);
+                st(gm, V, s, out);
+            }
+        }
     }
     if (a.GUd) {
         // U_d(z) is the first link of the + staple at z and of the - staple at
@@ -121,12 +140,12 @@ __global__ void __launch_bounds__(256) k_staple_adjoint(SmearGeom g, StapleAdjAr
         // at z - mu + d
         M3 acc = zero3();
         if (plus) {
-            acc = add(acc, mul_nn(mul_na(ld(a.M, V, pd), ld(a.Ud, V, pm)), ld(a.G, V, s)));
-            acc = add(acc, dag(mul_nn(mul_nn(ld(a.G, V, mm), ld(a.Ud, V, mm)), ld(a.M, V, mm_pd))));
+            acc = add(acc, mul_nn(mul_na(ld(a.M[0], V, pd), ld(a.Ud, V, pm)), ld_grad(a.G[0], V, s)));
+            acc = add(acc, dag(mul_nn(mul_nn(ld_grad(a.G[0], V, mm), ld(a.Ud, V, mm)), ld(a.M[0], V, mm_pd))));
         }
         if (minus) {
-            acc = add(acc, dag(mul_nn(mul_nn(ld(a.M, V, s), ld(a.Ud, V, pm)), ld(a.G, V, pd))));
-            acc = add(acc, mul_nn(mul_na(ld(a.G, V, mm_pd), ld(a.Ud, V, mm)), ld(a.M, V, mm)));
+            acc = add(acc, dag(mul_nn(mul_nn(ld(a.M[1], V, s), ld(a.Ud, V, pm)), ld_grad(a.G[1], V, pd))));
+            acc = add(acc, mul_nn(mul_na(ld_grad(a.G[1], V, mm_pd), ld(a.Ud, V, mm)), ld(a.M[1], V, mm)));
         }
         M3 out = ld(a.GUd, V, s);
         axpy(out, a.c, acc);
@@ -324,7 +343,7 @@ hipError_t launch_ff_outer(const SmearGeom &g, const OuterArgs &a, hipStream_t s
 
 hipError_t launch_staple_adjoint(const SmearGeom &g, const StapleAdjArgs &a, hipStream_t s)
 {
-    if (a.signs < 1 || a.signs > 3) return hipErrorInvalidValue;
+    if (!a.Ud || (!a.M[0] && !a.M[1]) || (a.M[0] && !a.G[0][0]) || (a.M[1] && !a.G[1][0])) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_staple_adjoint, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, s, g, a);
     return hipGetLastError();
 }

@@ -320,9 +320,9 @@ hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5]
     hipError_t e;
     auto U_ = [&](int d) { return Ul + (size_t)d * fsz; };
     auto GU_ = [&](int d) { return GU + (size_t)d * fsz; };
-    auto adj = [&](int mu, int d, int signs, const double2 *M, const double2 *Gin, double2 *GM, int gm_init,
-                   double2 *GUd, double coef) {
-        StapleAdjArgs a{U_(d), M, Gin, GM, GUd, coef, mu, d, signs, gm_init, {}};
+    // both signs of the staple through d, one field M, gradient Gin
+    auto adj = [&](int mu, int d, const double2 *M, const double2 *Gin, double2 *GM, double2 *GUd, double coef) {
+        StapleAdjArgs a{U_(d), {M, M}, {{Gin, nullptr}, {Gin, nullptr}}, {GM, GM}, GUd, coef, mu, d, 0, {}};
         const int f[2] = {d, mu};
         smear_order(f, 2, a.ord);
         return launch_staple_adjoint(g, a, s);
@@ -356,20 +356,29 @@ hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5]
                 const int sig = perp[k], inu = (k + 1) % 3, irho = (k + 2) % 3;
                 const int nu = perp[inu], rho = perp[irho];
                 if ((e = launch_field_axpby(GT2, 0.0, Gmu, c[2], fsz, s)) != hipSuccess) return e;
-                if (c[3] != 0.0 && (e = adj(mu, sig, 3, T2 + k * fsz, Gmu, GT2, 0, GU_(sig), c[3])) != hipSuccess)
-                    return e;
-                if ((e = adj(mu, rho, 3, T1 + inu * fsz, GT2, GT1 + inu * fsz, 0, GU_(rho), 1.0)) != hipSuccess) return e;
-                if ((e = adj(mu, nu, 3, T1 + irho * fsz, GT2, GT1 + irho * fsz, 0, GU_(nu), 1.0)) != hipSuccess) return e;
+                if (c[3] != 0.0 && (e = adj(mu, sig, T2 + k * fsz, Gmu, GT2, GU_(sig), c[3])) != hipSuccess) return e;
+                if ((e = adj(mu, rho, T1 + inu * fsz, GT2, GT1 + inu * fsz, GU_(rho), 1.0)) != hipSuccess) return e;
+                if ((e = adj(mu, nu, T1 + irho * fsz, GT2, GT1 + irho * fsz, GU_(nu), 1.0)) != hipSuccess) return e;
             }
         for (int k = 0; k < 3; k++) {
             const int nu = perp[k];
-            if ((e = adj(mu, nu, 3, U_(mu), GT1 + k * fsz, GU_(mu), 0, GU_(nu), 1.0)) != hipSuccess) return e;
-            if (!lep) continue;
-            // Lepage = S+(H+) + S-(H-), S+- the single-sign staples through nu
-            if ((e = adj(mu, nu, 1, Hp + k * fsz, Gmu, GHp, 1, GU_(nu), c[4])) != hipSuccess) return e;
-            if ((e = adj(mu, nu, 2, Hm + k * fsz, Gmu, GHm, 1, GU_(nu), c[4])) != hipSuccess) return e;
-            if ((e = adj(mu, nu, 1, U_(mu), GHp, GU_(mu), 0, GU_(nu), 1.0)) != hipSuccess) return e;
-            if ((e = adj(mu, nu, 2, U_(mu), GHm, GU_(mu), 0, GU_(nu), 1.0)) != hipSuccess) return e;
+            if (!lep) {
+                if ((e = adj(mu, nu, U_(mu), GT1 + k * fsz, GU_(mu), GU_(nu), 1.0)) != hipSuccess) return e;
+                continue;
+            }
+            // Lepage = S+(H+) + S-(H-), S+- the single-sign staples through nu:
+            // first the gradients of H+- (and the links' share), then every
+            // staple of U_mu through nu at once (its 3-staple gradient GT1 on
+            // both signs, GH+- on one each)
+            StapleAdjArgs a1{U_(nu), {Hp + k * fsz, Hm + k * fsz}, {{Gmu, nullptr}, {Gmu, nullptr}}, {GHp, GHm},
+                             GU_(nu), c[4], mu, nu, 1, {}};
+            StapleAdjArgs a2{U_(nu), {U_(mu), U_(mu)}, {{GT1 + k * fsz, GHp}, {GT1 + k * fsz, GHm}},
+                             {GU_(mu), GU_(mu)}, GU_(nu), 1.0, mu, nu, 0, {}};
+            const int f[2] = {nu, mu};
+            smear_order(f, 2, a1.ord);
+            smear_order(f, 2, a2.ord);
+            if ((e = launch_staple_adjoint(g, a1, s)) != hipSuccess) return e;
+            if ((e = launch_staple_adjoint(g, a2, s)) != hipSuccess) return e;
         }
     }
     return hipSuccess;
