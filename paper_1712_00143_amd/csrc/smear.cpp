@@ -447,31 +447,40 @@ hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const d
     hisq_status st = ff_check(lat, n, alpha, X, F);
     if (st != HISQ_OK) return st;
     if (!U) return set_err(lat, HISQ_ERR_ARG, "null argument");
-    // the smeared links become the lattice's links (the Dslash of Y = D_oe X)
-    if ((st = hisq_smear_links(lat, U, nullptr, nullptr, (flags & HISQ_DEVICE_PTR) | HISQ_LOAD_RESULT)) != HISQ_OK)
-        return st;
     HIPCHK(lat, hipSetDevice(lat->device));
     const size_t vb = (size_t)n * lat->h * 3 * sizeof(double2);
-    // fields: U 0-3, level-1 sum 4-7, W 8-11, GX 12-15, GN 16-19, GW 20-23,
-    // GU 24-27 (also the input and output staging), scratch 28-45
+    // fields: U 0-3, level-1 sum 4-7, W 8-11, level-2 sum then GX 12-15, GN
+    // 16-19, GW 20-23, GU 24-27 (also the input and output staging),
+    // scratch 28-45
     Work w;
     if ((st = get_work(lat, 46, w, 2 * vb + 64 * sizeof(double))) != HISQ_OK) return st;
     const size_t fsz = w.fsz;
-    double2 *Xd = (double2 *)w.part, *Yd = Xd + (size_t)n * lat->h * 3;
-    double *ad = (double *)(Yd + (size_t)n * lat->h * 3);
-    const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
-    HIPCHK(lat, hipMemcpyAsync(Xd, X, vb, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, lat->s));
-    HIPCHK(lat, hipMemcpyAsync(ad, alpha, n * sizeof(double), hipMemcpyHostToDevice, lat->s));
-    if ((st = ff_solutions_odd(lat, n, Xd, Yd)) != HISQ_OK) return st;
     const SmearGeom g = geom_of(lat);
+    const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
+    // the smearing, keeping its level-1 sum and projection for the chain rule;
+    // the smeared links become the lattice's links (the Dslash of D_oe X)
     const double2 *src;
     if ((st = stage_in(lat, U, flags, w.field(24), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    // forward: level-1 sum V and its projection W
     HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(28), w.field(31), LV1, fsz, lat->s));
     HIPCHK(lat, launch_field_axpby(w.field(8), 0.0, w.field(4), 1.0, 4 * fsz, lat->s));
     HIPCHK(lat, hipMemsetAsync(w.bad, 0, sizeof(int), lat->s));
     HIPCHK(lat, launch_smear_unitarize(g, w.field(8), w.bad, lat->s));
+    if ((st = check_projection(lat, w.bad)) != HISQ_OK) return st;
+    HIPCHK(lat, run_fat7(g, w.field(8), w.field(12), w.field(28), w.field(31), LV2, fsz, lat->s));
+    {
+        const size_t bytes = link_array_bytes(lat);
+        if (!lat->fat64) HIPCHK(lat, hipMalloc(&lat->fat64, bytes));
+        if (!lat->lng64) HIPCHK(lat, hipMalloc(&lat->lng64, bytes));
+        HIPCHK(lat, launch_smear_output(g, w.field(12), w.field(8), NAIK, (double2 *)lat->fat64, (double2 *)lat->lng64,
+                                        lat->s));
+        if ((st = adopt_device_links(lat)) != HISQ_OK) return st;
+    }
+    double2 *Xd = (double2 *)w.part, *Yd = Xd + (size_t)n * lat->h * 3;
+    double *ad = (double *)(Yd + (size_t)n * lat->h * 3);
+    HIPCHK(lat, hipMemcpyAsync(Xd, X, vb, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, lat->s));
+    HIPCHK(lat, hipMemcpyAsync(ad, alpha, n * sizeof(double), hipMemcpyHostToDevice, lat->s));
+    if ((st = ff_solutions_odd(lat, n, Xd, Yd)) != HISQ_OK) return st;
     // gradients with respect to the level-2 sum (phases folded) and the Naik product
     OuterArgs oa{Xd, Yd, ad, n, lat->h, w.field(12), w.field(16), 1, NAIK};
     HIPCHK(lat, launch_ff_outer(g, oa, lat->s));
@@ -488,7 +497,8 @@ hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const d
         HIPCHK(lat, launch_smear_from_planar(g, w.field(24), w.field(12), lat->s));
         HIPCHK(lat, hipMemcpyAsync(F, w.field(12), link_array_bytes(lat), hipMemcpyDeviceToHost, lat->s));
     }
-    return check_projection(lat, w.bad);
+    HIPCHK(lat, hipStreamSynchronize(lat->s));
+    return HISQ_OK;
 }
 
 }  // extern "C"
