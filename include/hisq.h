@@ -453,9 +453,9 @@ hisq_status hisq_fermion_force_links(hisq_lattice lat, int n, const double *alph
  * at the rate Re Tr(X F_mu(x)) (and S at minus that rate).  The chain rule
  * runs through the Naik product, the second fat7 level, the U(3) projection
  * and the first level.  U is smeared first and the result loaded as the
- * lattice's links (as hisq_smear_links with HISQ_LOAD_RESULT would).  Workspace:
- * 46 link-direction fields (144 V bytes each) and 2 n V/2 vectors, kept until
- * hisq_destroy.  Errors: HISQ_ERR_ARG, HISQ_ERR_BREAKDOWN (a level-1 link
+ * lattice's links (as hisq_smear_links with HISQ_LOAD_RESULT would).
+ * Workspace: 88 link-direction fields (144 V bytes each: 13.3 GB at 32^4)
+ * and 2 n V/2 vectors, kept until hisq_destroy.  Errors: HISQ_ERR_ARG, HISQ_ERR_BREAKDOWN (a level-1 link
  * has no U(3) projection; the lattice keeps the links it had),
  * HISQ_ERR_OOM / HISQ_ERR_HIP. */
 hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const double *alpha, const double *X,

@@ -78,14 +78,18 @@ hisq_status get_work(hisq_lattice lat, int nf, Work &w, size_t extra = 0)
 // then for each sig != mu pass 2 (the 5-staples avoiding sig) and pass 3
 // (their c5 share and the 7-staples through sig): 7 passes instead of one
 // kernel per path class and pair.
-hipError_t run_fat7(const SmearGeom &g, const double2 *U, double2 *out, double2 *T1, double2 *T2,
-                    const double c[5], size_t fsz, hipStream_t s)
+// keep: T1 and T2 hold 12 fields each and direction mu's intermediates stay
+// in their fields 3 mu .. 3 mu + 2 (for the adjoint); otherwise T1 holds
+// three fields and T2 one, reused for every direction.
+hipError_t run_fat7(const SmearGeom &g, const double2 *U, double2 *out, double2 *T1all, double2 *T2all,
+                    const double c[5], size_t fsz, hipStream_t s, bool keep = false)
 {
     const bool need5 = c[2] != 0.0 || c[3] != 0.0;
     for (int mu = 0; mu < 4; mu++) {
         int perp[3], np = 0;
         for (int d = 0; d < 4; d++)
             if (d != mu) perp[np++] = d;
+        double2 *T1 = keep ? T1all + (size_t)3 * mu * fsz : T1all;
         double2 *F = out + (size_t)mu * fsz;
         Pass1Args p1{U, F, {nullptr, nullptr, nullptr}, c[0], c[1], c[4], mu, {perp[0], perp[1], perp[2]}, {}};
         if (need5)
@@ -99,6 +103,7 @@ hipError_t run_fat7(const SmearGeom &g, const double2 *U, double2 *out, double2 
         for (int k = 0; k < 3; k++) {
             const int sig = perp[k], inu = (k + 1) % 3, irho = (k + 2) % 3;
             const int nu = perp[inu], rho = perp[irho];
+            double2 *T2 = keep ? T2all + (size_t)(3 * mu + k) * fsz : T2all;
             Pass2Args p2{U, T1 + (size_t)inu * fsz, T1 + (size_t)irho * fsz, T2, mu, nu, rho, {}};
             const int f2[3] = {nu, rho, mu};
             smear_order(f2, 3, p2.ord);
@@ -306,16 +311,15 @@ hisq_status hisq_gauge_action(hisq_lattice lat, const double *U, double beta, co
 namespace {
 
 // Gradient of sum Re Tr(fat7(Ul; c)_mu(x) G_mu(x)) with respect to Ul, added
-// to GU (four planar fields each): the forward intermediates of each output
-// direction are rebuilt (3-staples T1, 5-staples T2, the single-sign
-// 3-staples H+- of the Lepage term) and every pass is undone by its
-// gather-form adjoint.  sc: 18 scratch fields.
+// to GU (four planar fields each): every pass is undone by its gather-form
+// adjoint, reading the forward intermediates run_fat7 kept (T1all, T2all:
+// 12 fields each) and the single-sign 3-staples H+- of the Lepage term,
+// rebuilt here.  sc: 12 scratch fields.
 hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5], const double2 *G, double2 *GU,
-                        double2 *sc, size_t fsz, hipStream_t s)
+                        const double2 *T1all, const double2 *T2all, double2 *sc, size_t fsz, hipStream_t s)
 {
-    double2 *T1 = sc, *T2 = sc + 3 * fsz, *Hp = sc + 6 * fsz, *Hm = sc + 9 * fsz, *GT1 = sc + 12 * fsz;
-    double2 *GT2 = sc + 15 * fsz, *GHp = sc + 16 * fsz, *GHm = sc + 17 * fsz;
-    double2 *Fdummy = GT2;   // pass 1's own sum, not used here
+    double2 *Hp = sc, *Hm = sc + 3 * fsz, *GT1 = sc + 6 * fsz;
+    double2 *GT2 = sc + 9 * fsz, *GHp = sc + 10 * fsz, *GHm = sc + 11 * fsz;
     const bool need5 = c[2] != 0.0 || c[3] != 0.0, lep = c[4] != 0.0;
     hipError_t e;
     auto U_ = [&](int d) { return Ul + (size_t)d * fsz; };
@@ -332,21 +336,12 @@ hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5]
         for (int d = 0; d < 4; d++)
             if (d != mu) perp[np++] = d;
         const double2 *Gmu = G + (size_t)mu * fsz;
-        // forward intermediates
-        Pass1Args p1{Ul, Fdummy, {T1, T1 + fsz, T1 + 2 * fsz}, 0.0, 0.0, 0.0, mu, {perp[0], perp[1], perp[2]}, {}};
-        smear_order(perp, 0, p1.ord);
-        if ((e = launch_smear_pass1(g, p1, s)) != hipSuccess) return e;
+        // forward intermediates: the kept 3- and 5-staple fields of this
+        // direction, and the single-sign 3-staples of the Lepage term
+        const double2 *T1 = T1all + (size_t)3 * mu * fsz, *T2 = T2all + (size_t)3 * mu * fsz;
         if (lep)
             for (int k = 0; k < 3; k++)
                 if ((e = launch_ff_halves(g, Ul, mu, perp[k], Hp + k * fsz, Hm + k * fsz, s)) != hipSuccess) return e;
-        if (need5)
-            for (int k = 0; k < 3; k++) {
-                const int inu = (k + 1) % 3, irho = (k + 2) % 3;
-                Pass2Args p2{Ul, T1 + inu * fsz, T1 + irho * fsz, T2 + k * fsz, mu, perp[inu], perp[irho], {}};
-                const int f2[3] = {perp[inu], perp[irho], mu};
-                smear_order(f2, 3, p2.ord);
-                if ((e = launch_smear_pass2(g, p2, s)) != hipSuccess) return e;
-            }
         // reverse
         if ((e = launch_field_axpby(GU_(mu), 1.0, Gmu, c[0], fsz, s)) != hipSuccess) return e;
         for (int k = 0; k < 3; k++)
@@ -450,10 +445,11 @@ hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const d
     HIPCHK(lat, hipSetDevice(lat->device));
     const size_t vb = (size_t)n * lat->h * 3 * sizeof(double2);
     // fields: U 0-3, level-1 sum 4-7, W 8-11, level-2 sum then GX 12-15, GN
-    // 16-19, GW 20-23, GU 24-27 (also the input and output staging),
-    // scratch 28-45
+    // 16-19, GW 20-23, GU 24-27 (also the input and output staging), the
+    // kept 3- and 5-staples of level 1 28-51 and of level 2 52-75, scratch
+    // 76-87
     Work w;
-    if ((st = get_work(lat, 46, w, 2 * vb + 64 * sizeof(double))) != HISQ_OK) return st;
+    if ((st = get_work(lat, 88, w, 2 * vb + 64 * sizeof(double))) != HISQ_OK) return st;
     const size_t fsz = w.fsz;
     const SmearGeom g = geom_of(lat);
     const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
@@ -462,12 +458,12 @@ hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const d
     const double2 *src;
     if ((st = stage_in(lat, U, flags, w.field(24), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(28), w.field(31), LV1, fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(28), w.field(40), LV1, fsz, lat->s, true));
     HIPCHK(lat, launch_field_axpby(w.field(8), 0.0, w.field(4), 1.0, 4 * fsz, lat->s));
     HIPCHK(lat, hipMemsetAsync(w.bad, 0, sizeof(int), lat->s));
     HIPCHK(lat, launch_smear_unitarize(g, w.field(8), w.bad, lat->s));
     if ((st = check_projection(lat, w.bad)) != HISQ_OK) return st;
-    HIPCHK(lat, run_fat7(g, w.field(8), w.field(12), w.field(28), w.field(31), LV2, fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(8), w.field(12), w.field(52), w.field(64), LV2, fsz, lat->s, true));
     {
         const size_t bytes = link_array_bytes(lat);
         if (!lat->fat64) HIPCHK(lat, hipMalloc(&lat->fat64, bytes));
@@ -486,10 +482,12 @@ hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const d
     HIPCHK(lat, launch_ff_outer(g, oa, lat->s));
     HIPCHK(lat, hipMemsetAsync(w.field(20), 0, 4 * fsz * sizeof(double2), lat->s));
     HIPCHK(lat, launch_ff_naik_adjoint(g, w.field(8), w.field(16), w.field(20), lat->s));
-    HIPCHK(lat, fat7_adjoint(g, w.field(8), LV2, w.field(12), w.field(20), w.field(28), fsz, lat->s));
+    HIPCHK(lat, fat7_adjoint(g, w.field(8), LV2, w.field(12), w.field(20), w.field(52), w.field(64), w.field(76), fsz,
+                             lat->s));
     HIPCHK(lat, launch_ff_unitarize_adjoint(g, w.field(4), w.field(20), lat->s));
     HIPCHK(lat, hipMemsetAsync(w.field(24), 0, 4 * fsz * sizeof(double2), lat->s));
-    HIPCHK(lat, fat7_adjoint(g, w.field(0), LV1, w.field(20), w.field(24), w.field(28), fsz, lat->s));
+    HIPCHK(lat, fat7_adjoint(g, w.field(0), LV1, w.field(20), w.field(24), w.field(28), w.field(40), w.field(76), fsz,
+                             lat->s));
     HIPCHK(lat, launch_ff_project(g, w.field(0), w.field(24), w.field(24), lat->s));
     if (dev) {
         HIPCHK(lat, launch_smear_from_planar(g, w.field(24), (double2 *)F, lat->s));
