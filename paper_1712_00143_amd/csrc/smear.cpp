@@ -78,28 +78,23 @@ hisq_status get_work(hisq_lattice lat, int nf, Work &w, size_t extra = 0)
 // then for each sig != mu pass 2 (the 5-staples avoiding sig) and pass 3
 // (their c5 share and the 7-staples through sig): 7 passes instead of one
 // kernel per path class and pair.
-// keep: T1 and T2 hold 12 fields each and direction mu's intermediates stay
-// in their fields 3 mu .. 3 mu + 2 (for the adjoint); otherwise T1 holds
-// three fields and T2 one, reused for every direction.
+// T1all: 12 fields (every direction's 3-staples, from one pass-1 launch).
+// keep: T2all holds 12 fields and direction mu's 5-staple sums stay in its
+// fields 3 mu .. 3 mu + 2 (for the adjoint); otherwise T2all is one field,
+// reused for every direction.
 hipError_t run_fat7(const SmearGeom &g, const double2 *U, double2 *out, double2 *T1all, double2 *T2all,
                     const double c[5], size_t fsz, hipStream_t s, bool keep = false)
 {
     const bool need5 = c[2] != 0.0 || c[3] != 0.0;
+    Pass1Args p1{U, out, need5 ? T1all : nullptr, c[0], c[1], c[4]};
+    hipError_t e = launch_smear_pass1(g, p1, s);
+    if (e != hipSuccess || !need5) return e;
     for (int mu = 0; mu < 4; mu++) {
         int perp[3], np = 0;
         for (int d = 0; d < 4; d++)
             if (d != mu) perp[np++] = d;
-        double2 *T1 = keep ? T1all + (size_t)3 * mu * fsz : T1all;
+        double2 *T1 = T1all + (size_t)3 * mu * fsz;
         double2 *F = out + (size_t)mu * fsz;
-        Pass1Args p1{U, F, {nullptr, nullptr, nullptr}, c[0], c[1], c[4], mu, {perp[0], perp[1], perp[2]}, {}};
-        if (need5)
-            for (int k = 0; k < 3; k++) p1.T1[k] = T1 + (size_t)k * fsz;
-        smear_order(perp, 0, p1.ord);
-        hipError_t e = launch_smear_pass1(g, p1, s);
-        if (e != hipSuccess || !need5) {
-            if (e != hipSuccess) return e;
-            continue;
-        }
         for (int k = 0; k < 3; k++) {
             const int sig = perp[k], inu = (k + 1) % 3, irho = (k + 2) % 3;
             const int nu = perp[inu], rho = perp[irho];
@@ -150,13 +145,13 @@ hisq_status hisq_fat7(hisq_lattice lat, const double coef[5], const double *in, 
     if (!lat || !coef || !in || !out) return set_err(lat, HISQ_ERR_ARG, "null argument");
     HIPCHK(lat, hipSetDevice(lat->device));
     Work w;
-    hisq_status st = get_work(lat, 16, w);   // U 0-3, result 4-7, staging 8-11, T1 12-14, T2 15
+    hisq_status st = get_work(lat, 25, w);   // U 0-3, result 4-7, staging 8-11, T1 12-23, T2 24
     if (st != HISQ_OK) return st;
     const SmearGeom g = geom_of(lat);
     const double2 *src;
     if ((st = stage_in(lat, in, flags, w.field(8), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(15), coef, w.fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(24), coef, w.fsz, lat->s));
     if (flags & HISQ_DEVICE_PTR) {
         HIPCHK(lat, launch_smear_from_planar(g, w.field(4), (double2 *)out, lat->s));
     } else {
@@ -197,20 +192,20 @@ hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, 
     HIPCHK(lat, hipSetDevice(lat->device));
     const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
     // fields: thin U 0-3, level 1 / projected W 4-7, level 2 X 8-11 (also the
-    // host input staging), T1 12-14, T2 15, output staging 16-23 for host
+    // host input staging), T1 12-23, T2 24, output staging 25-32 for host
     // outputs that are not loaded
     const bool stage_out = !dev && !load;
     Work w;
-    hisq_status st = get_work(lat, stage_out ? 24 : 16, w);
+    hisq_status st = get_work(lat, stage_out ? 33 : 25, w);
     if (st != HISQ_OK) return st;
     const SmearGeom g = geom_of(lat);
     const double2 *src;
     if ((st = stage_in(lat, thin, flags, w.field(8), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(15), LV1, w.fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(24), LV1, w.fsz, lat->s));
     HIPCHK(lat, hipMemsetAsync(w.bad, 0, sizeof(int), lat->s));
     HIPCHK(lat, launch_smear_unitarize(g, w.field(4), w.bad, lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(4), w.field(8), w.field(12), w.field(15), LV2, w.fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(4), w.field(8), w.field(12), w.field(24), LV2, w.fsz, lat->s));
     double2 *of, *ol;
     if (load) {
         const size_t bytes = link_array_bytes(lat);
@@ -222,8 +217,8 @@ hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, 
         of = (double2 *)fat;
         ol = (double2 *)lng;
     } else {
-        of = w.field(16);
-        ol = w.field(20);
+        of = w.field(25);
+        ol = w.field(29);
     }
     HIPCHK(lat, launch_smear_output(g, w.field(8), w.field(4), NAIK, of, ol, lat->s));
     if ((st = check_projection(lat, w.bad)) != HISQ_OK) {

@@ -18,9 +18,11 @@ struct SmearGeom {
 
 // fat7(U; c1, c3, c5, c7; cL) of output direction mu in three kinds of
 // pass over planar fields (U: the four-direction input):
-//   pass 1       F = c1 U_mu + sum over nu != mu of (c3 T1_nu + cL Lep_nu),
-//                T1_nu = U_nu(x) U_mu(x+nu) U_nu(x+mu)^+ + (the -nu staple)
-//                stored for passes 2 (Lep_nu: the two-step staple);
+//   pass 1       (every mu in one launch) F_mu = c1 U_mu + sum over nu != mu
+//                of (c3 T1_nu + cL Lep_nu), T1_nu = U_nu(x) U_mu(x+nu)
+//                U_nu(x+mu)^+ + (the -nu staple) stored for passes 2 as
+//                T1 field 3 mu + k, nu the k-th direction other than mu
+//                (Lep_nu: the two-step staple);
 //   pass 2 (sig) T2 = staple of T1_nu through rho + staple of T1_rho through
 //                nu, {nu, rho} the two directions other than mu and sig
 //                (all 5-link staples whose steps avoid sig);
@@ -30,12 +32,9 @@ struct SmearGeom {
 // fastest); the directions a pass steps along come next.
 struct Pass1Args {
     const double2 *U;
-    double2 *F;
-    double2 *T1[3];   // null: not stored
+    double2 *F;    // four fields
+    double2 *T1;   // twelve fields, or null: not stored
     double c1, c3, cL;
-    int mu;
-    int perp[3];
-    int ord[4];
 };
 struct Pass2Args {
     const double2 *U;

@@ -56,19 +56,29 @@ __device__ __forceinline__ M3 lepage_at(const double2 *__restrict__ U, const dou
     return T;
 }
 
-// Pass 1 of output direction mu: the 3-link staples through all three nu
-// != mu, stored as T1[i] when WT, and
-//   F = c1 U_mu + sum_nu (c3 T1_nu + cL Lepage_nu).
+// Pass 1 of every output direction at once: a block holds 64 sites and one
+// wave per direction mu (the neighbour links one direction's staples fetch
+// serve the others from L1 / L2).  For each mu, the 3-link staples through
+// the three nu != mu, stored as T1[3 mu + k] when WT, and
+//   F_mu = c1 U_mu + sum_nu (c3 T1_nu + cL Lepage_nu).
 template <bool LEP, bool WT>
 __global__ void __launch_bounds__(256) k_smear_pass1(SmearGeom g, Pass1Args a)
 {
-    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
-    if (vi >= g.V) return;
+    const long long s = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 64 + (threadIdx.x & 63);
+    if (s >= g.V) return;
     const size_t V = (size_t)g.V;
-    int c[4];
-    const long long s = walk((unsigned)vi, g, a.ord, c);   // V <= 2^31
-    const int mu = a.mu;
-    const int Sm = pick(g.S, mu), Lm = pick(g.L, mu), xm = coord(c, a.ord, mu);
+    const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int x[4];
+    {
+        unsigned r = (unsigned)s;   // V <= 2^31
+        x[0] = (int)(r % (unsigned)g.L[0]);
+        r /= (unsigned)g.L[0];
+        x[1] = (int)(r % (unsigned)g.L[1]);
+        r /= (unsigned)g.L[1];
+        x[2] = (int)(r % (unsigned)g.L[2]);
+        x[3] = (int)(r / (unsigned)g.L[2]);
+    }
+    const int Sm = pick(g.S, mu), Lm = pick(g.L, mu), xm = pick(x, mu);
     const double2 *Umu = a.U + (size_t)mu * 9 * V;
     M3 F = ld(Umu, V, s);
 #pragma unroll
@@ -77,15 +87,15 @@ __global__ void __launch_bounds__(256) k_smear_pass1(SmearGeom g, Pass1Args a)
     // hoisted and spill
 #pragma unroll 1
     for (int k = 0; k < 3; k++) {
-        const int nu = a.perp[k];
-        const int Sn = pick(g.S, nu), Ln = pick(g.L, nu), xn = coord(c, a.ord, nu);
+        const int nu = k + (k >= mu ? 1 : 0);
+        const int Sn = pick(g.S, nu), Ln = pick(g.L, nu), xn = pick(x, nu);
         const double2 *Un = a.U + (size_t)nu * 9 * V;
         const M3 T = staple_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm);
         axpy(F, a.c3, T);
-        if constexpr (WT) st(k == 0 ? a.T1[0] : k == 1 ? a.T1[1] : a.T1[2], V, s, T);
+        if constexpr (WT) st(a.T1 + (size_t)(3 * mu + k) * 9 * V, V, s, T);
         if constexpr (LEP) axpy(F, a.cL, lepage_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm));
     }
-    st(a.F, V, s, F);
+    st(a.F + (size_t)mu * 9 * V, V, s, F);
 }
 
 // Pass 2 of (mu, sig): the 5-link staples whose transverse steps are the two
@@ -261,8 +271,8 @@ void smear_order(const int *first, int n, int ord[4])
 
 hipError_t launch_smear_pass1(const SmearGeom &g, const Pass1Args &a, hipStream_t s)
 {
-    const dim3 grid((unsigned)((g.V + 255) / 256)), blk(256);
-    const bool lep = a.cL != 0.0, wt = a.T1[0] != nullptr;
+    const dim3 grid((unsigned)((g.V + 63) / 64)), blk(256);
+    const bool lep = a.cL != 0.0, wt = a.T1 != nullptr;
     if (lep && wt) hipLaunchKernelGGL((k_smear_pass1<true, true>), grid, blk, 0, s, g, a);
     else if (lep) hipLaunchKernelGGL((k_smear_pass1<true, false>), grid, blk, 0, s, g, a);
     else if (wt) hipLaunchKernelGGL((k_smear_pass1<false, true>), grid, blk, 0, s, g, a);
