@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(256) k_ff_outer(SmearGeom g, OuterArgs a)
 {
     const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
     if (s >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     int x[4];
     coords4(g, s, x);
     const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
@@ -100,56 +100,80 @@ __device__ __forceinline__ M3 ld_grad(const double2 *const G[2], size_t V, long 
     return m;
 }
 
-__global__ void __launch_bounds__(256) k_staple_adjoint(SmearGeom g, StapleAdjArgs a)
+// A block holds 64 sites and three waves with one share of the work each, so
+// that each carries a short chain of loads and products (one thread doing all
+// of it needs over 200 registers and leaves two waves per SIMD): wave 0 the
+// gradient with respect to M (both signs), waves 1 and 2 the + and - staples'
+// shares of the gradient with respect to U_d, summed through LDS.
+__global__ void __launch_bounds__(192) k_staple_adjoint(SmearGeom g, StapleAdjArgs a)
 {
-    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
-    if (vi >= g.V) return;
-    const size_t V = (size_t)g.V;
-    int c[4];
-    const long long s = walk((unsigned)vi, g, a.ord, c);
-    const int Sm = pick(g.S, a.mu), Lm = pick(g.L, a.mu), xm = coord(c, a.ord, a.mu);
-    const int Sd = pick(g.S, a.d), Ld = pick(g.L, a.d), xd = coord(c, a.ord, a.d);
-    const long long pd = shift(s, xd, Sd, Ld, 1), md = shift(s, xd, Sd, Ld, -1);
-    const long long pm = shift(s, xm, Sm, Lm, 1), mm = shift(s, xm, Sm, Lm, -1);
-    const long long md_pm = shift(md, xm, Sm, Lm, 1), mm_pd = shift(mm, xd, Sd, Ld, 1);
+    const int lane = threadIdx.x & 63, role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 64 + lane;
+    const bool valid = vi < g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     const bool plus = a.M[0] != nullptr, minus = a.M[1] != nullptr;
-    // gradient with respect to M_s(y): the + staple at x = y - d and the -
-    // staple at x = y + d read it
-    if (a.GM[0] || a.GM[1]) {
-        M3 gp = zero3(), gmn = zero3();
-        if (plus && a.GM[0]) gp = mul_nn(mul_an(ld(a.Ud, V, md_pm), ld_grad(a.G[0], V, md)), ld(a.Ud, V, md));
-        if (minus && a.GM[1]) gmn = mul_na(mul_nn(ld(a.Ud, V, pm), ld_grad(a.G[1], V, pd)), ld(a.Ud, V, s));
-        if (a.GM[0] == a.GM[1]) {
-            M3 out = a.gm_init ? zero3() : ld(a.GM[0], V, s);
-            axpy(out, a.c, add(gp, gmn));
-            st(a.GM[0], V, s, out);
-        } else {
+    long long s = 0, pd = 0, md = 0, pm = 0, mm = 0, md_pm = 0, mm_pd = 0;
+    if (valid) {
+        int c[4];
+        s = walk((unsigned)vi, g, a.ord, c);
+        const int Sm = pick(g.S, a.mu), Lm = pick(g.L, a.mu), xm = coord(c, a.ord, a.mu);
+        const int Sd = pick(g.S, a.d), Ld = pick(g.L, a.d), xd = coord(c, a.ord, a.d);
+        pd = shift(s, xd, Sd, Ld, 1);
+        md = shift(s, xd, Sd, Ld, -1);
+        pm = shift(s, xm, Sm, Lm, 1);
+        mm = shift(s, xm, Sm, Lm, -1);
+        md_pm = shift(md, xm, Sm, Lm, 1);
+        mm_pd = shift(mm, xd, Sd, Ld, 1);
+    }
+    M3 acc = zero3();
+    if (role == 0) {
+        // gradient with respect to M_s(y): the + staple at x = y - d and the
+        // - staple at x = y + d read it
+        if (valid && (a.GM[0] || a.GM[1])) {
+            M3 gp = zero3(), gmn = zero3();
+            if (plus && a.GM[0]) gp = mul_nn(mul_an(ld(a.Ud, V, md_pm), ld_grad(a.G[0], V, md)), ld(a.Ud, V, md));
+            if (minus && a.GM[1]) gmn = mul_na(mul_nn(ld(a.Ud, V, pm), ld_grad(a.G[1], V, pd)), ld(a.Ud, V, s));
+            if (a.GM[0] == a.GM[1]) {
+                M3 out = a.gm_init ? zero3() : ld(a.GM[0], V, s);
+                axpy(out, a.c, add(gp, gmn));
+                st(a.GM[0], V, s, out);
+            } else {
 #pragma unroll
-            for (int k = 0; k < 2; k++) {
-                double2 *gm = a.GM[k];
-                if (!gm || !(k == 0 ? plus : minus)) continue;
-                M3 out = a.gm_init ? zero3() : ld(gm, V, s);
-                axpy(out, a.c, k == 0 ? gp : gmn);
-                st(gm, V, s, out);
+                for (int k = 0; k < 2; k++) {
+                    double2 *gm = a.GM[k];
+                    if (!gm || !(k == 0 ? plus : minus)) continue;
+                    M3 out = a.gm_init ? zero3() : ld(gm, V, s);
+                    axpy(out, a.c, k == 0 ? gp : gmn);
+                    st(gm, V, s, out);
+                }
             }
         }
-    }
-    if (a.GUd) {
+    } else if (valid && a.GUd) {
         // U_d(z) is the first link of the + staple at z and of the - staple at
         // z + d, the last link of the + staple at z - mu and of the - staple
         // at z - mu + d
-        M3 acc = zero3();
-        if (plus) {
-            acc = add(acc, mul_nn(mul_na(ld(a.M[0], V, pd), ld(a.Ud, V, pm)), ld_grad(a.G[0], V, s)));
+        if (role == 1 && plus) {
+            acc = mul_nn(mul_na(ld(a.M[0], V, pd), ld(a.Ud, V, pm)), ld_grad(a.G[0], V, s));
             acc = add(acc, dag(mul_nn(mul_nn(ld_grad(a.G[0], V, mm), ld(a.Ud, V, mm)), ld(a.M[0], V, mm_pd))));
         }
-        if (minus) {
-            acc = add(acc, dag(mul_nn(mul_nn(ld(a.M[1], V, s), ld(a.Ud, V, pm)), ld_grad(a.G[1], V, pd))));
+        if (role == 2 && minus) {
+            acc = dag(mul_nn(mul_nn(ld(a.M[1], V, s), ld(a.Ud, V, pm)), ld_grad(a.G[1], V, pd)));
             acc = add(acc, mul_nn(mul_na(ld_grad(a.G[1], V, mm_pd), ld(a.Ud, V, mm)), ld(a.M[1], V, mm)));
         }
-        M3 out = ld(a.GUd, V, s);
-        axpy(out, a.c, acc);
-        st(a.GUd, V, s, out);
+    }
+    if (a.GUd) {   // uniform over the block
+        __shared__ double2 red[9][64];
+        if (role == 2)
+#pragma unroll
+            for (int i = 0; i < 9; i++) red[i][lane] = acc.e[i];
+        __syncthreads();
+        if (role == 1 && valid) {
+#pragma unroll
+            for (int i = 0; i < 9; i++) acc.e[i] = make_double2(acc.e[i].x + red[i][lane].x, acc.e[i].y + red[i][lane].y);
+            M3 out = ld(a.GUd, V, s);
+            axpy(out, a.c, acc);
+            st(a.GUd, V, s, out);
+        }
     }
 }
 
@@ -158,7 +182,7 @@ __global__ void __launch_bounds__(256) k_ff_halves(SmearGeom g, const double2 *U
 {
     const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
     if (s >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     int x[4];
     coords4(g, s, x);
     const int Sm = pick(g.S, mu), Lm = pick(g.L, mu), Sn = pick(g.S, nu), Ln = pick(g.L, nu);
@@ -175,7 +199,7 @@ __global__ void __launch_bounds__(256) k_ff_naik_adjoint(SmearGeom g, const doub
 {
     const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
     if (s >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     const int mu = blockIdx.y;
     int x[4];
     coords4(g, s, x);
@@ -202,7 +226,7 @@ __global__ void __launch_bounds__(256) k_ff_unitarize_adjoint(SmearGeom g, const
 {
     const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
     if (s >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     const double2 *vf = Vf + (size_t)blockIdx.y * 9 * V;
     double2 *gf = Gf + (size_t)blockIdx.y * 9 * V;
     const M3 Vm = ld(vf, V, s), G = ld(gf, V, s);
@@ -318,7 +342,7 @@ __global__ void __launch_bounds__(256) k_ff_project(SmearGeom g, const double2 *
 {
     const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
     if (s >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     const size_t off = (size_t)blockIdx.y * 9 * V;
     const M3 M = mul_nn(ld(U + off, V, s), ld(G + off, V, s));
     const double im3 = (M.e[0].y + M.e[4].y + M.e[8].y) * (1.0 / 3.0);
@@ -344,7 +368,7 @@ hipError_t launch_ff_outer(const SmearGeom &g, const OuterArgs &a, hipStream_t s
 hipError_t launch_staple_adjoint(const SmearGeom &g, const StapleAdjArgs &a, hipStream_t s)
 {
     if (!a.Ud || (!a.M[0] && !a.M[1]) || (a.M[0] && !a.G[0][0]) || (a.M[1] && !a.G[1][0])) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_staple_adjoint, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, s, g, a);
+    hipLaunchKernelGGL(k_staple_adjoint, dim3((unsigned)((g.V + 63) / 64)), dim3(192), 0, s, g, a);
     return hipGetLastError();
 }
 

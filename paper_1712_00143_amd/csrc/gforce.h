@@ -21,8 +21,9 @@ struct GForceArgs {
     int ntile, tch;   // set by the launcher
 };
 
-// Grid of the kernel: ntile slabs of 64 x-y-z sites times runs of tch time
-// slices; nblocks (= the number of action partials).
+// Grid of the kernel (and of the smearing's pass 1): ntile tiles of 64
+// x-y-z sites times runs of tch time slices; nblocks (= the number of
+// action partials).
 void gauge_force_grid(const SmearGeom &g, int *ntile, int *tch, int *nblocks);
 
 hipError_t launch_gauge_force(const SmearGeom &g, const GForceArgs &a, int mode, hipStream_t s);

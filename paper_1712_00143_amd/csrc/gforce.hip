@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) k_gauge_force(SmearGeom g, GForceArgs a)
     const long long nxyz = (long long)g.L[0] * g.L[1] * g.L[2];
     const long long i = (long long)tile * 64 + (threadIdx.x & 63);
     const bool valid = i < nxyz;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Geo q;
     {

@@ -35,6 +35,7 @@ SmearGeom geom_of(hisq_lattice lat)
 {
     SmearGeom g;
     g.V = lat->V;
+    g.P = plane_stride(lat->V);
     for (int k = 0; k < 4; k++) g.L[k] = lat->L[k];
     g.S[0] = 1;
     g.S[1] = lat->L[0];
@@ -43,10 +44,10 @@ SmearGeom geom_of(hisq_lattice lat)
     return g;
 }
 
-// Workspace: nf one-direction planar fields (9 V double2 each), a 256-byte
+// Workspace: nf one-direction planar fields (9 P double2 each), a 256-byte
 // slot for the projection's failure counter and `extra` bytes of partials.
 struct Work {
-    double2 *f = nullptr;   // field k at f + k * 9 V
+    double2 *f = nullptr;   // field k at f + k * 9 P
     int *bad = nullptr;
     double *part = nullptr;
     size_t fsz = 0;         // double2 per field
@@ -55,7 +56,7 @@ struct Work {
 
 hisq_status get_work(hisq_lattice lat, int nf, Work &w, size_t extra = 0)
 {
-    w.fsz = (size_t)9 * lat->V;
+    w.fsz = (size_t)9 * plane_stride(lat->V);
     const size_t need = (size_t)nf * w.fsz * sizeof(double2) + 256 + extra;
     if (lat->smear_ws_bytes < need) {
         if (lat->smear_ws) {

@@ -1,10 +1,15 @@
 // Launchers of the HISQ link-smearing kernels (FP64).
 //
 // Working fields are site-planar: a field of nd directions is nd blocks of
-// nine planes (the 3x3 elements, row-major), each plane V double2 values
-// indexed by lex(x), so that a wavefront's load of one element is one
-// contiguous 1 KiB segment.  The library's link arrays ([V][4][3][3]
-// complex, site-major) are converted on the way in and out.
+// nine planes (the 3x3 elements, row-major), each plane P double2 slots of
+// which the first V hold the sites in lex(x) order, so that a wavefront's
+// load of one element is one contiguous 1 KiB segment.  P pads V so that
+// the planes of a field and successive fields start at different cache
+// sets: with P = V a power of two every plane of every field would map the
+// same site to the same L2 set, and a pass reading some fifty planes would
+// evict its neighbours' lines before they are used again.  The library's
+// link arrays ([V][4][3][3] complex, site-major) are converted on the way in
+// and out.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -12,9 +17,17 @@ namespace hisq {
 
 struct SmearGeom {
     long long V;
+    long long P;   // plane stride (plane_stride(V))
     int L[4];
     int S[4];   // lex strides 1, L0, L0 L1, L0 L1 L2
 };
+
+// V rounded up to 128-byte lines plus 37 lines: successive planes start 37
+// lines apart, which cycles through every L2 channel and set.
+inline long long plane_stride(long long V)
+{
+    return (V + 7) / 8 * 8 + 296;
+}
 
 // fat7(U; c1, c3, c5, c7; cL) of output direction mu in three kinds of
 // pass over planar fields (U: the four-direction input):

@@ -9,6 +9,7 @@
 // nu -> rho -> sigma and every pass reads the previous pass's output (see
 // smear.cpp).  Each pass touches a handful of planar fields once, so it is
 // bound by HBM traffic (about 1.1 flop per byte), not by the FP64 units.
+#include "gforce.h"
 #include "hisq_dev.h"
 #include "smear.h"
 #include "su3.h"
@@ -56,46 +57,55 @@ __device__ __forceinline__ M3 lepage_at(const double2 *__restrict__ U, const dou
     return T;
 }
 
-// Pass 1 of every output direction at once: a block holds 64 sites and one
-// wave per direction mu (the neighbour links one direction's staples fetch
-// serve the others from L1 / L2).  For each mu, the 3-link staples through
-// the three nu != mu, stored as T1[3 mu + k] when WT, and
+// Pass 1 of every output direction at once: a block holds 64 sites of one
+// x-y-z slab, one wave per direction mu, and walks a run of tch time slices
+// (the block grid of gauge_force_grid), so that the neighbour links one
+// direction's staples fetch serve the other directions from L1 / L2 and the
+// t neighbours are the block's own recent loads.  For each mu, the 3-link
+// staples through the three nu != mu, stored as T1[3 mu + k] when WT, and
 //   F_mu = c1 U_mu + sum_nu (c3 T1_nu + cL Lepage_nu).
 template <bool LEP, bool WT>
-__global__ void __launch_bounds__(256) k_smear_pass1(SmearGeom g, Pass1Args a)
+__global__ void __launch_bounds__(256) k_smear_pass1(SmearGeom g, Pass1Args a, int ntile, int tch)
 {
-    const long long s = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 64 + (threadIdx.x & 63);
-    if (s >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
+    const int chunk = lb / ntile, tile = lb - chunk * ntile;
+    const long long i = (long long)tile * 64 + (threadIdx.x & 63);
+    if (i >= (long long)g.S[3]) return;   // no barriers below
+    const size_t V = (size_t)g.P;   // plane stride
     const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int x[4];
     {
-        unsigned r = (unsigned)s;   // V <= 2^31
+        unsigned r = (unsigned)i;
         x[0] = (int)(r % (unsigned)g.L[0]);
         r /= (unsigned)g.L[0];
         x[1] = (int)(r % (unsigned)g.L[1]);
-        r /= (unsigned)g.L[1];
-        x[2] = (int)(r % (unsigned)g.L[2]);
-        x[3] = (int)(r / (unsigned)g.L[2]);
+        x[2] = (int)(r / (unsigned)g.L[1]);
     }
-    const int Sm = pick(g.S, mu), Lm = pick(g.L, mu), xm = pick(x, mu);
+    const int t0 = chunk * tch, t1 = t0 + tch < g.L[3] ? t0 + tch : g.L[3];
+    const int Sm = pick(g.S, mu), Lm = pick(g.L, mu);
     const double2 *Umu = a.U + (size_t)mu * 9 * V;
-    M3 F = ld(Umu, V, s);
-#pragma unroll
-    for (int i = 0; i < 9; i++) F.e[i] = make_double2(a.c1 * F.e[i].x, a.c1 * F.e[i].y);
-    // one direction at a time: unrolled, the three staples' loads are all
-    // hoisted and spill
 #pragma unroll 1
-    for (int k = 0; k < 3; k++) {
-        const int nu = k + (k >= mu ? 1 : 0);
-        const int Sn = pick(g.S, nu), Ln = pick(g.L, nu), xn = pick(x, nu);
-        const double2 *Un = a.U + (size_t)nu * 9 * V;
-        const M3 T = staple_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm);
-        axpy(F, a.c3, T);
-        if constexpr (WT) st(a.T1 + (size_t)(3 * mu + k) * 9 * V, V, s, T);
-        if constexpr (LEP) axpy(F, a.cL, lepage_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm));
+    for (int t = t0; t < t1; t++) {
+        x[3] = t;
+        const long long s = i + (long long)t * g.S[3];
+        const int xm = pick(x, mu);
+        M3 F = ld(Umu, V, s);
+#pragma unroll
+        for (int e = 0; e < 9; e++) F.e[e] = make_double2(a.c1 * F.e[e].x, a.c1 * F.e[e].y);
+        // one direction at a time: unrolled, the three staples' loads are all
+        // hoisted and spill
+#pragma unroll 1
+        for (int k = 0; k < 3; k++) {
+            const int nu = k + (k >= mu ? 1 : 0);
+            const int Sn = pick(g.S, nu), Ln = pick(g.L, nu), xn = pick(x, nu);
+            const double2 *Un = a.U + (size_t)nu * 9 * V;
+            const M3 T = staple_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm);
+            axpy(F, a.c3, T);
+            if constexpr (WT) st(a.T1 + (size_t)(3 * mu + k) * 9 * V, V, s, T);
+            if constexpr (LEP) axpy(F, a.cL, lepage_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm));
+        }
+        st(a.F + (size_t)mu * 9 * V, V, s, F);
     }
-    st(a.F + (size_t)mu * 9 * V, V, s, F);
 }
 
 // Pass 2 of (mu, sig): the 5-link staples whose transverse steps are the two
@@ -105,7 +115,7 @@ __global__ void __launch_bounds__(256) k_smear_pass2(SmearGeom g, Pass2Args a)
 {
     const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
     if (vi >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     int c[4];
     const long long s = walk((unsigned)vi, g, a.ord, c);
     const int Sm = pick(g.S, a.mu), Lm = pick(g.L, a.mu), xm = coord(c, a.ord, a.mu);
@@ -124,7 +134,7 @@ __global__ void __launch_bounds__(256) k_smear_pass3(SmearGeom g, Pass3Args a)
 {
     const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
     if (vi >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     int c[4];
     const long long s = walk((unsigned)vi, g, a.ord, c);
     const int Sm = pick(g.S, a.mu), Lm = pick(g.L, a.mu), xm = coord(c, a.ord, a.mu);
@@ -150,7 +160,7 @@ __global__ void __launch_bounds__(256) k_smear_to_planar(SmearGeom g, const doub
     const int sl = threadIdx.x & (SB - 1), d = threadIdx.x >> 6;
     const long long s = s0 + sl;
     if (s >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     double2 *f = pl + (size_t)d * 9 * V;
 #pragma unroll
     for (int e = 0; e < 9; e++) f[e * V + s] = buf[(sl * 4 + d) * 9 + e];
@@ -167,7 +177,7 @@ __global__ void __launch_bounds__(256) k_smear_out(SmearGeom g, const double2 *_
     const int sl = threadIdx.x & (SB - 1), d = threadIdx.x >> 6;
     const long long s = s0 + sl;
     const bool valid = s < g.V;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     const unsigned sc = valid ? (unsigned)s : 0u;
     const int x0 = (int)(sc % (unsigned)g.L[0]), x1 = (int)((sc / (unsigned)g.S[1]) % (unsigned)g.L[1]);
     const int x2 = (int)((sc / (unsigned)g.S[2]) % (unsigned)g.L[2]), x3 = (int)(sc / (unsigned)g.S[3]);
@@ -206,7 +216,7 @@ __global__ void __launch_bounds__(256) k_smear_unitarize(SmearGeom g, double2 *_
 {
     const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
     if (s >= g.V) return;
-    const size_t V = (size_t)g.V;
+    const size_t V = (size_t)g.P;   // plane stride
     const int d = blockIdx.y;
     double2 *f = pl + (size_t)d * 9 * V;
     const M3 Vm = ld(f, V, s);
@@ -271,12 +281,14 @@ void smear_order(const int *first, int n, int ord[4])
 
 hipError_t launch_smear_pass1(const SmearGeom &g, const Pass1Args &a, hipStream_t s)
 {
-    const dim3 grid((unsigned)((g.V + 63) / 64)), blk(256);
+    int ntile, tch, nb;
+    gauge_force_grid(g, &ntile, &tch, &nb);
+    const dim3 grid((unsigned)nb), blk(256);
     const bool lep = a.cL != 0.0, wt = a.T1 != nullptr;
-    if (lep && wt) hipLaunchKernelGGL((k_smear_pass1<true, true>), grid, blk, 0, s, g, a);
-    else if (lep) hipLaunchKernelGGL((k_smear_pass1<true, false>), grid, blk, 0, s, g, a);
-    else if (wt) hipLaunchKernelGGL((k_smear_pass1<false, true>), grid, blk, 0, s, g, a);
-    else hipLaunchKernelGGL((k_smear_pass1<false, false>), grid, blk, 0, s, g, a);
+    if (lep && wt) hipLaunchKernelGGL((k_smear_pass1<true, true>), grid, blk, 0, s, g, a, ntile, tch);
+    else if (lep) hipLaunchKernelGGL((k_smear_pass1<true, false>), grid, blk, 0, s, g, a, ntile, tch);
+    else if (wt) hipLaunchKernelGGL((k_smear_pass1<false, true>), grid, blk, 0, s, g, a, ntile, tch);
+    else hipLaunchKernelGGL((k_smear_pass1<false, false>), grid, blk, 0, s, g, a, ntile, tch);
     return hipGetLastError();
 }
 

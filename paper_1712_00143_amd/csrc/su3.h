@@ -21,10 +21,19 @@ __device__ __forceinline__ M3 ld(const double2 *__restrict__ f, size_t V, long l
     return m;
 }
 
+// Stores are non-temporal: the passes write as many bytes as they read or
+// more (pass 1 four times as many), and write-allocated lines would push the
+// neighbour links the next sites reuse out of L2.  Every stored field is read
+// again only by a later launch.
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ void st(double2 *__restrict__ f, size_t V, long long s, const M3 &m)
 {
 #pragma unroll
-    for (int i = 0; i < 9; i++) f[i * V + s] = m.e[i];
+    for (int i = 0; i < 9; i++) {
+        const nt_double2 v = {m.e[i].x, m.e[i].y};
+        __builtin_nontemporal_store(v, reinterpret_cast<nt_double2 *>(f + i * V + s));
+    }
 }
 
 // c = a b
