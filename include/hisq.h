@@ -375,7 +375,7 @@ hisq_status hisq_residual_history(hisq_lattice lat, int problem, double *out, in
  * Arrays use the link layout above ([V][4][3][3] complex FP64, site-major;
  * thin links without phases), host pointers or, with HISQ_DEVICE_PTR, device
  * pointers.  FP64 throughout; synchronous.  The library keeps a device
- * workspace of 25 link-direction fields (33 with host outputs that are not
+ * workspace of 27 link-direction fields (35 with host outputs that are not
  * loaded; 144 V bytes each) per lattice until hisq_destroy.
  *
  * hisq_smear_links: thin -> (fat, lng).  With HISQ_LOAD_RESULT the result

@@ -74,15 +74,12 @@ hisq_status get_work(hisq_lattice lat, int nf, Work &w, size_t extra = 0)
     return HISQ_OK;
 }
 
-// out (4 planar fields) = fat7(U (4 planar fields)); T1: three fields, T2:
-// one.  Per output direction: pass 1 (3-staples, Lepage, one-link term),
-// then for each sig != mu pass 2 (the 5-staples avoiding sig) and pass 3
-// (their c5 share and the 7-staples through sig): 7 passes instead of one
-// kernel per path class and pair.
-// T1all: 12 fields (every direction's 3-staples, from one pass-1 launch).
-// keep: T2all holds 12 fields and direction mu's 5-staple sums stay in its
-// fields 3 mu .. 3 mu + 2 (for the adjoint); otherwise T2all is one field,
-// reused for every direction.
+// out (4 planar fields) = fat7(U (4 planar fields)): one pass 1 for every
+// direction, then per output direction one pass 2 (its 5-staple sums) and
+// one pass 3 (their c5 share and the 7-staples).  T1all: 12 fields (every
+// direction's 3-staples).  keep: T2all holds 12 fields and direction mu's
+// 5-staple sums stay in its fields 3 mu .. 3 mu + 2 (for the adjoint);
+// otherwise T2all is three fields, reused for every direction.
 hipError_t run_fat7(const SmearGeom &g, const double2 *U, double2 *out, double2 *T1all, double2 *T2all,
                     const double c[5], size_t fsz, hipStream_t s, bool keep = false)
 {
@@ -91,24 +88,11 @@ hipError_t run_fat7(const SmearGeom &g, const double2 *U, double2 *out, double2 
     hipError_t e = launch_smear_pass1(g, p1, s);
     if (e != hipSuccess || !need5) return e;
     for (int mu = 0; mu < 4; mu++) {
-        int perp[3], np = 0;
-        for (int d = 0; d < 4; d++)
-            if (d != mu) perp[np++] = d;
-        double2 *T1 = T1all + (size_t)3 * mu * fsz;
-        double2 *F = out + (size_t)mu * fsz;
-        for (int k = 0; k < 3; k++) {
-            const int sig = perp[k], inu = (k + 1) % 3, irho = (k + 2) % 3;
-            const int nu = perp[inu], rho = perp[irho];
-            double2 *T2 = keep ? T2all + (size_t)(3 * mu + k) * fsz : T2all;
-            Pass2Args p2{U, T1 + (size_t)inu * fsz, T1 + (size_t)irho * fsz, T2, mu, nu, rho, {}};
-            const int f2[3] = {nu, rho, mu};
-            smear_order(f2, 3, p2.ord);
-            if ((e = launch_smear_pass2(g, p2, s)) != hipSuccess) return e;
-            Pass3Args p3{U, T2, F, c[2], c[3], mu, sig, {}};
-            const int f3[2] = {sig, mu};
-            smear_order(f3, 2, p3.ord);
-            if ((e = launch_smear_pass3(g, p3, s)) != hipSuccess) return e;
-        }
+        double2 *T2 = keep ? T2all + (size_t)3 * mu * fsz : T2all;
+        const Pass2Args p2{U, T1all + (size_t)3 * mu * fsz, T2, mu};
+        if ((e = launch_smear_pass2(g, p2, s)) != hipSuccess) return e;
+        const Pass3Args p3{U, T2, out + (size_t)mu * fsz, c[2], c[3], mu};
+        if ((e = launch_smear_pass3(g, p3, s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -146,7 +130,7 @@ hisq_status hisq_fat7(hisq_lattice lat, const double coef[5], const double *in, 
     if (!lat || !coef || !in || !out) return set_err(lat, HISQ_ERR_ARG, "null argument");
     HIPCHK(lat, hipSetDevice(lat->device));
     Work w;
-    hisq_status st = get_work(lat, 25, w);   // U 0-3, result 4-7, staging 8-11, T1 12-23, T2 24
+    hisq_status st = get_work(lat, 27, w);   // U 0-3, result 4-7, staging 8-11, T1 12-23, T2 24-26
     if (st != HISQ_OK) return st;
     const SmearGeom g = geom_of(lat);
     const double2 *src;
@@ -193,11 +177,11 @@ hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, 
     HIPCHK(lat, hipSetDevice(lat->device));
     const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
     // fields: thin U 0-3, level 1 / projected W 4-7, level 2 X 8-11 (also the
-    // host input staging), T1 12-23, T2 24, output staging 25-32 for host
-    // outputs that are not loaded
+    // host input staging), T1 12-23, T2 24-26, output staging 27-34 for
+    // host outputs that are not loaded
     const bool stage_out = !dev && !load;
     Work w;
-    hisq_status st = get_work(lat, stage_out ? 33 : 25, w);
+    hisq_status st = get_work(lat, stage_out ? 35 : 27, w);
     if (st != HISQ_OK) return st;
     const SmearGeom g = geom_of(lat);
     const double2 *src;
@@ -218,8 +202,8 @@ hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, 
         of = (double2 *)fat;
         ol = (double2 *)lng;
     } else {
-        of = w.field(25);
-        ol = w.field(29);
+        of = w.field(27);
+        ol = w.field(31);
     }
     HIPCHK(lat, launch_smear_output(g, w.field(8), w.field(4), NAIK, of, ol, lat->s));
     if ((st = check_projection(lat, w.bad)) != HISQ_OK) {

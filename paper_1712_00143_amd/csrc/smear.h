@@ -29,20 +29,18 @@ inline long long plane_stride(long long V)
     return (V + 7) / 8 * 8 + 296;
 }
 
-// fat7(U; c1, c3, c5, c7; cL) of output direction mu in three kinds of
-// pass over planar fields (U: the four-direction input):
-//   pass 1       (every mu in one launch) F_mu = c1 U_mu + sum over nu != mu
-//                of (c3 T1_nu + cL Lep_nu), T1_nu = U_nu(x) U_mu(x+nu)
-//                U_nu(x+mu)^+ + (the -nu staple) stored for passes 2 as
-//                T1 field 3 mu + k, nu the k-th direction other than mu
-//                (Lep_nu: the two-step staple);
-//   pass 2 (sig) T2 = staple of T1_nu through rho + staple of T1_rho through
-//                nu, {nu, rho} the two directions other than mu and sig
-//                (all 5-link staples whose steps avoid sig);
-//   pass 3 (sig) F += c5 T2 + c7 (staple of T2 through sig) (the 7-link
-//                staples through sig).
-// ord: the site visiting order, an axis permutation with ord[0] = 0 (x
-// fastest); the directions a pass steps along come next.
+// fat7(U; c1, c3, c5, c7; cL) in three kinds of pass over planar fields
+// (U: the four-direction input); for output direction mu, nu_k denotes the
+// k-th direction other than mu (k = 0, 1, 2):
+//   pass 1       (every mu in one launch) F_mu = c1 U_mu + sum over k of
+//                (c3 T1_k + cL Lep_k), T1_k = U_nu(x) U_mu(x+nu) U_nu(x+mu)^+
+//                + (the -nu staple), nu = nu_k, stored for pass 2 as T1 field
+//                3 mu + k (Lep_k: the two-step staple);
+//   pass 2 (mu)  for each k, sig = nu_k and {nu, rho} the other two:
+//                T2_k = staple of T1_nu through rho + staple of T1_rho
+//                through nu (all 5-link staples whose steps avoid sig);
+//   pass 3 (mu)  F_mu += sum over k of c5 T2_k + c7 (staple of T2_k through
+//                sig) (the 7-link staples through sig).
 struct Pass1Args {
     const double2 *U;
     double2 *F;    // four fields
@@ -51,18 +49,16 @@ struct Pass1Args {
 };
 struct Pass2Args {
     const double2 *U;
-    const double2 *T1nu, *T1rho;
-    double2 *T2;
-    int mu, nu, rho;
-    int ord[4];
+    const double2 *T1;   // the three T1 fields of mu
+    double2 *T2;         // three fields
+    int mu;
 };
 struct Pass3Args {
     const double2 *U;
-    const double2 *T2;
-    double2 *F;
+    const double2 *T2;   // three fields
+    double2 *F;          // the field of mu
     double c5, c7;
-    int mu, sig;
-    int ord[4];
+    int mu;
 };
 
 hipError_t launch_smear_pass1(const SmearGeom &g, const Pass1Args &a, hipStream_t s);

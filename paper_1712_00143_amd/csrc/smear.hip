@@ -108,41 +108,105 @@ __global__ void __launch_bounds__(256) k_smear_pass1(SmearGeom g, Pass1Args a, i
     }
 }
 
-// Pass 2 of (mu, sig): the 5-link staples whose transverse steps are the two
-// directions nu, rho other than mu and sig, in both orders:
-//   T2 = staple(T1_nu through rho) + staple(T1_rho through nu).
-__global__ void __launch_bounds__(256) k_smear_pass2(SmearGeom g, Pass2Args a)
+// Passes 2 and 3 of output direction mu take its three sig at once, one
+// wave per sig on the same 64 sites (they share the fields they read), with
+// the block grid and time-slice walk of pass 1; k is the index of sig among
+// the directions other than mu, {nu, rho} the other two.
+__device__ __forceinline__ int other_dir(int k, int mu) { return k + (k >= mu ? 1 : 0); }
+
+// Pass 2: T2_k = staple(T1_nu through rho) + staple(T1_rho through nu), the
+// 5-link staples whose transverse steps avoid sig, in both orders.
+// (two waves per SIMD: left alone the compiler takes every register and one)
+__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2))) k_smear_pass2(SmearGeom g, Pass2Args a,
+                                                                                            int ntile, int tch)
 {
-    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
-    if (vi >= g.V) return;
+    const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
+    const int chunk = lb / ntile, tile = lb - chunk * ntile;
+    const long long i = (long long)tile * 64 + (threadIdx.x & 63);
+    if (i >= (long long)g.S[3]) return;   // no barriers below
     const size_t V = (size_t)g.P;   // plane stride
-    int c[4];
-    const long long s = walk((unsigned)vi, g, a.ord, c);
-    const int Sm = pick(g.S, a.mu), Lm = pick(g.L, a.mu), xm = coord(c, a.ord, a.mu);
-    const int Sn = pick(g.S, a.nu), Ln = pick(g.L, a.nu), xn = coord(c, a.ord, a.nu);
-    const int Sr = pick(g.S, a.rho), Lr = pick(g.L, a.rho), xr = coord(c, a.ord, a.rho);
-    M3 T = staple_at(a.U + (size_t)a.rho * 9 * V, a.T1nu, V, s, xr, Sr, Lr, xm, Sm, Lm);
-    const M3 Q = staple_at(a.U + (size_t)a.nu * 9 * V, a.T1rho, V, s, xn, Sn, Ln, xm, Sm, Lm);
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), mu = a.mu;
+    const int inu = k == 2 ? 0 : k + 1, irho = k == 0 ? 2 : k - 1;
+    const int nu = other_dir(inu, mu), rho = other_dir(irho, mu);
+    int x[4];
+    {
+        unsigned r = (unsigned)i;
+        x[0] = (int)(r % (unsigned)g.L[0]);
+        r /= (unsigned)g.L[0];
+        x[1] = (int)(r % (unsigned)g.L[1]);
+        x[2] = (int)(r / (unsigned)g.L[1]);
+    }
+    const int Sm = pick(g.S, mu), Lm = pick(g.L, mu);
+    const int Sn = pick(g.S, nu), Ln = pick(g.L, nu), Sr = pick(g.S, rho), Lr = pick(g.L, rho);
+    const double2 *Ur = a.U + (size_t)rho * 9 * V, *Un = a.U + (size_t)nu * 9 * V;
+    const double2 *T1n = a.T1 + (size_t)inu * 9 * V, *T1r = a.T1 + (size_t)irho * 9 * V;
+    double2 *T2 = a.T2 + (size_t)k * 9 * V;
+    const int t0 = chunk * tch, t1 = t0 + tch < g.L[3] ? t0 + tch : g.L[3];
+#pragma unroll 1
+    for (int t = t0; t < t1; t++) {
+        x[3] = t;
+        const long long s = i + (long long)t * g.S[3];
+        const int xm = pick(x, mu), xn = pick(x, nu), xr = pick(x, rho);
+        M3 T = staple_at(Ur, T1n, V, s, xr, Sr, Lr, xm, Sm, Lm);
+        const M3 Q = staple_at(Un, T1r, V, s, xn, Sn, Ln, xm, Sm, Lm);
 #pragma unroll
-    for (int i = 0; i < 9; i++) T.e[i] = make_double2(T.e[i].x + Q.e[i].x, T.e[i].y + Q.e[i].y);
-    st(a.T2, V, s, T);
+        for (int e = 0; e < 9; e++) T.e[e] = make_double2(T.e[e].x + Q.e[e].x, T.e[e].y + Q.e[e].y);
+        st(T2, V, s, T);
+    }
 }
 
-// Pass 3 of (mu, sig): F += c5 T2 + c7 staple(T2 through sig), the
-// 7-link staples being the staples of the 5-link ones.
-__global__ void __launch_bounds__(256) k_smear_pass3(SmearGeom g, Pass3Args a)
+// Pass 3: F_mu += sum over sig of (c5 T2_k + c7 staple(T2_k through sig)),
+// the 7-link staples being the staples of the 5-link ones; the three waves'
+// terms meet in LDS and wave 0 updates F once, adding them in the order of k.
+__global__ void __launch_bounds__(192) k_smear_pass3(SmearGeom g, Pass3Args a, int ntile, int tch)
 {
-    const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 256 + threadIdx.x;
-    if (vi >= g.V) return;
+    const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
+    const int chunk = lb / ntile, tile = lb - chunk * ntile;
+    const int lane = threadIdx.x & 63;
+    const long long i0 = (long long)tile * 64 + lane;
+    const bool valid = i0 < (long long)g.S[3];
+    const long long i = valid ? i0 : 0;
     const size_t V = (size_t)g.P;   // plane stride
-    int c[4];
-    const long long s = walk((unsigned)vi, g, a.ord, c);
-    const int Sm = pick(g.S, a.mu), Lm = pick(g.L, a.mu), xm = coord(c, a.ord, a.mu);
-    const int Ss = pick(g.S, a.sig), Ls = pick(g.L, a.sig), xs = coord(c, a.ord, a.sig);
-    M3 F = ld(a.F, V, s);
-    axpy(F, a.c5, ld(a.T2, V, s));
-    axpy(F, a.c7, staple_at(a.U + (size_t)a.sig * 9 * V, a.T2, V, s, xs, Ss, Ls, xm, Sm, Lm));
-    st(a.F, V, s, F);
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), mu = a.mu;
+    const int sig = other_dir(k, mu);
+    int x[4];
+    {
+        unsigned r = (unsigned)i;
+        x[0] = (int)(r % (unsigned)g.L[0]);
+        r /= (unsigned)g.L[0];
+        x[1] = (int)(r % (unsigned)g.L[1]);
+        x[2] = (int)(r / (unsigned)g.L[1]);
+    }
+    const int Sm = pick(g.S, mu), Lm = pick(g.L, mu), Ss = pick(g.S, sig), Ls = pick(g.L, sig);
+    const double2 *Us = a.U + (size_t)sig * 9 * V, *T2 = a.T2 + (size_t)k * 9 * V;
+    double2 *F = a.F;
+    __shared__ double2 red[2][9][64];
+    const int t0 = chunk * tch, t1 = t0 + tch < g.L[3] ? t0 + tch : g.L[3];
+#pragma unroll 1
+    for (int t = t0; t < t1; t++) {
+        x[3] = t;
+        const long long s = i + (long long)t * g.S[3];
+        M3 T = zero3();
+        if (valid) {
+            axpy(T, a.c5, ld(T2, V, s));
+            axpy(T, a.c7, staple_at(Us, T2, V, s, pick(x, sig), Ss, Ls, pick(x, mu), Sm, Lm));
+        }
+        if (k > 0)
+#pragma unroll
+            for (int e = 0; e < 9; e++) red[k - 1][e][lane] = T.e[e];
+        __syncthreads();
+        if (k == 0 && valid) {
+            M3 f = ld(F, V, s);
+#pragma unroll
+            for (int e = 0; e < 9; e++) {
+                f.e[e] = make_double2(f.e[e].x + T.e[e].x, f.e[e].y + T.e[e].y);
+                f.e[e] = make_double2(f.e[e].x + red[0][e][lane].x, f.e[e].y + red[0][e][lane].y);
+                f.e[e] = make_double2(f.e[e].x + red[1][e][lane].x, f.e[e].y + red[1][e][lane].y);
+            }
+            st(F, V, s, f);
+        }
+        __syncthreads();
+    }
 }
 
 // Blocks of 64 sites x 4 directions; the [64][4][9] slab of the site-major
@@ -294,13 +358,17 @@ hipError_t launch_smear_pass1(const SmearGeom &g, const Pass1Args &a, hipStream_
 
 hipError_t launch_smear_pass2(const SmearGeom &g, const Pass2Args &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_smear_pass2, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, s, g, a);
+    int ntile, tch, nb;
+    gauge_force_grid(g, &ntile, &tch, &nb);
+    hipLaunchKernelGGL(k_smear_pass2, dim3((unsigned)nb), dim3(192), 0, s, g, a, ntile, tch);
     return hipGetLastError();
 }
 
 hipError_t launch_smear_pass3(const SmearGeom &g, const Pass3Args &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_smear_pass3, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, s, g, a);
+    int ntile, tch, nb;
+    gauge_force_grid(g, &ntile, &tch, &nb);
+    hipLaunchKernelGGL(k_smear_pass3, dim3((unsigned)nb), dim3(192), 0, s, g, a, ntile, tch);
     return hipGetLastError();
 }
 
