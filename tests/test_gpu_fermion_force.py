@@ -84,10 +84,13 @@ def test_fermion_force_parity(dims):
     lat.close()
 
 
-def test_fermion_force_16x16x16x16_tiled_and_gauge_rotated():
+# 16^4: one time slice per block; 32^3x8: runs of two time slices per block
+@pytest.mark.parametrize("reps", [(2, 2, 2, 2), (4, 4, 4, 1)], ids=["16x16x16x16", "32x32x32x8"])
+def test_fermion_force_tiled_and_gauge_rotated(reps):
     import torch
     H = _hisq()
-    small, reps, dims = (8, 8, 8, 8), (2, 2, 2, 2), (16, 16, 16, 16)
+    small = (8, 8, 8, 8)
+    dims = tuple(a * b for a, b in zip(small, reps))
     U8 = synth.thin_links(small, 0.4, 150)
     xs8 = _vectors(small, 151)
     F8 = oracle.hisq_fermion_force(small, U8, ALPHAS, xs8)
@@ -109,7 +112,7 @@ def test_fermion_force_16x16x16x16_tiled_and_gauge_rotated():
     Ut = torch.from_numpy(U.view(np.float64)).cuda()
     Xt = torch.from_numpy(np.stack(xs).view(np.float64)).cuda()
     F = lat.fermion_force(Ut, ALPHAS, Xt)
-    check(_links(F.cpu().numpy().view(np.complex128)), _links(ref), 1e-12, "force 16^4")
+    check(_links(F.cpu().numpy().view(np.complex128)), _links(ref), 1e-12, ("force", dims))
     lat.close()
 
 

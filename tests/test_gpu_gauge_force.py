@@ -53,10 +53,14 @@ def test_force_and_action_parity(dims, coefs):
     lat.close()
 
 
-def test_force_32x32x32x32_tiled_and_gauge_rotated():
+# 32^4: runs of 8 time slices per block; 24^3x48: runs of 5 with a last run of 3
+@pytest.mark.parametrize("small,reps", [((8, 8, 8, 8), (4, 4, 4, 4)), ((12, 12, 12, 12), (2, 2, 2, 4))],
+                         ids=["32x32x32x32", "24x24x24x48"])
+def test_force_tiled_and_gauge_rotated(small, reps):
     import torch
     H = _hisq()
-    small, reps, dims = (8, 8, 8, 8), (4, 4, 4, 4), (32, 32, 32, 32)
+    dims = tuple(a * b for a, b in zip(small, reps))
+    ncopy = reps[0] * reps[1] * reps[2] * reps[3]
     U8 = synth.thin_links(small, 0.5, 121)
     F8 = oracle.gauge_force(small, U8, 6.0, ONE_LOOP)
     s8 = oracle.gauge_action(small, U8, 6.0, ONE_LOOP)
@@ -71,9 +75,9 @@ def test_force_32x32x32x32_tiled_and_gauge_rotated():
     t = torch.from_numpy(U.view(np.float64)).cuda()
     del U
     F = lat.gauge_force(t, 6.0, ONE_LOOP)
-    check(_links(F.cpu().numpy().view(np.complex128)), _links(ref), TOL, "force 32^4")
+    check(_links(F.cpu().numpy().view(np.complex128)), _links(ref), TOL, ("force", dims))
     s = lat.gauge_action(t, 6.0, ONE_LOOP)
-    assert abs(s - 256 * s8) <= 1e-12 * abs(s), (s, 256 * s8)
+    assert abs(s - ncopy * s8) <= 1e-12 * abs(s), (s, ncopy * s8)
     lat.close()
 
 

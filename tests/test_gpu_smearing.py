@@ -90,11 +90,14 @@ def test_smear_links_device_pointers_and_free_field():
     lat.close()
 
 
-def test_smear_links_32x32x32x32_tiled_and_gauge_rotated():
+# 32^4: runs of 8 time slices per block; 24^3x48: runs of 5 with a last run of
+# 3, and a tile count that is not a power of two
+@pytest.mark.parametrize("small,reps", [((8, 8, 8, 8), (4, 4, 4, 4)), ((12, 12, 12, 12), (2, 2, 2, 4))],
+                         ids=["32x32x32x32", "24x24x24x48"])
+def test_smear_links_tiled_and_gauge_rotated(small, reps):
     import torch
     H = _hisq()
-    small, reps = (8, 8, 8, 8), (4, 4, 4, 4)
-    dims = (32, 32, 32, 32)
+    dims = tuple(a * b for a, b in zip(small, reps))
     U8 = synth.thin_links(small, 0.4, 80)
     fat8, lng8 = oracle.hisq_smear(small, U8)
     g = synth.random_su3(synth.volume(dims), 81)
@@ -109,8 +112,8 @@ def test_smear_links_32x32x32x32_tiled_and_gauge_rotated():
     t = torch.from_numpy(U.view(np.float64)).cuda()
     del U
     fat, lng = lat.smear_links(t)
-    check(_links(fat.cpu().numpy().view(np.complex128)), _links(fat_ref), TOL, "fat 32^4")
-    check(_links(lng.cpu().numpy().view(np.complex128)), _links(lng_ref), TOL, "long 32^4")
+    check(_links(fat.cpu().numpy().view(np.complex128)), _links(fat_ref), TOL, ("fat", dims))
+    check(_links(lng.cpu().numpy().view(np.complex128)), _links(lng_ref), TOL, ("long", dims))
     lat.close()
 
 
