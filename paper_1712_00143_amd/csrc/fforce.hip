@@ -10,8 +10,9 @@
 // site's links, so there are no scattered updates); the U(3) projection has
 // a closed-form adjoint from the Cayley-Hamilton form of (V^+ V)^{-1/2},
 // whose coefficients are symmetric functions of the singular values and
-// stay finite when they coincide.  Every kernel is a one-thread-per-site
-// FP64 pass over planar fields, bound by memory traffic and latency.
+// stay finite when they coincide.  Every kernel is an FP64 pass over planar
+// fields (one thread per site, except the staple adjoint's three waves per
+// 64 sites), bound by memory traffic and latency.
 #include "fforce.h"
 #include "hisq_dev.h"
 #include "su3.h"

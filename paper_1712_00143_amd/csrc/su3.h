@@ -1,6 +1,7 @@
 // FP64 3x3 complex matrices in registers, loaded from and stored to
-// site-planar fields (nine planes of V double2, element (i, j) in plane
-// 3i + j), and the lattice shifts the link kernels use.
+// site-planar fields (nine planes, element (i, j) in plane 3i + j; the
+// argument V of ld / st is the plane stride, SmearGeom::P), and the lattice
+// shifts the link kernels use.
 #pragma once
 #include <hip/hip_runtime.h>
 
