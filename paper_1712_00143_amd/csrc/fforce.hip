@@ -11,7 +11,7 @@
 // a closed-form adjoint from the Cayley-Hamilton form of (V^+ V)^{-1/2},
 // whose coefficients are symmetric functions of the singular values and
 // stay finite when they coincide.  Every kernel is an FP64 pass over planar
-// fields (one thread per site, except the staple adjoint's three waves per
+// fields (one thread per site, except the staple adjoint's four waves per
 // 64 sites), bound by memory traffic and latency.
 #include "fforce.h"
 #include "hisq_dev.h"
@@ -101,18 +101,19 @@ __device__ __forceinline__ M3 ld_grad(const double2 *const G[2], size_t V, long 
     return m;
 }
 
-// A block holds 64 sites and three waves with one share of the work each, so
+// A block holds 64 sites and four waves with one share of the work each, so
 // that each carries a short chain of loads and products (one thread doing all
-// of it needs over 200 registers and leaves two waves per SIMD): wave 0 the
-// gradient with respect to M (both signs), waves 1 and 2 the + and - staples'
-// shares of the gradient with respect to U_d, summed through LDS.
-__global__ void __launch_bounds__(192) k_staple_adjoint(SmearGeom g, StapleAdjArgs a)
+// of it needs over 200 registers and leaves two waves per SIMD): waves 0 and
+// 1 the + and - staples' gradients with respect to M, waves 2 and 3 their
+// shares of the gradient with respect to U_d, each pair summed through LDS.
+__global__ void __launch_bounds__(256) k_staple_adjoint(SmearGeom g, StapleAdjArgs a)
 {
     const int lane = threadIdx.x & 63, role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long vi = (long long)xcd_tile(blockIdx.x, gridDim.x, 1) * 64 + lane;
     const bool valid = vi < g.V;
     const size_t V = (size_t)g.P;   // plane stride
     const bool plus = a.M[0] != nullptr, minus = a.M[1] != nullptr;
+    const bool gm = a.GM[0] || a.GM[1], gm_one = a.GM[0] == a.GM[1];
     long long s = 0, pd = 0, md = 0, pm = 0, mm = 0, md_pm = 0, mm_pd = 0;
     if (valid) {
         int c[4];
@@ -126,55 +127,56 @@ __global__ void __launch_bounds__(192) k_staple_adjoint(SmearGeom g, StapleAdjAr
         md_pm = shift(md, xm, Sm, Lm, 1);
         mm_pd = shift(mm, xd, Sd, Ld, 1);
     }
-    M3 acc = zero3();
-    if (role == 0) {
-        // gradient with respect to M_s(y): the + staple at x = y - d and the
-        // - staple at x = y + d read it
-        if (valid && (a.GM[0] || a.GM[1])) {
-            M3 gp = zero3(), gmn = zero3();
-            if (plus && a.GM[0]) gp = mul_nn(mul_an(ld(a.Ud, V, md_pm), ld_grad(a.G[0], V, md)), ld(a.Ud, V, md));
-            if (minus && a.GM[1]) gmn = mul_na(mul_nn(ld(a.Ud, V, pm), ld_grad(a.G[1], V, pd)), ld(a.Ud, V, s));
-            if (a.GM[0] == a.GM[1]) {
-                M3 out = a.gm_init ? zero3() : ld(a.GM[0], V, s);
-                axpy(out, a.c, add(gp, gmn));
-                st(a.GM[0], V, s, out);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 2; k++) {
-                    double2 *gm = a.GM[k];
-                    if (!gm || !(k == 0 ? plus : minus)) continue;
-                    M3 out = a.gm_init ? zero3() : ld(gm, V, s);
-                    axpy(out, a.c, k == 0 ? gp : gmn);
-                    st(gm, V, s, out);
-                }
+    // gradient with respect to M_s(y): the + staple at x = y - d and the -
+    // staple at x = y + d read it.  U_d(z) is the first link of the + staple
+    // at z and of the - staple at z + d, the last link of the + staple at
+    // z - mu and of the - staple at z - mu + d.
+    M3 t = zero3();
+    if (valid) {
+        if (role == 0) {
+            if (plus && a.GM[0]) t = mul_nn(mul_an(ld(a.Ud, V, md_pm), ld_grad(a.G[0], V, md)), ld(a.Ud, V, md));
+        } else if (role == 1) {
+            if (minus && a.GM[1]) t = mul_na(mul_nn(ld(a.Ud, V, pm), ld_grad(a.G[1], V, pd)), ld(a.Ud, V, s));
+        } else if (role == 2) {
+            if (plus && a.GUd) {
+                t = mul_nn(mul_na(ld(a.M[0], V, pd), ld(a.Ud, V, pm)), ld_grad(a.G[0], V, s));
+                t = add(t, dag(mul_nn(mul_nn(ld_grad(a.G[0], V, mm), ld(a.Ud, V, mm)), ld(a.M[0], V, mm_pd))));
+            }
+        } else {
+            if (minus && a.GUd) {
+                t = dag(mul_nn(mul_nn(ld(a.M[1], V, s), ld(a.Ud, V, pm)), ld_grad(a.G[1], V, pd)));
+                t = add(t, mul_nn(mul_na(ld_grad(a.G[1], V, mm_pd), ld(a.Ud, V, mm)), ld(a.M[1], V, mm)));
             }
         }
-    } else if (valid && a.GUd) {
-        // U_d(z) is the first link of the + staple at z and of the - staple at
-        // z + d, the last link of the + staple at z - mu and of the - staple
-        // at z - mu + d
-        if (role == 1 && plus) {
-            acc = mul_nn(mul_na(ld(a.M[0], V, pd), ld(a.Ud, V, pm)), ld_grad(a.G[0], V, s));
-            acc = add(acc, dag(mul_nn(mul_nn(ld_grad(a.G[0], V, mm), ld(a.Ud, V, mm)), ld(a.M[0], V, mm_pd))));
-        }
-        if (role == 2 && minus) {
-            acc = dag(mul_nn(mul_nn(ld(a.M[1], V, s), ld(a.Ud, V, pm)), ld_grad(a.G[1], V, pd)));
-            acc = add(acc, mul_nn(mul_na(ld_grad(a.G[1], V, mm_pd), ld(a.Ud, V, mm)), ld(a.M[1], V, mm)));
+    }
+    // separate gradient fields per sign: each of waves 0 and 1 writes its own
+    if (valid && gm && !gm_one && role < 2) {
+        double2 *f = a.GM[role];
+        if (f && (role == 0 ? plus : minus)) {
+            M3 out = a.gm_init ? zero3() : ld(f, V, s);
+            axpy(out, a.c, t);
+            st(f, V, s, out);
         }
     }
-    if (a.GUd) {   // uniform over the block
-        __shared__ double2 red[9][64];
-        if (role == 2)
+    __shared__ double2 red[2][9][64];   // the partials of waves 1 and 3
+    if (role & 1)
 #pragma unroll
-            for (int i = 0; i < 9; i++) red[i][lane] = acc.e[i];
-        __syncthreads();
-        if (role == 1 && valid) {
+        for (int i = 0; i < 9; i++) red[role >> 1][i][lane] = t.e[i];
+    __syncthreads();
+    if (!valid) return;
+    if (role == 0 && gm && gm_one) {
+        M3 out = a.gm_init ? zero3() : ld(a.GM[0], V, s);
 #pragma unroll
-            for (int i = 0; i < 9; i++) acc.e[i] = make_double2(acc.e[i].x + red[i][lane].x, acc.e[i].y + red[i][lane].y);
-            M3 out = ld(a.GUd, V, s);
-            axpy(out, a.c, acc);
-            st(a.GUd, V, s, out);
-        }
+        for (int i = 0; i < 9; i++) t.e[i] = make_double2(t.e[i].x + red[0][i][lane].x, t.e[i].y + red[0][i][lane].y);
+        axpy(out, a.c, t);
+        st(a.GM[0], V, s, out);
+    }
+    if (role == 2 && a.GUd) {
+#pragma unroll
+        for (int i = 0; i < 9; i++) t.e[i] = make_double2(t.e[i].x + red[1][i][lane].x, t.e[i].y + red[1][i][lane].y);
+        M3 out = ld(a.GUd, V, s);
+        axpy(out, a.c, t);
+        st(a.GUd, V, s, out);
     }
 }
 
@@ -369,7 +371,7 @@ hipError_t launch_ff_outer(const SmearGeom &g, const OuterArgs &a, hipStream_t s
 hipError_t launch_staple_adjoint(const SmearGeom &g, const StapleAdjArgs &a, hipStream_t s)
 {
     if (!a.Ud || (!a.M[0] && !a.M[1]) || (a.M[0] && !a.G[0][0]) || (a.M[1] && !a.G[1][0])) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_staple_adjoint, dim3((unsigned)((g.V + 63) / 64)), dim3(192), 0, s, g, a);
+    hipLaunchKernelGGL(k_staple_adjoint, dim3((unsigned)((g.V + 63) / 64)), dim3(256), 0, s, g, a);
     return hipGetLastError();
 }
 
