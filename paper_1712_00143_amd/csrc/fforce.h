@@ -35,7 +35,11 @@ hipError_t launch_ff_outer(const SmearGeom &g, const OuterArgs &a, hipStream_t s
 //   GM[s] (= or +=)  the gradient with respect to M_s (GM[0] may equal GM[1]),
 //   GUd +=           the gradient with respect to the links U_d.
 // Sign index 0 is +d, 1 is -d; M[s] null leaves that sign out; GM[s] and
-// GUd may be null.
+// GUd may be null.  With one field for both signs (GM[0] == GM[1]) and Gb
+// not null, that field also receives gb Gb:
+//   GM = (gm_init ? 0 : GM) + gb Gb + c (adjoint),
+// the initial share a gradient field takes directly from G (the one-link
+// and lower staple terms), so that no separate pass writes it.
 struct StapleAdjArgs {
     const double2 *Ud;
     const double2 *M[2];
@@ -45,6 +49,8 @@ struct StapleAdjArgs {
     double c;
     int mu, d, gm_init;
     int ord[4];
+    const double2 *Gb;
+    double gb;
 };
 hipError_t launch_staple_adjoint(const SmearGeom &g, const StapleAdjArgs &a, hipStream_t s);
 

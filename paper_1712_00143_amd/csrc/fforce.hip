@@ -166,6 +166,7 @@ __global__ void __launch_bounds__(256) k_staple_adjoint(SmearGeom g, StapleAdjAr
     if (!valid) return;
     if (role == 0 && gm && gm_one) {
         M3 out = a.gm_init ? zero3() : ld(a.GM[0], V, s);
+        if (a.Gb) axpy(out, a.gb, ld(a.Gb, V, s));
 #pragma unroll
         for (int i = 0; i < 9; i++) t.e[i] = make_double2(t.e[i].x + red[0][i][lane].x, t.e[i].y + red[0][i][lane].y);
         axpy(out, a.c, t);

@@ -304,9 +304,11 @@ hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5]
     hipError_t e;
     auto U_ = [&](int d) { return Ul + (size_t)d * fsz; };
     auto GU_ = [&](int d) { return GU + (size_t)d * fsz; };
-    // both signs of the staple through d, one field M, gradient Gin
-    auto adj = [&](int mu, int d, const double2 *M, const double2 *Gin, double2 *GM, double2 *GUd, double coef) {
-        StapleAdjArgs a{U_(d), {M, M}, {{Gin, nullptr}, {Gin, nullptr}}, {GM, GM}, GUd, coef, mu, d, 0, {}};
+    // both signs of the staple through d, one field M, gradient Gin; with Gb,
+    // GM starts from gb Gb (gm_init) or adds it
+    auto adj = [&](int mu, int d, const double2 *M, const double2 *Gin, double2 *GM, double2 *GUd, double coef,
+                   const double2 *Gb = nullptr, double gb = 0.0, int init = 0) {
+        StapleAdjArgs a{U_(d), {M, M}, {{Gin, nullptr}, {Gin, nullptr}}, {GM, GM}, GUd, coef, mu, d, init, {}, Gb, gb};
         const int f[2] = {d, mu};
         smear_order(f, 2, a.ord);
         return launch_staple_adjoint(g, a, s);
@@ -322,23 +324,42 @@ hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5]
         if (lep)
             for (int k = 0; k < 3; k++)
                 if ((e = launch_ff_halves(g, Ul, mu, perp[k], Hp + k * fsz, Hm + k * fsz, s)) != hipSuccess) return e;
-        // reverse
-        if ((e = launch_field_axpby(GU_(mu), 1.0, Gmu, c[0], fsz, s)) != hipSuccess) return e;
-        for (int k = 0; k < 3; k++)
-            if ((e = launch_field_axpby(GT1 + k * fsz, 0.0, Gmu, c[1], fsz, s)) != hipSuccess) return e;
-        if (need5)
+        // reverse.  The direct shares of G_mu (c1 on U_mu, c3 on each T1,
+        // c5 on each T2) enter with the first pass that writes the gradient
+        // field (Gb / gb of the staple adjoint) instead of passes of their own.
+        if (need5) {
+            // the 3-staple gradients GT1_j are first written by the 5-staple
+            // adjoints of k = 0 (j = 1, 2) and k = 1 (j = 0)
+            bool gt1_set[3] = {false, false, false};
             for (int k = 0; k < 3; k++) {
                 const int sig = perp[k], inu = (k + 1) % 3, irho = (k + 2) % 3;
                 const int nu = perp[inu], rho = perp[irho];
-                if ((e = launch_field_axpby(GT2, 0.0, Gmu, c[2], fsz, s)) != hipSuccess) return e;
-                if (c[3] != 0.0 && (e = adj(mu, sig, T2 + k * fsz, Gmu, GT2, GU_(sig), c[3])) != hipSuccess) return e;
-                if ((e = adj(mu, rho, T1 + inu * fsz, GT2, GT1 + inu * fsz, GU_(rho), 1.0)) != hipSuccess) return e;
-                if ((e = adj(mu, nu, T1 + irho * fsz, GT2, GT1 + irho * fsz, GU_(nu), 1.0)) != hipSuccess) return e;
+                if (c[3] != 0.0) {
+                    if ((e = adj(mu, sig, T2 + k * fsz, Gmu, GT2, GU_(sig), c[3], Gmu, c[2], 1)) != hipSuccess) return e;
+                } else if ((e = launch_field_axpby(GT2, 0.0, Gmu, c[2], fsz, s)) != hipSuccess) {
+                    return e;
+                }
+                for (const int j : {inu, irho}) {
+                    // T1_nu is transported through rho and T1_rho through nu
+                    const int dj = j == inu ? rho : nu;
+                    const bool first = !gt1_set[j];
+                    gt1_set[j] = true;
+                    if ((e = adj(mu, dj, T1 + j * fsz, GT2, GT1 + j * fsz, GU_(dj), 1.0, first ? Gmu : nullptr,
+                                 first ? c[1] : 0.0, first ? 1 : 0)) != hipSuccess)
+                        return e;
+                }
             }
+        } else {
+            for (int k = 0; k < 3; k++)
+                if ((e = launch_field_axpby(GT1 + k * fsz, 0.0, Gmu, c[1], fsz, s)) != hipSuccess) return e;
+        }
         for (int k = 0; k < 3; k++) {
             const int nu = perp[k];
+            // the one-link share c1 G_mu joins U_mu's gradient in its first pass
+            const double2 *gb = k == 0 ? Gmu : nullptr;
+            const double cb = k == 0 ? c[0] : 0.0;
             if (!lep) {
-                if ((e = adj(mu, nu, U_(mu), GT1 + k * fsz, GU_(mu), GU_(nu), 1.0)) != hipSuccess) return e;
+                if ((e = adj(mu, nu, U_(mu), GT1 + k * fsz, GU_(mu), GU_(nu), 1.0, gb, cb)) != hipSuccess) return e;
                 continue;
             }
             // Lepage = S+(H+) + S-(H-), S+- the single-sign staples through nu:
@@ -348,7 +369,7 @@ hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5]
             StapleAdjArgs a1{U_(nu), {Hp + k * fsz, Hm + k * fsz}, {{Gmu, nullptr}, {Gmu, nullptr}}, {GHp, GHm},
                              GU_(nu), c[4], mu, nu, 1, {}};
             StapleAdjArgs a2{U_(nu), {U_(mu), U_(mu)}, {{GT1 + k * fsz, GHp}, {GT1 + k * fsz, GHm}},
-                             {GU_(mu), GU_(mu)}, GU_(nu), 1.0, mu, nu, 0, {}};
+                             {GU_(mu), GU_(mu)}, GU_(nu), 1.0, mu, nu, 0, {}, gb, cb};
             const int f[2] = {nu, mu};
             smear_order(f, 2, a1.ord);
             smear_order(f, 2, a2.ord);
