@@ -879,6 +879,13 @@ def run_c4(args):
     # the specified 1 -> 4 -> 4 -> 1 network, trained from small random weights
     net, tl, t_train, losses = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, args.nfield,
                                                     args.nsrc, args.train_steps, chans=chans, init="random", **fmt)
+    # the two-layer 1 -> 4 -> 1 network (the specified one without its middle
+    # layer: four layer applications per iteration instead of six), trained
+    # from small random weights on the same fields
+    chans4 = (1, 4, 1)
+    net4, tl4, t_train4, losses4 = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, args.nfield,
+                                                        args.nsrc, args.train_steps, chans=chans4, init="random",
+                                                        **fmt)
     # the two-layer 1 -> 2 -> 1 network (the smallest that holds the polynomial
     # preconditioner), on a quarter of the fields, from random weights and
     # from the polynomial start
@@ -888,6 +895,7 @@ def run_c4(args):
     net3, tl3, t_train3, losses3 = train_preconditioner(H, synth, w.dims, w.eps, w.mass, 4000, nq, sq,
                                                         args.train_steps, chans=(1, 2, 1), init="poly", **fmt)
     names = ["plain_f64", "mixed_f32", "mixed_f16_r12", "learned_fcg", "learned_fcg_untrained_start",
+             "learned_fcg_141_random", "learned_fcg_141_random_untrained_start",
              "learned_fcg_121_random", "learned_fcg_121_random_untrained_start", "learned_fcg_121_poly",
              "poly_fcg_121_untrained", "identity_fcg"]
     res = {k: [] for k in names}
@@ -899,6 +907,7 @@ def run_c4(args):
         L.prepare_links(2, 12)
         nets = {}
         for name, ch, wts in (("learned_fcg_untrained_start", chans, random_start(chans, 4000)),
+                              ("learned_fcg_141_random_untrained_start", chans4, random_start(chans4, 4000)),
                               ("learned_fcg_121_random_untrained_start", (1, 2, 1), random_start((1, 2, 1), 4000)),
                               ("identity_fcg", chans, None)):
             n = H.PTC(L, ch)
@@ -915,6 +924,7 @@ def run_c4(args):
         poly.init_polynomial(a=4.0, c=1.2)
         nets["poly_fcg_121_untrained"] = poly
         nets["learned_fcg"] = net
+        nets["learned_fcg_141_random"] = net4
         nets["learned_fcg_121_random"] = net2
         nets["learned_fcg_121_poly"] = net3
         for s in range(2):
@@ -940,8 +950,8 @@ def run_c4(args):
                 tr = oracle.true_residual(w.dims, fat, lng, w.mass, b, xh)
                 res[name].append((info["iters"], dt, tr, info.get("fell_back", 0)))
             log(f"held-out field {j}, source {s}: " + ", ".join(f"{k} {v[-1][0]} it {v[-1][1]:.4f}s" for k, v in res.items()))
-        for name in ("learned_fcg_untrained_start", "learned_fcg_121_random_untrained_start", "identity_fcg",
-                     "poly_fcg_121_untrained"):
+        for name in ("learned_fcg_untrained_start", "learned_fcg_141_random_untrained_start",
+                     "learned_fcg_121_random_untrained_start", "identity_fcg", "poly_fcg_121_untrained"):
             nets[name].close()
         L.close()
     summ = {k: {"iters_mean": round(float(np.mean([r[0] for r in v])), 1),
@@ -959,6 +969,7 @@ def run_c4(args):
                     f"transports (training and inference), FP16 inference activations, FP64 true residual 1e-10",
         "training": {"steps": args.train_steps, "loss": "energy norm of the error (HISQ_LOSS_ENERGY)",
                      "learned_fcg (1-4-4-1, random start)": loss_info(losses, t_train),
+                     "learned_fcg_141_random (1-4-1, random start)": loss_info(losses4, t_train4),
                      "learned_fcg_121_random (1-2-1, random start)": loss_info(losses2, t_train2),
                      "learned_fcg_121_poly (1-2-1, polynomial start)": loss_info(losses3, t_train3),
                      "what": "harvest_s: synthetic fields generated on the host, loaded, and plain CG to 1e-12 per "
@@ -967,13 +978,15 @@ def run_c4(args):
         "time_gain_vs_plain_f64": {k: round(plain / v["time_s_mean"], 3) for k, v in summ.items()},
         "iteration_gain_of_training": {
             "1-4-4-1": round(summ["learned_fcg_untrained_start"]["iters_mean"] / summ["learned_fcg"]["iters_mean"], 3),
+            "1-4-1 random start": round(summ["learned_fcg_141_random_untrained_start"]["iters_mean"]
+                                        / summ["learned_fcg_141_random"]["iters_mean"], 3),
             "1-2-1 random start": round(summ["learned_fcg_121_random_untrained_start"]["iters_mean"]
                                         / summ["learned_fcg_121_random"]["iters_mean"], 3),
             "1-2-1 polynomial start": round(summ["poly_fcg_121_untrained"]["iters_mean"]
                                             / summ["learned_fcg_121_poly"]["iters_mean"], 3)}}), flush=True)
-    for n in (net, net2, net3):
+    for n in (net, net4, net2, net3):
         n.close()
-    for L in tl + tl2 + tl3:
+    for L in tl + tl4 + tl2 + tl3:
         L.close()
 
 

@@ -231,7 +231,8 @@ def test_fcg_falls_back_on_breakdown():
     lat.close()
 
 
-def test_training_lowers_loss_and_reports_gain():
+@pytest.mark.parametrize("chans", [(1, 4, 4, 1), (1, 4, 1)], ids=["1-4-4-1", "1-4-1"])
+def test_training_lowers_loss_and_reports_gain(chans):
     """Train from small random weights on fields 0..3 (pairs harvested by the
     solver itself, energy-norm loss), test on a held-out field.  Asserted: the
     training loss falls, the flexible CG with the trained network reaches the
@@ -242,7 +243,6 @@ def test_training_lowers_loss_and_reports_gain():
     H = _hisq()
     dims = (8, 8, 8, 8)
     m = 0.02
-    chans = (1, 4, 4, 1)
     lats = []
     net = None
     for j in range(4):
