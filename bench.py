@@ -11,8 +11,13 @@ already resident in HBM:
   * the 16^3x32 workload (eps 0.2, m 0.02): the half-Dslash in every format,
     and CG to FP64 true residual 1e-10 from one source: plain FP64, mixed
     FP32 (recon-18), mixed FP16 storage (recon-12), and the flexible CG with
-    the learned preconditioner (trained before the timed region on pairs the
-    solver harvests from two other sources).
+    the learned preconditioner (a 1-4-1 network trained from small random
+    weights before the timed region, on pairs the solver harvests on four
+    other fields of the same size and recipe; its untrained start is solved
+    once for comparison);
+  * the HISQ smearing, the Symanzik gauge force and the HISQ fermion force
+    on 32^4 (outside the timed steps, each checked against the oracle on
+    sampled links).
 value = FP64 recon-18 streamed half-Dslash throughput on 32^4 in algorithmic
 GB/s (16 links + one input + one output colour vector per output site) from
 HIP events recorded on the stream the kernels run on.  Reported beside it:
