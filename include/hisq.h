@@ -375,9 +375,9 @@ hisq_status hisq_residual_history(hisq_lattice lat, int problem, double *out, in
  * Arrays use the link layout above ([V][4][3][3] complex FP64, site-major;
  * thin links without phases), host pointers or, with HISQ_DEVICE_PTR, device
  * pointers.  FP64 throughout; synchronous.  The library keeps a device
- * workspace of 27 link-direction fields (35 with host outputs that are not
- * loaded; 144 P bytes each, P = V rounded up to 8 plus 296 sites of padding)
- * per lattice until hisq_destroy.
+ * workspace of 51 link-direction fields (59 with host outputs that are not
+ * loaded; 144 P bytes each, P = V rounded up to 8 plus 296 sites of padding:
+ * 7.7 GB at 32^4) per lattice until hisq_destroy.
  *
  * hisq_smear_links: thin -> (fat, lng).  With HISQ_LOAD_RESULT the result
  * also becomes the lattice's links (fat and lng may then be NULL), ready for
@@ -455,8 +455,8 @@ hisq_status hisq_fermion_force_links(hisq_lattice lat, int n, const double *alph
  * runs through the Naik product, the second fat7 level, the U(3) projection
  * and the first level.  U is smeared first and the result loaded as the
  * lattice's links (as hisq_smear_links with HISQ_LOAD_RESULT would).
- * Workspace: 88 link-direction fields (144 P bytes each, P as for
- * hisq_smear_links: 13.3 GB at 32^4)
+ * Workspace: 106 link-direction fields (144 P bytes each, P as for
+ * hisq_smear_links: 16.0 GB at 32^4)
  * and 2 n V/2 vectors, kept until hisq_destroy.  Errors: HISQ_ERR_ARG, HISQ_ERR_BREAKDOWN (a level-1 link
  * has no U(3) projection; the lattice keeps the links it had),
  * HISQ_ERR_OOM / HISQ_ERR_HIP. */

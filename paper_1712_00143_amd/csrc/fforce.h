@@ -54,11 +54,6 @@ struct StapleAdjArgs {
 };
 hipError_t launch_staple_adjoint(const SmearGeom &g, const StapleAdjArgs &a, hipStream_t s);
 
-// Single-sign staples of U_mu through nu: Hp = U_nu(x) U_mu(x+nu) U_nu(x+mu)^+,
-// Hm = U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu).
-hipError_t launch_ff_halves(const SmearGeom &g, const double2 *U, int mu, int nu, double2 *Hp, double2 *Hm,
-                            hipStream_t s);
-
 // GW += gradient of sum Re Tr(N_mu(x) GN_mu(x)), N_mu(x) = W_mu(x) W_mu(x+mu) W_mu(x+2mu)
 // (four-direction planar fields).
 hipError_t launch_ff_naik_adjoint(const SmearGeom &g, const double2 *W, const double2 *GN, double2 *GW,

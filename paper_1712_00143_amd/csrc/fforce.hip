@@ -181,23 +181,6 @@ __global__ void __launch_bounds__(256) k_staple_adjoint(SmearGeom g, StapleAdjAr
     }
 }
 
-__global__ void __launch_bounds__(256) k_ff_halves(SmearGeom g, const double2 *U, int mu, int nu, double2 *Hp,
-                                                   double2 *Hm)
-{
-    const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (s >= g.V) return;
-    const size_t V = (size_t)g.P;   // plane stride
-    int x[4];
-    coords4(g, s, x);
-    const int Sm = pick(g.S, mu), Lm = pick(g.L, mu), Sn = pick(g.S, nu), Ln = pick(g.L, nu);
-    const int xm = pick(x, mu), xn = pick(x, nu);
-    const double2 *Un = U + (size_t)nu * 9 * V, *Um = U + (size_t)mu * 9 * V;
-    const long long pn = shift(s, xn, Sn, Ln, 1), mn = shift(s, xn, Sn, Ln, -1), pm = shift(s, xm, Sm, Lm, 1);
-    const long long mn_pm = shift(mn, xm, Sm, Lm, 1);
-    st(Hp, V, s, mul_na(mul_nn(ld(Un, V, s), ld(Um, V, pn)), ld(Un, V, pm)));
-    st(Hm, V, s, mul_nn(mul_an(ld(Un, V, mn), ld(Um, V, mn)), ld(Un, V, mn_pm)));
-}
-
 __global__ void __launch_bounds__(256) k_ff_naik_adjoint(SmearGeom g, const double2 *W, const double2 *GN,
                                                          double2 *GW)
 {
@@ -373,13 +356,6 @@ hipError_t launch_staple_adjoint(const SmearGeom &g, const StapleAdjArgs &a, hip
 {
     if (!a.Ud || (!a.M[0] && !a.M[1]) || (a.M[0] && !a.G[0][0]) || (a.M[1] && !a.G[1][0])) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_staple_adjoint, dim3((unsigned)((g.V + 63) / 64)), dim3(256), 0, s, g, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_ff_halves(const SmearGeom &g, const double2 *U, int mu, int nu, double2 *Hp, double2 *Hm,
-                            hipStream_t s)
-{
-    hipLaunchKernelGGL(k_ff_halves, dim3((unsigned)((g.V + 255) / 256)), dim3(256), 0, s, g, U, mu, nu, Hp, Hm);
     return hipGetLastError();
 }
 

@@ -75,17 +75,24 @@ hisq_status get_work(hisq_lattice lat, int nf, Work &w, size_t extra = 0)
 }
 
 // out (4 planar fields) = fat7(U (4 planar fields)): one pass 1 for every
-// direction, then per output direction one pass 2 (its 5-staple sums) and
-// one pass 3 (their c5 share and the 7-staples).  T1all: 12 fields (every
-// direction's 3-staples).  keep: T2all holds 12 fields and direction mu's
-// 5-staple sums stay in its fields 3 mu .. 3 mu + 2 (for the adjoint);
-// otherwise T2all is three fields, reused for every direction.
+// direction, with a Lepage term one Lepage pass, then per output direction
+// one pass 2 (its 5-staple sums) and one pass 3 (their c5 share and the
+// 7-staples).  T1all: 12 fields (every direction's 3-staples).  Hall: 24
+// fields for the single-sign 3-staples, needed when cL != 0 (and kept for
+// the adjoint).  keep: T2all holds 12 fields and direction mu's 5-staple
+// sums stay in its fields 3 mu .. 3 mu + 2 (for the adjoint); otherwise
+// T2all is three fields, reused for every direction.
 hipError_t run_fat7(const SmearGeom &g, const double2 *U, double2 *out, double2 *T1all, double2 *T2all,
-                    const double c[5], size_t fsz, hipStream_t s, bool keep = false)
+                    double2 *Hall, const double c[5], size_t fsz, hipStream_t s, bool keep = false)
 {
-    const bool need5 = c[2] != 0.0 || c[3] != 0.0;
-    Pass1Args p1{U, out, need5 ? T1all : nullptr, c[0], c[1], c[4]};
+    const bool need5 = c[2] != 0.0 || c[3] != 0.0, lep = c[4] != 0.0;
+    if (lep && !Hall) return hipErrorInvalidValue;
+    Pass1Args p1{U, out, need5 ? T1all : nullptr, lep ? Hall : nullptr, c[0], c[1]};
     hipError_t e = launch_smear_pass1(g, p1, s);
+    if (e == hipSuccess && lep) {
+        const LepageArgs la{U, Hall, out, c[4]};
+        e = launch_smear_lepage(g, la, s);
+    }
     if (e != hipSuccess || !need5) return e;
     for (int mu = 0; mu < 4; mu++) {
         double2 *T2 = keep ? T2all + (size_t)3 * mu * fsz : T2all;
@@ -130,13 +137,13 @@ hisq_status hisq_fat7(hisq_lattice lat, const double coef[5], const double *in, 
     if (!lat || !coef || !in || !out) return set_err(lat, HISQ_ERR_ARG, "null argument");
     HIPCHK(lat, hipSetDevice(lat->device));
     Work w;
-    hisq_status st = get_work(lat, 27, w);   // U 0-3, result 4-7, staging 8-11, T1 12-23, T2 24-26
+    hisq_status st = get_work(lat, 51, w);   // U 0-3, result 4-7, staging 8-11, T1 12-23, T2 24-26, H 27-50
     if (st != HISQ_OK) return st;
     const SmearGeom g = geom_of(lat);
     const double2 *src;
     if ((st = stage_in(lat, in, flags, w.field(8), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(24), coef, w.fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(24), w.field(27), coef, w.fsz, lat->s));
     if (flags & HISQ_DEVICE_PTR) {
         HIPCHK(lat, launch_smear_from_planar(g, w.field(4), (double2 *)out, lat->s));
     } else {
@@ -177,20 +184,20 @@ hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, 
     HIPCHK(lat, hipSetDevice(lat->device));
     const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
     // fields: thin U 0-3, level 1 / projected W 4-7, level 2 X 8-11 (also the
-    // host input staging), T1 12-23, T2 24-26, output staging 27-34 for
-    // host outputs that are not loaded
+    // host input staging), T1 12-23, T2 24-26, H 27-50, output staging 51-58
+    // for host outputs that are not loaded
     const bool stage_out = !dev && !load;
     Work w;
-    hisq_status st = get_work(lat, stage_out ? 35 : 27, w);
+    hisq_status st = get_work(lat, stage_out ? 59 : 51, w);
     if (st != HISQ_OK) return st;
     const SmearGeom g = geom_of(lat);
     const double2 *src;
     if ((st = stage_in(lat, thin, flags, w.field(8), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(24), LV1, w.fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(12), w.field(24), nullptr, LV1, w.fsz, lat->s));
     HIPCHK(lat, hipMemsetAsync(w.bad, 0, sizeof(int), lat->s));
     HIPCHK(lat, launch_smear_unitarize(g, w.field(4), w.bad, lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(4), w.field(8), w.field(12), w.field(24), LV2, w.fsz, lat->s));
+    HIPCHK(lat, run_fat7(g, w.field(4), w.field(8), w.field(12), w.field(24), w.field(27), LV2, w.fsz, lat->s));
     double2 *of, *ol;
     if (load) {
         const size_t bytes = link_array_bytes(lat);
@@ -202,8 +209,8 @@ hisq_status hisq_smear_links(hisq_lattice lat, const double *thin, double *fat, 
         of = (double2 *)fat;
         ol = (double2 *)lng;
     } else {
-        of = w.field(27);
-        ol = w.field(31);
+        of = w.field(51);
+        ol = w.field(55);
     }
     HIPCHK(lat, launch_smear_output(g, w.field(8), w.field(4), NAIK, of, ol, lat->s));
     if ((st = check_projection(lat, w.bad)) != HISQ_OK) {
@@ -293,14 +300,15 @@ namespace {
 // Gradient of sum Re Tr(fat7(Ul; c)_mu(x) G_mu(x)) with respect to Ul, added
 // to GU (four planar fields each): every pass is undone by its gather-form
 // adjoint, reading the forward intermediates run_fat7 kept (T1all, T2all:
-// 12 fields each) and the single-sign 3-staples H+- of the Lepage term,
-// rebuilt here.  sc: 12 scratch fields.
+// 12 fields each; Hall: the 24 single-sign 3-staples of the Lepage term,
+// needed when cL != 0).  sc: 6 scratch fields.
 hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5], const double2 *G, double2 *GU,
-                        const double2 *T1all, const double2 *T2all, double2 *sc, size_t fsz, hipStream_t s)
+                        const double2 *T1all, const double2 *T2all, const double2 *Hall, double2 *sc, size_t fsz,
+                        hipStream_t s)
 {
-    double2 *Hp = sc, *Hm = sc + 3 * fsz, *GT1 = sc + 6 * fsz;
-    double2 *GT2 = sc + 9 * fsz, *GHp = sc + 10 * fsz, *GHm = sc + 11 * fsz;
+    double2 *GT1 = sc, *GT2 = sc + 3 * fsz, *GHp = sc + 4 * fsz, *GHm = sc + 5 * fsz;
     const bool need5 = c[2] != 0.0 || c[3] != 0.0, lep = c[4] != 0.0;
+    if (lep && !Hall) return hipErrorInvalidValue;
     hipError_t e;
     auto U_ = [&](int d) { return Ul + (size_t)d * fsz; };
     auto GU_ = [&](int d) { return GU + (size_t)d * fsz; };
@@ -319,11 +327,8 @@ hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5]
             if (d != mu) perp[np++] = d;
         const double2 *Gmu = G + (size_t)mu * fsz;
         // forward intermediates: the kept 3- and 5-staple fields of this
-        // direction, and the single-sign 3-staples of the Lepage term
+        // direction (and, for the Lepage term, its single-sign 3-staples)
         const double2 *T1 = T1all + (size_t)3 * mu * fsz, *T2 = T2all + (size_t)3 * mu * fsz;
-        if (lep)
-            for (int k = 0; k < 3; k++)
-                if ((e = launch_ff_halves(g, Ul, mu, perp[k], Hp + k * fsz, Hm + k * fsz, s)) != hipSuccess) return e;
         // reverse.  The direct shares of G_mu (c1 on U_mu, c3 on each T1,
         // c5 on each T2) enter with the first pass that writes the gradient
         // field (Gb / gb of the staple adjoint) instead of passes of their own.
@@ -366,8 +371,9 @@ hipError_t fat7_adjoint(const SmearGeom &g, const double2 *Ul, const double c[5]
             // first the gradients of H+- (and the links' share), then every
             // staple of U_mu through nu at once (its 3-staple gradient GT1 on
             // both signs, GH+- on one each)
-            StapleAdjArgs a1{U_(nu), {Hp + k * fsz, Hm + k * fsz}, {{Gmu, nullptr}, {Gmu, nullptr}}, {GHp, GHm},
-                             GU_(nu), c[4], mu, nu, 1, {}};
+            const double2 *Hp = Hall + (size_t)(6 * mu + 2 * k) * fsz, *Hm = Hp + fsz;
+            StapleAdjArgs a1{U_(nu), {Hp, Hm}, {{Gmu, nullptr}, {Gmu, nullptr}}, {GHp, GHm}, GU_(nu), c[4], mu, nu, 1,
+                             {}};
             StapleAdjArgs a2{U_(nu), {U_(mu), U_(mu)}, {{GT1 + k * fsz, GHp}, {GT1 + k * fsz, GHm}},
                              {GU_(mu), GU_(mu)}, GU_(nu), 1.0, mu, nu, 0, {}, gb, cb};
             const int f[2] = {nu, mu};
@@ -447,10 +453,10 @@ hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const d
     const size_t vb = (size_t)n * lat->h * 3 * sizeof(double2);
     // fields: U 0-3, level-1 sum 4-7, W 8-11, level-2 sum then GX 12-15, GN
     // 16-19, GW 20-23, GU 24-27 (also the input and output staging), the
-    // kept 3- and 5-staples of level 1 28-51 and of level 2 52-75, scratch
-    // 76-87
+    // kept 3- and 5-staples of level 1 28-51 and of level 2 52-75, the
+    // single-sign 3-staples of level 2 76-99, scratch 100-105
     Work w;
-    if ((st = get_work(lat, 88, w, 2 * vb + 64 * sizeof(double))) != HISQ_OK) return st;
+    if ((st = get_work(lat, 106, w, 2 * vb + 64 * sizeof(double))) != HISQ_OK) return st;
     const size_t fsz = w.fsz;
     const SmearGeom g = geom_of(lat);
     const bool dev = (flags & HISQ_DEVICE_PTR) != 0;
@@ -459,12 +465,12 @@ hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const d
     const double2 *src;
     if ((st = stage_in(lat, U, flags, w.field(24), &src)) != HISQ_OK) return st;
     HIPCHK(lat, launch_smear_to_planar(g, src, w.field(0), lat->s));
-    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(28), w.field(40), LV1, fsz, lat->s, true));
+    HIPCHK(lat, run_fat7(g, w.field(0), w.field(4), w.field(28), w.field(40), nullptr, LV1, fsz, lat->s, true));
     HIPCHK(lat, launch_field_axpby(w.field(8), 0.0, w.field(4), 1.0, 4 * fsz, lat->s));
     HIPCHK(lat, hipMemsetAsync(w.bad, 0, sizeof(int), lat->s));
     HIPCHK(lat, launch_smear_unitarize(g, w.field(8), w.bad, lat->s));
     if ((st = check_projection(lat, w.bad)) != HISQ_OK) return st;
-    HIPCHK(lat, run_fat7(g, w.field(8), w.field(12), w.field(52), w.field(64), LV2, fsz, lat->s, true));
+    HIPCHK(lat, run_fat7(g, w.field(8), w.field(12), w.field(52), w.field(64), w.field(76), LV2, fsz, lat->s, true));
     {
         const size_t bytes = link_array_bytes(lat);
         if (!lat->fat64) HIPCHK(lat, hipMalloc(&lat->fat64, bytes));
@@ -483,12 +489,12 @@ hisq_status hisq_fermion_force(hisq_lattice lat, const double *U, int n, const d
     HIPCHK(lat, launch_ff_outer(g, oa, lat->s));
     HIPCHK(lat, hipMemsetAsync(w.field(20), 0, 4 * fsz * sizeof(double2), lat->s));
     HIPCHK(lat, launch_ff_naik_adjoint(g, w.field(8), w.field(16), w.field(20), lat->s));
-    HIPCHK(lat, fat7_adjoint(g, w.field(8), LV2, w.field(12), w.field(20), w.field(52), w.field(64), w.field(76), fsz,
-                             lat->s));
+    HIPCHK(lat, fat7_adjoint(g, w.field(8), LV2, w.field(12), w.field(20), w.field(52), w.field(64), w.field(76),
+                             w.field(100), fsz, lat->s));
     HIPCHK(lat, launch_ff_unitarize_adjoint(g, w.field(4), w.field(20), lat->s));
     HIPCHK(lat, hipMemsetAsync(w.field(24), 0, 4 * fsz * sizeof(double2), lat->s));
-    HIPCHK(lat, fat7_adjoint(g, w.field(0), LV1, w.field(20), w.field(24), w.field(28), w.field(40), w.field(76), fsz,
-                             lat->s));
+    HIPCHK(lat, fat7_adjoint(g, w.field(0), LV1, w.field(20), w.field(24), w.field(28), w.field(40), nullptr,
+                             w.field(100), fsz, lat->s));
     HIPCHK(lat, launch_ff_project(g, w.field(0), w.field(24), w.field(24), lat->s));
     if (dev) {
         HIPCHK(lat, launch_smear_from_planar(g, w.field(24), (double2 *)F, lat->s));

@@ -32,10 +32,14 @@ inline long long plane_stride(long long V)
 // fat7(U; c1, c3, c5, c7; cL) in three kinds of pass over planar fields
 // (U: the four-direction input); for output direction mu, nu_k denotes the
 // k-th direction other than mu (k = 0, 1, 2):
-//   pass 1       (every mu in one launch) F_mu = c1 U_mu + sum over k of
-//                (c3 T1_k + cL Lep_k), T1_k = U_nu(x) U_mu(x+nu) U_nu(x+mu)^+
-//                + (the -nu staple), nu = nu_k, stored for pass 2 as T1 field
-//                3 mu + k (Lep_k: the two-step staple);
+//   pass 1       (every mu in one launch) F_mu = c1 U_mu + c3 sum over k of
+//                T1_k, T1_k = H+_k + H-_k, H+_k = U_nu(x) U_mu(x+nu)
+//                U_nu(x+mu)^+ and H-_k the -nu staple (nu = nu_k), stored for
+//                pass 2 as T1 field 3 mu + k, and with a Lepage term its
+//                halves as H fields 6 mu + 2 k (H+) and 6 mu + 2 k + 1 (H-);
+//   Lepage       (every mu in one launch) F_mu += cL sum over k of the
+//                staple through nu_k of H+_k (+ sign) and H-_k (- sign): the
+//                two-step staples;
 //   pass 2 (mu)  for each k, sig = nu_k and {nu, rho} the other two:
 //                T2_k = staple of T1_nu through rho + staple of T1_rho
 //                through nu (all 5-link staples whose steps avoid sig);
@@ -45,7 +49,14 @@ struct Pass1Args {
     const double2 *U;
     double2 *F;    // four fields
     double2 *T1;   // twelve fields, or null: not stored
-    double c1, c3, cL;
+    double2 *H;    // twenty-four fields, or null: not stored
+    double c1, c3;
+};
+struct LepageArgs {
+    const double2 *U;
+    const double2 *H;   // the twenty-four H fields of pass 1
+    double2 *F;         // four fields, updated
+    double cL;
 };
 struct Pass2Args {
     const double2 *U;
@@ -62,6 +73,7 @@ struct Pass3Args {
 };
 
 hipError_t launch_smear_pass1(const SmearGeom &g, const Pass1Args &a, hipStream_t s);
+hipError_t launch_smear_lepage(const SmearGeom &g, const LepageArgs &a, hipStream_t s);
 hipError_t launch_smear_pass2(const SmearGeom &g, const Pass2Args &a, hipStream_t s);
 hipError_t launch_smear_pass3(const SmearGeom &g, const Pass3Args &a, hipStream_t s);
 

@@ -20,38 +20,41 @@ using namespace su3;
 
 namespace {
 
-// One-step staple of field M through direction (S, L) at site y, whose
-// coordinates along that direction and along mu are yd and ym:
-// U(y) M(y+d) U(y+mu)^+ + U(y-d)^+ M(y-d) U(y-d+mu).
-__device__ __forceinline__ M3 staple_at(const double2 *__restrict__ U, const double2 *__restrict__ M, size_t V,
-                                        long long y, int yd, int S, int L, int ym, int Sm, int Lm)
+// The two single-sign staples of field M through direction (S, L) at site
+// y, whose coordinates along that direction and along mu are yd and ym:
+// P = U(y) M(y+d) U(y+mu)^+, Q = U(y-d)^+ M(y-d) U(y-d+mu).
+__device__ __forceinline__ void staple_halves(const double2 *__restrict__ U, const double2 *__restrict__ M, size_t V,
+                                              long long y, int yd, int S, int L, int ym, int Sm, int Lm, M3 &P, M3 &Q)
 {
     const long long pd = shift(y, yd, S, L, 1), md = shift(y, yd, S, L, -1);
     const long long pm = shift(y, ym, Sm, Lm, 1), md_pm = shift(md, ym, Sm, Lm, 1);
-    M3 T = mul_na(mul_nn(ld(U, V, y), ld(M, V, pd)), ld(U, V, pm));
-    const M3 Q = mul_nn(mul_an(ld(U, V, md), ld(M, V, md)), ld(U, V, md_pm));
+    P = mul_na(mul_nn(ld(U, V, y), ld(M, V, pd)), ld(U, V, pm));
+    Q = mul_nn(mul_an(ld(U, V, md), ld(M, V, md)), ld(U, V, md_pm));
+}
+
+// The one-step staple P + Q of M through (S, L).
+__device__ __forceinline__ M3 staple_at(const double2 *__restrict__ U, const double2 *__restrict__ M, size_t V,
+                                        long long y, int yd, int S, int L, int ym, int Sm, int Lm)
+{
+    M3 T, Q;
+    staple_halves(U, M, V, y, yd, S, L, ym, Sm, Lm, T, Q);
 #pragma unroll
     for (int i = 0; i < 9; i++) T.e[i] = make_double2(T.e[i].x + Q.e[i].x, T.e[i].y + Q.e[i].y);
     return T;
 }
 
-// Two-step (Lepage) staple of M through direction (S, L) at y:
-// U(y) U(y+d) M(y+2d) U(y+d+mu)^+ U(y+mu)^+ + U(y-d)^+ U(y-2d)^+ M(y-2d) U(y-2d+mu) U(y-d+mu).
-__device__ __forceinline__ M3 lepage_at(const double2 *__restrict__ U, const double2 *__restrict__ M, size_t V,
-                                        long long y, int yd, int S, int L, int ym, int Sm, int Lm)
+// A staple through (S, L) whose two signs transport different fields:
+// U(y) Mp(y+d) U(y+mu)^+ + U(y-d)^+ Mm(y-d) U(y-d+mu).  With Mp, Mm the
+// single-sign 3-staples of U_mu through d this is the two-step (Lepage)
+// staple U(y) U(y+d) U_mu(y+2d) U(y+d+mu)^+ U(y+mu)^+ + (its -d image).
+__device__ __forceinline__ M3 staple_pm(const double2 *__restrict__ U, const double2 *__restrict__ Mp,
+                                        const double2 *__restrict__ Mm, size_t V, long long y, int yd, int S, int L,
+                                        int ym, int Sm, int Lm)
 {
     const long long pd = shift(y, yd, S, L, 1), md = shift(y, yd, S, L, -1);
-    const long long p2d = shift(y, yd, S, L, 2), m2d = shift(y, yd, S, L, -2);
-    const long long pm = shift(y, ym, Sm, Lm, 1), pd_pm = shift(pd, ym, Sm, Lm, 1);
-    const long long md_pm = shift(md, ym, Sm, Lm, 1), m2d_pm = shift(m2d, ym, Sm, Lm, 1);
-    M3 P = mul_nn(ld(U, V, y), ld(U, V, pd));
-    P = mul_nn(P, ld(M, V, p2d));
-    P = mul_na(P, ld(U, V, pd_pm));
-    M3 T = mul_na(P, ld(U, V, pm));
-    P = mul_nn(ld(U, V, m2d), ld(U, V, md));
-    P = mul_an(P, ld(M, V, m2d));
-    P = mul_nn(P, ld(U, V, m2d_pm));
-    const M3 Q = mul_nn(P, ld(U, V, md_pm));
+    const long long pm = shift(y, ym, Sm, Lm, 1), md_pm = shift(md, ym, Sm, Lm, 1);
+    M3 T = mul_na(mul_nn(ld(U, V, y), ld(Mp, V, pd)), ld(U, V, pm));
+    const M3 Q = mul_nn(mul_an(ld(U, V, md), ld(Mm, V, md)), ld(U, V, md_pm));
 #pragma unroll
     for (int i = 0; i < 9; i++) T.e[i] = make_double2(T.e[i].x + Q.e[i].x, T.e[i].y + Q.e[i].y);
     return T;
@@ -62,9 +65,10 @@ __device__ __forceinline__ M3 lepage_at(const double2 *__restrict__ U, const dou
 // (the block grid of gauge_force_grid), so that the neighbour links one
 // direction's staples fetch serve the other directions from L1 / L2 and the
 // t neighbours are the block's own recent loads.  For each mu, the 3-link
-// staples through the three nu != mu, stored as T1[3 mu + k] when WT, and
-//   F_mu = c1 U_mu + sum_nu (c3 T1_nu + cL Lepage_nu).
-template <bool LEP, bool WT>
+// staples through the three nu != mu, stored as T1[3 mu + k] when WT (and
+// their single-sign halves as H[6 mu + 2 k], H[6 mu + 2 k + 1] when WH), and
+//   F_mu = c1 U_mu + c3 sum_nu T1_nu.
+template <bool WT, bool WH>
 __global__ void __launch_bounds__(256) k_smear_pass1(SmearGeom g, Pass1Args a, int ntile, int tch)
 {
     const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
@@ -99,12 +103,61 @@ __global__ void __launch_bounds__(256) k_smear_pass1(SmearGeom g, Pass1Args a, i
             const int nu = k + (k >= mu ? 1 : 0);
             const int Sn = pick(g.S, nu), Ln = pick(g.L, nu), xn = pick(x, nu);
             const double2 *Un = a.U + (size_t)nu * 9 * V;
-            const M3 T = staple_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm);
+            M3 T;
+            if constexpr (WH) {
+                M3 Q;
+                staple_halves(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm, T, Q);
+                st(a.H + (size_t)(6 * mu + 2 * k) * 9 * V, V, s, T);
+                st(a.H + (size_t)(6 * mu + 2 * k + 1) * 9 * V, V, s, Q);
+#pragma unroll
+                for (int e = 0; e < 9; e++) T.e[e] = make_double2(T.e[e].x + Q.e[e].x, T.e[e].y + Q.e[e].y);
+            } else {
+                T = staple_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm);
+            }
             axpy(F, a.c3, T);
             if constexpr (WT) st(a.T1 + (size_t)(3 * mu + k) * 9 * V, V, s, T);
-            if constexpr (LEP) axpy(F, a.cL, lepage_at(Un, Umu, V, s, xn, Sn, Ln, xm, Sm, Lm));
         }
         st(a.F + (size_t)mu * 9 * V, V, s, F);
+    }
+}
+
+// The Lepage term of every output direction, with the block grid of pass 1:
+//   F_mu += cL sum over nu != mu of staple_pm(U_nu; H+, H-),
+// H+- the single-sign 3-staples of U_mu through nu that pass 1 stored.
+__global__ void __launch_bounds__(256) k_smear_lepage(SmearGeom g, LepageArgs a, int ntile, int tch)
+{
+    const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
+    const int chunk = lb / ntile, tile = lb - chunk * ntile;
+    const long long i = (long long)tile * 64 + (threadIdx.x & 63);
+    if (i >= (long long)g.S[3]) return;   // no barriers below
+    const size_t V = (size_t)g.P;   // plane stride
+    const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int x[4];
+    {
+        unsigned r = (unsigned)i;
+        x[0] = (int)(r % (unsigned)g.L[0]);
+        r /= (unsigned)g.L[0];
+        x[1] = (int)(r % (unsigned)g.L[1]);
+        x[2] = (int)(r / (unsigned)g.L[1]);
+    }
+    const int t0 = chunk * tch, t1 = t0 + tch < g.L[3] ? t0 + tch : g.L[3];
+    const int Sm = pick(g.S, mu), Lm = pick(g.L, mu);
+    double2 *Fmu = a.F + (size_t)mu * 9 * V;
+#pragma unroll 1
+    for (int t = t0; t < t1; t++) {
+        x[3] = t;
+        const long long s = i + (long long)t * g.S[3];
+        const int xm = pick(x, mu);
+        M3 F = ld(Fmu, V, s);
+#pragma unroll 1
+        for (int k = 0; k < 3; k++) {
+            const int nu = k + (k >= mu ? 1 : 0);
+            const double2 *Hp = a.H + (size_t)(6 * mu + 2 * k) * 9 * V;
+            axpy(F, a.cL,
+                 staple_pm(a.U + (size_t)nu * 9 * V, Hp, Hp + 9 * V, V, s, pick(x, nu), pick(g.S, nu), pick(g.L, nu),
+                           xm, Sm, Lm));
+        }
+        st(Fmu, V, s, F);
     }
 }
 
@@ -348,11 +401,19 @@ hipError_t launch_smear_pass1(const SmearGeom &g, const Pass1Args &a, hipStream_
     int ntile, tch, nb;
     gauge_force_grid(g, &ntile, &tch, &nb);
     const dim3 grid((unsigned)nb), blk(256);
-    const bool lep = a.cL != 0.0, wt = a.T1 != nullptr;
-    if (lep && wt) hipLaunchKernelGGL((k_smear_pass1<true, true>), grid, blk, 0, s, g, a, ntile, tch);
-    else if (lep) hipLaunchKernelGGL((k_smear_pass1<true, false>), grid, blk, 0, s, g, a, ntile, tch);
-    else if (wt) hipLaunchKernelGGL((k_smear_pass1<false, true>), grid, blk, 0, s, g, a, ntile, tch);
+    const bool wt = a.T1 != nullptr, wh = a.H != nullptr;
+    if (wt && wh) hipLaunchKernelGGL((k_smear_pass1<true, true>), grid, blk, 0, s, g, a, ntile, tch);
+    else if (wt) hipLaunchKernelGGL((k_smear_pass1<true, false>), grid, blk, 0, s, g, a, ntile, tch);
+    else if (wh) hipLaunchKernelGGL((k_smear_pass1<false, true>), grid, blk, 0, s, g, a, ntile, tch);
     else hipLaunchKernelGGL((k_smear_pass1<false, false>), grid, blk, 0, s, g, a, ntile, tch);
+    return hipGetLastError();
+}
+
+hipError_t launch_smear_lepage(const SmearGeom &g, const LepageArgs &a, hipStream_t s)
+{
+    int ntile, tch, nb;
+    gauge_force_grid(g, &ntile, &tch, &nb);
+    hipLaunchKernelGGL(k_smear_lepage, dim3((unsigned)nb), dim3(256), 0, s, g, a, ntile, tch);
     return hipGetLastError();
 }
 
