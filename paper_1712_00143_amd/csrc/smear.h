@@ -78,7 +78,9 @@ hipError_t launch_smear_pass2(const SmearGeom &g, const Pass2Args &a, hipStream_
 hipError_t launch_smear_pass3(const SmearGeom &g, const Pass3Args &a, hipStream_t s);
 
 // Visiting order x, then the directions of `first` (in that order, skipping
-// x and repeats), then the rest.
+// x and repeats), then the rest: the order in which the fermion force's
+// staple adjoints visit the sites (the smearing passes instead walk runs of
+// time slices per x-y-z tile).
 void smear_order(const int *first, int n, int ord[4]);
 
 // [V][4][3][3] complex (site-major) -> four-direction planar field.
