@@ -417,10 +417,25 @@ hipError_t launch_smear_lepage(const SmearGeom &g, const LepageArgs &a, hipStrea
     return hipGetLastError();
 }
 
+// The tile grid of gauge_force_grid aimed at `target` blocks: fewer blocks
+// walk longer runs of time slices.  Passes 2 and 3 take 512 (at 32^4 every
+// block walks the whole time extent: pass 3 310 us against 322 with 2048
+// blocks, pass 2 unchanged).
+static void tile_grid(const SmearGeom &g, int target, int *ntile, int *tch, int *nblocks)
+{
+    const long long nxyz = (long long)g.L[0] * g.L[1] * g.L[2];
+    *ntile = (int)((nxyz + 63) / 64);
+    int nchunk = (int)((target + *ntile - 1) / *ntile);
+    nchunk = nchunk < 1 ? 1 : (nchunk > g.L[3] ? g.L[3] : nchunk);
+    *tch = (g.L[3] + nchunk - 1) / nchunk;
+    nchunk = (g.L[3] + *tch - 1) / *tch;
+    *nblocks = *ntile * nchunk;
+}
+
 hipError_t launch_smear_pass2(const SmearGeom &g, const Pass2Args &a, hipStream_t s)
 {
     int ntile, tch, nb;
-    gauge_force_grid(g, &ntile, &tch, &nb);
+    tile_grid(g, 512, &ntile, &tch, &nb);
     hipLaunchKernelGGL(k_smear_pass2, dim3((unsigned)nb), dim3(192), 0, s, g, a, ntile, tch);
     return hipGetLastError();
 }
@@ -428,7 +443,7 @@ hipError_t launch_smear_pass2(const SmearGeom &g, const Pass2Args &a, hipStream_
 hipError_t launch_smear_pass3(const SmearGeom &g, const Pass3Args &a, hipStream_t s)
 {
     int ntile, tch, nb;
-    gauge_force_grid(g, &ntile, &tch, &nb);
+    tile_grid(g, 512, &ntile, &tch, &nb);
     hipLaunchKernelGGL(k_smear_pass3, dim3((unsigned)nb), dim3(192), 0, s, g, a, ntile, tch);
     return hipGetLastError();
 }
