@@ -48,6 +48,11 @@ def test_fat7_and_projection_stages(dims):
     for seed in (61, 62):
         c = tuple(np.random.default_rng(seed).uniform(-1.0, 1.0, 5))
         check(_links(lat.fat7(c, U)), _links(oracle.fat7(dims, U, c)), TOL, ("fat7", dims, seed))
+    # path classes switched off: no 5- and 7-staples (pass 1 and the Lepage
+    # pass only), the Lepage term alone, no 7-staples, no Lepage term
+    for c in ((0.3, -0.2, 0.0, 0.0, 0.7), (0.0, 0.0, 0.0, 0.0, -0.5), (0.4, 0.1, -0.3, 0.0, 0.2),
+              (0.5, 0.2, 0.1, 0.3, 0.0)):
+        check(_links(lat.fat7(c, U)), _links(oracle.fat7(dims, U, c)), TOL, ("fat7", dims, c))
     for lv in (oracle.HISQ_LEVEL1, oracle.HISQ_LEVEL2):
         check(_links(lat.fat7(lv, U)), _links(oracle.fat7(dims, U, lv)), TOL, ("fat7 level", dims))
     v = oracle.fat7(dims, U, oracle.HISQ_LEVEL1)
