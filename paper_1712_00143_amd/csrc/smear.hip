@@ -47,14 +47,15 @@ __device__ __forceinline__ M3 staple_at(const double2 *__restrict__ U, const dou
 // U(y) Mp(y+d) U(y+mu)^+ + U(y-d)^+ Mm(y-d) U(y-d+mu).  With Mp, Mm the
 // single-sign 3-staples of U_mu through d this is the two-step (Lepage)
 // staple U(y) U(y+d) U_mu(y+2d) U(y+d+mu)^+ U(y+mu)^+ + (its -d image).
+// Every element of Mp and Mm is read by one site only: non-temporal loads.
 __device__ __forceinline__ M3 staple_pm(const double2 *__restrict__ U, const double2 *__restrict__ Mp,
                                         const double2 *__restrict__ Mm, size_t V, long long y, int yd, int S, int L,
                                         int ym, int Sm, int Lm)
 {
     const long long pd = shift(y, yd, S, L, 1), md = shift(y, yd, S, L, -1);
     const long long pm = shift(y, ym, Sm, Lm, 1), md_pm = shift(md, ym, Sm, Lm, 1);
-    M3 T = mul_na(mul_nn(ld(U, V, y), ld(Mp, V, pd)), ld(U, V, pm));
-    const M3 Q = mul_nn(mul_an(ld(U, V, md), ld(Mm, V, md)), ld(U, V, md_pm));
+    M3 T = mul_na(mul_nn(ld(U, V, y), ld_nt(Mp, V, pd)), ld(U, V, pm));
+    const M3 Q = mul_nn(mul_an(ld(U, V, md), ld_nt(Mm, V, md)), ld(U, V, md_pm));
 #pragma unroll
     for (int i = 0; i < 9; i++) T.e[i] = make_double2(T.e[i].x + Q.e[i].x, T.e[i].y + Q.e[i].y);
     return T;

@@ -28,6 +28,19 @@ __device__ __forceinline__ M3 ld(const double2 *__restrict__ f, size_t V, long l
 // again only by a later launch.
 typedef double nt_double2 __attribute__((ext_vector_type(2)));
 
+// A load of a field element that no other site reads again (non-temporal, so
+// that it does not push reusable lines out of L2).
+__device__ __forceinline__ M3 ld_nt(const double2 *__restrict__ f, size_t V, long long s)
+{
+    M3 m;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2 *>(f + i * V + s));
+        m.e[i] = make_double2(v.x, v.y);
+    }
+    return m;
+}
+
 __device__ __forceinline__ void st(double2 *__restrict__ f, size_t V, long long s, const M3 &m)
 {
 #pragma unroll
