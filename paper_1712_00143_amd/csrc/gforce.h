@@ -26,6 +26,21 @@ struct GForceArgs {
 // action partials).
 void gauge_force_grid(const SmearGeom &g, int *ntile, int *tch, int *nblocks);
 
+// The x-y-z tile a block of that grid takes for its tile index, a
+// permutation of [0, ntile): when a tile is two whole x rows (L0 = 32) and
+// L1, L2 are multiples of 8, each run of 32 consecutive tiles covers 8 y rows
+// by 8 z planes instead of two whole z planes, so that the blocks an XCD
+// holds at once read fewer neighbour planes of other blocks; otherwise the
+// identity.
+__device__ __forceinline__ int brick_tile(int tile, const SmearGeom &g)
+{
+    if (g.L[0] != 32 || (g.L[1] & 7) || (g.L[2] & 7)) return tile;
+    const int rows = g.L[1] >> 1, nby = g.L[1] >> 3;   // tiles per z plane, y bricks
+    const int b = tile >> 5, q = tile & 31;
+    const int zb = b / nby, yb = b - zb * nby;
+    return (zb * 8 + (q >> 2)) * rows + yb * 4 + (q & 3);
+}
+
 hipError_t launch_gauge_force(const SmearGeom &g, const GForceArgs &a, int mode, hipStream_t s);
 
 }  // namespace hisq

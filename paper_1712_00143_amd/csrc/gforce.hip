@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(256) k_gauge_force(SmearGeom g, GForceArgs a)
     // next slices, from L1 / L2 (the t neighbours are the block's own recent
     // loads instead of a lattice-volume stride away).
     const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
-    const int chunk = lb / a.ntile, tile = lb - chunk * a.ntile;
+    const int chunk = lb / a.ntile, tile = brick_tile(lb - chunk * a.ntile, g);
     const long long nxyz = (long long)g.L[0] * g.L[1] * g.L[2];
     const long long i = (long long)tile * 64 + (threadIdx.x & 63);
     const bool valid = i < nxyz;
