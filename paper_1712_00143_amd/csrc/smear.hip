@@ -122,13 +122,15 @@ __global__ void __launch_bounds__(256) k_smear_pass1(SmearGeom g, Pass1Args a, i
     }
 }
 
-// The Lepage term of every output direction, with the block grid of pass 1:
+// The Lepage term of every output direction, with the block grid of pass 1
+// (its tiles in the brick order of brick_tile, as in passes 2 and 3; pass 1
+// itself is 4 % faster in the plain order):
 //   F_mu += cL sum over nu != mu of staple_pm(U_nu; H+, H-),
 // H+- the single-sign 3-staples of U_mu through nu that pass 1 stored.
 __global__ void __launch_bounds__(256) k_smear_lepage(SmearGeom g, LepageArgs a, int ntile, int tch)
 {
     const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
-    const int chunk = lb / ntile, tile = lb - chunk * ntile;
+    const int chunk = lb / ntile, tile = brick_tile(lb - chunk * ntile, g);
     const long long i = (long long)tile * 64 + (threadIdx.x & 63);
     if (i >= (long long)g.S[3]) return;   // no barriers below
     const size_t V = (size_t)g.P;   // plane stride
@@ -180,7 +182,7 @@ __global__ void __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(1, 2))
                                                                                                int tch)
 {
     const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
-    const int chunk = lb / ntile, tile = lb - chunk * ntile;
+    const int chunk = lb / ntile, tile = brick_tile(lb - chunk * ntile, g);
     const int lane = threadIdx.x & 63;
     const long long i0 = (long long)tile * 64 + lane;
     const bool valid = i0 < (long long)g.S[3];
@@ -229,7 +231,7 @@ __global__ void __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(1, 2))
 __global__ void __launch_bounds__(192) k_smear_pass3(SmearGeom g, Pass3Args a, int ntile, int tch)
 {
     const int lb = xcd_tile(blockIdx.x, gridDim.x, 1);
-    const int chunk = lb / ntile, tile = lb - chunk * ntile;
+    const int chunk = lb / ntile, tile = brick_tile(lb - chunk * ntile, g);
     const int lane = threadIdx.x & 63;
     const long long i0 = (long long)tile * 64 + lane;
     const bool valid = i0 < (long long)g.S[3];
