@@ -38,7 +38,9 @@ def _dag(m):
     return np.conj(np.swapaxes(m, -1, -2))
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 6, 10), (6, 4, 4, 4), (8, 8, 8, 8)])
+# (32, 8, 16, 4): the brick tile order (two whole x rows per tile, y and z
+# multiples of 8) on a field that is not a tiled copy
+@pytest.mark.parametrize("dims", [(4, 4, 6, 10), (6, 4, 4, 4), (8, 8, 8, 8), (32, 8, 16, 4)])
 @pytest.mark.parametrize("coefs", [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0), ONE_LOOP])
 def test_force_and_action_parity(dims, coefs):
     H = _hisq()

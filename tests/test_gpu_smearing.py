@@ -64,7 +64,8 @@ def test_fat7_and_projection_stages(dims):
     lat.close()
 
 
-@pytest.mark.parametrize("dims", [(6, 4, 6, 10), (2, 4, 2, 6), (8, 8, 8, 8)])
+# (32, 8, 16, 4): the brick tile order of the Lepage pass and passes 2 and 3
+@pytest.mark.parametrize("dims", [(6, 4, 6, 10), (2, 4, 2, 6), (8, 8, 8, 8), (32, 8, 16, 4)])
 def test_smear_links_host_pointers(dims):
     H = _hisq()
     lat = H.Lattice(dims)
