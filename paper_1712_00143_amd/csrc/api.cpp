@@ -73,11 +73,7 @@ void SolveSet::release()
         hist.clear();
         return;
     }
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    gexec = nullptr;
-    graph = nullptr;
-    gkey.clear();
+    chunks.release();
     if (fred) (void)hipFree(fred);
     fred = nullptr;
     for (DVec *v : {&b, &xhi, &rhi, &thi, &xlo, &rlo, &Ap, &p, &t, &fz}) dvec_free(*v);

@@ -309,11 +309,7 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
     hipStream_t s = lat0->s;
     const int rprec = mode == 0 ? 0 : 1;
     if (S.mode != mode) {
-        if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
-        if (S.graph) (void)hipGraphDestroy(S.graph);
-        S.gexec = nullptr;
-        S.graph = nullptr;
-        S.gkey.clear();
+        S.chunks.release();
         S.mode = mode;
     }
     if (S.borrowed) {
@@ -401,22 +397,19 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
            << S.one_lattice;
         for (int nr = 1; nr <= 4; nr++) ks << ":" << pl.mrhs[nr].W << pl.mrhs[nr].remap;
         ks << ":" << pl.group64 << pl.mrhs64.W << pl.mrhs64.remap << ":" << fused_step(S);
-        if (S.gkey != ks.str() || !S.gexec) {
-            if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
-            if (S.graph) (void)hipGraphDestroy(S.graph);
-            S.gexec = nullptr;
-            S.graph = nullptr;
-            HIPCHK(lat0, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            hipError_t ce = enqueue_iters(S, pl, kchunk, s);
-            hipGraph_t g = nullptr;
-            hipError_t ee = hipStreamEndCapture(s, &g);
-            if (ce != hipSuccess) return hip_err(lat0, ce, "graph capture");
-            if (ee != hipSuccess) return hip_err(lat0, ee, "hipStreamEndCapture");
-            S.graph = g;
-            HIPCHK(lat0, hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0));
-            S.gkey = ks.str();
+        if (S.chunks.key != ks.str() || !S.chunks.ready()) {
+            hipError_t ce = S.chunks.capture(kchunk, s, [&](int len) { return enqueue_iters(S, pl, len, s); });
+            if (ce != hipSuccess) {
+                S.chunks.release();
+                return hip_err(lat0, ce, "graph capture");
+            }
+            S.chunks.key = ks.str();
         }
     }
+    // one problem: chunks sized to end near the next pause; a batch keeps
+    // fixed chunks (its paused problems' tiles exit while the others run)
+    ChunkPlanner plan(kchunk);
+    if (S.nprob == 1) plan.rebase(S.hst[0]);
 
     std::vector<int> gave_up(S.nprob, 0);
     S.hist.assign(S.nprob, std::vector<double>());
@@ -433,10 +426,12 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
         for (int k = 0; k < S.nprob; k++)
             if (S.hst[k].status == ST_RUNNING) active = true;
         if (!active) break;
-        if (use_graph) HIPCHK(lat0, hipGraphLaunch(S.gexec, s));
-        else HIPCHK(lat0, enqueue_iters(S, pl, kchunk, s));
+        const int len = S.nprob == 1 ? plan.next(S.hst[0]) : kchunk;
+        if (use_graph) HIPCHK(lat0, S.chunks.launch(len, s));
+        else HIPCHK(lat0, enqueue_iters(S, pl, len, s));
         HIPCHK(lat0, hipMemcpyAsync(S.hst, S.dst, sizeof(SolveState) * S.nprob, hipMemcpyDeviceToHost, s));
         HIPCHK(lat0, hipStreamSynchronize(s));
+        if (S.nprob == 1 && (S.hst[0].status == ST_RUNNING || S.hst[0].status == ST_RELIABLE)) plan.observe(S.hst[0]);
         if (hook) HIPCHK(lat0, hook(S, hook_ctx, s));
         bool rel = false;
         for (int k = 0; k < S.nprob; k++)
@@ -471,6 +466,7 @@ hisq_status run_cg(hisq_lattice lat0, SolveSet &S, const hisq_solver_params &prm
                 gave_up[k] = 1;
             }
         }
+        if (rel && S.nprob == 1 && S.hst[0].status == ST_RUNNING) plan.rebase(S.hst[0]);
     }
 
     long long clk0 = 0;

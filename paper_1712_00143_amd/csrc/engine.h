@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/hisq.h"
+#include "fcg_graph.h"
 #include "launch.h"
 
 namespace hisq {
@@ -42,9 +43,7 @@ struct SolveSet {
     double *dpart = nullptr;
     double *dred = nullptr;     // compact per-tile sums of the fused CG step: [2][ntile]
     DVec b, xhi, rhi, thi, xlo, rlo, Ap, p, t;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    std::string gkey;
+    ChunkGraphs chunks;   // captured iteration chunks (HISQ_USE_GRAPH)
     // flexible CG: z = M(r) and the compact tile sums of its fused iteration
     DVec fz;
     double *fred = nullptr;

@@ -31,7 +31,7 @@ using namespace hisq;
 hipError_t ptc_apply_internal(hisq_ptc n, hisq_lattice lat, int lslot, int prec, int recon, const float *r, float *z,
                               const PtcFuse *fz);
 std::string ptc_graph_key(hisq_ptc n);
-FcgGraphCache &ptc_fcg_graph(hisq_ptc n);
+ChunkGraphs &ptc_fcg_graph(hisq_ptc n);
 
 extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double mass, const double *b, double *x,
                                        const hisq_solver_params *params, hisq_solver_info *info)
@@ -156,6 +156,7 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
         return ptc_apply_internal(net, lat, pslot, pprec, precon, (const float *)S.rlo.p, (float *)z.p, fz);
     };
     const PtcFuse fuse{S.dst, ST_RUNNING, (const float *)S.Ap.p, S.fred + FRED_QZ * nt, nt};
+    const PtcFuse resume_gate{S.dst, ST_RESUME, nullptr, nullptr, nt};   // gated only
     // one iteration, no finisher launches and no host decisions: q = A p with
     // the (p, q) sums; alpha, x, r and the |r|^2 sums; z = M(r) with the (q, z)
     // sums; the status decision, beta, p and the (p, r) sums
@@ -199,54 +200,64 @@ extern "C" hisq_status hisq_cg_learned(hisq_lattice lat, hisq_ptc net, double ma
            << ":" << z.p << ":" << S.fred << ":" << S.dst << ":" << S.ddesc << ":" << S.dpart << ":" << nt << ":"
            << slot << ":" << recon << ":" << tc.W << ":" << tc.remap << ":" << tc.cpol << ":" << pslot << ":" << kchunk << ":"
            << ptc_graph_key(net);
-        FcgGraphCache &G = ptc_fcg_graph(net);
-        if (G.key != ks.str() || !G.exec) {
-            G.release();
-            HIPCHK(lat, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            hipError_t ce = hipSuccess;
-            for (int q = 0; q < kchunk && ce == hipSuccess; q++) ce = iteration();
-            hipGraph_t g = nullptr;
-            hipError_t ee = hipStreamEndCapture(s, &g);
+        ChunkGraphs &G = ptc_fcg_graph(net);
+        if (G.key != ks.str() || !G.ready()) {
+            hipError_t ce = G.capture(kchunk, s, [&](int len) -> hipError_t {
+                hipError_t e = hipSuccess;
+                for (int q = 0; q < len && e == hipSuccess; q++) e = iteration();
+                return e;
+            });
             if (ce != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
+                G.release();
                 return hip_err(lat, ce, "flexible CG graph capture");
             }
-            if (ee != hipSuccess) return hip_err(lat, ee, "hipStreamEndCapture");
-            G.graph = g;
-            HIPCHK(lat, hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0));
             G.key = ks.str();
         }
     }
-    hipGraphExec_t gexec = use_graph ? ptc_fcg_graph(net).exec : nullptr;
+    const ChunkGraphs *graphs = use_graph ? &ptc_fcg_graph(net) : nullptr;
+    ChunkPlanner plan(kchunk);
+    plan.rebase(hs);
     int fell_back = 0;
     S.hist.assign(1, std::vector<double>());
     lat->last_solve = &S;
     for (;;) {
-        if (use_graph) HIPCHK(lat, hipGraphLaunch(gexec, s));
+        const int len = plan.next(hs);
+        if (graphs) HIPCHK(lat, graphs->launch(len, s));
         else
-            for (int q = 0; q < kchunk; q++) HIPCHK(lat, iteration());
+            for (int q = 0; q < len; q++) HIPCHK(lat, iteration());
         HIPCHK(lat, hipMemcpyAsync(&hs, S.dst, sizeof hs, hipMemcpyDeviceToHost, s));
         HIPCHK(lat, hipStreamSynchronize(s));
+        if (hs.status == ST_RUNNING || hs.status == ST_RELIABLE) plan.observe(hs);
         if (hs.status == ST_RELIABLE) {
+            // FP64 reliable update: x_hi += x_lo and the true residual, whose
+            // finisher decides on the device (converged, or resume); the
+            // resume runs gated on that decision, so one host read follows:
+            // r = r_hi, z = M(r), the new direction and the (p, r) sums of
+            // the next iteration
             HIPCHK(lat, blas(BL_XACCUM, ST_RELIABLE, FIN_NONE));
             HIPCHK(lat, dslash(0, 0, 18, 8, 1, EPI_PLAIN, FIN_NONE, ST_RELIABLE, S.xhi, S.thi, nullptr));
             HIPCHK(lat, dslash(0, 0, 18, 8, 0, EPI_RES, FIN_TRUERES, ST_RELIABLE, S.thi, S.rhi, &S.xhi));
+            {
+                BlasLaunch bl;
+                memset(&bl, 0, sizeof bl);
+                bl.probs = S.ddesc;
+                bl.states = S.dst;
+                bl.want = ST_RESUME;
+                bl.fin = FIN_NONE;
+                bl.partials = S.dpart;
+                bl.v[0] = S.rhi.p;
+                bl.v[1] = S.rlo.p;
+                HIPCHK(lat, launch_blas(BL_COPY_D2F, 1, bl, S.ntile, 1, s));
+            }
+            HIPCHK(lat, precondition(&resume_gate));
+            HIPCHK(lat, fcg(FCG_DOTS_B, ST_RESUME, FIN_FCG_BETA, 2));
+            HIPCHK(lat, fcg(FCG_P, ST_RESUME, FIN_NONE, 0));
+            HIPCHK(lat, fcg(FCG_DOT_PR, ST_RESUME, FIN_NONE, 0));
+            HIPCHK(lat, blas(BL_STATUS, ST_RESUME, FIN_NONE));
             HIPCHK(lat, hipMemcpyAsync(&hs, S.dst, sizeof hs, hipMemcpyDeviceToHost, s));
             HIPCHK(lat, hipStreamSynchronize(s));
             if (hs.bb > 0) S.hist[0].push_back(std::sqrt(hs.rr_true / hs.bb));
-            if (hs.status == ST_RESUME) {
-                if (hs.iter >= hs.maxiter) break;
-                // continue from the true residual: r = r_hi, z = M(r), new
-                // direction, and the (p, r) sums of the next iteration
-                HIPCHK(lat, launch_convert(S.rhi.p, 0, S.rlo.p, 1, h * 3, s));
-                HIPCHK(lat, precondition(nullptr));
-                HIPCHK(lat, fcg(FCG_DOTS_B, ST_RESUME, FIN_FCG_BETA, 2));
-                HIPCHK(lat, fcg(FCG_P, ST_RESUME, FIN_NONE, 0));
-                HIPCHK(lat, fcg(FCG_DOT_PR, ST_RESUME, FIN_NONE, 0));
-                HIPCHK(lat, blas(BL_STATUS, ST_RESUME, FIN_NONE));
-                HIPCHK(lat, hipMemcpyAsync(&hs, S.dst, sizeof hs, hipMemcpyDeviceToHost, s));
-                HIPCHK(lat, hipStreamSynchronize(s));
-            }
+            if (hs.status == ST_RUNNING) plan.rebase(hs);
         }
         if (hs.status == ST_CONVERGED || hs.status == ST_BREAKDOWN) break;
         if (hs.status == ST_RUNNING && hs.iter >= hs.maxiter) break;

@@ -79,7 +79,7 @@ struct hisq_ptc_s {
     __half2 *inf16 = nullptr;
     float *infsc = nullptr;
     long long inf16V = 0;
-    FcgGraphCache fcg_graph;
+    ChunkGraphs fcg_graph;
 };
 
 namespace {
@@ -475,7 +475,7 @@ hipError_t ptc_apply_internal(hisq_ptc n, hisq_lattice lat, int lslot, int prec,
 
 // Everything of the network that a captured launch of apply_net holds by
 // value: the network, its weight and workspace pointers and its shape.
-FcgGraphCache &ptc_fcg_graph(hisq_ptc n)
+ChunkGraphs &ptc_fcg_graph(hisq_ptc n)
 {
     return n->fcg_graph;
 }
