@@ -289,7 +289,8 @@ def run_headline(args):
     bd = torch.from_numpy(b.view(np.float64)).cuda()
     solves = {
         "plain_f64": H.hisq_default_params(tol=1e-10, sloppy=0, recon=18, flags=H.HISQ_USE_GRAPH),
-        "mixed_f32_r18": H.hisq_default_params(tol=1e-10, sloppy=1, recon=18, flags=H.HISQ_USE_GRAPH),
+        "mixed_f32_r18": H.hisq_default_params(tol=1e-10, sloppy=1, recon=18, delta=args.delta,
+                                               flags=H.HISQ_USE_GRAPH),
         "mixed_f16_r12": H.hisq_default_params(tol=1e-10, sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH),
     }
     x_oracle = None
@@ -331,7 +332,8 @@ def run_headline(args):
         start.set_transport(2, 12)
         start.set_activations(2)
         start.set_weights(random_start(chans, w.seed))
-        _, info0 = start.cg_learned(lat, w.mass, b, params=H.hisq_default_params(tol=1e-10, sloppy=1, recon=18))
+        _, info0 = start.cg_learned(lat, w.mass, b, params=H.hisq_default_params(tol=1e-10, sloppy=1, recon=18,
+                                                                                  delta=args.delta))
         start.close()
         train_info = {"network": "1-4-1 PTC trained from small random weights, energy-norm loss, FP16 recon-12 "
                                  "transports, FP16 inference activations; pairs from four other fields of the "
@@ -361,7 +363,7 @@ def run_headline(args):
                 res["x"][name] = xd
             if net is not None:
                 xd = torch.zeros_like(bd)
-                prm = H.hisq_default_params(tol=1e-10, sloppy=1, recon=18, flags=H.HISQ_USE_GRAPH)
+                prm = H.hisq_default_params(tol=1e-10, sloppy=1, recon=18, delta=args.delta, flags=H.HISQ_USE_GRAPH)
                 (_, info), dt = solve_timed(torch, stream, lambda: net.cg_learned(lat, w.mass, bd, x=xd, params=prm))
                 info["wall_s"] = dt
                 res["cg"]["learned_fcg_f32"] = info
@@ -431,6 +433,8 @@ def run_headline(args):
                         "oracle_true_residual": float(f"{tr_or:.3e}"),
                         "error_vs_oracle_solution": float(f"{err:.3e}"),
                         "converged": bool(infos[-1]["converged"])}
+            if name == "mixed_f32_r18" or name.startswith("learned"):
+                cg[name]["reliable_update_delta"] = args.delta
             if name.startswith("learned"):
                 cg[name]["fell_back"] = bool(infos[-1]["fell_back"])
                 cg[name]["training"] = train_info
@@ -965,14 +969,16 @@ def run_c4(args):
                 if name == "plain_f64":
                     fn = lambda xd: L.cg(w.mass, bd, x=xd, params=H.hisq_default_params(sloppy=0, flags=H.HISQ_USE_GRAPH))
                 elif name == "mixed_f32":
-                    fn = lambda xd: L.cg(w.mass, bd, x=xd, params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))
+                    fn = lambda xd: L.cg(w.mass, bd, x=xd, params=H.hisq_default_params(sloppy=1, delta=args.delta,
+                                                                                        flags=H.HISQ_USE_GRAPH))
                 elif name == "mixed_f16_r12":
                     fn = lambda xd: L.cg(w.mass, bd, x=xd,
                                          params=H.hisq_default_params(sloppy=2, recon=12, flags=H.HISQ_USE_GRAPH))
                 else:
                     nn = nets[name]
                     fn = lambda xd: nn.cg_learned(L, w.mass, bd, x=xd,
-                                                  params=H.hisq_default_params(sloppy=1, flags=H.HISQ_USE_GRAPH))
+                                                  params=H.hisq_default_params(sloppy=1, delta=args.delta,
+                                                                               flags=H.HISQ_USE_GRAPH))
                 xd = torch.zeros_like(bd)
                 fn(xd)                                 # warm-up: tuning, graph capture
                 xd = torch.zeros_like(bd)
@@ -998,6 +1004,7 @@ def run_c4(args):
         "workload": f"learned PTC preconditioner 16^4, eps 0.25, m 0.005: trained on {args.nfield} fields x "
                     f"{args.nsrc} sources, tested on {args.nheld} held-out fields x 2 sources; FP16 recon-12 "
                     f"transports (training and inference), FP16 inference activations, FP64 true residual 1e-10",
+        "reliable_update_delta": {"mixed_f32_and_learned": args.delta, "mixed_f16_r12": 0.1},
         "training": {"steps": args.train_steps, "loss": "energy norm of the error (HISQ_LOSS_ENERGY)",
                      "learned_fcg (1-4-4-1, random start)": loss_info(losses, t_train),
                      "learned_fcg_141_random (1-4-1, random start)": loss_info(losses4, t_train4),
@@ -1048,6 +1055,8 @@ def main():
     ap.add_argument("--oracle-sample", type=int, default=8, help="c2/c3: solutions checked by the oracle")
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "copy", "smear", "gforce", "fforce"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--delta", type=float, default=0.01,
+                    help="reliable-update threshold of the FP32-sloppy solvers (mixed FP32 CG, learned FCG)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--dslash-only", action="store_true", help="time only the Dslash")
     ap.add_argument("--nper", type=int, default=16, help="c3: solves per lattice size")
