@@ -22,7 +22,7 @@
 namespace hisq {
 
 struct ChunkGraphs {
-    static constexpr int MAXG = 8;
+    static constexpr int MAXG = 12;
     int n = 0;
     int len[MAXG] = {};   // iterations per graph, decreasing
     hipGraph_t graph[MAXG] = {};
@@ -40,15 +40,15 @@ struct ChunkGraphs {
         key.clear();
     }
     bool ready() const { return n > 0; }
-    // lengths k, then the powers of two below k
+    // lengths k, then the powers of two below k (the smallest MAXG - 1 of
+    // them, so that 1 is always there and every count can be launched)
     static int lengths(int k, int out[MAXG])
     {
+        int pw[MAXG], np = 0;
+        for (int p = 1; p < k && np < MAXG - 1; p *= 2) pw[np++] = p;
         int m = 0;
         out[m++] = k;
-        int p = 1;
-        while (2 * p < k) p *= 2;
-        for (; p >= 1 && m < MAXG; p /= 2)
-            if (p < k) out[m++] = p;
+        while (np > 0) out[m++] = pw[--np];
         return m;
     }
     // capture every length: enqueue(len) puts len iterations on s
@@ -77,7 +77,8 @@ struct ChunkGraphs {
         }
         return hipSuccess;
     }
-    // iters iterations as the fewest graph launches (largest lengths first)
+    // iters iterations as graph launches, largest lengths first (the last
+    // length is 1, so every count is reached)
     hipError_t launch(int iters, hipStream_t s) const
     {
         for (int i = 0; i < n && iters > 0;) {
@@ -89,7 +90,7 @@ struct ChunkGraphs {
                 i++;
             }
         }
-        return hipSuccess;
+        return iters > 0 ? hipErrorInvalidValue : hipSuccess;
     }
 };
 

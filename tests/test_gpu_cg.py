@@ -70,6 +70,39 @@ def test_graph_replay_matches_eager_bitwise():
     lat.close()
 
 
+def test_chunk_lengths_do_not_change_the_solve():
+    """The host only chooses how many iterations run between its reads of the
+    solver state (planned from the residual's decay, at most check_every):
+    every launch behind a pause is gated, so the iterates, the iteration and
+    reliable-update counts and the solution are the same bits for any
+    check_every, eager or graph-captured (chunks of 32, 16, 8, 4, 2 and 1)."""
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    fat, lng = synth.make_links(dims, 0.3, seed=15)
+    b = synth.gaussian_even(dims, 16)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    lat.prepare_links(1, 18)
+    ref = None
+    for ce in (1, 3, 16, 32):
+        for fl in (0, H.HISQ_USE_GRAPH):
+            for delta in (0.1, 0.01):
+                p = H.hisq_default_params(tol=1e-10, sloppy=1, check_every=ce, delta=delta, flags=fl)
+                x, info = lat.cg(0.02, b, params=p)
+                assert info["converged"] == 1
+                key = (delta,)
+                if ref is None:
+                    ref = {}
+                if key not in ref:
+                    ref[key] = (x, info["iters"], info["reliable_updates"])
+                    assert oracle.true_residual(dims, fat, lng, 0.02, b, x) <= 1e-10
+                else:
+                    x0, it0, rel0 = ref[key]
+                    assert info["iters"] == it0 and info["reliable_updates"] == rel0, (ce, fl, delta)
+                    assert np.array_equal(x, x0), (ce, fl, delta)
+    lat.close()
+
+
 def test_warm_start_and_zero_source():
     H = _hisq()
     dims = (4, 4, 4, 8)

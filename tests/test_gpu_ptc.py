@@ -392,6 +392,38 @@ def test_fcg_graph_replay_matches_eager():
     lat.close()
 
 
+def test_fcg_chunk_lengths_do_not_change_the_solve():
+    """The flexible CG's chunk lengths (planned from the residual's decay, at
+    most check_every) and its device-gated restart after a reliable update
+    leave the solve unchanged bit for bit, eager or graph-captured."""
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    m = 0.01
+    fat, lng = synth.make_links(dims, 0.25, seed=81)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    net = H.PTC(lat, (1, 4, 4, 1))
+    net.init_polynomial(a=4.0, c=1.2)
+    b = synth.gaussian_even(dims, 82)
+    ref = {}
+    for ce in (1, 5, 16, 32):
+        for fl in (0, H.HISQ_USE_GRAPH):
+            for delta in (0.1, 0.01):
+                p = H.hisq_default_params(tol=1e-10, sloppy=1, check_every=ce, delta=delta, flags=fl)
+                x, info = net.cg_learned(lat, m, b, params=p)
+                assert info["converged"] == 1 and not info["fell_back"]
+                if delta not in ref:
+                    ref[delta] = (x, info["iters"], info["reliable_updates"])
+                    assert oracle.true_residual(dims, fat, lng, m, b, x) <= 1e-10
+                    assert len(lat.residual_history()) == info["reliable_updates"]
+                else:
+                    x0, it0, rel0 = ref[delta]
+                    assert info["iters"] == it0 and info["reliable_updates"] == rel0, (ce, fl, delta)
+                    assert np.array_equal(x, x0), (ce, fl, delta)
+    net.close()
+    lat.close()
+
+
 def test_checkpoint_save_load(tmp_path):
     """A saved network restores exactly: the same weights, and training goes
     on from the restored Adam state as it does in the network it came from.
