@@ -853,7 +853,7 @@ def c3_summary(args, oracle_sample=0):
         ms.append(wk.mass)
         links.append((wk.dims, fat, lng) if oracle_sample > 0 else None)
     setup_s = time.perf_counter() - t0
-    prm = H.hisq_default_params(tol=1e-10, sloppy=1, flags=H.HISQ_USE_GRAPH)
+    prm = H.hisq_default_params(tol=1e-10, sloppy=1, delta=args.delta, flags=H.HISQ_USE_GRAPH)
     H.hisq_batch_cg(lats, ms, bs, params=prm)          # warm-up: tuning, graph capture
     (xs, infos), dt = solve_timed(torch, None, lambda: H.hisq_batch_cg(lats, ms, bs, params=prm))
     tdone = np.array([i["t_done_s"] for i in infos])
@@ -873,7 +873,8 @@ def c3_summary(args, oracle_sample=0):
         "all_converged": all(i["converged"] for i in infos),
         "worst_true_residual_fp64": float(f"{max(i['true_residual'] for i in infos):.3e}"),
         "sequential_time_s": round(t_seq, 4), "batch_speedup": round(t_seq / dt, 3),
-        "setup_s": round(setup_s, 2)}
+        "setup_s": round(setup_s, 2), "reliable_update_delta": args.delta,
+        "reliable_updates_mean": round(float(np.mean([i["reliable_updates"] for i in infos])), 2)}
     if oracle_sample > 0:
         n = len(ws)
         # interleave the four sizes: problems are ordered size by size
