@@ -91,8 +91,13 @@ typedef struct {
     hisq_prec sloppy;    /* precision of the iteration: F64 = plain CG; F32 / F16 = mixed
                             precision with FP64 reliable updates */
     hisq_recon recon;    /* link reconstruction of the sloppy operator */
-    double delta;        /* reliable update when ||r|| < delta * max ||r|| since the last one */
-    int check_every;     /* iterations per launched chunk between host status checks */
+    double delta;        /* reliable update when ||r|| < delta * max ||r|| since the last one
+                            (FP32 sloppy at small mass: 0.01 halves the updates of 0.1 at the
+                            same iteration count; FP16 keeps 0.1) */
+    int check_every;     /* most iterations launched between host status checks; a single
+                            solve sizes each chunk from the residual's decay to end near the
+                            next reliable update, a batch launches check_every at a time (the
+                            chunk lengths never change the result) */
     int flags;           /* HISQ_DEVICE_PTR | HISQ_X_IS_GUESS | HISQ_USE_GRAPH | HISQ_NO_TUNE |
                             HISQ_STOP_STAGNATION */
 } hisq_solver_params;
