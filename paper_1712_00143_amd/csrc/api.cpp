@@ -339,7 +339,13 @@ static hisq_status pack_set(hisq_lattice lat, int prec, int recon)
             a[f] = m > 0 ? m : 1.0;
         }
     }
-    const size_t per_par = (size_t)lat->h * NDIR * link_bytes(prec, recon);
+    const long long hs = link_plane_stride(lat->h);
+    // the kernels address a direction block with 32-bit offsets
+    if ((double)hs * (double)link_bytes(prec, recon) >= 2147483648.0) {
+        (void)hipFree(dtmp);
+        return set_err(lat, HISQ_ERR_ARG, "lattice too large for this link format (one direction block >= 2 GiB)");
+    }
+    const size_t per_par = (size_t)hs * NDIR * link_bytes(prec, recon);
     for (int par = 0; par < 2; par++) {
         if (!lat->lk[slot][par]) {
             hipError_t e = hipMalloc(&lat->lk[slot][par], per_par);
@@ -356,6 +362,7 @@ static hisq_status pack_set(hisq_lattice lat, int prec, int recon)
         p.lng = lat->lng64;
         for (int k = 0; k < 4; k++) p.L[k] = lat->L[k];
         p.h = (int)lat->h;
+        p.hs = (int)hs;
         p.out_par = par;
         p.dst = lat->lk[slot][par];
         p.a[0] = a[0];
@@ -387,6 +394,7 @@ static hisq_status pack_set(hisq_lattice lat, int prec, int recon)
     ls.a[1] = a[1];
     ls.s[0] = s[0];
     ls.s[1] = s[1];
+    ls.hs = (int)hs;
     ls.valid = 1;
     ProbDesc d = lattice_desc(lat);
     HIPCHK(lat, hipMemcpyAsync(lat->ddesc, &d, sizeof d, hipMemcpyHostToDevice, lat->s));

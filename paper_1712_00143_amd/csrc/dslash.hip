@@ -39,6 +39,7 @@ __device__ __forceinline__ void dslash_body(const DslashLaunch &a)
     const int par = a.out_par;
     const LinkSet &ls = pd.ls[a.lslot];
     const char *lbase = (const char *)ls.ptr[par];
+    const int hs = ls.hs;   // link plane stride
     const long long voff = pd.voff;
     const int L0 = pd.L[0], L1 = pd.L[1], L2 = pd.L[2], L3 = pd.L[3];
 
@@ -78,7 +79,7 @@ __device__ __forceinline__ void dslash_body(const DslashLaunch &a)
             if constexpr (CP < 2) {
 #pragma unroll
                 for (int g = 0; g < G; g++)
-                    load_link_raw_wave<LT, R, CP>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
+                    load_link_raw_wave<LT, R, CP>(lbase + (size_t)(wave * DPW + g0 + g) * hs * F::BYTES, i, hs, raw[g]);
             } else {
                 // part of the operator kept in the Infinity Cache: direction
                 // blocks below a.cpol load cached, the rest stream.  The choice
@@ -88,17 +89,17 @@ __device__ __forceinline__ void dslash_body(const DslashLaunch &a)
                 if (dg + G <= a.cpol) {
 #pragma unroll
                     for (int g = 0; g < G; g++)
-                        load_link_raw_wave<LT, R, 1>(lbase + (size_t)(dg + g) * h * F::BYTES, i, h, raw[g]);
+                        load_link_raw_wave<LT, R, 1>(lbase + (size_t)(dg + g) * hs * F::BYTES, i, hs, raw[g]);
                 } else if (dg >= a.cpol) {
 #pragma unroll
                     for (int g = 0; g < G; g++)
-                        load_link_raw_wave<LT, R, 0>(lbase + (size_t)(dg + g) * h * F::BYTES, i, h, raw[g]);
+                        load_link_raw_wave<LT, R, 0>(lbase + (size_t)(dg + g) * hs * F::BYTES, i, hs, raw[g]);
                 } else {
 #pragma unroll
                     for (int g = 0; g < G; g++) {
-                        const char *db = lbase + (size_t)(dg + g) * h * F::BYTES;
-                        if (dg + g < a.cpol) load_link_raw_wave<LT, R, 1>(db, i, h, raw[g]);
-                        else load_link_raw_wave<LT, R, 0>(db, i, h, raw[g]);
+                        const char *db = lbase + (size_t)(dg + g) * hs * F::BYTES;
+                        if (dg + g < a.cpol) load_link_raw_wave<LT, R, 1>(db, i, hs, raw[g]);
+                        else load_link_raw_wave<LT, R, 0>(db, i, hs, raw[g]);
                     }
                 }
             }

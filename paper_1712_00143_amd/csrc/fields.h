@@ -100,17 +100,18 @@ template <class LT, int R> struct RawLink {
     uint32_t w[LinkFmt<LT, R>::BYTES / 4];
 };
 
-// Issue the loads of one packed link of direction block `dirbase` at site i.
-// Links are streamed exactly once per Dslash, so they are loaded
-// non-temporally to leave the caches to the gathered colour vectors.
+// Issue the loads of one packed link of direction block `dirbase` at site i;
+// hs is the link set's plane stride in sites (LinkSet::hs).  Links are
+// streamed exactly once per Dslash, so they are loaded non-temporally to
+// leave the caches to the gathered colour vectors.
 template <class LT, int R>
-__device__ __forceinline__ void load_link_raw(const char *__restrict__ dirbase, int i, int h,
+__device__ __forceinline__ void load_link_raw(const char *__restrict__ dirbase, int i, int hs,
                                               RawLink<LT, R> &raw)
 {
     using F = LinkFmt<LT, R>;
 #pragma unroll
     for (int q = 0; q < F::NQ; q++) {
-        u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(dirbase + ((size_t)q * h + i) * 16));
+        u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(dirbase + ((size_t)q * hs + i) * 16));
         raw.w[4 * q + 0] = v.x;
         raw.w[4 * q + 1] = v.y;
         raw.w[4 * q + 2] = v.z;
@@ -118,12 +119,12 @@ __device__ __forceinline__ void load_link_raw(const char *__restrict__ dirbase, 
     }
     if constexpr (F::REM == 8) {
         u32x2 v = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x2 *>(dirbase + (size_t)F::NQ * h * 16 + (size_t)i * 8));
+            reinterpret_cast<const u32x2 *>(dirbase + (size_t)F::NQ * hs * 16 + (size_t)i * 8));
         raw.w[4 * F::NQ + 0] = v.x;
         raw.w[4 * F::NQ + 1] = v.y;
     } else if constexpr (F::REM == 4) {
         raw.w[4 * F::NQ] = __builtin_nontemporal_load(
-            reinterpret_cast<const uint32_t *>(dirbase + (size_t)F::NQ * h * 16 + (size_t)i * 4));
+            reinterpret_cast<const uint32_t *>(dirbase + (size_t)F::NQ * hs * 16 + (size_t)i * 4));
     }
 }
 
@@ -136,26 +137,26 @@ __device__ __forceinline__ void load_link_raw(const char *__restrict__ dirbase, 
 // ordinary loads, so that an operator that fits the Infinity Cache stays
 // there from one application to the next.
 template <class LT, int R, int CP = 0>
-__device__ __forceinline__ void load_link_raw_wave(const char *dirbase, int i, int h, RawLink<LT, R> &raw)
+__device__ __forceinline__ void load_link_raw_wave(const char *dirbase, int i, int hs, RawLink<LT, R> &raw)
 {
     using F = LinkFmt<LT, R>;
     constexpr int NT = CP ? 0 : 2;   // cache-policy bits of the load
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void *)dirbase, (short)0, h * F::BYTES, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)dirbase, (short)0, hs * F::BYTES, 0x00020000);
 #pragma unroll
     for (int q = 0; q < F::NQ; q++) {
-        u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, i * 16, q * h * 16, NT));
+        u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, i * 16, q * hs * 16, NT));
         raw.w[4 * q + 0] = v.x;
         raw.w[4 * q + 1] = v.y;
         raw.w[4 * q + 2] = v.z;
         raw.w[4 * q + 3] = v.w;
     }
     if constexpr (F::REM == 8) {
-        u32x2 v = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, i * 8, F::NQ * h * 16, NT));
+        u32x2 v = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, i * 8, F::NQ * hs * 16, NT));
         raw.w[4 * F::NQ + 0] = v.x;
         raw.w[4 * F::NQ + 1] = v.y;
     } else if constexpr (F::REM == 4) {
-        raw.w[4 * F::NQ] = __builtin_amdgcn_raw_buffer_load_b32(rs, i * 4, F::NQ * h * 16, NT);
+        raw.w[4 * F::NQ] = __builtin_amdgcn_raw_buffer_load_b32(rs, i * 4, F::NQ * hs * 16, NT);
     }
 }
 
@@ -190,10 +191,10 @@ __device__ __forceinline__ void decode_link(const RawLink<LT, R> &raw, Cx<A> u[3
 }
 
 template <class LT, int R, class A>
-__device__ __forceinline__ void load_link(const char *__restrict__ dirbase, int i, int h, Cx<A> u[3][3])
+__device__ __forceinline__ void load_link(const char *__restrict__ dirbase, int i, int hs, Cx<A> u[3][3])
 {
     RawLink<LT, R> raw;
-    load_link_raw<LT, R>(dirbase, i, h, raw);
+    load_link_raw<LT, R>(dirbase, i, hs, raw);
     decode_link<LT, R, A>(raw, u);
 }
 

@@ -33,8 +33,19 @@ struct LinkSet {
     double a[2];          // per-field scale (fat, long): stored value = link / (a * sign)
     int s[2];             // recon-12 sign of the field (+1 / -1), 0 for recon-18
     int valid;
-    int pad;
+    int hs;               // plane stride of the packed links, in sites (link_plane_stride(h))
 };
+
+// Plane stride (in sites) of a packed link set: h rounded up to 8 sites plus
+// 296, i.e. 37 lines of 128 bytes for the 16-byte chunks.  With a stride of
+// exactly h the 16 x NQ chunk planes of a parity start at multiples of a
+// large power of two whenever the half volume is one (8 MiB at 32^4), so one
+// wavefront's loads of a link all fall on the same memory channel and cache
+// set; the odd line offset spreads them.
+inline long long link_plane_stride(long long h)
+{
+    return (h + 7) / 8 * 8 + 296;
+}
 
 // Precision slots: index = prec * 2 + (recon == 12)
 constexpr int NLINKSET = 6;

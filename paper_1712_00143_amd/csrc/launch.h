@@ -75,6 +75,7 @@ struct PackLaunch {
     const double *lng;
     int L[4];
     int h;
+    int hs;              // plane stride of the destination, in sites (>= h)
     int out_par;
     void *dst;           // packed destination for this parity
     double a[2];

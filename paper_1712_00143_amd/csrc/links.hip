@@ -89,16 +89,16 @@ __global__ void k_pack(PackLaunch p)
         e[2 * k + 1] = (LT)(m[r][c].im * inv);
     }
     const uint32_t *raw = reinterpret_cast<const uint32_t *>(e);
-    char *dirbase = (char *)p.dst + (size_t)d * p.h * F::BYTES;
+    char *dirbase = (char *)p.dst + (size_t)d * p.hs * F::BYTES;
 #pragma unroll
     for (int q = 0; q < F::NQ; q++)
-        *reinterpret_cast<uint4 *>(dirbase + ((size_t)q * p.h + i) * 16) =
+        *reinterpret_cast<uint4 *>(dirbase + ((size_t)q * p.hs + i) * 16) =
             make_uint4(raw[4 * q], raw[4 * q + 1], raw[4 * q + 2], raw[4 * q + 3]);
     if constexpr (F::REM == 8)
-        *reinterpret_cast<uint2 *>(dirbase + (size_t)F::NQ * p.h * 16 + (size_t)i * 8) =
+        *reinterpret_cast<uint2 *>(dirbase + (size_t)F::NQ * p.hs * 16 + (size_t)i * 8) =
             make_uint2(raw[4 * F::NQ], raw[4 * F::NQ + 1]);
     else if constexpr (F::REM == 4)
-        *reinterpret_cast<uint32_t *>(dirbase + (size_t)F::NQ * p.h * 16 + (size_t)i * 4) = raw[4 * F::NQ];
+        *reinterpret_cast<uint32_t *>(dirbase + (size_t)F::NQ * p.hs * 16 + (size_t)i * 4) = raw[4 * F::NQ];
 }
 
 template <class LT, int R>

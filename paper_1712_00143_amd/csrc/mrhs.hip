@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(64 * W) k_dslash_mrhs(MrhsLaunch a)
             RawLink<LT, R> raw[G];
 #pragma unroll
             for (int g = 0; g < G; g++)
-                load_link_raw_wave<LT, R>(lbase + (size_t)(wave * DPW + g0 + g) * h * F::BYTES, i, h, raw[g]);
+                load_link_raw_wave<LT, R>(lbase + (size_t)(wave * DPW + g0 + g) * ls.hs * F::BYTES, i, ls.hs, raw[g]);
             Cx<A> v[G][NR][3];
 #pragma unroll
             for (int g = 0; g < G; g++)

@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) k_dslash_mrhs_mfma(MrhsLaunch a)
         v += v < 0 ? Lm : 0;
         const int nb = (lex + (v - x) * Sm) >> 1;
         RawLink<LT, R> raw;
-        load_link_raw_wave<LT, R, 0>(lbase + (size_t)d * h * F::BYTES, ic, h, raw);
+        load_link_raw_wave<LT, R, 0>(lbase + (size_t)d * ls.hs * F::BYTES, ic, ls.hs, raw);
         float2 vv[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
         if (valid && act) {
             const float2 *p = in + ((long long)rhs * a.vstride + nb) * 3;

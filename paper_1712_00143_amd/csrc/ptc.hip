@@ -63,7 +63,7 @@ __device__ __forceinline__ void path_load(const ProbDesc &pd, const LinkSet &ls,
         const int d = 4 * mu + (fwd ? 0 : 1);
         // the fat links are re-read by every layer of every application: keep
         // them cached (temporal loads)
-        load_link_raw_wave<LT, R, 1>((const char *)ls.ptr[par] + (size_t)d * h * F::BYTES, i, (int)h, raw);
+        load_link_raw_wave<LT, R, 1>((const char *)ls.ptr[par] + (size_t)d * ls.hs * F::BYTES, i, ls.hs, raw);
     }
 #pragma unroll
     for (int c = 0; c < CIN; c++) {

@@ -163,7 +163,7 @@ __device__ __forceinline__ void ptc_mix_mfma(const PtcInferLaunch &a, const Prob
                 site = nbr1(co, lex, mu, fwd ? 1 : -1, pd.L);
                 sp = 1 - par;
                 const int d = 4 * mu + (fwd ? 0 : 1);
-                load_link_raw_wave<LT, R, 1>((const char *)ls.ptr[par] + (size_t)d * h * F::BYTES, i, h, raw[g]);
+                load_link_raw_wave<LT, R, 1>((const char *)ls.ptr[par] + (size_t)d * ls.hs * F::BYTES, i, ls.hs, raw[g]);
             }
             if constexpr (IK == 0) {
                 const float2 *p = reinterpret_cast<const float2 *>(a.in32) + (size_t)site * 3;
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(64 * W) k_ptc_infer(PtcInferLaunch a)
                     sp = 1 - par;
                     const int d = 4 * mu + (fwd ? 0 : 1);
                     // the fat links are read by every layer: cached loads
-                    load_link_raw_wave<LT, R, 1>((const char *)ls.ptr[par] + (size_t)d * h * F::BYTES, i, h, raw[g]);
+                    load_link_raw_wave<LT, R, 1>((const char *)ls.ptr[par] + (size_t)d * ls.hs * F::BYTES, i, ls.hs, raw[g]);
                 }
                 if constexpr (IK == 0) {
                     const float2 *p = reinterpret_cast<const float2 *>(a.in32) + (size_t)site * 3;
