@@ -582,10 +582,12 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
     // alternating launches); when they do not, a part of the direction blocks
     // cached (a stream larger than the cache would only evict itself) or none.
     // Each candidate is timed the same way from the same start: an emptied
-    // cache, six warm-up applications, then the best of three trials of 10.
-    // A partly cached operator changes which block shape and tile order are
-    // best, so there every shape and order is tried with every candidate;
-    // otherwise the ones found above are kept.
+    // cache, six warm-up applications, then the best of three trials of 10
+    // (40 for an operator that fits the cache).  Cached loads change which block shape and tile order are best, so every
+    // shape and order is tried with every cached candidate; streaming keeps
+    // the shape found above.  An operator that fits is timed over longer
+    // trials: the streamed policy loses rate over a long run of alternating
+    // applications that a trial of ten does not show.
     if (best.us < 1e29) {
         const double op_bytes = 2.0 * (double)nsite * (double)link_site_bytes(prec, recon);
         const bool partial = op_bytes > 200e6;
@@ -597,8 +599,9 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
         for (int wi = 0; wi < NWS; wi++)
         for (int rm = 0; rm < 2; rm++) {
             const int W = Ws[wi];
-            if (!okc[wi][rm] || (!partial && (W != best.W || rm != best.remap))) continue;
+            if (!okc[wi][rm]) continue;
             for (size_t ci = 0; ci < cands.size(); ci++) {
+                if (cands[ci] == 0 && (W != best.W || rm != best.remap)) continue;
                 const DslashLaunch a0 = make(rm, 0, cands[ci]), a1 = make(rm, 1, cands[ci]);
                 flush_cache();
                 bool ok = true;
@@ -607,7 +610,7 @@ TuneChoice pick_shape(hisq_lattice lat, int prec, int recon, const ProbDesc *dde
                 if (!ok) continue;
                 double t = 1e30;
                 for (int trial = 0; trial < 3; trial++) {
-                    const int reps = 10;
+                    const int reps = partial ? 10 : 40;
                     (void)hipEventRecord(e0, lat->s);
                     for (int r = 0; r < reps; r++)
                         (void)launch_dslash(prec, recon, prec, EPI_PLAIN, W, r & 1 ? a1 : a0, ntile, lat->s);
