@@ -143,7 +143,11 @@ hisq_status hisq_load_links(hisq_lattice lat, const double *fat, const double *l
 /* Build the packed operator in precision `prec` with reconstruction `recon`
  * from the loaded FP64 links (on the device).  Recon-12 requires each link to
  * be c * SU(3), c = s * eta_mu(x) * a with one a > 0 and one s = +-1 per
- * field; it returns HISQ_ERR_RECON if row 3 is not recovered to 1e-10 * a. */
+ * field; it returns HISQ_ERR_RECON if row 3 is not recovered to 1e-10 * a.
+ * The packed links of one direction are addressed with 32-bit offsets:
+ * HISQ_ERR_ARG if one direction block (about V/2 sites x the link's bytes,
+ * 144 in FP64 recon-18) would reach 2 GiB, i.e. V above about 29.8 million
+ * sites in FP64 recon-18 (59.6 million in FP32). */
 hisq_status hisq_prepare_links(hisq_lattice lat, hisq_prec prec, hisq_recon recon);
 
 /* out = D_{out_parity, 1-out_parity} in, i.e. D_eo (HISQ_EVEN) or D_oe
