@@ -137,7 +137,8 @@ hisq_status hisq_destroy(hisq_lattice lat);
 
 /* Load fat and long links (layout above, phases folded; host pointers, or
  * device pointers with HISQ_DEVICE_PTR).  Keeps a device FP64 copy and packs
- * the FP64 recon-18 operator.  Discards earlier link sets. */
+ * the FP64 recon-18 operator (errors of that packing as hisq_prepare_links).
+ * Discards earlier link sets. */
 hisq_status hisq_load_links(hisq_lattice lat, const double *fat, const double *lng, int flags);
 
 /* Build the packed operator in precision `prec` with reconstruction `recon`
