@@ -197,7 +197,7 @@ def test_long_link_phase_fold_order():
 @pytest.mark.parametrize("sigma", [0.0, 0.3])
 @pytest.mark.parametrize("target", [1.0, 1e-3, 1e-11])
 def test_true_residual_matches_dense_definition(dims, sigma, target):
-    """The oracle's true residual ||b - (A + sigma) x|| / ||b|| (the judge of
+    """The oracle's true residual ||b - (A + sigma) x|| / ||b|| (the arbiter of
     every solver comparison) against the same quantity computed here from the
     dense D assembled term by term above: A = (4m^2 + sigma) - D_eo D_oe on
     even sites.  x = the dense solution plus a random perturbation scaled so
