@@ -11,6 +11,7 @@
 #include <vector>
 
 #include <cmath>
+#include <cstring>
 
 #include "fforce.h"
 #include "gforce.h"
@@ -396,13 +397,26 @@ hisq_status ff_check(hisq_lattice lat, int n, const double *alpha, const double 
 }
 
 // Y_k = D_oe X_k on the lattice's FP64 links; X, Y device [n][h][3] complex.
+// One multi-right-hand-side launch: each link read serves four vectors.
 hisq_status ff_solutions_odd(hisq_lattice lat, int n, const double2 *X, double2 *Y)
 {
-    for (int k = 0; k < n; k++) {
-        hisq_status st = hisq_dslash(lat, HISQ_ODD, HISQ_F64, HISQ_RECON_18, X + (size_t)k * lat->h * 3,
-                                     Y + (size_t)k * lat->h * 3, 1, HISQ_DEVICE_PTR);
-        if (st != HISQ_OK) return st;
-    }
+    if (n < 1) return HISQ_OK;
+    const int group = n < 4 ? n : 4;
+    const TuneChoice tc = pick_shape_mrhs(lat, 0, 18, group, false);
+    MrhsLaunch a;
+    memset(&a, 0, sizeof a);
+    a.probs = lat->ddesc;
+    a.desc_stride = 0;
+    a.remap = tc.remap;
+    a.out_par = HISQ_ODD;
+    a.lslot = 0;   // FP64 recon-18
+    a.nrhs = n;
+    a.vstride = lat->h;
+    a.in = X;
+    a.out = Y;
+    a.epi = EPI_PLAIN;
+    hipError_t e = launch_dslash_mrhs(0, 18, group, tc.W, a, lat->ntile, lat->s);
+    if (e != hipSuccess) return hip_err(lat, e, "D_oe of the solution vectors");
     return HISQ_OK;
 }
 
