@@ -84,6 +84,22 @@ def test_fermion_force_parity(dims):
     lat.close()
 
 
+@pytest.mark.parametrize("nterm", [1, 4, 5, 9])
+def test_fermion_force_term_counts(nterm):
+    """The D_oe of the solution vectors runs four vectors per link read: one
+    term, a full group, and groups with a partial last one."""
+    H = _hisq()
+    dims = (4, 4, 4, 6)
+    U = synth.thin_links(dims, 0.4, 160)
+    alphas = tuple(np.random.default_rng(161).uniform(0.1, 1.0, nterm))
+    xs = [synth.gaussian_even(dims, 170 + k) for k in range(nterm)]
+    lat = H.Lattice(dims)
+    F = lat.fermion_force(U, alphas, np.stack(xs))
+    ref = oracle.hisq_fermion_force(dims, U, alphas, xs)
+    check(_links(F), _links(ref), 1e-12, ("force", dims, nterm))
+    lat.close()
+
+
 # 16^4: one time slice per block; 32^3x8: runs of two time slices per block
 @pytest.mark.parametrize("reps", [(2, 2, 2, 2), (4, 4, 4, 1)], ids=["16x16x16x16", "32x32x32x8"])
 def test_fermion_force_tiled_and_gauge_rotated(reps):
