@@ -231,6 +231,35 @@ def test_fcg_falls_back_on_breakdown():
     lat.close()
 
 
+@pytest.mark.parametrize("flags", [0, 4], ids=["eager", "graph"])
+def test_fcg_hands_over_at_half_maxiter(flags):
+    """The flexible CG stops at maxiter / 2 iterations (checked after each
+    chunk and after each device-gated restart) and hands its iterate to CG,
+    which gets the rest of maxiter: enough here to converge, and the same
+    solution as without the cap to the solver tolerance."""
+    H = _hisq()
+    dims = (8, 8, 8, 8)
+    m = 0.01
+    fat, lng = synth.make_links(dims, 0.25, seed=4010)
+    lat = H.Lattice(dims)
+    lat.load_links(fat, lng)
+    net = H.PTC(lat, (1, 4, 4, 1))
+    net.init_polynomial(a=4.0, c=1.2)
+    b = synth.gaussian_even(dims, 4510)
+    _, free = net.cg_learned(lat, m, b, params=H.hisq_default_params(tol=1e-10, sloppy=1, flags=flags))
+    assert free["fell_back"] == 0
+    cap = free["iters"]   # the FCG stops near cap / 2 iterations
+    p = H.hisq_default_params(tol=1e-10, sloppy=1, maxiter=cap, check_every=8, flags=flags)
+    x, info = net.cg_learned(lat, m, b, params=p, raise_on_fail=False)
+    assert info["fell_back"] == 1
+    assert cap // 2 <= info["fcg_iters"] <= cap // 2 + 8
+    if info["converged"]:
+        assert oracle.true_residual(dims, fat, lng, m, b, x) <= 1.5e-10
+    assert info["iters"] <= cap + 8
+    net.close()
+    lat.close()
+
+
 @pytest.mark.parametrize("chans", [(1, 4, 4, 1), (1, 4, 1)], ids=["1-4-4-1", "1-4-1"])
 def test_training_lowers_loss_and_reports_gain(chans):
     """Train from small random weights on fields 0..3 (pairs harvested by the
