@@ -187,7 +187,7 @@ def test_dslash_long_extent_exact_division_path():
 def test_dslash_32x32x32x32_beyond_cache():
     """The 32^4 lattice the benchmark uses beyond the Infinity Cache (629 MB of
     FP32 links per half-Dslash), FP64 recon-18 (the headline format), FP32
-    recon-18 and FP16 recon-12, both parities, in the tuned launch and with
+    recon-18, FP32 recon-12 and FP16 recon-12, both parities, in the tuned launch and with
     every link streamed (HISQ_STREAM_LINKS, the benchmark's headline launch),
     every output against the oracle."""
     H = _hisq()
@@ -198,7 +198,7 @@ def test_dslash_32x32x32x32_beyond_cache():
     for par in (0, 1):
         psi = synth.gaussian_even(dims, 1950 + par)
         ref = oracle.dslash_half(dims, fat, lng, par, psi)
-        for p, r in [(0, 18), (1, 18), (2, 12)]:
+        for p, r in [(0, 18), (1, 18), (1, 12), (2, 12)]:
             lat.prepare_links(p, r)
             for flags in (0, H.HISQ_STREAM_LINKS):   # tuned policy, and streamed links (the headline launch)
                 out = np.zeros_like(psi)
